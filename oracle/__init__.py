@@ -1,0 +1,204 @@
+"""FP64 CPU oracle: plain, slow, obviously correct reference results.
+
+TEST INFRASTRUCTURE. Only the test suite, the smoke check and the bench's
+CPU-baseline leg import this package. The HIP product path never imports,
+links or calls it, and it shares no code with that path: both sides take the
+same seeded inputs from ``paper_2306_14011_amd.inputs`` and nothing else.
+
+Contents:
+  * ``liboracle.so`` (from ``fv_oracle.cpp``): MUSCL-minmod, Roe flux, residual,
+    CFL wave-speed reduction and SSP-RK3 step (Eq. QF, residual, flux of the
+    paper), plus complex-step derivatives of the residual and the step.
+  * ``exact.py``: Toro's exact Riemann solver for the Sod tube.
+  * ``adjoint.py``: reverse-mode gradient of the discrete step map.
+  * ``mlp.py``: the runtime-regression network of the autotuner in FP64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_u32_p = ctypes.POINTER(ctypes.c_uint32)
+
+
+class OrGrid(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("limiter", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+    ]
+
+
+FLAG_NAN = 1
+FLAG_RHO = 2
+FLAG_P = 4
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = ctypes.CDLL(path)
+        L.or_psi_minmod.restype = ctypes.c_double
+        L.or_psi_minmod.argtypes = [ctypes.c_double]
+        L.or_limited.restype = ctypes.c_double
+        L.or_limited.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.or_muscl.restype = None
+        L.or_muscl.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, ctypes.c_double, c_double_p, c_double_p]
+        L.or_phys_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, c_double_p, c_double_p]
+        L.or_roe_flux.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, c_double_p, c_double_p, c_double_p]
+        g = ctypes.POINTER(OrGrid)
+        L.or_residual.argtypes = [g, c_double_p, c_double_p]
+        L.or_residual_cs.argtypes = [g, c_double_p, c_double_p, ctypes.c_double, c_double_p, c_double_p]
+        L.or_max_wavespeed.restype = ctypes.c_double
+        L.or_max_wavespeed.argtypes = [g, c_double_p, c_u32_p]
+        L.or_dt.restype = ctypes.c_double
+        L.or_dt.argtypes = [g, c_double_p, c_u32_p]
+        L.or_rk3_step.argtypes = [g, c_double_p, ctypes.c_double]
+        L.or_rk3_step_cs.argtypes = [g, c_double_p, c_double_p, ctypes.c_double, ctypes.c_double,
+                                     c_double_p, c_double_p]
+        L.or_run.argtypes = [g, c_double_p, ctypes.c_int32, c_double_p, c_double_p, c_u32_p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(c_double_p)
+
+
+def make_grid(spec, limiter=True, kappa=-1.0):
+    """OrGrid from any object with ndim, n, lo, hi, bc, gamma, cfl attributes."""
+    g = OrGrid()
+    g.ndim = spec.ndim
+    g.limiter = 1 if limiter else 0
+    for d in range(3):
+        g.n[d] = int(spec.n[d])
+        g.dx[d] = (spec.hi[d] - spec.lo[d]) / spec.n[d]
+        g.bc[d][0] = int(spec.bc[d][0])
+        g.bc[d][1] = int(spec.bc[d][1])
+    g.gamma = float(spec.gamma)
+    g.cfl = float(spec.cfl)
+    g.kappa = float(kappa)
+    return g
+
+
+def _arr(U):
+    return np.ascontiguousarray(U, dtype=np.float64)
+
+
+def psi_minmod(r):
+    return lib().or_psi_minmod(float(r))
+
+
+def limited(num, den, limiter=True):
+    return lib().or_limited(float(num), float(den), 1 if limiter else 0)
+
+
+def muscl(qm1, q0, qp1, qp2, limiter=True, kappa=-1.0):
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    lib().or_muscl(qm1, q0, qp1, qp2, 1 if limiter else 0, kappa, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def phys_flux(ndim, ax, Q, gamma=1.4):
+    Q = _arr(Q)
+    F = np.zeros(ndim + 2)
+    lib().or_phys_flux(ndim, ax, gamma, _p(Q), _p(F))
+    return F
+
+
+def roe_flux(ndim, ax, QL, QR, gamma=1.4):
+    QL = _arr(QL)
+    QR = _arr(QR)
+    F = np.zeros(ndim + 2)
+    lib().or_roe_flux(ndim, ax, gamma, _p(QL), _p(QR), _p(F))
+    return F
+
+
+def residual(spec, U, limiter=True, kappa=-1.0):
+    g = make_grid(spec, limiter, kappa)
+    U = _arr(U)
+    R = np.zeros_like(U)
+    lib().or_residual(ctypes.byref(g), _p(U), _p(R))
+    return R
+
+
+def residual_cs(spec, U, V, h=1e-30, limiter=True):
+    g = make_grid(spec, limiter)
+    U = _arr(U)
+    V = _arr(V)
+    R = np.zeros_like(U)
+    dR = np.zeros_like(U)
+    lib().or_residual_cs(ctypes.byref(g), _p(U), _p(V), h, _p(R), _p(dR))
+    return R, dR
+
+
+def max_wavespeed(spec, U):
+    g = make_grid(spec)
+    U = _arr(U)
+    fl = ctypes.c_uint32(0)
+    lam = lib().or_max_wavespeed(ctypes.byref(g), _p(U), ctypes.byref(fl))
+    return lam, fl.value
+
+
+def dt(spec, U):
+    g = make_grid(spec)
+    U = _arr(U)
+    fl = ctypes.c_uint32(0)
+    v = lib().or_dt(ctypes.byref(g), _p(U), ctypes.byref(fl))
+    return v, fl.value
+
+
+def rk3_step(spec, U, dt_, limiter=True, kappa=-1.0):
+    g = make_grid(spec, limiter, kappa)
+    U = _arr(U).copy()
+    lib().or_rk3_step(ctypes.byref(g), _p(U), float(dt_))
+    return U
+
+
+def rk3_step_cs(spec, U, V, dt_, h=1e-30, limiter=True):
+    g = make_grid(spec, limiter)
+    U = _arr(U)
+    V = _arr(V)
+    Un = np.zeros_like(U)
+    dUn = np.zeros_like(U)
+    lib().or_rk3_step_cs(ctypes.byref(g), _p(U), _p(V), h, float(dt_), _p(Un), _p(dUn))
+    return Un, dUn
+
+
+def run(spec, U, nsteps, dt_in=None, limiter=True, kappa=-1.0):
+    """Advance ``nsteps`` SSP-RK3 steps; returns (U, dt per step, flags)."""
+    g = make_grid(spec, limiter, kappa)
+    U = _arr(U).copy()
+    dts = np.zeros(max(nsteps, 1))
+    fl = ctypes.c_uint32(0)
+    dti = None
+    if dt_in is not None:
+        dti = _arr(dt_in)
+    lib().or_run(ctypes.byref(g), _p(U), int(nsteps), _p(dti) if dti is not None else None,
+                 _p(dts), ctypes.byref(fl))
+    return U, dts[:nsteps], fl.value
+
+
+def omp_threads():
+    """Threads the oracle's OpenMP loops use (OMP_NUM_THREADS or all cores)."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    if v:
+        try:
+            return int(v)
+        except ValueError:
+            pass
+    return os.cpu_count() or 1

@@ -1,0 +1,384 @@
+// FP64 CPU oracle for the explicit finite-volume Euler step.
+//
+// TEST INFRASTRUCTURE ONLY. Nothing on the product path links, loads or calls
+// this file; only the test suite, the smoke check and the CPU-baseline leg of
+// the bench do. It shares no code, header or constant with the HIP library.
+//
+// What it computes, each part following the paper's description of SENSEI:
+//   * cell-wise semi-discrete form |Omega_k| dU/dt + R = 0 (Eq. spatial_residual),
+//   * residual R = sum over faces of the normal inviscid flux times face area,
+//     source term zero (Eq. residual; the inviscid flux of Eq. QF),
+//   * face states by MUSCL extrapolation with epsilon = 1 and a limiter Psi
+//     (Eq. flux); kappa is a parameter, -1 (fully upwind) on the measured path,
+//   * an explicit Runge-Kutta march (Sec. "A Test Case"), here the three-stage
+//     strong-stability-preserving scheme of Shu and Osher,
+//   * a stability-limited time step (Sec. "The CFD Code Base": the ODE solver is
+//     used "provided stability conditions are met"): dt = CFL / max_cells
+//     sum_d (|u_d| + c) / dx_d.
+// The paper names no limiter, flux function or Runge-Kutta order; this oracle
+// uses the minmod limiter, Roe's approximate Riemann solver (Roe 1981; Toro,
+// "Riemann Solvers and Numerical Methods for Fluid Dynamics", ch. 11) and
+// SSP-RK3, taken in the textbook form written out below.
+//
+// Layout: interior cells only, U[v][k][j][i], v over (rho, rho u, rho v,
+// [rho w], E). Boundary conditions are index maps: a periodic face wraps the
+// index, a transmissive face clamps it to the nearest interior cell (a
+// zero-gradient ghost state). Two ghost layers are implied by the 4-cell
+// MUSCL stencil.
+//
+// Every routine is a template over the scalar type so that the same code runs
+// on std::complex<double> for complex-step derivatives (Squire & Trapp 1998):
+// branches (limiter, |lambda|) are taken on the real part.
+//
+// Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (see oracle/build.py).
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+typedef std::complex<double> cplx;
+
+extern "C" {
+// Grid description passed from Python (ctypes mirrors this struct).
+struct OrGrid {
+    int32_t ndim;       // 2 or 3
+    int32_t limiter;    // 1 = minmod, 0 = unlimited (Psi = 1), test use only
+    int64_t n[3];       // cells per axis (n[2] = 1 in 2D)
+    double dx[3];       // cell widths
+    int32_t bc[3][2];   // 0 = periodic, 1 = transmissive, per axis and side
+    double gamma;       // ratio of specific heats
+    double cfl;         // CFL number for the stable time step
+    double kappa;       // MUSCL kappa (-1 on the measured path)
+};
+}
+
+// Flag bits returned by the wave-speed reduction.
+static const uint32_t OR_FLAG_NAN = 1u;
+static const uint32_t OR_FLAG_RHO = 2u;
+static const uint32_t OR_FLAG_P = 4u;
+
+static inline double re(double x) { return x; }
+static inline double re(const cplx& x) { return x.real(); }
+
+// |x| with the branch taken on the real part; the derivative at 0 is 0.
+template <class T> static inline T absr(const T& x) {
+    if (re(x) > 0.0) return x;
+    if (re(x) < 0.0) return -x;
+    return T(0.0);
+}
+
+// minmod limiter function Psi(r) = max(0, min(1, r)) (Roe / Sweby form).
+template <class T> static inline T psi_minmod(const T& r) {
+    if (!(re(r) > 0.0)) return T(0.0);
+    if (re(r) < 1.0) return r;
+    return T(1.0);
+}
+
+// Limited difference Psi(num/den) * den, with Psi * 0 := 0.
+// For Psi = minmod this equals minmod(den, num); with the limiter off Psi = 1.
+template <class T> static inline T limited(const T& num, const T& den, int limiter) {
+    if (!limiter) return den;
+    if (re(den) == 0.0) return T(0.0);
+    return psi_minmod(num / den) * den;
+}
+
+// MUSCL extrapolation to face k+1/2 from cells k-1, k, k+1, k+2 (Eq. flux):
+//   QL = Q_k     + eps/4 [(1-kappa) Psi+_{k-1/2} (Q_k - Q_{k-1})
+//                       + (1+kappa) Psi-_{k+1/2} (Q_{k+1} - Q_k)]
+//   QR = Q_{k+1} - eps/4 [(1+kappa) Psi+_{k+1/2} (Q_{k+1} - Q_k)
+//                       + (1-kappa) Psi-_{k+3/2} (Q_{k+2} - Q_{k+1})]
+// with eps = 1 and the ratios r+_{j} = dQ_{j+1}/dQ_{j}, r-_{j} = dQ_{j-1}/dQ_{j}
+// of consecutive differences dQ_{k-1/2}, dQ_{k+1/2}, dQ_{k+3/2}.
+template <class T>
+static inline void muscl(const T& qm1, const T& q0, const T& qp1, const T& qp2,
+                         int limiter, double kappa, T& qL, T& qR) {
+    const double eps = 1.0;
+    T dm = q0 - qm1;   // dQ_{k-1/2}
+    T d0 = qp1 - q0;   // dQ_{k+1/2}
+    T dp = qp2 - qp1;  // dQ_{k+3/2}
+    T lim_m_plus = limited(d0, dm, limiter);   // Psi+_{k-1/2} dQ_{k-1/2}
+    T lim_0_minus = limited(dm, d0, limiter);  // Psi-_{k+1/2} dQ_{k+1/2}
+    T lim_0_plus = limited(dp, d0, limiter);   // Psi+_{k+1/2} dQ_{k+1/2}
+    T lim_p_minus = limited(d0, dp, limiter);  // Psi-_{k+3/2} dQ_{k+3/2}
+    qL = q0 + (eps / 4.0) * ((1.0 - kappa) * lim_m_plus + (1.0 + kappa) * lim_0_minus);
+    qR = qp1 - (eps / 4.0) * ((1.0 + kappa) * lim_0_plus + (1.0 - kappa) * lim_p_minus);
+}
+
+// Physical inviscid flux normal to axis `ax` (Eq. QF with n = e_ax).
+template <class T>
+static void phys_flux(int ndim, int ax, double gam, const T* Q, T* F) {
+    const int ie = ndim + 1;
+    T rho = Q[0];
+    T u[3];
+    T qq = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        u[d] = Q[1 + d] / rho;
+        qq = qq + u[d] * u[d];
+    }
+    T p = (gam - 1.0) * (Q[ie] - 0.5 * rho * qq);
+    T vn = u[ax];
+    F[0] = rho * vn;
+    for (int d = 0; d < ndim; ++d) F[1 + d] = rho * u[d] * vn + (d == ax ? p : T(0.0));
+    F[ie] = (Q[ie] + p) * vn;  // rho h_t V_n with h_t = (E + p)/rho
+}
+
+// Roe flux normal to axis `ax`: F = (F(QL) + F(QR))/2 - sum_k |lambda_k| alpha_k r_k / 2.
+template <class T>
+static void roe_flux(int ndim, int ax, double gam, const T* QL, const T* QR, T* F) {
+    const int nv = ndim + 2;
+    const int ie = ndim + 1;
+    T FL[5], FR[5];
+    phys_flux(ndim, ax, gam, QL, FL);
+    phys_flux(ndim, ax, gam, QR, FR);
+
+    T rL = QL[0], rR = QR[0];
+    T uL[3], uR[3];
+    T qqL = T(0.0), qqR = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        uL[d] = QL[1 + d] / rL;
+        uR[d] = QR[1 + d] / rR;
+        qqL = qqL + uL[d] * uL[d];
+        qqR = qqR + uR[d] * uR[d];
+    }
+    T pL = (gam - 1.0) * (QL[ie] - 0.5 * rL * qqL);
+    T pR = (gam - 1.0) * (QR[ie] - 0.5 * rR * qqR);
+    T HL = (QL[ie] + pL) / rL;
+    T HR = (QR[ie] + pR) / rR;
+
+    // Roe-averaged state.
+    T sL = std::sqrt(rL), sR = std::sqrt(rR);
+    T ut[3];
+    T qqt = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        ut[d] = (sL * uL[d] + sR * uR[d]) / (sL + sR);
+        qqt = qqt + ut[d] * ut[d];
+    }
+    T Ht = (sL * HL + sR * HR) / (sL + sR);
+    T rt = sL * sR;
+    T c2 = (gam - 1.0) * (Ht - 0.5 * qqt);
+    T c = std::sqrt(c2);
+    T un = ut[ax];
+
+    // Wave strengths.
+    T drho = rR - rL;
+    T dpr = pR - pL;
+    T du[3];
+    for (int d = 0; d < ndim; ++d) du[d] = uR[d] - uL[d];
+    T a1 = (dpr - rt * c * du[ax]) / (2.0 * c2);
+    T a2 = drho - dpr / c2;
+    T a5 = (dpr + rt * c * du[ax]) / (2.0 * c2);
+
+    // Wave speeds.
+    T l1 = absr(un - c), l2 = absr(un), l5 = absr(un + c);
+
+    // Sum of |lambda_k| alpha_k r_k, eigenvector by eigenvector.
+    T D[5];
+    for (int v = 0; v < nv; ++v) D[v] = T(0.0);
+    // acoustic wave u_n - c: r1 = (1, u - c e_ax, H - u_n c)
+    D[0] = D[0] + l1 * a1;
+    for (int d = 0; d < ndim; ++d) D[1 + d] = D[1 + d] + l1 * a1 * (ut[d] - (d == ax ? c : T(0.0)));
+    D[ie] = D[ie] + l1 * a1 * (Ht - un * c);
+    // entropy wave u_n: r2 = (1, u, |u|^2/2)
+    D[0] = D[0] + l2 * a2;
+    for (int d = 0; d < ndim; ++d) D[1 + d] = D[1 + d] + l2 * a2 * ut[d];
+    D[ie] = D[ie] + l2 * a2 * (0.5 * qqt);
+    // shear waves u_n, one per tangential axis t: r_t = (0, e_t, u_t), alpha_t = rho du_t
+    for (int t = 0; t < ndim; ++t) {
+        if (t == ax) continue;
+        T at = rt * du[t];
+        D[1 + t] = D[1 + t] + l2 * at;
+        D[ie] = D[ie] + l2 * at * ut[t];
+    }
+    // acoustic wave u_n + c: r5 = (1, u + c e_ax, H + u_n c)
+    D[0] = D[0] + l5 * a5;
+    for (int d = 0; d < ndim; ++d) D[1 + d] = D[1 + d] + l5 * a5 * (ut[d] + (d == ax ? c : T(0.0)));
+    D[ie] = D[ie] + l5 * a5 * (Ht + un * c);
+
+    for (int v = 0; v < nv; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
+}
+
+// Ghost-index map of one axis: periodic wraps, transmissive clamps.
+static inline int64_t bc_index(int64_t i, int64_t n, int lo_kind, int hi_kind) {
+    if (i < 0) {
+        if (lo_kind == 0) return ((i % n) + n) % n;
+        return 0;
+    }
+    if (i >= n) {
+        if (hi_kind == 0) return i % n;
+        return n - 1;
+    }
+    return i;
+}
+
+static inline int64_t cell_offset(const OrGrid* g, int64_t i, int64_t j, int64_t k) {
+    return (k * g->n[1] + j) * g->n[0] + i;
+}
+
+// Flux through the face between cell c and cell c + e_ax (c given by i, j, k).
+template <class T>
+static void face_flux(const OrGrid* g, const T* U, int ax, int64_t i, int64_t j, int64_t k, T* F) {
+    const int nv = g->ndim + 2;
+    const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+    int64_t idx[3] = {i, j, k};
+    int64_t off[4];
+    for (int m = 0; m < 4; ++m) {
+        int64_t c[3] = {idx[0], idx[1], idx[2]};
+        c[ax] = idx[ax] - 1 + m;  // cells k-1, k, k+1, k+2 along the axis
+        c[ax] = bc_index(c[ax], g->n[ax], g->bc[ax][0], g->bc[ax][1]);
+        off[m] = cell_offset(g, c[0], c[1], c[2]);
+    }
+    T QL[5], QR[5];
+    for (int v = 0; v < nv; ++v) {
+        const T* Uv = U + v * ncell;
+        muscl(Uv[off[0]], Uv[off[1]], Uv[off[2]], Uv[off[3]], g->limiter, g->kappa, QL[v], QR[v]);
+    }
+    roe_flux(g->ndim, ax, g->gamma, QL, QR, F);
+}
+
+static inline double face_area(const OrGrid* g, int ax) {
+    double a = 1.0;
+    for (int d = 0; d < g->ndim; ++d)
+        if (d != ax) a *= g->dx[d];
+    return a;
+}
+
+static inline double cell_volume(const OrGrid* g) {
+    double v = 1.0;
+    for (int d = 0; d < g->ndim; ++d) v *= g->dx[d];
+    return v;
+}
+
+// R_c = sum_ax (F_{c+1/2} - F_{c-1/2}) * A_ax   (Eq. residual, S = 0).
+template <class T>
+static void residual(const OrGrid* g, const T* U, T* R) {
+    const int nv = g->ndim + 2;
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t ncell = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < ncell; ++c) {
+        int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        T acc[5];
+        for (int v = 0; v < nv; ++v) acc[v] = T(0.0);
+        for (int ax = 0; ax < g->ndim; ++ax) {
+            int64_t im[3] = {i, j, k};
+            im[ax] -= 1;  // the cell on the low side of face c-1/2
+            T Fp[5], Fm[5];
+            face_flux(g, U, ax, i, j, k, Fp);
+            face_flux(g, U, ax, im[0], im[1], im[2], Fm);
+            double A = face_area(g, ax);
+            for (int v = 0; v < nv; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]) * A;
+        }
+        for (int v = 0; v < nv; ++v) R[v * ncell + c] = acc[v];
+    }
+}
+
+// One SSP-RK3 step (Shu-Osher form) with L(U) = -R(U)/|Omega|:
+//   U1 = U + dt L(U);  U2 = 3/4 U + 1/4 (U1 + dt L(U1));  U' = 1/3 U + 2/3 (U2 + dt L(U2)).
+template <class T>
+static void rk3_step(const OrGrid* g, T* U, double dt) {
+    const int nv = g->ndim + 2;
+    const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+    const int64_t N = nv * ncell;
+    const double vol = cell_volume(g);
+    std::vector<T> R(N), U1(N), U2(N);
+    residual(g, U, R.data());
+    for (int64_t e = 0; e < N; ++e) U1[e] = U[e] + dt * (-R[e] / vol);
+    residual(g, U1.data(), R.data());
+    for (int64_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * (-R[e] / vol));
+    residual(g, U2.data(), R.data());
+    for (int64_t e = 0; e < N; ++e) U[e] = (1.0 / 3.0) * U[e] + (2.0 / 3.0) * (U2[e] + dt * (-R[e] / vol));
+}
+
+extern "C" {
+
+double or_psi_minmod(double r) { return psi_minmod(r); }
+
+double or_limited(double num, double den, int limiter) { return limited(num, den, limiter); }
+
+void or_muscl(double qm1, double q0, double qp1, double qp2, int limiter, double kappa,
+              double* qL, double* qR) {
+    muscl(qm1, q0, qp1, qp2, limiter, kappa, *qL, *qR);
+}
+
+void or_phys_flux(int ndim, int ax, double gam, const double* Q, double* F) {
+    phys_flux(ndim, ax, gam, Q, F);
+}
+
+void or_roe_flux(int ndim, int ax, double gam, const double* QL, const double* QR, double* F) {
+    roe_flux(ndim, ax, gam, QL, QR, F);
+}
+
+void or_residual(const OrGrid* g, const double* U, double* R) { residual(g, U, R); }
+
+// Directional derivative of R along V by the complex step: R(U + i h V) = R + i h dR.
+void or_residual_cs(const OrGrid* g, const double* U, const double* V, double h, double* R, double* dR) {
+    const int64_t N = (int64_t)(g->ndim + 2) * g->n[0] * g->n[1] * g->n[2];
+    std::vector<cplx> Uc(N), Rc(N);
+    for (int64_t e = 0; e < N; ++e) Uc[e] = cplx(U[e], h * V[e]);
+    residual(g, Uc.data(), Rc.data());
+    for (int64_t e = 0; e < N; ++e) {
+        R[e] = Rc[e].real();
+        dR[e] = Rc[e].imag() / h;
+    }
+}
+
+// max over cells of sum_d (|u_d| + c)/dx_d, with flags for NaN, rho <= 0, p <= 0.
+double or_max_wavespeed(const OrGrid* g, const double* U, uint32_t* flags) {
+    const int ndim = g->ndim, ie = ndim + 1;
+    const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+    double lmax = 0.0;
+    uint32_t fl = 0;
+#pragma omp parallel for reduction(max : lmax) reduction(| : fl) schedule(static)
+    for (int64_t c = 0; c < ncell; ++c) {
+        double rho = U[c];
+        double u[3], qq = 0.0;
+        for (int d = 0; d < ndim; ++d) {
+            u[d] = U[(1 + d) * ncell + c] / rho;
+            qq += u[d] * u[d];
+        }
+        double p = (g->gamma - 1.0) * (U[ie * ncell + c] - 0.5 * rho * qq);
+        double cs = std::sqrt(g->gamma * p / rho);
+        double lam = 0.0;
+        for (int d = 0; d < ndim; ++d) lam += (std::fabs(u[d]) + cs) / g->dx[d];
+        if (std::isnan(lam) || std::isnan(rho) || std::isnan(p)) fl |= OR_FLAG_NAN;
+        if (!(rho > 0.0)) fl |= OR_FLAG_RHO;
+        if (!(p > 0.0)) fl |= OR_FLAG_P;
+        if (lam > lmax) lmax = lam;
+    }
+    if (flags) *flags |= fl;
+    return lmax;
+}
+
+double or_dt(const OrGrid* g, const double* U, uint32_t* flags) {
+    return g->cfl / or_max_wavespeed(g, U, flags);
+}
+
+void or_rk3_step(const OrGrid* g, double* U, double dt) { rk3_step(g, U, dt); }
+
+// Complex-step directional derivative of one RK3 step (dt frozen) along V.
+void or_rk3_step_cs(const OrGrid* g, const double* U, const double* V, double h, double dt,
+                    double* Unew, double* dUnew) {
+    const int64_t N = (int64_t)(g->ndim + 2) * g->n[0] * g->n[1] * g->n[2];
+    std::vector<cplx> Uc(N);
+    for (int64_t e = 0; e < N; ++e) Uc[e] = cplx(U[e], h * V[e]);
+    rk3_step(g, Uc.data(), dt);
+    for (int64_t e = 0; e < N; ++e) {
+        Unew[e] = Uc[e].real();
+        dUnew[e] = Uc[e].imag() / h;
+    }
+}
+
+// nsteps SSP-RK3 steps. dt per step is dt_in[s] if dt_in is given, else
+// CFL / max wave speed of the state at the start of the step.
+void or_run(const OrGrid* g, double* U, int32_t nsteps, const double* dt_in, double* dt_out,
+            uint32_t* flags) {
+    for (int32_t s = 0; s < nsteps; ++s) {
+        double dt = dt_in ? dt_in[s] : or_dt(g, U, flags);
+        if (dt_out) dt_out[s] = dt;
+        rk3_step(g, U, dt);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+"""Pins of the oracle's face-level pieces: limiter, MUSCL, physical and Roe flux.
+
+Each check is fixed by the mathematics (hand-computed values, textbook
+identities, symmetries), never by re-running the oracle's own formula.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+GAM = 1.4
+
+
+def textbook_minmod(a, b):
+    """minmod(a, b): zero unless a and b share a strict sign, else the smaller magnitude."""
+    if a > 0 and b > 0:
+        return min(a, b)
+    if a < 0 and b < 0:
+        return max(a, b)
+    return 0.0
+
+
+@pytest.mark.parametrize("num,den", [
+    (1.0, 2.0), (2.0, 1.0), (-1.0, -4.0), (-4.0, -1.0), (3.0, -1.0), (-3.0, 1.0),
+    (0.0, 1.0), (1.0, 0.0), (0.0, 0.0), (2.0, 2.0), (-0.5, -0.5), (0.75, 3.0),
+    (5e-310, 1e-300), (1e300, 1e-300), (-8.0, 0.25),
+])
+def test_limited_slope_is_minmod(num, den):
+    # Psi(num/den)*den with the minmod Psi is minmod(den, num); dyadic values make it exact
+    assert oracle.limited(num, den) == textbook_minmod(den, num)
+
+
+def test_psi_minmod_shape():
+    assert oracle.psi_minmod(-2.0) == 0.0
+    assert oracle.psi_minmod(0.0) == 0.0
+    assert oracle.psi_minmod(0.25) == 0.25
+    assert oracle.psi_minmod(1.0) == 1.0
+    assert oracle.psi_minmod(7.0) == 1.0
+    assert oracle.limited(3.0, 1.0, limiter=False) == 1.0  # Psi = 1 when the limiter is off
+
+
+def test_muscl_hand_values():
+    # linear data: both face states are the exact midpoint value, for any kappa
+    for kappa in (-1.0, 0.0, 1.0 / 3.0, 1.0):
+        assert oracle.muscl(0.0, 1.0, 2.0, 3.0, kappa=kappa) == (1.5, 1.5)
+    # one-sided data 0, 0, 1, 3 with kappa = -1, limiter off:
+    #   QL = 0 + (0 - 0)/2 = 0,  QR = 1 - (3 - 1)/2 = 0
+    assert oracle.muscl(0.0, 0.0, 1.0, 3.0, limiter=False) == (0.0, 0.0)
+    # same data, minmod: QL = 0 + minmod(0, 1)/2 = 0, QR = 1 - minmod(2, 1)/2 = 0.5
+    assert oracle.muscl(0.0, 0.0, 1.0, 3.0) == (0.0, 0.5)
+    # a local maximum at k: the left state falls back to first order
+    qL, qR = oracle.muscl(0.0, 2.0, 1.0, 0.0)
+    assert qL == 2.0 and qR == 1.0 - 0.5 * textbook_minmod(-1.0, -1.0)
+    # kappa = 1, limiter off: central average of Q_k and Q_{k+1} on both sides
+    assert oracle.muscl(5.0, 1.0, 3.0, -7.0, limiter=False, kappa=1.0) == (2.0, 2.0)
+
+
+def test_physical_flux_hand_values():
+    # rho = 1, u = (2, 0), p = 1 -> E = 1/0.4 + 0.5*4 = 4.5
+    Q = [1.0, 2.0, 0.0, 4.5]
+    assert np.allclose(oracle.phys_flux(2, 0, Q), [2.0, 5.0, 0.0, 11.0], rtol=0, atol=1e-14)
+    assert np.allclose(oracle.phys_flux(2, 1, Q), [0.0, 0.0, 1.0, 0.0], rtol=0, atol=1e-14)
+    # 3D: rho = 2, u = (1, -1, 0.5), p = 3: E = 3/0.4 + 0.5*2*2.25 = 9.75
+    Q = [2.0, 2.0, -2.0, 1.0, 9.75]
+    Fz = oracle.phys_flux(3, 2, Q)
+    assert np.allclose(Fz, [1.0, 1.0, -1.0, 0.5 + 3.0, (9.75 + 3.0) * 0.5], rtol=0, atol=1e-14)
+
+
+def random_state(rng, ndim, mach_max=0.8):
+    rho = rng.uniform(0.2, 3.0)
+    p = rng.uniform(0.2, 3.0)
+    c = math.sqrt(GAM * p / rho)
+    u = rng.uniform(-1, 1, ndim) * mach_max * c / math.sqrt(ndim)
+    return np.array([rho, *(rho * u), p / (GAM - 1) + 0.5 * rho * (u @ u)])
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_roe_consistency_bitwise(ndim):
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        Q = random_state(rng, ndim)
+        for ax in range(ndim):
+            assert np.array_equal(oracle.roe_flux(ndim, ax, Q, Q), oracle.phys_flux(ndim, ax, Q))
+
+
+def supersonic_pair(rng, ndim, ax, sign):
+    """Two states whose normal velocity exceeds the sound speed on both sides."""
+    out = []
+    for _ in range(2):
+        rho = rng.uniform(0.5, 2.0)
+        p = rng.uniform(0.5, 2.0)
+        c = math.sqrt(GAM * p / rho)
+        u = rng.uniform(-0.3, 0.3, ndim) * c
+        u[ax] = sign * rng.uniform(3.0, 5.0) * c
+        out.append(np.array([rho, *(rho * u), p / (GAM - 1) + 0.5 * rho * (u @ u)]))
+    return out
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_roe_supersonic_upwinding(ndim):
+    # all Roe wave speeds > 0: sum_k lambda_k alpha_k r_k = F(QR) - F(QL) (Roe's property),
+    # hence F = F(QL); all < 0 gives F(QR). This pins every wave strength, speed and
+    # eigenvector component of the dissipation term.
+    rng = np.random.default_rng(2)
+    for _ in range(40):
+        for ax in range(ndim):
+            QL, QR = supersonic_pair(rng, ndim, ax, +1)
+            F = oracle.roe_flux(ndim, ax, QL, QR)
+            FL = oracle.phys_flux(ndim, ax, QL)
+            assert np.allclose(F, FL, rtol=1e-12, atol=1e-12 * np.abs(FL).max())
+            QL, QR = supersonic_pair(rng, ndim, ax, -1)
+            F = oracle.roe_flux(ndim, ax, QL, QR)
+            FR = oracle.phys_flux(ndim, ax, QR)
+            assert np.allclose(F, FR, rtol=1e-12, atol=1e-12 * np.abs(FR).max())
+
+
+def test_roe_stationary_contact_exact():
+    # density jump at rest with equal pressure: Roe's flux keeps the contact exactly
+    p = 0.7
+    QL = np.array([1.0, 0.0, 0.0, p / (GAM - 1)])
+    QR = np.array([0.125, 0.0, 0.0, p / (GAM - 1)])
+    F = oracle.roe_flux(2, 0, QL, QR)
+    assert np.allclose(F, [0.0, p, 0.0, 0.0], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_roe_mirror_symmetry(ndim):
+    # reflecting the normal axis and swapping sides flips the sign of every flux
+    # component except the normal momentum
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        for ax in range(ndim):
+            QL = random_state(rng, ndim, 1.5)
+            QR = random_state(rng, ndim, 1.5)
+            M = np.ones(ndim + 2)
+            M[1 + ax] = -1.0
+            F = oracle.roe_flux(ndim, ax, QL, QR)
+            Fm = oracle.roe_flux(ndim, ax, QR * M, QL * M)
+            assert np.allclose(Fm, -F * M, rtol=1e-13, atol=1e-13 * np.abs(F).max())
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_roe_axis_permutation(ndim):
+    # the flux along axis a of a state equals the x flux of the state with the
+    # velocity components of axes a and 0 exchanged, components exchanged back
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        QL = random_state(rng, ndim, 1.5)
+        QR = random_state(rng, ndim, 1.5)
+        for ax in range(1, ndim):
+            perm = list(range(ndim + 2))
+            perm[1], perm[1 + ax] = perm[1 + ax], perm[1]
+            Fa = oracle.roe_flux(ndim, ax, QL, QR)
+            F0 = oracle.roe_flux(ndim, 0, QL[perm], QR[perm])
+            # bitwise in 2D; in 3D |u|^2 is summed in another order, so roundoff
+            assert np.allclose(Fa, F0[perm], rtol=1e-14, atol=1e-14 * np.abs(Fa).max())
+
+
+def test_roe_upwind_limit_small_jump():
+    # for a small jump the Roe flux approaches F(Q) - |A| dQ / 2 with A the flux Jacobian;
+    # checked against a finite-difference Jacobian of the physical flux, eigen-decomposed
+    rng = np.random.default_rng(5)
+    Q = random_state(rng, 2)
+    dQ = rng.standard_normal(4) * 1e-6
+    QL, QR = Q - dQ / 2, Q + dQ / 2
+    h = 1e-7
+    A = np.zeros((4, 4))
+    for j in range(4):
+        e = np.zeros(4)
+        e[j] = h
+        A[:, j] = (oracle.phys_flux(2, 0, Q + e) - oracle.phys_flux(2, 0, Q - e)) / (2 * h)
+    w, V = np.linalg.eig(A)
+    absA = (V @ np.diag(np.abs(w)) @ np.linalg.inv(V)).real
+    expect = 0.5 * (oracle.phys_flux(2, 0, QL) + oracle.phys_flux(2, 0, QR)) - 0.5 * absA @ dQ
+    F = oracle.roe_flux(2, 0, QL, QR)
+    assert np.allclose(F, expect, rtol=0, atol=1e-11)
