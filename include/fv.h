@@ -1,0 +1,180 @@
+/*
+ * fv.h - C ABI of libfv.so, an explicit finite-volume solver for the
+ * compressible Euler equations on uniform Cartesian grids, FP64, for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is the cell-centred finite-volume scheme of the paper's
+ * Sec. "The CFD Code Base": conserved variables and inviscid normal flux of
+ * Eq. (QF), the semi-discrete cell form of Eq. (spatial_residual), the face-sum
+ * residual of Eq. (residual) with a zero source term, and face states by MUSCL
+ * extrapolation, Eq. (flux), with epsilon = 1, kappa = -1 and the minmod
+ * limiter. Face fluxes are Roe's approximate Riemann solver; the explicit
+ * Runge-Kutta march is the three-stage SSP scheme of Shu and Osher; the time
+ * step is the CFL limit dt = cfl / max_cells sum_d (|u_d| + c) / dx_d.
+ *
+ * The launch parameters of the seven kernels that make up a step are exposed
+ * as 14 integers, two per kernel, mirroring the seven gang/vector pairs of the
+ * paper's Table "Tuning Parameters" (Sec. "Tuning Parameters").
+ *
+ * Conventions shared by every entry point:
+ *  - Memory: every pointer argument of type double* or void* workspace is a
+ *    DEVICE pointer, owned by the caller, which must keep it valid until the
+ *    work enqueued on the context's stream has completed. The library never
+ *    allocates device memory: scratch comes from the caller's workspace.
+ *  - State layout ("ghosted SoA"): FP64, variables outermost, x fastest:
+ *      U[v * s_v + (k + g3) * s_z + (j + 2) * s_y + (i + 2)]
+ *    for interior cell (i, j, k), v in (rho, rho u, rho v, [rho w], E),
+ *    g3 = 2 in 3D and 0 in 2D. Two ghost layers per face along each active
+ *    axis. The strides come from fv_query. Ghost cells are overwritten by the
+ *    library; only interior cells are read as input.
+ *  - Residual layout ("dense interior"): R[v * ncell + (k * ny + j) * nx + i].
+ *  - Asynchrony: calls enqueue work on the context's HIP stream and return
+ *    without waiting, except fv_status, which synchronises that stream.
+ *  - Errors: the return value is FV_OK or a negative FV_E* code for argument,
+ *    workspace and launch errors; no state is changed when a call returns
+ *    FV_EINVAL. Non-physical states (NaN, rho <= 0, p <= 0) are recorded in a
+ *    device status word read by fv_status. fv_last_error gives a message.
+ *  - Threading: a context is used from one host thread at a time.
+ */
+#ifndef FV_H
+#define FV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FV_OK = 0,
+    FV_EINVAL = -1,      /* bad argument: no state changed */
+    FV_EDEVICE = -2,     /* a HIP call or kernel launch failed */
+    FV_ENONPHYS = -3,    /* the status word holds a non-physical flag */
+    FV_ENOTSUP = -4,     /* configuration not supported */
+    FV_EWORKSPACE = -5   /* workspace missing, too small or misaligned */
+};
+
+enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1 };
+
+/* Status-word bits (set by the time-step reduction over the state). */
+enum { FV_FLAG_NAN = 1u, FV_FLAG_RHO = 2u, FV_FLAG_P = 4u, FV_FLAG_DT = 8u };
+
+/* Launch sites: the kernels of one step. Slot 2*s holds the first and slot
+ * 2*s+1 the second parameter of site s. */
+enum {
+    FV_SITE_FLUX_X = 0,   /* MUSCL + Roe flux on x faces (paper: xi limiter/flux) */
+    FV_SITE_FLUX_Y = 1,   /* the same on y faces (paper: eta limiter/flux)        */
+    FV_SITE_FLUX_Z = 2,   /* the same on z faces (3D only; inert in 2D)           */
+    FV_SITE_RESIDUAL = 3, /* face-flux differences times areas (paper: RHS)       */
+    FV_SITE_UPDATE = 4,   /* Runge-Kutta stage update (paper: update solution)    */
+    FV_SITE_BC = 5,       /* ghost-layer fill                                     */
+    FV_SITE_CFL = 6,      /* wave-speed max-reduction for dt                      */
+    FV_NSITES = 7
+};
+
+/* Grid description. ndim is 2 or 3; n[2] must be 1 in 2D. The box is
+ * [lo, hi] per axis with n cells each. bc[d][0] / bc[d][1] is the low / high
+ * face kind of axis d; periodic must be set on both faces of an axis. */
+typedef struct fv_grid_desc {
+    int32_t ndim;
+    int32_t reserved;   /* must be 0 */
+    int64_t n[3];
+    double lo[3];
+    double hi[3];
+    int32_t bc[3][2];
+    double gamma;       /* ratio of specific heats, > 1 */
+    double cfl;         /* CFL number, > 0 */
+} fv_grid_desc;
+
+/* Launch parameters, two per site (FV_SITE_* order).
+ *  Stencil sites (flux x/y/z): p[2s] = block width along x, a power of two in
+ *    [1, 1024]; p[2s+1] = threads per block, a power of two in [64, 1024],
+ *    >= p[2s]. The block height is p[2s+1] / p[2s].
+ *  One-dimensional sites (residual, update, bc, cfl): p[2s] = number of blocks
+ *    ("gang"), 0 for one thread per element or a power of two in [1, 65536]
+ *    for a grid-stride loop; p[2s+1] = threads per block, a power of two in
+ *    [64, 1024].
+ * Every valid vector yields bitwise-identical results. */
+typedef struct fv_launch {
+    int32_t p[14];
+} fv_launch;
+
+typedef struct fv_ctx fv_ctx;   /* opaque, library-owned host object */
+
+/* Writes the defaults: stencil sites (64, 256), one-dimensional sites (0, 256). */
+void fv_default_launch(fv_launch* out);
+
+/* Validates g and reports the ghosted state strides (elements):
+ * strides_out = {s_x = 1, s_y, s_z, s_v}, the state size is nvar * s_v
+ * doubles, and *workspace_bytes the scratch a context needs. Either output
+ * may be NULL. Returns FV_EINVAL for an invalid description. */
+int fv_query(const fv_grid_desc* g, int64_t strides_out[4], size_t* workspace_bytes);
+
+/* Creates a context for grid g on the current HIP device. workspace is a
+ * device buffer of at least the queried size, 256-byte aligned, owned by the
+ * caller and used exclusively by this context until fv_destroy. stream is a
+ * hipStream_t (NULL = the default stream). The launch table starts at the
+ * defaults and the status word at 0. */
+int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, void* stream,
+              fv_ctx** out);
+
+/* Releases the host object; does not touch the caller's device memory. */
+int fv_destroy(fv_ctx* ctx);
+
+/* Rebinds the context to another HIP stream (NULL = the default stream). */
+int fv_set_stream(fv_ctx* ctx, void* stream);
+
+/* Spatial residual of Eq. (residual): R = sum over the 2*ndim faces of the
+ * Roe flux of the MUSCL face states times the face area, S = 0. Fills the
+ * ghost layers of U (the interior is not changed) and writes R in the dense
+ * interior layout (nvar * ncell doubles). */
+int fv_residual(fv_ctx* ctx, double* U, double* R);
+
+/* Advances U (ghosted layout, in place) by nsteps SSP-RK3 steps:
+ *   U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1)),
+ *   U <- 1/3 U + 2/3 (U2 + dt L(U2)),  L = -R / |Omega|,
+ * ghosts refilled before every stage. dt of step s is dt_in[s] when dt_in
+ * (device, nsteps doubles) is non-NULL, else cfl / max wave speed of U at the
+ * start of the step. dt_out (device, nsteps doubles, may be NULL) receives the
+ * dt used by each step. The status word collects the flags of every step. */
+int fv_step(fv_ctx* ctx, double* U, int32_t nsteps, const double* dt_in, double* dt_out);
+
+/* Reverse (adjoint) of one SSP-RK3 step with the step size frozen at *dt
+ * (device scalar): on entry lam (dense interior layout) holds dJ/dU^{n+1};
+ * on return it holds dJ/dU^n, where U^{n+1} = step(U_n, dt). U_n (ghosted
+ * layout) is the state at the start of the step; its interior is not changed,
+ * its ghosts are. The stage states are recomputed internally. */
+int fv_adjoint_step(fv_ctx* ctx, double* U_n, const double* dt, double* lam);
+
+/* Sets / reads the 14 launch parameters. An invalid vector returns FV_EINVAL
+ * and leaves the previous one in place. */
+int fv_set_launch(fv_ctx* ctx, const fv_launch* launch);
+int fv_get_launch(const fv_ctx* ctx, fv_launch* out);
+
+/* Synchronises the context's stream and reads the status word (FV_FLAG_*).
+ * Returns FV_ENONPHYS when any flag is set, FV_OK otherwise. */
+int fv_status(fv_ctx* ctx, uint32_t* flags);
+
+/* Enqueues a reset of the status word to 0. */
+int fv_clear_status(fv_ctx* ctx);
+
+/* Per-site kernel timing, a diagnostic for profiling and the autotuner's
+ * measurements. When enabled, every kernel launch of fv_step / fv_residual /
+ * fv_adjoint_step is bracketed by two HIP events on the context's stream and
+ * each call waits for its last event, so enabling it serialises the host with
+ * the stream; kernel durations themselves are unaffected. fv_get_timing
+ * writes, per FV_SITE_*, the accumulated milliseconds and number of launches
+ * since the last read, then resets them. Either output may be NULL. */
+int fv_set_timing(fv_ctx* ctx, int enable);
+int fv_get_timing(fv_ctx* ctx, double ms_out[7], int64_t launches_out[7]);
+
+/* Message of the last failing call on ctx (or of fv_query / fv_create when
+ * ctx is NULL). Never NULL. */
+const char* fv_last_error(const fv_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FV_H */

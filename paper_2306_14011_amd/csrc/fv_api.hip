@@ -1,0 +1,484 @@
+// C ABI of libfv.so: context, workspace carving, launch-table validation and
+// the orchestration of a step out of the kernels in fv_kernels.hip.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/fv.h"
+#include "fv_internal.h"
+
+using fvk::Geo;
+
+struct fv_ctx {
+    fv_grid_desc desc;
+    Geo g;
+    hipStream_t stream;
+    fv_launch launch;
+    int device;
+    // carved from the caller's workspace
+    uint32_t* status;
+    double* dt;
+    double* partial;
+    int max_partial;
+    double* U1;
+    double* U2;
+    double* F[3];
+    double* R;
+    double* lamA;
+    double* lamB;
+    // per-site event timing (diagnostic)
+    static const int kMaxEv = 64;
+    bool timing;
+    bool ev_ready;
+    hipEvent_t ev[2 * kMaxEv];
+    int ev_site[kMaxEv];
+    int nev;
+    double acc_ms[FV_NSITES];
+    int64_t acc_n[FV_NSITES];
+    char err[256];
+};
+
+static char g_err[256] = "";
+
+static int fail(fv_ctx* c, int code, const char* fmt, const char* detail = "") {
+    char* dst = c ? c->err : g_err;
+    snprintf(dst, 256, fmt, detail);
+    return code;
+}
+
+static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+namespace {
+
+struct Layout {
+    int nvar;
+    int64_t pitch, sy, sz, sv;
+    int64_t faces[3];
+    int64_t ncell;
+    int max_partial;
+    size_t off_status, off_dt, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int validate(const fv_grid_desc* g, Layout* L, char* why) {
+    if (!g) {
+        snprintf(why, 256, "null grid description");
+        return FV_EINVAL;
+    }
+    if (g->ndim != 2 && g->ndim != 3) {
+        snprintf(why, 256, "ndim must be 2 or 3");
+        return FV_EINVAL;
+    }
+    if (g->reserved != 0) {
+        snprintf(why, 256, "reserved field must be 0");
+        return FV_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 1 || g->n[d] > 65534) {
+            snprintf(why, 256, "cell counts must be in [1, 65534]");
+            return FV_EINVAL;
+        }
+    }
+    if (g->ndim == 2 && g->n[2] != 1) {
+        snprintf(why, 256, "n[2] must be 1 in 2D");
+        return FV_EINVAL;
+    }
+    for (int d = 0; d < g->ndim; ++d) {
+        if (!(g->hi[d] > g->lo[d])) {
+            snprintf(why, 256, "hi must exceed lo on every axis");
+            return FV_EINVAL;
+        }
+        for (int s = 0; s < 2; ++s)
+            if (g->bc[d][s] != FV_BC_PERIODIC && g->bc[d][s] != FV_BC_TRANSMISSIVE) {
+                snprintf(why, 256, "unknown boundary kind");
+                return FV_EINVAL;
+            }
+        if ((g->bc[d][0] == FV_BC_PERIODIC) != (g->bc[d][1] == FV_BC_PERIODIC)) {
+            snprintf(why, 256, "periodic must be set on both faces of an axis");
+            return FV_EINVAL;
+        }
+    }
+    if (!(g->gamma > 1.0) || !(g->cfl > 0.0)) {
+        snprintf(why, 256, "gamma must exceed 1 and cfl must be positive");
+        return FV_EINVAL;
+    }
+    const int nd = g->ndim;
+    L->nvar = nd + 2;
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    // row pitch padded to a multiple of 8 doubles (64 B)
+    L->pitch = ((nx + 2 * fvk::NG) + 7) / 8 * 8;
+    L->sy = L->pitch;
+    L->sz = L->sy * (ny + 2 * fvk::NG);
+    L->sv = L->sz * (nd == 3 ? nz + 2 * fvk::NG : 1);
+    if (L->sv >= (int64_t)1 << 31) {
+        snprintf(why, 256, "grid too large: one variable must hold fewer than 2^31 doubles");
+        return FV_EINVAL;
+    }
+    L->ncell = nx * ny * nz;
+    L->faces[0] = (nx + 1) * ny * nz;
+    L->faces[1] = nx * (ny + 1) * nz;
+    L->faces[2] = nd == 3 ? nx * ny * (nz + 1) : 0;
+    const int64_t maxp = (L->ncell + 63) / 64;
+    L->max_partial = (int)(maxp > 65536 ? maxp : 65536);
+    size_t o = 0;
+    L->off_status = o;
+    o += 256;
+    L->off_dt = o;
+    o += 256;
+    L->off_partial = o;
+    o = align256(o + (size_t)L->max_partial * 8);
+    const size_t state = (size_t)L->nvar * L->sv * 8;
+    const size_t dense = (size_t)L->nvar * L->ncell * 8;
+    L->off_U1 = o;
+    o = align256(o + state);
+    L->off_U2 = o;
+    o = align256(o + state);
+    for (int d = 0; d < 3; ++d) {
+        L->off_F[d] = o;
+        o = align256(o + (size_t)L->nvar * L->faces[d] * 8);
+    }
+    L->off_R = o;
+    o = align256(o + dense);
+    L->off_lamA = o;
+    o = align256(o + dense);
+    L->off_lamB = o;
+    o = align256(o + dense);
+    L->total = o;
+    return FV_OK;
+}
+
+int validate_launch(const fv_launch* l, int ndim, char* why) {
+    for (int s = 0; s < FV_NSITES; ++s) {
+        const int a = l->p[2 * s], b = l->p[2 * s + 1];
+        if (s <= FV_SITE_FLUX_Z) {
+            if (s == FV_SITE_FLUX_Z && ndim == 2 && a == 0 && b == 0) continue;
+            if (!is_pow2(a) || a > 1024 || !is_pow2(b) || b < 64 || b > 1024 || a > b) {
+                snprintf(why, 256, "site %d: block width must be a power of two <= threads, threads in [64, 1024]", s);
+                return FV_EINVAL;
+            }
+        } else {
+            if (!(a == 0 || (is_pow2(a) && a <= 65536)) || !is_pow2(b) || b < 64 || b > 1024) {
+                snprintf(why, 256, "site %d: gang must be 0 or a power of two <= 65536, threads in [64, 1024]", s);
+                return FV_EINVAL;
+            }
+        }
+    }
+    return FV_OK;
+}
+
+Geo make_geo(const fv_grid_desc* d, const Layout& L) {
+    Geo g;
+    memset(&g, 0, sizeof(g));
+    g.ndim = d->ndim;
+    g.nvar = L.nvar;
+    for (int a = 0; a < 3; ++a) g.n[a] = (int)d->n[a];
+    g.sy = (int)L.sy;
+    g.sz = (int)L.sz;
+    g.sv = L.sv;
+    g.off0 = (int)(fvk::NG + fvk::NG * L.sy + (d->ndim == 3 ? fvk::NG * L.sz : 0));
+    g.ncell = (int)L.ncell;
+    for (int a = 0; a < 3; ++a) g.fsv[a] = L.faces[a];
+    g.dnx = fvk::make_divmod((uint32_t)d->n[0]);
+    g.dny = fvk::make_divmod((uint32_t)d->n[1]);
+    double dx[3];
+    for (int a = 0; a < 3; ++a) dx[a] = a < d->ndim ? (d->hi[a] - d->lo[a]) / (double)d->n[a] : 1.0;
+    double vol = 1.0;
+    for (int a = 0; a < d->ndim; ++a) vol *= dx[a];
+    for (int a = 0; a < 3; ++a) {
+        g.inv_dx[a] = 1.0 / dx[a];
+        double ar = 1.0;
+        for (int b = 0; b < d->ndim; ++b)
+            if (b != a) ar *= dx[b];
+        g.area[a] = ar;
+    }
+    g.inv_vol = 1.0 / vol;
+    g.gamma = d->gamma;
+    g.gm1 = d->gamma - 1.0;
+    g.cfl = d->cfl;
+    for (int a = 0; a < 3; ++a) {
+        g.bc[a][0] = d->bc[a][0];
+        g.bc[a][1] = d->bc[a][1];
+    }
+    return g;
+}
+
+int check_launch_error(fv_ctx* c) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, FV_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return FV_OK;
+}
+
+inline int P(const fv_ctx* c, int site, int k) { return c->launch.p[2 * site + k]; }
+
+// Event bracket around one site's launch when timing is enabled.
+struct SiteTimer {
+    fv_ctx* c;
+    int slot;
+    SiteTimer(fv_ctx* ctx, int site) : c(ctx), slot(-1) {
+        if (c->timing && c->nev < fv_ctx::kMaxEv) {
+            slot = c->nev++;
+            c->ev_site[slot] = site;
+            (void)hipEventRecord(c->ev[2 * slot], c->stream);
+        }
+    }
+    ~SiteTimer() {
+        if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+    }
+};
+
+// Waits for the recorded events and accumulates their durations per site.
+int drain_timing(fv_ctx* c) {
+    if (!c->timing || c->nev == 0) return FV_OK;
+    hipError_t e = hipEventSynchronize(c->ev[2 * (c->nev - 1) + 1]);
+    if (e != hipSuccess) return fail(c, FV_EDEVICE, "event wait failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < c->nev; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) {
+            c->acc_ms[c->ev_site[i]] += ms;
+            c->acc_n[c->ev_site[i]] += 1;
+        }
+    }
+    c->nev = 0;
+    return FV_OK;
+}
+
+void enqueue_bc(fv_ctx* c, double* U) {
+    SiteTimer t(c, FV_SITE_BC);
+    fvk::launch_bc_fill(U, c->g, P(c, FV_SITE_BC, 0), P(c, FV_SITE_BC, 1), c->stream);
+}
+
+void enqueue_fluxes(fv_ctx* c, const double* U) {
+    for (int ax = 0; ax < c->g.ndim; ++ax) {
+        SiteTimer t(c, FV_SITE_FLUX_X + ax);
+        fvk::launch_flux(ax, U, c->F[ax], c->g, P(c, FV_SITE_FLUX_X + ax, 0), P(c, FV_SITE_FLUX_X + ax, 1),
+                         c->stream);
+    }
+}
+
+void enqueue_residual(fv_ctx* c, double* R) {
+    SiteTimer t(c, FV_SITE_RESIDUAL);
+    fvk::launch_residual(c->F[0], c->F[1], c->F[2], R, c->g, P(c, FV_SITE_RESIDUAL, 0), P(c, FV_SITE_RESIDUAL, 1),
+                         c->stream);
+}
+
+void enqueue_update(fv_ctx* c, int stage, const double* Un, const double* Us, double* Ud) {
+    SiteTimer t(c, FV_SITE_UPDATE);
+    fvk::launch_update(stage, Un, Us, Ud, c->R, c->dt, c->g, P(c, FV_SITE_UPDATE, 0), P(c, FV_SITE_UPDATE, 1),
+                       c->stream);
+}
+
+void enqueue_cfl(fv_ctx* c, const double* U, const double* dt_in, double* dt_out) {
+    SiteTimer t(c, FV_SITE_CFL);
+    fvk::launch_cfl(U, c->partial, c->status, dt_in, c->dt, dt_out, c->g, P(c, FV_SITE_CFL, 0), P(c, FV_SITE_CFL, 1),
+                    c->stream);
+}
+
+// L(Us) into c->R, then the stage combination into Ud.
+void enqueue_stage(fv_ctx* c, int stage, const double* Un, double* Us, double* Ud) {
+    enqueue_bc(c, Us);
+    enqueue_fluxes(c, Us);
+    enqueue_residual(c, c->R);
+    enqueue_update(c, stage, Un, Us, Ud);
+}
+
+}  // namespace
+
+extern "C" {
+
+void fv_default_launch(fv_launch* out) {
+    if (!out) return;
+    for (int s = 0; s < FV_NSITES; ++s) {
+        if (s <= FV_SITE_FLUX_Z) {
+            out->p[2 * s] = 64;
+            out->p[2 * s + 1] = 256;
+        } else {
+            out->p[2 * s] = 0;
+            out->p[2 * s + 1] = 256;
+        }
+    }
+}
+
+int fv_query(const fv_grid_desc* g, int64_t strides_out[4], size_t* workspace_bytes) {
+    Layout L;
+    int rc = validate(g, &L, g_err);
+    if (rc != FV_OK) return rc;
+    if (strides_out) {
+        strides_out[0] = 1;
+        strides_out[1] = L.sy;
+        strides_out[2] = L.sz;
+        strides_out[3] = L.sv;
+    }
+    if (workspace_bytes) *workspace_bytes = L.total;
+    return FV_OK;
+}
+
+int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, void* stream, fv_ctx** out) {
+    if (!out) return fail(nullptr, FV_EINVAL, "null output pointer%s");
+    *out = nullptr;
+    Layout L;
+    int rc = validate(g, &L, g_err);
+    if (rc != FV_OK) return rc;
+    if (!workspace) return fail(nullptr, FV_EWORKSPACE, "null workspace%s");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, FV_EWORKSPACE, "workspace must be 256-byte aligned%s");
+    if (workspace_bytes < L.total) return fail(nullptr, FV_EWORKSPACE, "workspace too small%s");
+    fv_ctx* c = new (std::nothrow) fv_ctx;
+    if (!c) return fail(nullptr, FV_EDEVICE, "host allocation failed%s");
+    memset(c, 0, sizeof(*c));
+    c->desc = *g;
+    c->g = make_geo(g, L);
+    c->stream = (hipStream_t)stream;
+    fv_default_launch(&c->launch);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, FV_EDEVICE, "hipGetDevice failed%s");
+    }
+    char* base = (char*)workspace;
+    c->status = (uint32_t*)(base + L.off_status);
+    c->dt = (double*)(base + L.off_dt);
+    c->partial = (double*)(base + L.off_partial);
+    c->max_partial = L.max_partial;
+    c->U1 = (double*)(base + L.off_U1);
+    c->U2 = (double*)(base + L.off_U2);
+    for (int d = 0; d < 3; ++d) c->F[d] = (double*)(base + L.off_F[d]);
+    c->R = (double*)(base + L.off_R);
+    c->lamA = (double*)(base + L.off_lamA);
+    c->lamB = (double*)(base + L.off_lamB);
+    fvk::launch_set_u32(c->status, 0u, c->stream);
+    if (check_launch_error(c) != FV_OK) {
+        snprintf(g_err, 256, "%s", c->err);
+        delete c;
+        return FV_EDEVICE;
+    }
+    *out = c;
+    return FV_OK;
+}
+
+int fv_destroy(fv_ctx* c) {
+    if (!c) return FV_EINVAL;
+    if (c->ev_ready)
+        for (int i = 0; i < 2 * fv_ctx::kMaxEv; ++i) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+    return FV_OK;
+}
+
+int fv_set_stream(fv_ctx* c, void* stream) {
+    if (!c) return FV_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return FV_OK;
+}
+
+int fv_residual(fv_ctx* c, double* U, double* R) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (!U || !R) return fail(c, FV_EINVAL, "null state or residual pointer%s");
+    enqueue_bc(c, U);
+    enqueue_fluxes(c, U);
+    enqueue_residual(c, R);
+    int rc = check_launch_error(c);
+    if (rc != FV_OK) return rc;
+    return drain_timing(c);
+}
+
+int fv_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (!U) return fail(c, FV_EINVAL, "null state pointer%s");
+    if (nsteps < 0) return fail(c, FV_EINVAL, "negative step count%s");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        enqueue_bc(c, U);
+        enqueue_cfl(c, U, dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr);
+        // stage 1: U1 = U + dt L(U)   (ghosts of U already filled)
+        enqueue_fluxes(c, U);
+        enqueue_residual(c, c->R);
+        enqueue_update(c, 0, U, U, c->U1);
+        // stage 2: U2 = 3/4 U + 1/4 (U1 + dt L(U1)), in place over U1
+        enqueue_stage(c, 1, U, c->U1, c->U1);
+        // stage 3: U = 1/3 U + 2/3 (U2 + dt L(U2)), in place over U
+        enqueue_stage(c, 2, U, c->U1, U);
+        int rc = check_launch_error(c);
+        if (rc != FV_OK) return rc;
+        rc = drain_timing(c);
+        if (rc != FV_OK) return rc;
+    }
+    return FV_OK;
+}
+
+int fv_adjoint_step(fv_ctx* c, double* U_n, const double* dt, double* lam) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    (void)U_n;
+    (void)dt;
+    (void)lam;
+    return fail(c, FV_ENOTSUP, "adjoint step not available in this build%s");
+}
+
+int fv_set_launch(fv_ctx* c, const fv_launch* l) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (!l) return fail(c, FV_EINVAL, "null launch table%s");
+    char why[256];
+    if (validate_launch(l, c->g.ndim, why) != FV_OK) return fail(c, FV_EINVAL, "%s", why);
+    const int cb = fvk::cfl_blocks(c->g, l->p[2 * FV_SITE_CFL], l->p[2 * FV_SITE_CFL + 1]);
+    if (cb > c->max_partial) return fail(c, FV_EINVAL, "cfl gang exceeds the partial buffer%s");
+    c->launch = *l;
+    if (c->g.ndim == 2) {
+        // the z-flux pair is inert in 2D: keep a valid placeholder
+        c->launch.p[2 * FV_SITE_FLUX_Z] = l->p[2 * FV_SITE_FLUX_Z] ? l->p[2 * FV_SITE_FLUX_Z] : 64;
+        c->launch.p[2 * FV_SITE_FLUX_Z + 1] = l->p[2 * FV_SITE_FLUX_Z + 1] ? l->p[2 * FV_SITE_FLUX_Z + 1] : 256;
+    }
+    return FV_OK;
+}
+
+int fv_get_launch(const fv_ctx* c, fv_launch* out) {
+    if (!c || !out) return FV_EINVAL;
+    *out = c->launch;
+    return FV_OK;
+}
+
+int fv_status(fv_ctx* c, uint32_t* flags) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    uint32_t h = 0;
+    hipError_t e = hipMemcpyAsync(&h, c->status, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FV_EDEVICE, "status read failed: %s", hipGetErrorString(e));
+    if (flags) *flags = h;
+    return h ? FV_ENONPHYS : FV_OK;
+}
+
+int fv_clear_status(fv_ctx* c) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    fvk::launch_set_u32(c->status, 0u, c->stream);
+    return check_launch_error(c);
+}
+
+int fv_set_timing(fv_ctx* c, int enable) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (enable && !c->ev_ready) {
+        for (int i = 0; i < 2 * fv_ctx::kMaxEv; ++i) {
+            hipError_t e = hipEventCreate(&c->ev[i]);
+            if (e != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->ev[j]);
+                return fail(c, FV_EDEVICE, "event creation failed: %s", hipGetErrorString(e));
+            }
+        }
+        c->ev_ready = true;
+    }
+    c->timing = enable != 0;
+    c->nev = 0;
+    return FV_OK;
+}
+
+int fv_get_timing(fv_ctx* c, double ms_out[7], int64_t launches_out[7]) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    int rc = drain_timing(c);
+    if (rc != FV_OK) return rc;
+    for (int s = 0; s < FV_NSITES; ++s) {
+        if (ms_out) ms_out[s] = c->acc_ms[s];
+        if (launches_out) launches_out[s] = c->acc_n[s];
+        c->acc_ms[s] = 0.0;
+        c->acc_n[s] = 0;
+    }
+    return FV_OK;
+}
+
+const char* fv_last_error(const fv_ctx* c) { return c ? c->err : g_err; }
+
+}  // extern "C"

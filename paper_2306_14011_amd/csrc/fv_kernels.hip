@@ -1,0 +1,368 @@
+// Primal kernels of the split step for gfx950 (FP64): ghost fill, MUSCL-Roe
+// face fluxes per axis, residual assembly, SSP-RK3 stage update and the
+// wave-speed max-reduction for the CFL time step.
+//
+// Every output element is computed by exactly one thread with an arithmetic
+// sequence that does not depend on the launch shape, and the reduction is a
+// max (exact and order-independent), so every valid launch configuration
+// produces bitwise-identical results.
+#include "fv_internal.h"
+
+namespace fvk {
+
+// ---------------------------------------------------------------------------
+// Ghost fill. Element e enumerates, axis by axis, the 4 ghost layers
+// (-2, -1, n, n+1) times the interior cross-section of that axis; layer is the
+// fastest index. Periodic faces copy the opposite interior layers,
+// transmissive faces copy the nearest interior cell (zero gradient).
+template <int NV>
+__global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g, int total, int seg0,
+                                                   int seg1, int stride_all) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride_all) {
+        int ax, q, layer;
+        if (e < seg0) {
+            ax = 0;
+            q = e >> 2;
+        } else if (e < seg0 + seg1) {
+            ax = 1;
+            q = (e - seg0) >> 2;
+        } else {
+            ax = 2;
+            q = (e - seg0 - seg1) >> 2;
+        }
+        layer = e & 3;
+        int c[3];
+        // cross-section coordinates, first remaining axis fastest
+        if (ax == 0) {
+            c[1] = q % g.n[1];
+            c[2] = q / g.n[1];
+        } else if (ax == 1) {
+            c[0] = q % g.n[0];
+            c[2] = q / g.n[0];
+        } else {
+            c[0] = q % g.n[0];
+            c[1] = q / g.n[0];
+        }
+        const int n = g.n[ax];
+        const int gpos = layer < 2 ? layer - 2 : n + layer - 2;  // -2, -1, n, n+1
+        int src;
+        const bool lo = layer < 2;
+        const int kind = g.bc[ax][lo ? 0 : 1];
+        if (kind == 0) {
+            src = ((gpos % n) + n) % n;
+        } else {
+            src = lo ? 0 : n - 1;
+        }
+        int cg[3] = {c[0], c[1], c[2]};
+        int cs[3] = {c[0], c[1], c[2]};
+        cg[ax] = gpos;
+        cs[ax] = src;
+        if (g.ndim == 2) {
+            cg[2] = 0;
+            cs[2] = 0;
+        }
+        const int og = g.off0 + cg[0] + cg[1] * g.sy + cg[2] * g.sz;
+        const int os = g.off0 + cs[0] + cs[1] * g.sy + cs[2] * g.sz;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U[v * g.sv + og] = U[v * g.sv + os];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Face fluxes along axis AX. Face (i, j, k) lies between cells (i,j,k) - e_AX
+// and (i,j,k); its flux is stored at F[v * fsv + (k * rows_j + j) * cols + i]
+// with cols = nx (+1 on x) and rows_j = ny (+1 on y). Threads: x -> i,
+// y -> j (grid-stride), blockIdx.z -> k.
+template <int NDIM, int AX, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_flux(const double* __restrict__ U, double* __restrict__ F,
+                                               Geo g) {
+    constexpr int NV = NDIM + 2;
+    const int cols = g.n[0] + (AX == 0 ? 1 : 0);
+    const int rows_j = g.n[1] + (AX == 1 ? 1 : 0);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cols) return;
+    const int k = blockIdx.z;
+    const int st = AX == 0 ? 1 : (AX == 1 ? g.sy : g.sz);
+    const long long fsv = g.fsv[AX];
+    for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < rows_j; j += gridDim.y * blockDim.y) {
+        const int c = g.off0 + i + j * g.sy + k * g.sz;  // right cell of the face
+        double qL[NV], qR[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double* Uv = U + v * g.sv;
+            const double q0 = Uv[c - 2 * st], q1 = Uv[c - st], q2 = Uv[c], q3 = Uv[c + st];
+            muscl_minmod(q0, q1, q2, q3, qL[v], qR[v]);
+        }
+        double Fl[NV];
+        roe_flux<NDIM, AX>(qL, qR, g.gm1, Fl);
+        const long long f = (long long)(k * rows_j + j) * cols + i;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v * fsv + f] = Fl[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Interior cell e -> (i, j, k) and its offset in the ghosted layout.
+__device__ __forceinline__ void decode_cell(int e, const Geo& g, int& i, int& j, int& k) {
+    const uint32_t t = divq((uint32_t)e, g.dnx);
+    i = e - (int)t * g.n[0];
+    k = (int)divq(t, g.dny);
+    j = (int)t - k * g.n[1];
+}
+
+// R[v][e] = sum_d (F_d[face e + e_d] - F_d[face e]) * area_d.
+template <int NDIM, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_residual(const double* __restrict__ Fx,
+                                                   const double* __restrict__ Fy,
+                                                   const double* __restrict__ Fz, double* __restrict__ R,
+                                                   Geo g, int stride_all) {
+    constexpr int NV = NDIM + 2;
+    const int nx = g.n[0], ny = g.n[1];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += stride_all) {
+        int i, j, k;
+        decode_cell(e, g, i, j, k);
+        const long long fx = (long long)(k * ny + j) * (nx + 1) + i;
+        const long long fy = (long long)(k * (ny + 1) + j) * nx + i;
+        const long long fz = (long long)(k * ny + j) * nx + i;
+        const long long zs = (long long)ny * nx;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double r = (Fx[v * g.fsv[0] + fx + 1] - Fx[v * g.fsv[0] + fx]) * g.area[0];
+            r += (Fy[v * g.fsv[1] + fy + nx] - Fy[v * g.fsv[1] + fy]) * g.area[1];
+            if (NDIM == 3) r += (Fz[v * g.fsv[2] + fz + zs] - Fz[v * g.fsv[2] + fz]) * g.area[2];
+            R[(long long)v * g.ncell + e] = r;
+        }
+    }
+}
+
+// SSP-RK3 stage update with L = -R / |Omega| and dt read from device memory.
+//   STAGE 0: Ud = Un + dt L
+//   STAGE 1: Ud = 3/4 Un + 1/4 (Us + dt L)          (Ud may alias Us)
+//   STAGE 2: Ud = 1/3 Un + 2/3 (Us + dt L)          (Ud may alias Un)
+template <int NDIM, int STAGE, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_update(const double* Un, const double* Us, double* Ud,
+                                                 const double* __restrict__ R,
+                                                 const double* __restrict__ dtp, Geo g, int stride_all) {
+    constexpr int NV = NDIM + 2;
+    const double dt = *dtp;
+    const double s = -dt * g.inv_vol;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += stride_all) {
+        int i, j, k;
+        decode_cell(e, g, i, j, k);
+        const int o = g.off0 + i + j * g.sy + k * g.sz;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double Lr = R[(long long)v * g.ncell + e];
+            const long long p = v * g.sv + o;
+            double out;
+            if (STAGE == 0) {
+                out = Un[p] + s * Lr;
+            } else if (STAGE == 1) {
+                out = 0.75 * Un[p] + 0.25 * (Us[p] + s * Lr);
+            } else {
+                out = (1.0 / 3.0) * Un[p] + (2.0 / 3.0) * (Us[p] + s * Lr);
+            }
+            Ud[p] = out;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-speed reduction: lambda(cell) = sum_d (|u_d| + c) / dx_d, block max into
+// partial[blockIdx.x]; NaN / rho <= 0 / p <= 0 set bits of the status word.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int NDIM, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_cfl_partial(const double* __restrict__ U, double* __restrict__ partial,
+                                                      uint32_t* __restrict__ status, Geo g, int stride_all) {
+    constexpr int IE = NDIM + 1;
+    __shared__ double sm[MAXT / 64];
+    double lmax = 0.0;
+    uint32_t fl = 0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += stride_all) {
+        int i, j, k;
+        decode_cell(e, g, i, j, k);
+        const int o = g.off0 + i + j * g.sy + k * g.sz;
+        const double rho = U[o];
+        const double ir = 1.0 / rho;
+        double u[NDIM];
+        double qq = 0.0;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+            u[d] = U[(1 + d) * g.sv + o] * ir;
+            qq += u[d] * u[d];
+        }
+        const double p = g.gm1 * (U[IE * g.sv + o] - 0.5 * rho * qq);
+        const double c = sqrt(g.gamma * p * ir);
+        double lam = 0.0;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) lam += (fabs(u[d]) + c) * g.inv_dx[d];
+        if (isnan(lam) || isnan(rho) || isnan(p)) fl |= 1u;
+        if (!(rho > 0.0)) fl |= 2u;
+        if (!(p > 0.0)) fl |= 4u;
+        lmax = fmax(lmax, lam);
+    }
+    if (fl) atomicOr(status, fl);
+    lmax = wave_max(lmax);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sm[w] = lmax;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int nw = blockDim.x >> 6;
+        double v = threadIdx.x < nw ? sm[threadIdx.x] : 0.0;
+        v = wave_max(v);
+        if (threadIdx.x == 0) partial[blockIdx.x] = v;
+    }
+}
+
+// One block: max over the partials, dt = cfl / max (or the frozen dt_in).
+__global__ void __launch_bounds__(1024) k_cfl_final(const double* __restrict__ partial, int npart,
+                                                    const double* __restrict__ dt_in, double* __restrict__ dt,
+                                                    double* __restrict__ dt_out, uint32_t* __restrict__ status,
+                                                    double cfl) {
+    __shared__ double sm[16];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < npart; t += blockDim.x) m = fmax(m, partial[t]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int nw = blockDim.x >> 6;
+        double v = threadIdx.x < nw ? sm[threadIdx.x] : 0.0;
+        v = wave_max(v);
+        if (threadIdx.x == 0) {
+            double d = dt_in ? *dt_in : cfl / v;
+            if (!(v > 0.0) || !(d > 0.0) || isinf(d) || isnan(d)) atomicOr(status, 8u);
+            *dt = d;
+            if (dt_out) *dt_out = d;
+        }
+    }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static inline int blocks_for(int64_t n, int threads) { return (int)((n + threads - 1) / threads); }
+
+// 1-D sites: gang 0 -> one thread per element; else a grid-stride loop.
+static inline void grid1d(int64_t n, int gang, int threads, int& blocks, int& stride_all) {
+    blocks = gang > 0 ? gang : blocks_for(n, threads);
+    if (blocks < 1) blocks = 1;
+    stride_all = blocks * threads;
+}
+
+#define FV_DISPATCH_THREADS(T, MACRO) \
+    switch (T) {                      \
+        case 64: MACRO(64); break;    \
+        case 128: MACRO(128); break;  \
+        case 256: MACRO(256); break;  \
+        case 512: MACRO(512); break;  \
+        default: MACRO(1024); break;  \
+    }
+
+void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t s) {
+    const int seg0 = 4 * g.n[1] * g.n[2];
+    const int seg1 = 4 * g.n[0] * g.n[2];
+    const int seg2 = g.ndim == 3 ? 4 * g.n[0] * g.n[1] : 0;
+    const int total = seg0 + seg1 + seg2;
+    int blocks, stride_all;
+    grid1d(total, gang, threads, blocks, stride_all);
+    if (g.ndim == 2)
+        hipLaunchKernelGGL(k_bc_fill<4>, dim3(blocks), dim3(threads), 0, s, U, g, total, seg0, seg1, stride_all);
+    else
+        hipLaunchKernelGGL(k_bc_fill<5>, dim3(blocks), dim3(threads), 0, s, U, g, total, seg0, seg1, stride_all);
+}
+
+template <int NDIM, int AX>
+static void launch_flux_t(const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s) {
+    const int by = threads / bx;
+    const int cols = g.n[0] + (AX == 0 ? 1 : 0);
+    const int rows_j = g.n[1] + (AX == 1 ? 1 : 0);
+    const int rows_k = NDIM == 3 ? g.n[2] + (AX == 2 ? 1 : 0) : 1;
+    int gy = blocks_for(rows_j, by);
+    if (gy > 65535) gy = 65535;
+    dim3 grid(blocks_for(cols, bx), gy, rows_k);
+    dim3 block(bx, by);
+#define FV_LF(T) hipLaunchKernelGGL((k_flux<NDIM, AX, T>), grid, block, 0, s, U, F, g)
+    FV_DISPATCH_THREADS(threads, FV_LF)
+#undef FV_LF
+}
+
+void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s) {
+    if (g.ndim == 2) {
+        if (ax == 0) launch_flux_t<2, 0>(U, F, g, bx, threads, s);
+        else launch_flux_t<2, 1>(U, F, g, bx, threads, s);
+    } else {
+        if (ax == 0) launch_flux_t<3, 0>(U, F, g, bx, threads, s);
+        else if (ax == 1) launch_flux_t<3, 1>(U, F, g, bx, threads, s);
+        else launch_flux_t<3, 2>(U, F, g, bx, threads, s);
+    }
+}
+
+void launch_residual(const double* Fx, const double* Fy, const double* Fz, double* R, const Geo& g, int gang,
+                     int threads, hipStream_t s) {
+    int blocks, stride_all;
+    grid1d(g.ncell, gang, threads, blocks, stride_all);
+#define FV_LR(T)                                                                                       \
+    if (g.ndim == 2)                                                                                   \
+        hipLaunchKernelGGL((k_residual<2, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, R, g, stride_all); \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_residual<3, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, R, g, stride_all);
+    FV_DISPATCH_THREADS(threads, FV_LR)
+#undef FV_LR
+}
+
+template <int STAGE>
+static void launch_update_t(const double* Un, const double* Us, double* Ud, const double* R, const double* dt,
+                            const Geo& g, int gang, int threads, hipStream_t s) {
+    int blocks, stride_all;
+    grid1d(g.ncell, gang, threads, blocks, stride_all);
+#define FV_LU(T)                                                                                              \
+    if (g.ndim == 2)                                                                                          \
+        hipLaunchKernelGGL((k_update<2, STAGE, T>), dim3(blocks), dim3(T), 0, s, Un, Us, Ud, R, dt, g, stride_all); \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_update<3, STAGE, T>), dim3(blocks), dim3(T), 0, s, Un, Us, Ud, R, dt, g, stride_all);
+    FV_DISPATCH_THREADS(threads, FV_LU)
+#undef FV_LU
+}
+
+void launch_update(int stage, const double* Un, const double* Us, double* Ud, const double* R, const double* dt,
+                   const Geo& g, int gang, int threads, hipStream_t s) {
+    if (stage == 0) launch_update_t<0>(Un, Us, Ud, R, dt, g, gang, threads, s);
+    else if (stage == 1) launch_update_t<1>(Un, Us, Ud, R, dt, g, gang, threads, s);
+    else launch_update_t<2>(Un, Us, Ud, R, dt, g, gang, threads, s);
+}
+
+int cfl_blocks(const Geo& g, int gang, int threads) {
+    int blocks, stride_all;
+    grid1d(g.ncell, gang, threads, blocks, stride_all);
+    return blocks;
+}
+
+void launch_cfl(const double* U, double* partial, uint32_t* status, const double* dt_in, double* dt,
+                double* dt_out, const Geo& g, int gang, int threads, hipStream_t s) {
+    int blocks, stride_all;
+    grid1d(g.ncell, gang, threads, blocks, stride_all);
+#define FV_LC(T)                                                                                             \
+    if (g.ndim == 2)                                                                                         \
+        hipLaunchKernelGGL((k_cfl_partial<2, T>), dim3(blocks), dim3(T), 0, s, U, partial, status, g, stride_all); \
+    else                                                                                                     \
+        hipLaunchKernelGGL((k_cfl_partial<3, T>), dim3(blocks), dim3(T), 0, s, U, partial, status, g, stride_all);
+    FV_DISPATCH_THREADS(threads, FV_LC)
+#undef FV_LC
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, s, partial, blocks, dt_in, dt, dt_out, status, g.cfl);
+}
+
+void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, p, v);
+}
+
+}  // namespace fvk

@@ -1,0 +1,305 @@
+"""Thin ctypes binding of ``libfv.so`` (declared in ``include/fv.h``).
+
+The functions carry the C names and only marshal arguments: every step of
+the method runs in the library's HIP kernels. PyTorch provides device memory
+and streams. There is no fallback: when the library is missing, loading it
+raises.
+
+``Solver`` is a convenience that owns the torch buffers of one grid (ghosted
+state, workspace) and converts between the dense ``(nvar, nz, ny, nx)``
+interior layout and the library's ghosted layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfv.so")
+
+FV_OK = 0
+FV_EINVAL = -1
+FV_EDEVICE = -2
+FV_ENONPHYS = -3
+FV_ENOTSUP = -4
+FV_EWORKSPACE = -5
+
+FV_BC_PERIODIC = 0
+FV_BC_TRANSMISSIVE = 1
+
+FV_FLAG_NAN = 1
+FV_FLAG_RHO = 2
+FV_FLAG_P = 4
+FV_FLAG_DT = 8
+
+SITES = ("flux_x", "flux_y", "flux_z", "residual", "update", "bc", "cfl")
+NSITES = 7
+
+
+class fv_grid_desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+class fv_launch(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32 * 14)]
+
+
+class FvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fv error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2306_14011_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fv_default_launch.argtypes = [ctypes.POINTER(fv_launch)]
+        L.fv_default_launch.restype = None
+        L.fv_query.argtypes = [ctypes.POINTER(fv_grid_desc), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_size_t)]
+        L.fv_create.argtypes = [ctypes.POINTER(fv_grid_desc), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+        L.fv_destroy.argtypes = [_vp]
+        L.fv_set_stream.argtypes = [_vp, _vp]
+        L.fv_residual.argtypes = [_vp, _vp, _vp]
+        L.fv_step.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
+        L.fv_adjoint_step.argtypes = [_vp, _vp, _vp, _vp]
+        L.fv_set_launch.argtypes = [_vp, ctypes.POINTER(fv_launch)]
+        L.fv_get_launch.argtypes = [_vp, ctypes.POINTER(fv_launch)]
+        L.fv_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.fv_clear_status.argtypes = [_vp]
+        L.fv_set_timing.argtypes = [_vp, ctypes.c_int]
+        L.fv_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.fv_last_error.argtypes = [_vp]
+        L.fv_last_error.restype = ctypes.c_char_p
+        for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
+                     "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
+                     "fv_set_timing", "fv_get_timing"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != FV_OK:
+        msg = lib().fv_last_error(ctx).decode()
+        raise FvError(rc, msg)
+    return rc
+
+
+def make_desc(spec) -> fv_grid_desc:
+    """fv_grid_desc from any object with ndim, n, lo, hi, bc, gamma, cfl."""
+    d = fv_grid_desc()
+    d.ndim = spec.ndim
+    d.reserved = 0
+    for a in range(3):
+        d.n[a] = int(spec.n[a])
+        d.lo[a] = float(spec.lo[a])
+        d.hi[a] = float(spec.hi[a])
+        d.bc[a][0] = int(spec.bc[a][0])
+        d.bc[a][1] = int(spec.bc[a][1])
+    d.gamma = float(spec.gamma)
+    d.cfl = float(spec.cfl)
+    return d
+
+
+# --- C-named functions -------------------------------------------------------
+
+def fv_default_launch():
+    out = fv_launch()
+    lib().fv_default_launch(ctypes.byref(out))
+    return list(out.p)
+
+
+def fv_query(desc):
+    strides = (ctypes.c_int64 * 4)()
+    ws = ctypes.c_size_t()
+    _check(lib().fv_query(ctypes.byref(desc), strides, ctypes.byref(ws)))
+    return list(strides), ws.value
+
+
+def fv_create(desc, workspace_ptr, workspace_bytes, stream_ptr):
+    out = _vp()
+    _check(lib().fv_create(ctypes.byref(desc), _vp(workspace_ptr), workspace_bytes, _vp(stream_ptr),
+                           ctypes.byref(out)))
+    return out.value
+
+
+def fv_destroy(ctx):
+    return _check(lib().fv_destroy(_vp(ctx)))
+
+
+def fv_set_stream(ctx, stream_ptr):
+    return _check(lib().fv_set_stream(_vp(ctx), _vp(stream_ptr)), ctx)
+
+
+def fv_residual(ctx, U_ptr, R_ptr):
+    return _check(lib().fv_residual(_vp(ctx), _vp(U_ptr), _vp(R_ptr)), ctx)
+
+
+def fv_step(ctx, U_ptr, nsteps, dt_in_ptr=None, dt_out_ptr=None):
+    return _check(lib().fv_step(_vp(ctx), _vp(U_ptr), int(nsteps), _vp(dt_in_ptr), _vp(dt_out_ptr)), ctx)
+
+
+def fv_adjoint_step(ctx, U_ptr, dt_ptr, lam_ptr):
+    return _check(lib().fv_adjoint_step(_vp(ctx), _vp(U_ptr), _vp(dt_ptr), _vp(lam_ptr)), ctx)
+
+
+def fv_set_launch(ctx, params):
+    l = fv_launch()
+    for i, v in enumerate(params):
+        l.p[i] = int(v)
+    return _check(lib().fv_set_launch(_vp(ctx), ctypes.byref(l)), ctx)
+
+
+def fv_get_launch(ctx):
+    l = fv_launch()
+    _check(lib().fv_get_launch(_vp(ctx), ctypes.byref(l)), ctx)
+    return list(l.p)
+
+
+def fv_status(ctx):
+    """(return code, flags); syncs the context's stream."""
+    fl = ctypes.c_uint32()
+    rc = lib().fv_status(_vp(ctx), ctypes.byref(fl))
+    if rc not in (FV_OK, FV_ENONPHYS):
+        _check(rc, ctx)
+    return rc, fl.value
+
+
+def fv_clear_status(ctx):
+    return _check(lib().fv_clear_status(_vp(ctx)), ctx)
+
+
+def fv_set_timing(ctx, enable):
+    return _check(lib().fv_set_timing(_vp(ctx), 1 if enable else 0), ctx)
+
+
+def fv_get_timing(ctx):
+    """(ms per site, launches per site) accumulated since the last read."""
+    ms = (ctypes.c_double * NSITES)()
+    n = (ctypes.c_int64 * NSITES)()
+    _check(lib().fv_get_timing(_vp(ctx), ms, n), ctx)
+    return list(ms), list(n)
+
+
+def fv_last_error(ctx=None):
+    return lib().fv_last_error(_vp(ctx)).decode()
+
+
+# --- torch-side convenience ----------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_ptr(device=None):
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Solver:
+    """One grid's device buffers and context.
+
+    ``U`` is the ghosted state (a flat float64 tensor of nvar * s_v elements);
+    ``interior()`` is a strided view of its interior cells, shape
+    ``(nvar, nz, ny, nx)``.
+    """
+
+    def __init__(self, spec, device="cuda", stream=None):
+        torch = _torch()
+        self.spec = spec
+        self.desc = make_desc(spec)
+        self.strides, self.ws_bytes = fv_query(self.desc)
+        self.nvar = spec.ndim + 2
+        self.device = torch.device(device)
+        sx, sy, sz, sv = self.strides
+        self.U = torch.zeros(self.nvar * sv, dtype=torch.float64, device=self.device)
+        # workspace: torch's allocator returns blocks aligned to at least 256 B
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        assert self.workspace.data_ptr() % 256 == 0
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = fv_create(self.desc, self.workspace.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            fv_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _view(self, flat):
+        torch = _torch()
+        sx, sy, sz, sv = self.strides
+        nx, ny, nz = (int(v) for v in self.spec.n)
+        g3 = 2 if self.spec.ndim == 3 else 0
+        off = 2 + 2 * sy + g3 * sz
+        return torch.as_strided(flat, (self.nvar, nz, ny, nx), (sv, sz, sy, 1), off)
+
+    def interior(self):
+        return self._view(self.U)
+
+    def set_state(self, U_dense):
+        torch = _torch()
+        src = torch.as_tensor(np.ascontiguousarray(U_dense), dtype=torch.float64)
+        self.interior().copy_(src.to(self.device))
+
+    def get_state(self):
+        return self.interior().detach().cpu().numpy().copy()
+
+    def dense_zeros(self):
+        torch = _torch()
+        return torch.zeros(self.spec.shape, dtype=torch.float64, device=self.device)
+
+    def residual(self):
+        R = self.dense_zeros()
+        fv_residual(self.ctx, self.U.data_ptr(), R.data_ptr())
+        return R
+
+    def step(self, nsteps, dt_in=None, dt_out=None):
+        fv_step(self.ctx, self.U.data_ptr(), nsteps,
+                dt_in.data_ptr() if dt_in is not None else None,
+                dt_out.data_ptr() if dt_out is not None else None)
+
+    def set_launch(self, params):
+        fv_set_launch(self.ctx, params)
+
+    def get_launch(self):
+        return fv_get_launch(self.ctx)
+
+    def status(self):
+        return fv_status(self.ctx)
+
+    def set_timing(self, enable):
+        fv_set_timing(self.ctx, enable)
+
+    def get_timing(self):
+        return fv_get_timing(self.ctx)
+
+    def clear_status(self):
+        fv_clear_status(self.ctx)

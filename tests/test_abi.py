@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/*.h declares, and validates descriptions and launch tables
+without touching a GPU. Also checks that the oracle and the product path
+share no code."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2306_14011_amd import fv, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(fv_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("fv_query", "fv_create", "fv_destroy", "fv_residual", "fv_step",
+                     "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(fv.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_query_strides_and_workspace():
+    g = inputs.grid2d(64, 64)
+    strides, ws = fv.fv_query(fv.make_desc(g))
+    sx, sy, sz, sv = strides
+    assert sx == 1 and sy >= 64 + 4 and sy % 8 == 0
+    assert sz == sy * (64 + 4) and sv == sz
+    assert ws > 0
+    g3 = inputs.grid3d(10, 12, 14)
+    sx, sy, sz, sv = fv.fv_query(fv.make_desc(g3))[0]
+    assert sy >= 14 and sz == sy * 16 and sv == sz * 18
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda d: setattr(d, "ndim", 4),
+    lambda d: d.n.__setitem__(0, 0),
+    lambda d: d.n.__setitem__(2, 3),            # 2D with nz != 1
+    lambda d: d.bc[0].__setitem__(0, 1),        # periodic on one face only
+    lambda d: d.bc[1].__setitem__(1, 7),        # unknown kind
+    lambda d: setattr(d, "gamma", 1.0),
+    lambda d: setattr(d, "cfl", 0.0),
+    lambda d: setattr(d, "reserved", 1),
+    lambda d: d.hi.__setitem__(0, d.lo[0]),
+])
+def test_query_rejects_invalid_descriptions(mutate):
+    d = fv.make_desc(inputs.grid2d(16, 16))
+    mutate(d)
+    with pytest.raises(fv.FvError) as e:
+        fv.fv_query(d)
+    assert e.value.code == fv.FV_EINVAL
+    assert fv.fv_last_error()
+
+
+def test_query_rejects_oversized_grid():
+    d = fv.make_desc(inputs.grid3d(1400, 1400, 1400))
+    with pytest.raises(fv.FvError):
+        fv.fv_query(d)
+
+
+def test_default_launch():
+    p = fv.fv_default_launch()
+    assert p[:6] == [64, 256] * 3
+    assert p[6:] == [0, 256] * 4
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(fv, "_lib", None)
+    monkeypatch.setattr(fv, "LIB_PATH", "/nonexistent/libfv.so")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        fv.lib()
+
+
+def _sources(pattern):
+    return [p for p in glob.glob(os.path.join(ROOT, pattern), recursive=True)]
+
+
+def test_oracle_and_product_share_nothing():
+    for path in _sources("oracle/**/*.py") + _sources("oracle/**/*.cpp"):
+        text = open(path).read()
+        assert not re.search(r"^\s*(from|import)\s+paper_2306_14011_amd", text, re.M), path
+        assert "fv.h" not in text and "csrc" not in text, path
+    for path in _sources("paper_2306_14011_amd/**/*.py") + _sources("paper_2306_14011_amd/csrc/*"):
+        text = open(path).read()
+        assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), path
+        assert "liboracle" not in text and "fv_oracle" not in text, path
