@@ -1,0 +1,280 @@
+"""Machine-learning autotuning of the step's launch parameters (the paper's method).
+
+Following Sec. "Data Collection" and "Results" of the paper:
+  1. draw launch vectors at random from the 14-parameter space,
+  2. time the solver with each (solver time only, excluding launch set-up and
+     host-device copies) and keep the valid ones,
+  3. split 75 % / 25 % into training and test sets,
+  4. standardise the features (mean removal, unit variance),
+  5. train a fully connected ReLU network on runtime with Adam
+     (Table para-setting), report R^2 (Eq. R_square) on the test set,
+  6. use the network to find the configurations with the lowest predicted
+     runtime; here the whole space is predicted on the GPU and the best k
+     are measured again, and the fastest measured one is kept.
+The network is trained and evaluated by the library's FP32 kernels
+(fv_mlp_train / fv_mlp_predict / fv_mlp_sweep). This module is host-side
+orchestration only.
+
+A sample is valid when its launch produced a state bitwise equal to the
+default launch's (every launch of the split step computes identical
+arithmetic) and no device flag was raised; a launch the library rejects is
+recorded as invalid and left out of the training data.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fv, inputs
+from .tune_space import LaunchSpace
+
+# Table para-setting of the paper.
+PAPER_HPARAMS = dict(lr=9e-4, beta1=0.95, beta2=0.90, eps=1e-9, alpha=1e-4, tol=1e-6, batch=200,
+                     max_epochs=200, n_iter_no_change=10)
+
+
+def r2_score(y, yhat):
+    y = np.asarray(y, dtype=np.float64)
+    yhat = np.asarray(yhat, dtype=np.float64)
+    return float(1.0 - np.sum((y - yhat) ** 2) / np.sum((y - y.mean()) ** 2))
+
+
+def split_indices(n: int, seed: int, train_frac=0.75):
+    rng = np.random.default_rng(seed + 17)
+    perm = rng.permutation(n)
+    k = int(round(train_frac * n))
+    return perm[:k], perm[k:]
+
+
+class Network:
+    """FP32 network parameters and Adam state in device memory."""
+
+    def __init__(self, seed: int, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = torch.as_tensor(inputs.mlp_init(seed), dtype=torch.float32).to(self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.seed = seed
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def train(self, X, y, order=None, **hp):
+        torch = self.torch
+        h = dict(PAPER_HPARAMS)
+        h.update(hp)
+        X = torch.as_tensor(np.ascontiguousarray(X), dtype=torch.float32).to(self.device)
+        y = torch.as_tensor(np.ascontiguousarray(y), dtype=torch.float32).to(self.device)
+        n = X.shape[0]
+        if order is None:
+            order = inputs.epoch_orders(n, h["max_epochs"], self.seed)
+        order_t = torch.as_tensor(np.ascontiguousarray(order), dtype=torch.int32).to(self.device)
+        hpc = fv.fv_mlp_hparams(h["lr"], h["beta1"], h["beta2"], h["eps"], h["alpha"], h["tol"], h["batch"],
+                                h["max_epochs"], h["n_iter_no_change"], 0)
+        ws_bytes = fv.fv_mlp_workspace(min(h["batch"], n))
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        losses = torch.zeros(max(h["max_epochs"], 1), dtype=torch.float32, device=self.device)
+        ne = torch.zeros(1, dtype=torch.int32, device=self.device)
+        fv.fv_mlp_train(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.t.data_ptr(),
+                        X.data_ptr(), y.data_ptr(), n, order_t.data_ptr(), hpc, losses.data_ptr(), ne.data_ptr(),
+                        ws.data_ptr(), ws_bytes, self._stream())
+        nrun = int(ne.item())
+        return losses.cpu().numpy()[:nrun]
+
+    def loss_grad(self, X, y, alpha):
+        torch = self.torch
+        X = torch.as_tensor(np.ascontiguousarray(X), dtype=torch.float32).to(self.device)
+        y = torch.as_tensor(np.ascontiguousarray(y), dtype=torch.float32).to(self.device)
+        n = X.shape[0]
+        ws_bytes = fv.fv_mlp_workspace(n)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        g = torch.zeros_like(self.params)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        fv.fv_mlp_loss_grad(self.params.data_ptr(), X.data_ptr(), y.data_ptr(), n, alpha, g.data_ptr(),
+                            loss.data_ptr(), ws.data_ptr(), ws_bytes, self._stream())
+        return float(loss.item()), g.cpu().numpy()
+
+    def predict(self, X):
+        torch = self.torch
+        X = torch.as_tensor(np.ascontiguousarray(X), dtype=torch.float32).to(self.device)
+        n = X.shape[0]
+        out = torch.zeros(n, dtype=torch.float32, device=self.device)
+        fv.fv_mlp_predict(self.params.data_ptr(), X.data_ptr(), n, out.data_ptr(), self._stream())
+        return out.cpu().numpy()
+
+    def sweep(self, space_struct, begin, count, k):
+        torch = self.torch
+        ws_bytes = fv.fv_mlp_sweep_workspace()
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        ti = torch.zeros(k, dtype=torch.int64, device=self.device)
+        tv = torch.zeros(k, dtype=torch.float32, device=self.device)
+        fv.fv_mlp_sweep(self.params.data_ptr(), space_struct, begin, count, k, ti.data_ptr(), tv.data_ptr(),
+                        ws.data_ptr(), ws_bytes, self._stream())
+        return ti.cpu().numpy().tolist(), tv.cpu().numpy().tolist()
+
+
+@dataclass
+class Sample:
+    index: int
+    launch: list
+    ms: float          # median per-step time
+    valid: bool
+    reps: list = field(default_factory=list)
+
+
+class Autotuner:
+    """Runs the paper's tuning loop on one grid through the split step."""
+
+    def __init__(self, spec, U0, seed=0, repeats=3, warmup=3, min_ms=20.0, check_steps=2, log_path=None):
+        import torch
+        self.torch = torch
+        self.spec = spec
+        self.space = LaunchSpace(spec.ndim)
+        self.solver = fv.Solver(spec)
+        self.U0 = U0
+        self.seed = seed
+        self.repeats = repeats
+        self.warmup = warmup
+        self.min_ms = min_ms
+        self.check_steps = check_steps
+        self.log_path = log_path
+        self.solver.set_state(U0)
+        self.U_start = self.solver.U.clone()
+        self.default = fv.fv_default_launch()
+        self.ref = self._reference_state(self.default)
+        self.steps = 1
+        t = self._time(self.default, 1, 1)
+        self.steps = max(1, int(math.ceil(self.min_ms / max(t, 1e-3))))
+
+    def _reference_state(self, launch):
+        s = self.solver
+        s.set_launch(launch)
+        s.U.copy_(self.U_start)
+        s.step(self.check_steps)
+        return s.U.clone()
+
+    def _time(self, launch, steps, repeats):
+        torch = self.torch
+        s = self.solver
+        s.set_launch(launch)
+        stream = torch.cuda.current_stream()
+        s.step(self.warmup)
+        reps = []
+        for _ in range(repeats):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            e1.synchronize()
+            reps.append(e0.elapsed_time(e1) / steps)
+        self._last_reps = reps
+        return float(np.median(reps))
+
+    def measure(self, launch):
+        """(median ms per step, valid) for one launch vector."""
+        torch = self.torch
+        s = self.solver
+        try:
+            s.set_launch(launch)
+        except fv.FvError:
+            return float("nan"), False
+        s.U.copy_(self.U_start)
+        s.step(self.check_steps)
+        valid = bool(torch.equal(s.U, self.ref))
+        rc, flags = s.status()
+        if flags:
+            s.clear_status()
+            valid = False
+        s.U.copy_(self.U_start)
+        ms = self._time(launch, self.steps, self.repeats)
+        return ms, valid
+
+    def collect(self, count):
+        samples = []
+        done = {}
+        if self.log_path and os.path.exists(self.log_path):
+            for line in open(self.log_path):
+                r = json.loads(line)
+                done[r["index"]] = Sample(r["index"], r["launch"], r["ms"], r["valid"], r.get("reps", []))
+        for idx in self.space.sample(count, self.seed):
+            if idx in done:
+                samples.append(done[idx])
+                continue
+            launch = self.space.decode(idx)
+            ms, valid = self.measure(launch)
+            smp = Sample(idx, launch, ms, valid, list(self._last_reps))
+            samples.append(smp)
+            if self.log_path:
+                with open(self.log_path, "a") as f:
+                    f.write(json.dumps(smp.__dict__) + "\n")
+        return samples
+
+    def fit(self, samples):
+        good = [s for s in samples if s.valid and np.isfinite(s.ms)]
+        tr, te = split_indices(len(good), self.seed)
+        F = LaunchSpace.raw_features([s.launch for s in good])
+        t = np.array([s.ms for s in good])
+        scale = float(np.median(t[tr]))
+        y = t / scale
+        mean = F[tr].mean(axis=0)
+        std = F[tr].std(axis=0)
+        std = np.where(std == 0.0, 1.0, std)
+        X = (F - mean) / std
+        net = Network(self.seed)
+        losses = net.train(X[tr], y[tr])
+        r2_test = r2_score(y[te], net.predict(X[te]))
+        r2_train = r2_score(y[tr], net.predict(X[tr]))
+        return dict(net=net, mean=mean, std=std, scale=scale, r2_test=r2_test, r2_train=r2_train,
+                    losses=losses, n_train=len(tr), n_test=len(te), good=good)
+
+    def sweep(self, model, k=8):
+        sp = self.space.struct(model["mean"], model["std"])
+        t0 = time.perf_counter()
+        idx, val = model["net"].sweep(sp, 0, self.space.size, k)
+        self.torch.cuda.synchronize()
+        return idx, val, time.perf_counter() - t0
+
+    def interleaved(self, launches, rounds=5, steps=None):
+        """Median per-step ms of each launch, timed A/B/A/B... over `rounds`."""
+        steps = steps or self.steps
+        res = [[] for _ in launches]
+        for _ in range(rounds):
+            for i, l in enumerate(launches):
+                res[i].append(self._time(l, steps, 1))
+        return [float(np.median(r)) for r in res]
+
+    def run(self, count=300, k=8, rounds=5, final_steps=None):
+        t0 = time.perf_counter()
+        samples = self.collect(count)
+        t_collect = time.perf_counter() - t0
+        model = self.fit(samples)
+        top_idx, top_val, t_sweep = self.sweep(model, k)
+        cands = [self.space.decode(i) for i in top_idx]
+        cand_ms = [self.measure(l) for l in cands]
+        ok = [(ms, i) for i, (ms, v) in enumerate(cand_ms) if v]
+        best = cands[min(ok)[1]] if ok else self.default
+        good = model["good"]
+        best_random = min(good, key=lambda s: s.ms).launch
+        final = self.interleaved([self.default, best, best_random], rounds=rounds, steps=final_steps)
+        return dict(
+            default_launch=self.default, tuned_launch=best, best_random_launch=best_random,
+            default_ms=final[0], tuned_ms=final[1], best_random_ms=final[2],
+            factor_vs_default=final[0] / final[1], factor_vs_best_random=final[2] / final[1],
+            r2_test=model["r2_test"], r2_train=model["r2_train"], n_samples=len(samples),
+            n_valid=len(good), n_train=model["n_train"], n_test=model["n_test"],
+            epochs=len(model["losses"]), final_loss=float(model["losses"][-1]) if len(model["losses"]) else None,
+            space_size=self.space.size, sweep_seconds=t_sweep, collect_seconds=t_collect,
+            top_pred=top_val, top_measured_ms=[m for m, _ in cand_ms], steps_per_sample=self.steps,
+        )
+
+    def close(self):
+        self.solver.close()

@@ -1,0 +1,552 @@
+// FP32 kernels of the launch-parameter autotuner's regression network:
+// training (forward, backward and Adam over minibatches, one workgroup),
+// loss/gradient, prediction, and the exhaustive sweep of the launch space
+// with a top-k selection of the lowest predicted runtimes.
+//
+// Network 14 -> 64 -> 64 -> 64 -> 1 with ReLU hidden layers; parameters are
+// one flat array W1[64][14], b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4.
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/fv.h"
+#include "fv_device.h"
+
+namespace mlp {
+
+constexpr int IN = FV_MLP_IN;
+constexpr int H = FV_MLP_HID;
+constexpr int oW1 = 0;
+constexpr int oB1 = oW1 + H * IN;
+constexpr int oW2 = oB1 + H;
+constexpr int oB2 = oW2 + H * H;
+constexpr int oW3 = oB2 + H;
+constexpr int oB3 = oW3 + H * H;
+constexpr int oW4 = oB3 + H;
+constexpr int oB4 = oW4 + H;
+constexpr int NP = oB4 + 1;
+static_assert(NP == FV_MLP_NPARAM, "parameter count");
+constexpr int MAXN = 65536;
+constexpr int TB = 1024;  // threads of the single-workgroup kernels
+
+// Scratch of the training / gradient kernels for n rows.
+struct Scratch {
+    float* Z1;    // [n][H] pre-activations
+    float* Z2;
+    float* Z3;
+    float* Da;    // [n][H] deltas
+    float* Db;
+    float* out;   // [n]
+    float* dout;  // [n]
+    float* grad;  // [NP]
+};
+
+inline size_t scratch_bytes(int n) { return ((size_t)5 * n * H + 2 * (size_t)n + NP) * sizeof(float) + 256; }
+
+inline Scratch carve(void* ws, int n) {
+    float* p = (float*)ws;
+    Scratch s;
+    s.Z1 = p;
+    p += (size_t)n * H;
+    s.Z2 = p;
+    p += (size_t)n * H;
+    s.Z3 = p;
+    p += (size_t)n * H;
+    s.Da = p;
+    p += (size_t)n * H;
+    s.Db = p;
+    p += (size_t)n * H;
+    s.out = p;
+    p += n;
+    s.dout = p;
+    p += n;
+    s.grad = p;
+    return s;
+}
+
+__device__ __forceinline__ float relu(float z) { return z > 0.f ? z : 0.f; }
+
+// Block-wide sum; every thread gets the result. sm holds TB/64 floats.
+__device__ float block_sum(float v, float* sm) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sm[w] = v;
+    __syncthreads();
+    float t = 0.f;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) t += sm[i];
+    __syncthreads();
+    return t;
+}
+
+// Row r of the minibatch -> row of X.
+__device__ __forceinline__ int row_of(const int32_t* rows, int r) { return rows ? rows[r] : r; }
+
+// Dense layer over a minibatch: Z[r][o] = b[o] + sum_i W[o][i] act(A[r][i]).
+// act is identity for the input layer (A = X rows) and ReLU otherwise.
+template <int NIN, bool INPUT>
+__device__ void layer_fwd(const float* __restrict__ P, int oW, int oB, const float* A, const float* __restrict__ X,
+                          const int32_t* rows, int sz, float* Z) {
+    for (int e = threadIdx.x; e < sz * H; e += blockDim.x) {
+        const int r = e / H, o = e - r * H;
+        float a = P[oB + o];
+        if (INPUT) {
+            const float* x = X + (size_t)row_of(rows, r) * IN;
+            for (int i = 0; i < NIN; ++i) a = fmaf(P[oW + o * NIN + i], x[i], a);
+        } else {
+            const float* h = A + (size_t)r * H;
+            for (int i = 0; i < NIN; ++i) a = fmaf(P[oW + o * NIN + i], relu(h[i]), a);
+        }
+        Z[e] = a;
+    }
+}
+
+// Forward + loss + backward over sz rows; gradient into s.grad, returns the loss.
+__device__ float forward_backward(const float* __restrict__ P, const float* __restrict__ X,
+                                  const float* __restrict__ Y, const int32_t* rows, int sz, float alpha,
+                                  const Scratch& s, float* sm) {
+    layer_fwd<IN, true>(P, oW1, oB1, nullptr, X, rows, sz, s.Z1);
+    __syncthreads();
+    layer_fwd<H, false>(P, oW2, oB2, s.Z1, X, rows, sz, s.Z2);
+    __syncthreads();
+    layer_fwd<H, false>(P, oW3, oB3, s.Z2, X, rows, sz, s.Z3);
+    __syncthreads();
+    float sq = 0.f;
+    const float inv = 1.0f / (float)sz;
+    for (int r = threadIdx.x; r < sz; r += blockDim.x) {
+        float a = P[oB4];
+        const float* h = s.Z3 + (size_t)r * H;
+        for (int i = 0; i < H; ++i) a = fmaf(P[oW4 + i], relu(h[i]), a);
+        s.out[r] = a;
+        const float d = a - Y[row_of(rows, r)];
+        s.dout[r] = d * inv;
+        sq += d * d;
+    }
+    float w2 = 0.f;
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+        const bool bias = (p >= oB1 && p < oW2) || (p >= oB2 && p < oW3) || (p >= oB3 && p < oW4) || p == oB4;
+        if (!bias) w2 += P[p] * P[p];
+    }
+    sq = block_sum(sq, sm);
+    w2 = block_sum(w2, sm);
+    const float loss = 0.5f * sq * inv + 0.5f * alpha * w2 * inv;
+    const float lam = alpha * inv;
+
+    // output layer: gW4[i] = sum_r dout_r relu(Z3[r][i]) + lam W4[i]; gb4 = sum_r dout_r
+    for (int i = threadIdx.x; i < H + 1; i += blockDim.x) {
+        float g = 0.f;
+        if (i < H) {
+            for (int r = 0; r < sz; ++r) g = fmaf(s.dout[r], relu(s.Z3[(size_t)r * H + i]), g);
+            s.grad[oW4 + i] = g + lam * P[oW4 + i];
+        } else {
+            for (int r = 0; r < sz; ++r) g += s.dout[r];
+            s.grad[oB4] = g;
+        }
+    }
+    // D3[r][i] = dout_r W4[i] [Z3 > 0]
+    for (int e = threadIdx.x; e < sz * H; e += blockDim.x) {
+        const int r = e / H, i = e - r * H;
+        s.Da[e] = s.Z3[e] > 0.f ? s.dout[r] * P[oW4 + i] : 0.f;
+    }
+    __syncthreads();
+    // hidden layers 3 and 2: weight gradients from the delta, then the delta below
+    const float* Zin[2] = {s.Z2, s.Z1};
+    const int oWs[2] = {oW3, oW2};
+    const int oBs[2] = {oB3, oB2};
+    float* Dcur = s.Da;
+    float* Dnext = s.Db;
+    for (int L = 0; L < 2; ++L) {
+        const float* Zi = Zin[L];
+        const int oW = oWs[L], oB = oBs[L];
+        for (int e = threadIdx.x; e < H * H + H; e += blockDim.x) {
+            float g = 0.f;
+            if (e < H * H) {
+                const int o = e / H, i = e - o * H;
+                for (int r = 0; r < sz; ++r) g = fmaf(Dcur[(size_t)r * H + o], relu(Zi[(size_t)r * H + i]), g);
+                s.grad[oW + e] = g + lam * P[oW + e];
+            } else {
+                const int o = e - H * H;
+                for (int r = 0; r < sz; ++r) g += Dcur[(size_t)r * H + o];
+                s.grad[oB + o] = g;
+            }
+        }
+        for (int e = threadIdx.x; e < sz * H; e += blockDim.x) {
+            const int r = e / H, i = e - r * H;
+            float a = 0.f;
+            for (int o = 0; o < H; ++o) a = fmaf(Dcur[(size_t)r * H + o], P[oW + o * H + i], a);
+            Dnext[e] = Zi[e] > 0.f ? a : 0.f;
+        }
+        __syncthreads();
+        float* t = Dcur;
+        Dcur = Dnext;
+        Dnext = t;
+    }
+    // input layer: gW1[o][i] = sum_r D1[r][o] x_r[i] + lam W1; gb1
+    for (int e = threadIdx.x; e < H * IN + H; e += blockDim.x) {
+        float g = 0.f;
+        if (e < H * IN) {
+            const int o = e / IN, i = e - o * IN;
+            for (int r = 0; r < sz; ++r) g = fmaf(Dcur[(size_t)r * H + o], X[(size_t)row_of(rows, r) * IN + i], g);
+            s.grad[oW1 + e] = g + lam * P[oW1 + e];
+        } else {
+            const int o = e - H * IN;
+            for (int r = 0; r < sz; ++r) g += Dcur[(size_t)r * H + o];
+            s.grad[oB1 + o] = g;
+        }
+    }
+    __syncthreads();
+    return loss;
+}
+
+__global__ void __launch_bounds__(TB) k_loss_grad(const float* __restrict__ P, const float* __restrict__ X,
+                                                  const float* __restrict__ Y, int n, float alpha, float* grad,
+                                                  float* loss, Scratch s) {
+    __shared__ float sm[TB / 64];
+    const float l = forward_backward(P, X, Y, nullptr, n, alpha, s, sm);
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) grad[p] = s.grad[p];
+    if (threadIdx.x == 0) *loss = l;
+}
+
+__global__ void __launch_bounds__(TB) k_train(float* P, float* M, float* V, int32_t* tptr, const float* __restrict__ X,
+                                              const float* __restrict__ Y, int n, const int32_t* __restrict__ order,
+                                              fv_mlp_hparams hp, float* epoch_loss, int32_t* epochs_run, Scratch s) {
+    __shared__ float sm[TB / 64];
+    int t = *tptr;
+    float best = FLT_MAX;
+    int noimp = 0;
+    int e = 0;
+    for (; e < hp.max_epochs; ++e) {
+        float acc = 0.f;
+        for (int start = 0; start < n; start += hp.batch) {
+            const int sz = min(hp.batch, n - start);
+            const float lb = forward_backward(P, X, Y, order + (size_t)e * n + start, sz, hp.alpha, s, sm);
+            acc += lb * (float)sz;
+            ++t;
+            // bias-corrected step size, scalar, in double
+            const double c2 = 1.0 - pow((double)hp.beta2, (double)t);
+            const double c1 = 1.0 - pow((double)hp.beta1, (double)t);
+            const float lrt = (float)((double)hp.lr * sqrt(c2) / c1);
+            for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+                const float g = s.grad[p];
+                const float m = hp.beta1 * M[p] + (1.f - hp.beta1) * g;
+                const float v = hp.beta2 * V[p] + (1.f - hp.beta2) * g * g;
+                M[p] = m;
+                V[p] = v;
+                P[p] -= lrt * m / (sqrtf(v) + hp.eps);
+            }
+            __syncthreads();
+        }
+        const float el = acc / (float)n;
+        if (threadIdx.x == 0) epoch_loss[e] = el;
+        if (el > best - hp.tol) ++noimp;
+        else noimp = 0;
+        if (el < best) best = el;
+        if (noimp > hp.n_iter_no_change) {
+            ++e;
+            break;
+        }
+    }
+    if (threadIdx.x == 0) {
+        *epochs_run = e;
+        *tptr = t;
+    }
+}
+
+// Forward pass of one row, weights read uniformly across the wave.
+__device__ __forceinline__ float forward_row(const float* __restrict__ P, const float* x) {
+    float h1[H], h2[H];
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+        float a = P[oB1 + o];
+#pragma unroll
+        for (int i = 0; i < IN; ++i) a = fmaf(P[oW1 + o * IN + i], x[i], a);
+        h1[o] = relu(a);
+    }
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+        float a = P[oB2 + o];
+#pragma unroll
+        for (int i = 0; i < H; ++i) a = fmaf(P[oW2 + o * H + i], h1[i], a);
+        h2[o] = relu(a);
+    }
+    float out = P[oB4];
+#pragma unroll
+    for (int o = 0; o < H; ++o) {
+        float a = P[oB3 + o];
+#pragma unroll
+        for (int i = 0; i < H; ++i) a = fmaf(P[oW3 + o * H + i], h2[i], a);
+        out = fmaf(P[oW4 + o], relu(a), out);
+    }
+    return out;
+}
+
+__global__ void __launch_bounds__(256) k_predict(const float* __restrict__ P, const float* __restrict__ X, int n,
+                                                 float* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    float x[IN];
+#pragma unroll
+    for (int i = 0; i < IN; ++i) x[i] = X[(size_t)r * IN + i];
+    out[r] = forward_row(P, x);
+}
+
+// ---------------------------------------------------------------------------
+// Sweep of the launch space.
+
+constexpr int KMAX = 8;
+constexpr int SWEEP_T = 256;
+constexpr int SWEEP_MAXB = 4096;
+
+struct SweepTab {
+    int32_t radix[FV_NSITES];
+    float f1[FV_NSITES][FV_SPACE_MAXC];
+    float f2[FV_NSITES][FV_SPACE_MAXC];
+};
+
+// (v, i) orders before (w, j): lower value, ties to the lower index; NaN last.
+__device__ __forceinline__ bool before(float v, long long i, float w, long long j) {
+    return v < w || (v == w && i < j);
+}
+
+// Thread-local ascending top-k list.
+struct TopK {
+    float v[KMAX];
+    long long i[KMAX];
+    __device__ void init() {
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            v[q] = FLT_MAX;
+            i[q] = LLONG_MAX;
+        }
+    }
+    __device__ void insert(float val, long long idx) {
+        if (!(val == val)) val = FLT_MAX;  // NaN never wins
+        if (!before(val, idx, v[KMAX - 1], i[KMAX - 1])) return;
+        float cv = val;
+        long long ci = idx;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+            if (before(cv, ci, v[q], i[q])) {
+                const float tv = v[q];
+                const long long ti = i[q];
+                v[q] = cv;
+                i[q] = ci;
+                cv = tv;
+                ci = ti;
+            }
+        }
+    }
+};
+
+// k rounds of block-wide argmin over cnt (value, index) pairs in vals/idxs
+// (LDS or global); selected entries are overwritten with FLT_MAX/LLONG_MAX.
+// Thread 0 writes the winners to ov/oi in ascending order.
+__device__ void select_topk(float* vals, long long* idxs, int cnt, int k, float* ov, long long* oi, float* smv,
+                            long long* smi, int* smp) {
+    for (int round = 0; round < k; ++round) {
+        float bv = FLT_MAX;
+        long long bi = LLONG_MAX;
+        int bp = -1;
+        for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+            if (before(vals[p], idxs[p], bv, bi)) {
+                bv = vals[p];
+                bi = idxs[p];
+                bp = p;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float ov2 = __shfl_xor(bv, off, 64);
+            const long long oi2 = __shfl_xor(bi, off, 64);
+            const int op2 = __shfl_xor(bp, off, 64);
+            if (before(ov2, oi2, bv, bi)) {
+                bv = ov2;
+                bi = oi2;
+                bp = op2;
+            }
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            smv[w] = bv;
+            smi[w] = bi;
+            smp[w] = bp;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nw = blockDim.x >> 6;
+            for (int q = 1; q < nw; ++q)
+                if (before(smv[q], smi[q], bv, bi)) {
+                    bv = smv[q];
+                    bi = smi[q];
+                    bp = smp[q];
+                }
+            ov[round] = bv;
+            oi[round] = bi;
+            if (bp >= 0) {
+                vals[bp] = FLT_MAX;
+                idxs[bp] = LLONG_MAX;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(SWEEP_T) k_sweep(const float* __restrict__ P, SweepTab tab, long long begin,
+                                                    long long count, int k, float* __restrict__ pv,
+                                                    long long* __restrict__ pi) {
+    __shared__ float lv[SWEEP_T * KMAX];
+    __shared__ long long li[SWEEP_T * KMAX];
+    __shared__ float smv[SWEEP_T / 64];
+    __shared__ long long smi[SWEEP_T / 64];
+    __shared__ int smp[SWEEP_T / 64];
+    TopK top;
+    top.init();
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride) {
+        const long long idx = begin + t;
+        unsigned long long rem = (unsigned long long)idx;
+        float x[IN];
+#pragma unroll
+        for (int site = 0; site < FV_NSITES; ++site) {
+            const unsigned r = (unsigned)tab.radix[site];
+            const unsigned c = (unsigned)(rem % r);
+            rem /= r;
+            x[2 * site] = tab.f1[site][c];
+            x[2 * site + 1] = tab.f2[site][c];
+        }
+        // an opaque copy of the (uniform) weight pointer per iteration keeps the
+        // ~9k scalar weight loads inside the loop instead of hoisted out of it
+        const float* Pl = P;
+        asm volatile("" : "+s"(Pl));
+        top.insert(forward_row(Pl, x), idx);
+    }
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        lv[threadIdx.x * KMAX + q] = top.v[q];
+        li[threadIdx.x * KMAX + q] = top.i[q];
+    }
+    __syncthreads();
+    select_topk(lv, li, SWEEP_T * KMAX, k, pv + (size_t)blockIdx.x * KMAX, pi + (size_t)blockIdx.x * KMAX, smv, smi,
+                smp);
+    if (threadIdx.x == 0)
+        for (int q = k; q < KMAX; ++q) {
+            pv[(size_t)blockIdx.x * KMAX + q] = FLT_MAX;
+            pi[(size_t)blockIdx.x * KMAX + q] = LLONG_MAX;
+        }
+}
+
+__global__ void __launch_bounds__(1024) k_sweep_final(float* pv, long long* pi, int cnt, int k, float* top_val,
+                                                      long long* top_idx) {
+    __shared__ float smv[16];
+    __shared__ long long smi[16];
+    __shared__ int smp[16];
+    __shared__ float ov[KMAX];
+    __shared__ long long oi[KMAX];
+    select_topk(pv, pi, cnt, k, ov, oi, smv, smi, smp);
+    if (threadIdx.x < k) {
+        top_val[threadIdx.x] = ov[threadIdx.x];
+        top_idx[threadIdx.x] = oi[threadIdx.x];
+    }
+}
+
+}  // namespace mlp
+
+// ---------------------------------------------------------------------------
+// C ABI.
+
+static int mlp_check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        fprintf(stderr, "fv_mlp: launch failed: %s\n", hipGetErrorString(e));
+        return FV_EDEVICE;
+    }
+    return FV_OK;
+}
+
+extern "C" {
+
+int fv_mlp_workspace(int32_t n, size_t* bytes) {
+    if (n < 1 || n > mlp::MAXN || !bytes) return FV_EINVAL;
+    *bytes = mlp::scratch_bytes(n);
+    return FV_OK;
+}
+
+int fv_mlp_loss_grad(const float* params, const float* X, const float* y, int32_t n, float alpha, float* grad,
+                     float* loss, void* workspace, size_t ws_bytes, void* stream) {
+    if (!params || !X || !y || !grad || !loss || !workspace) return FV_EINVAL;
+    if (n < 1 || n > mlp::MAXN || !(alpha >= 0.f)) return FV_EINVAL;
+    if (ws_bytes < mlp::scratch_bytes(n)) return FV_EWORKSPACE;
+    mlp::Scratch s = mlp::carve(workspace, n);
+    hipLaunchKernelGGL(mlp::k_loss_grad, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params, X, y, n, alpha, grad,
+                       loss, s);
+    return mlp_check_launch();
+}
+
+int fv_mlp_predict(const float* params, const float* X, int32_t n, float* out, void* stream) {
+    if (!params || !X || !out || n < 0) return FV_EINVAL;
+    if (n == 0) return FV_OK;
+    hipLaunchKernelGGL(mlp::k_predict, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, X, n, out);
+    return mlp_check_launch();
+}
+
+int fv_mlp_train(float* params, float* adam_m, float* adam_v, int32_t* adam_t, const float* X, const float* y,
+                 int32_t n, const int32_t* order, const fv_mlp_hparams* hp, float* epoch_loss, int32_t* epochs_run,
+                 void* workspace, size_t ws_bytes, void* stream) {
+    if (!params || !adam_m || !adam_v || !adam_t || !X || !y || !order || !hp || !epoch_loss || !epochs_run ||
+        !workspace)
+        return FV_EINVAL;
+    if (n < 1 || n > mlp::MAXN || hp->batch < 1 || hp->max_epochs < 0 || hp->n_iter_no_change < 0) return FV_EINVAL;
+    if (!(hp->lr > 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
+        !(hp->eps > 0.f) || !(hp->alpha >= 0.f))
+        return FV_EINVAL;
+    const int bmax = hp->batch < n ? hp->batch : n;
+    if (ws_bytes < mlp::scratch_bytes(bmax)) return FV_EWORKSPACE;
+    mlp::Scratch s = mlp::carve(workspace, bmax);
+    hipLaunchKernelGGL(mlp::k_train, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params, adam_m, adam_v, adam_t, X,
+                       y, n, order, *hp, epoch_loss, epochs_run, s);
+    return mlp_check_launch();
+}
+
+int fv_mlp_sweep_workspace(size_t* bytes) {
+    if (!bytes) return FV_EINVAL;
+    *bytes = (size_t)mlp::SWEEP_MAXB * mlp::KMAX * (sizeof(float) + sizeof(long long)) + 256;
+    return FV_OK;
+}
+
+int fv_mlp_sweep(const float* params, const fv_tune_space* space, int64_t begin, int64_t count, int32_t k,
+                 int64_t* top_idx, float* top_val, void* workspace, size_t ws_bytes, void* stream) {
+    if (!params || !space || !top_idx || !top_val || !workspace) return FV_EINVAL;
+    if (k < 1 || k > mlp::KMAX || begin < 0 || count < 1) return FV_EINVAL;
+    size_t need = 0;
+    fv_mlp_sweep_workspace(&need);
+    if (ws_bytes < need) return FV_EWORKSPACE;
+    mlp::SweepTab tab;
+    int64_t total = 1;
+    for (int s = 0; s < FV_NSITES; ++s) {
+        const int r = space->radix[s];
+        if (r < 1 || r > FV_SPACE_MAXC) return FV_EINVAL;
+        tab.radix[s] = r;
+        total *= r;
+        for (int c = 0; c < FV_SPACE_MAXC; ++c) {
+            tab.f1[s][c] = c < r ? space->f1[s][c] : 0.f;
+            tab.f2[s][c] = c < r ? space->f2[s][c] : 0.f;
+        }
+    }
+    if (begin + count > total) return FV_EINVAL;
+    long long blocks = (count + mlp::SWEEP_T - 1) / mlp::SWEEP_T;
+    if (blocks > mlp::SWEEP_MAXB) blocks = mlp::SWEEP_MAXB;
+    float* pv = (float*)workspace;
+    long long* pi = (long long*)((char*)workspace + (((size_t)mlp::SWEEP_MAXB * mlp::KMAX * sizeof(float) + 255) & ~(size_t)255));
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(mlp::k_sweep, dim3((unsigned)blocks), dim3(mlp::SWEEP_T), 0, st, params, tab,
+                       (long long)begin, (long long)count, k, pv, pi);
+    hipLaunchKernelGGL(mlp::k_sweep_final, dim3(1), dim3(1024), 0, st, pv, pi, (int)(blocks * mlp::KMAX), k, top_val,
+                       (long long*)top_idx);
+    return mlp_check_launch();
+}
+
+}  // extern "C"

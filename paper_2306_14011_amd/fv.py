@@ -55,6 +55,37 @@ class fv_launch(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32 * 14)]
 
 
+FV_MLP_IN = 14
+FV_MLP_HID = 64
+FV_MLP_NPARAM = 9345
+FV_SPACE_MAXC = 32
+
+
+class fv_mlp_hparams(ctypes.Structure):
+    _fields_ = [
+        ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("alpha", ctypes.c_float),
+        ("tol", ctypes.c_float),
+        ("batch", ctypes.c_int32),
+        ("max_epochs", ctypes.c_int32),
+        ("n_iter_no_change", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class fv_tune_space(ctypes.Structure):
+    _fields_ = [
+        ("radix", ctypes.c_int32 * NSITES),
+        ("p1", (ctypes.c_int32 * FV_SPACE_MAXC) * NSITES),
+        ("p2", (ctypes.c_int32 * FV_SPACE_MAXC) * NSITES),
+        ("f1", (ctypes.c_float * FV_SPACE_MAXC) * NSITES),
+        ("f2", (ctypes.c_float * FV_SPACE_MAXC) * NSITES),
+    ]
+
+
 class FvError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"fv error {code}: {msg}")
@@ -92,9 +123,19 @@ def lib():
         L.fv_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fv_last_error.argtypes = [_vp]
         L.fv_last_error.restype = ctypes.c_char_p
+        L.fv_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.fv_mlp_sweep_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
+        L.fv_mlp_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp, _vp,
+                                       ctypes.c_size_t, _vp]
+        L.fv_mlp_predict.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
+        L.fv_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+                                   ctypes.POINTER(fv_mlp_hparams), _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.fv_mlp_sweep.argtypes = [_vp, ctypes.POINTER(fv_tune_space), ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
                      "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
-                     "fv_set_timing", "fv_get_timing"):
+                     "fv_set_timing", "fv_get_timing", "fv_mlp_workspace", "fv_mlp_sweep_workspace",
+                     "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -205,6 +246,48 @@ def fv_get_timing(ctx):
 
 def fv_last_error(ctx=None):
     return lib().fv_last_error(_vp(ctx)).decode()
+
+
+def fv_mlp_workspace(n):
+    b = ctypes.c_size_t()
+    _check(lib().fv_mlp_workspace(int(n), ctypes.byref(b)))
+    return b.value
+
+
+def fv_mlp_sweep_workspace():
+    b = ctypes.c_size_t()
+    _check(lib().fv_mlp_sweep_workspace(ctypes.byref(b)))
+    return b.value
+
+
+def _mlp_check(rc, what):
+    if rc != FV_OK:
+        raise FvError(rc, what)
+    return rc
+
+
+def fv_mlp_loss_grad(params_ptr, X_ptr, y_ptr, n, alpha, grad_ptr, loss_ptr, ws_ptr, ws_bytes, stream_ptr):
+    return _mlp_check(lib().fv_mlp_loss_grad(_vp(params_ptr), _vp(X_ptr), _vp(y_ptr), int(n), float(alpha),
+                                             _vp(grad_ptr), _vp(loss_ptr), _vp(ws_ptr), ws_bytes,
+                                             _vp(stream_ptr)), "fv_mlp_loss_grad")
+
+
+def fv_mlp_predict(params_ptr, X_ptr, n, out_ptr, stream_ptr):
+    return _mlp_check(lib().fv_mlp_predict(_vp(params_ptr), _vp(X_ptr), int(n), _vp(out_ptr), _vp(stream_ptr)),
+                      "fv_mlp_predict")
+
+
+def fv_mlp_train(params_ptr, m_ptr, v_ptr, t_ptr, X_ptr, y_ptr, n, order_ptr, hp, loss_ptr, epochs_ptr,
+                 ws_ptr, ws_bytes, stream_ptr):
+    return _mlp_check(lib().fv_mlp_train(_vp(params_ptr), _vp(m_ptr), _vp(v_ptr), _vp(t_ptr), _vp(X_ptr),
+                                         _vp(y_ptr), int(n), _vp(order_ptr), ctypes.byref(hp), _vp(loss_ptr),
+                                         _vp(epochs_ptr), _vp(ws_ptr), ws_bytes, _vp(stream_ptr)), "fv_mlp_train")
+
+
+def fv_mlp_sweep(params_ptr, space, begin, count, k, top_idx_ptr, top_val_ptr, ws_ptr, ws_bytes, stream_ptr):
+    return _mlp_check(lib().fv_mlp_sweep(_vp(params_ptr), ctypes.byref(space), int(begin), int(count), int(k),
+                                         _vp(top_idx_ptr), _vp(top_val_ptr), _vp(ws_ptr), ws_bytes,
+                                         _vp(stream_ptr)), "fv_mlp_sweep")
 
 
 # --- torch-side convenience ----------------------------------------------------

@@ -257,3 +257,28 @@ def random_directions(shape, count, seed, scales):
         d /= np.max(np.abs(d))
         out.append(d)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Random draws of the autotuner's network (passed to both the GPU kernels and
+# the oracle): initial parameters and the row order of every epoch.
+
+MLP_LAYERS = ((14, 64), (64, 64), (64, 64), (64, 1))
+
+
+def mlp_init(seed: int):
+    """Flat float64 parameters W1, b1, ..., W4, b4 (W[out][in]); every layer
+    uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot & Bengio 2010)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in MLP_LAYERS:
+        b = math.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-b, b, size=(fo, fi)).ravel())
+        parts.append(rng.uniform(-b, b, size=fo))
+    return np.concatenate(parts)
+
+
+def epoch_orders(n: int, epochs: int, seed: int):
+    """One random permutation of range(n) per epoch, shape (epochs, n), int32."""
+    rng = np.random.default_rng(seed + 104729)
+    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)

@@ -1,0 +1,189 @@
+"""The network kernels (FP32, through the C ABI) against the FP64 oracle, and
+the tuning method on a synthetic cost with a known optimum."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2306_14011_amd import inputs
+from paper_2306_14011_amd.tune_space import LaunchSpace
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(n=225, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, 14)).astype(np.float32).astype(np.float64)
+    y = 1.0 + 0.3 * np.sin(X[:, 0]) + 0.2 * X[:, 3] * X[:, 5] + 0.05 * rng.standard_normal(n)
+    return X, y
+
+
+def net(seed):
+    from paper_2306_14011_amd.autotune import Network
+    return Network(seed)
+
+
+def f32(theta):
+    return theta.astype(np.float32).astype(np.float64)
+
+
+def test_loss_and_gradient_match_oracle():
+    X, y = problem()
+    N = net(3)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    assert np.array_equal(theta, f32(inputs.mlp_init(3)))
+    for alpha in (0.0, 1e-4, 0.5):
+        L, g = N.loss_grad(X, y, alpha)
+        Lr, gr = mlp.loss_grad(theta, X, y, alpha)
+        assert abs(L - Lr) <= 1e-5 * abs(Lr)
+        assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+        assert np.abs(g - gr).max() <= 1e-4 * np.abs(gr).max()
+
+
+def test_predict_matches_oracle():
+    X, _ = problem(1000, 1)
+    N = net(4)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    out = N.predict(X)
+    ref = mlp.predict(theta, X)
+    assert np.abs(out - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_first_adam_step_closed_form():
+    X, y = problem(150, 2)
+    N = net(5)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    _, gr = mlp.loss_grad(theta, X, y, 1e-4)
+    N.train(X, y, order=inputs.epoch_orders(150, 1, 0), max_epochs=1, batch=200)
+    step = N.params.cpu().numpy().astype(np.float64) - theta
+    expect = -9e-4 * gr / (np.abs(gr) + 1e-9 / math.sqrt(1 - 0.90))
+    big = np.abs(gr) > 1e-3 * np.abs(gr).max()   # sign of tiny gradients is FP32 noise
+    assert big.sum() > 1000
+    assert np.allclose(step[big], expect[big], rtol=2e-3, atol=1e-9)
+    assert int(N.t.item()) == 1
+
+
+def test_training_tracks_oracle():
+    X, y = problem(225, 3)
+    order = inputs.epoch_orders(225, 30, 7)
+    N = net(6)
+    theta0 = N.params.cpu().numpy().astype(np.float64)
+    losses = N.train(X, y, order=order, max_epochs=30)
+    th_ref, lref, ne, _, _, _ = mlp.train(theta0, X, y, order, max_epochs=30)
+    assert len(losses) == ne == 30
+    assert np.allclose(losses, lref, rtol=2e-3, atol=0)
+    pred = N.predict(X)
+    assert np.abs(pred - mlp.predict(th_ref, X)).max() <= 1e-2 * np.abs(y).max()
+
+
+def test_sweep_topk_matches_brute_force():
+    sp = LaunchSpace(2)
+    rng = np.random.default_rng(8)
+    train_idx = sp.sample(200, 3)
+    F = np.log2(np.asarray([sp.decode(i) for i in train_idx], dtype=float))
+    mean, std = mlp.standard_scaler(F)
+    N = net(9)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    begin, count = 1_234_567, 100_000
+    ti, tv = N.sweep(sp.struct(mean, std), begin, count, 8)
+    # oracle: FP64 predictions of every index of the window
+    idx = np.arange(begin, begin + count)
+    d = []
+    rem = idx.copy()
+    for r in sp.radix:
+        d.append(rem % r)
+        rem //= r
+    f1, f2 = sp.tables(mean, std)
+    Xw = np.zeros((count, 14))
+    for s in range(7):
+        Xw[:, 2 * s] = np.asarray(f1[s], dtype=np.float32)[d[s]]
+        Xw[:, 2 * s + 1] = np.asarray(f2[s], dtype=np.float32)[d[s]]
+    pred = mlp.predict(theta, Xw)
+    order = np.argsort(pred, kind="stable")
+    scale = np.abs(pred).max()
+    assert all(begin <= i < begin + count for i in ti)
+    assert list(tv) == sorted(tv)
+    # values agree with the 8 lowest oracle predictions; each returned index is
+    # within FP32 roundoff of the oracle's prediction for it
+    assert np.allclose(tv, pred[order[:8]], rtol=0, atol=2e-5 * scale)
+    for i, v in zip(ti, tv):
+        assert abs(pred[i - begin] - v) <= 2e-5 * scale
+    assert abs(pred[ti[0] - begin] - pred[order[0]]) <= 2e-5 * scale
+
+
+def synthetic_cost(sp, vecs, rng=None, noise=0.02):
+    """Separable quadratic in log2 P plus two pairwise terms (sites 3-4 and 5-6)."""
+    L = np.log2(np.asarray(vecs, dtype=float))
+    opt = np.array([5, 8, 6, 8, 6, 8, 11, 9, 9, 7, 10, 8, 8, 9], dtype=float)
+    w = np.array([0.3, 0.2, 0.25, 0.15, 0.0, 0.0, 0.1, 0.2, 0.15, 0.1, 0.05, 0.05, 0.1, 0.1])
+    c = 1.0 + (w * (L - opt) ** 2).sum(axis=1)
+    c += 0.05 * (L[:, 6] - L[:, 8]) ** 2 + 0.04 * (L[:, 11] - L[:, 13]) ** 2
+    if rng is not None:
+        c *= 1.0 + noise * rng.standard_normal(len(c))
+    return c
+
+
+def test_tuner_finds_known_optimum_and_beats_random():
+    sp = LaunchSpace(2)
+    rng = np.random.default_rng(11)
+    idx = sp.sample(300, 21)
+    vecs = [sp.decode(i) for i in idx]
+    t = synthetic_cost(sp, vecs, rng)
+    tr = np.arange(225)
+    F = np.log2(np.asarray(vecs, dtype=float))
+    mean, std = mlp.standard_scaler(F[tr])
+    scale = np.median(t[tr])
+    X = (F - mean) / std
+    y = t / scale
+    N = net(12)
+    N.train(X[tr], y[tr])
+    from paper_2306_14011_amd.autotune import r2_score
+    r2 = r2_score(y[225:], N.predict(X[225:]))
+    ti, tv = N.sweep(sp.struct(mean, std), 0, sp.size, 8)
+    cand = synthetic_cost(sp, [sp.decode(i) for i in ti])
+    best_tuned = cand.min()
+    best_random = synthetic_cost(sp, vecs).min()
+    # true optimum: sites 0 and 1 are independent, sites (3, 4) and (5, 6) are
+    # coupled pairwise and searched jointly, site 2 is pinned
+    def cost_of(choice):
+        v = []
+        for s in range(7):
+            v += list(sp.choices[s][choice[s]])
+        return v
+    # independent sites: minimise one at a time from a fixed base
+    choice = [0] * 7
+    for s in (0, 1):
+        cs = [synthetic_cost(sp, [cost_of(choice[:s] + [c] + choice[s + 1:])])[0] for c in range(sp.radix[s])]
+        choice[s] = int(np.argmin(cs))
+    for s1, s2 in ((3, 4), (5, 6)):
+        best_c, best_v = None, np.inf
+        for c1 in range(sp.radix[s1]):
+            for c2 in range(sp.radix[s2]):
+                ch = list(choice)
+                ch[s1], ch[s2] = c1, c2
+                v = synthetic_cost(sp, [cost_of(ch)])[0]
+                if v < best_v:
+                    best_c, best_v = (c1, c2), v
+        choice[s1], choice[s2] = best_c
+    optimum = synthetic_cost(sp, [cost_of(choice)])[0]
+    info = dict(r2=r2, best_tuned=best_tuned, optimum=optimum, best_random=best_random)
+    # 225 training rows and the paper's 200-epoch budget (400 Adam steps here)
+    # leave the fit short of exact; the selection is what the method needs
+    assert best_tuned <= 1.05 * optimum, info
+    assert best_tuned < best_random, info
+    assert r2 > 0.7, info
+
+
+def test_end_to_end_tuning_on_a_small_grid():
+    # the whole loop on a 256^2 vortex with a reduced budget: every sampled
+    # launch is bitwise valid, the network is trained and the sweep covers the space
+    from paper_2306_14011_amd.autotune import Autotuner
+    g, U0 = inputs.vortex_bumps_case(256, seed=1)
+    at = Autotuner(g, U0, seed=2, repeats=1, warmup=1, min_ms=2.0)
+    res = at.run(count=40, k=4, rounds=1)
+    at.close()
+    assert res["n_samples"] == 40 and res["n_valid"] == 40
+    assert res["n_train"] == 30 and res["n_test"] == 10
+    assert res["space_size"] == 77_440_000
+    assert res["tuned_ms"] > 0 and res["default_ms"] > 0
