@@ -8,9 +8,9 @@ same seeded inputs from ``paper_2306_14011_amd.inputs`` and nothing else.
 Contents:
   * ``liboracle.so`` (from ``fv_oracle.cpp``): MUSCL-minmod, Roe flux, residual,
     CFL wave-speed reduction and SSP-RK3 step (Eq. QF, residual, flux of the
-    paper), plus complex-step derivatives of the residual and the step.
+    paper), complex-step derivatives of the residual and the step, and the
+    reverse-mode gradient of the residual and of one step at frozen dt.
   * ``exact.py``: Toro's exact Riemann solver for the Sod tube.
-  * ``adjoint.py``: reverse-mode gradient of the discrete step map.
   * ``mlp.py``: the runtime-regression network of the autotuner in FP64.
 """
 from __future__ import annotations
@@ -70,6 +70,8 @@ def lib():
         L.or_rk3_step_cs.argtypes = [g, c_double_p, c_double_p, ctypes.c_double, ctypes.c_double,
                                      c_double_p, c_double_p]
         L.or_run.argtypes = [g, c_double_p, ctypes.c_int32, c_double_p, c_double_p, c_u32_p]
+        L.or_residual_vjp.argtypes = [g, c_double_p, c_double_p, c_double_p]
+        L.or_rk3_step_vjp.argtypes = [g, c_double_p, ctypes.c_double, c_double_p]
         _lib = L
     return _lib
 
@@ -191,6 +193,25 @@ def run(spec, U, nsteps, dt_in=None, limiter=True, kappa=-1.0):
     lib().or_run(ctypes.byref(g), _p(U), int(nsteps), _p(dti) if dti is not None else None,
                  _p(dts), ctypes.byref(fl))
     return U, dts[:nsteps], fl.value
+
+
+def residual_vjp(spec, U, w, limiter=True):
+    """(dR/dU)^T w."""
+    g = make_grid(spec, limiter)
+    U = _arr(U)
+    w = _arr(w)
+    mu = np.zeros_like(U)
+    lib().or_residual_vjp(ctypes.byref(g), _p(U), _p(w), _p(mu))
+    return mu
+
+
+def rk3_step_vjp(spec, U, dt_, lam, limiter=True):
+    """dJ/dU^n from dJ/dU^{n+1} = lam for one step at frozen dt."""
+    g = make_grid(spec, limiter)
+    U = _arr(U)
+    lam = _arr(lam).copy()
+    lib().or_rk3_step_vjp(ctypes.byref(g), _p(U), float(dt_), _p(lam))
+    return lam
 
 
 def omp_threads():

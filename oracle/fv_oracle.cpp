@@ -59,8 +59,17 @@ static const uint32_t OR_FLAG_NAN = 1u;
 static const uint32_t OR_FLAG_RHO = 2u;
 static const uint32_t OR_FLAG_P = 4u;
 
+// Real part used for branch decisions. Under the complex step, products of
+// imaginary parts shift real parts by O(h^2) (about 1e-60 for h = 1e-30); a real
+// value that is exactly zero in the real evaluation (a state at rest, a flat
+// stencil) would then take an arbitrary branch. Magnitudes below 1e-50 are read
+// as zero so every branch matches the real evaluation. Real arithmetic is
+// unaffected.
 static inline double re(double x) { return x; }
-static inline double re(const cplx& x) { return x.real(); }
+static inline double re(const cplx& x) {
+    const double r = x.real();
+    return std::fabs(r) < 1e-50 ? 0.0 : r;
+}
 
 // |x| with the branch taken on the real part; the derivative at 0 is 0.
 template <class T> static inline T absr(const T& x) {
@@ -81,7 +90,11 @@ template <class T> static inline T psi_minmod(const T& r) {
 template <class T> static inline T limited(const T& num, const T& den, int limiter) {
     if (!limiter) return den;
     if (re(den) == 0.0) return T(0.0);
-    return psi_minmod(num / den) * den;
+    // the branch of Psi is taken on the ratio of the real parts
+    const double rr = re(num) / re(den);
+    if (!(rr > 0.0)) return T(0.0);
+    if (rr < 1.0) return (num / den) * den;
+    return den;
 }
 
 // MUSCL extrapolation to face k+1/2 from cells k-1, k, k+1, k+2 (Eq. flux):
@@ -356,6 +369,107 @@ double or_dt(const OrGrid* g, const double* U, uint32_t* flags) {
 }
 
 void or_rk3_step(const OrGrid* g, double* U, double dt) { rk3_step(g, U, dt); }
+
+// mu = (dR/dU)^T w. Each face of each axis contributes F*A to the residual of
+// its low-side cell and -F*A to its high-side cell (when those are interior),
+// so its flux adjoint is A (w_low - w_high). The face flux depends on its four
+// stencil cells (ghosts mapped to the interior cell they copy); its Jacobian
+// columns are taken one input at a time by the complex step, which is exact to
+// roundoff, and the transposed products are added to those cells.
+void or_residual_vjp(const OrGrid* g, const double* U, const double* w, double* mu) {
+    const int nv = g->ndim + 2;
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t ncell = nx * ny * nz;
+    const double h = 1e-30;
+    for (int64_t e = 0; e < nv * ncell; ++e) mu[e] = 0.0;
+    std::vector<cplx> Uc((size_t)nv * ncell);
+    for (int64_t e = 0; e < nv * ncell; ++e) Uc[e] = cplx(U[e], 0.0);
+    for (int ax = 0; ax < g->ndim; ++ax) {
+        const double A = face_area(g, ax);
+        const int64_t n = g->n[ax];
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    int64_t idx[3] = {i, j, k};
+                    // faces with low-side cell index -1 .. n-1 along ax; visit each
+                    // once, through the cell on its high side (index 0 .. n) or, for
+                    // the last face, through the last cell
+                    const int64_t a = idx[ax];
+                    int64_t lows[2];
+                    int nl = 0;
+                    lows[nl++] = a - 1;            // face between a-1 and a
+                    if (a == n - 1) lows[nl++] = a; // face between n-1 and n
+                    for (int q = 0; q < nl; ++q) {
+                        const int64_t lo = lows[q];
+                        int64_t cc[3] = {i, j, k};
+                        cc[ax] = lo;  // face_flux takes the low-side cell
+                        double Fb[5];
+                        for (int v = 0; v < nv; ++v) {
+                            double wl = 0.0, wh = 0.0;
+                            if (lo >= 0) {
+                                int64_t c2[3] = {i, j, k};
+                                c2[ax] = lo;
+                                wl = w[v * ncell + cell_offset(g, c2[0], c2[1], c2[2])];
+                            }
+                            if (lo + 1 <= n - 1) {
+                                int64_t c2[3] = {i, j, k};
+                                c2[ax] = lo + 1;
+                                wh = w[v * ncell + cell_offset(g, c2[0], c2[1], c2[2])];
+                            }
+                            Fb[v] = A * (wl - wh);
+                        }
+                        // stencil cells lo-1 .. lo+2, mapped to the interior
+                        int64_t off[4];
+                        for (int m = 0; m < 4; ++m) {
+                            int64_t c2[3] = {i, j, k};
+                            c2[ax] = bc_index(lo - 1 + m, n, g->bc[ax][0], g->bc[ax][1]);
+                            off[m] = cell_offset(g, c2[0], c2[1], c2[2]);
+                        }
+                        // perturb one stencil entry (slot m, variable v) at a time
+                        for (int m = 0; m < 4; ++m)
+                            for (int v = 0; v < nv; ++v) {
+                                // a ghost slot that maps to the same cell as another slot is
+                                // still its own input of the face flux; perturb the slot, not the cell
+                                cplx Q[4][5];
+                                for (int mm = 0; mm < 4; ++mm)
+                                    for (int vv = 0; vv < nv; ++vv) Q[mm][vv] = Uc[vv * ncell + off[mm]];
+                                Q[m][v] += cplx(0.0, h);
+                                cplx QL[5], QR[5], F[5];
+                                for (int vv = 0; vv < nv; ++vv)
+                                    muscl(Q[0][vv], Q[1][vv], Q[2][vv], Q[3][vv], g->limiter, g->kappa, QL[vv], QR[vv]);
+                                roe_flux(g->ndim, ax, g->gamma, QL, QR, F);
+                                double dot = 0.0;
+                                for (int vv = 0; vv < nv; ++vv) dot += F[vv].imag() / h * Fb[vv];
+                                mu[v * ncell + off[m]] += dot;
+                            }
+                    }
+                }
+    }
+}
+
+// Reverse of one SSP-RK3 step at frozen dt: lam holds dJ/dU^{n+1} on entry and
+// dJ/dU^n on return. With L = -R/|Omega| and the stages
+//   U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1)), U' = 1/3 U + 2/3 (U2 + dt L(U2)),
+// the chain rule gives
+//   l2 = 2/3 lam + 2/3 dt J(U2)^T lam,  l1 = 1/4 l2 + 1/4 dt J(U1)^T l2,
+//   dJ/dU = 1/3 lam + 3/4 l2 + l1 + dt J(U)^T l1,   J = dL/dU = -(dR/dU)/|Omega|.
+void or_rk3_step_vjp(const OrGrid* g, const double* U, double dt, double* lam) {
+    const int nv = g->ndim + 2;
+    const int64_t N = (int64_t)nv * g->n[0] * g->n[1] * g->n[2];
+    const double vol = cell_volume(g);
+    std::vector<double> R(N), U1(N), U2(N), mu(N), l2(N), l1(N);
+    residual(g, U, R.data());
+    for (int64_t e = 0; e < N; ++e) U1[e] = U[e] + dt * (-R[e] / vol);
+    residual(g, U1.data(), R.data());
+    for (int64_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * (-R[e] / vol));
+    or_residual_vjp(g, U2.data(), lam, mu.data());
+    for (int64_t e = 0; e < N; ++e) l2[e] = (2.0 / 3.0) * lam[e] + (2.0 / 3.0) * dt * (-mu[e] / vol);
+    or_residual_vjp(g, U1.data(), l2.data(), mu.data());
+    for (int64_t e = 0; e < N; ++e) l1[e] = 0.25 * l2[e] + 0.25 * dt * (-mu[e] / vol);
+    or_residual_vjp(g, U, l1.data(), mu.data());
+    for (int64_t e = 0; e < N; ++e)
+        lam[e] = (1.0 / 3.0) * lam[e] + 0.75 * l2[e] + l1[e] + dt * (-mu[e] / vol);
+}
 
 // Complex-step directional derivative of one RK3 step (dt frozen) along V.
 void or_rk3_step_cs(const OrGrid* g, const double* U, const double* V, double h, double dt,

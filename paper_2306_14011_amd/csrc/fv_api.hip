@@ -27,6 +27,7 @@ struct fv_ctx {
     double* R;
     double* lamA;
     double* lamB;
+    double* G[3];   // face adjoint contributions [4][nvar][faces] per axis
     // per-site event timing (diagnostic)
     static const int kMaxEv = 64;
     bool timing;
@@ -57,7 +58,7 @@ struct Layout {
     int64_t faces[3];
     int64_t ncell;
     int max_partial;
-    size_t off_status, off_dt, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, total;
+    size_t off_status, off_dt, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_G[3], total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -145,6 +146,10 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     o = align256(o + dense);
     L->off_lamB = o;
     o = align256(o + dense);
+    for (int d = 0; d < 3; ++d) {
+        L->off_G[d] = o;
+        o = align256(o + (size_t)4 * L->nvar * L->faces[d] * 8);
+    }
     L->total = o;
     return FV_OK;
 }
@@ -263,10 +268,17 @@ void enqueue_residual(fv_ctx* c, double* R) {
                          c->stream);
 }
 
-void enqueue_update(fv_ctx* c, int stage, const double* Un, const double* Us, double* Ud) {
+void enqueue_update(fv_ctx* c, int stage, const double* Un, const double* Us, double* Ud,
+                    const double* dtp = nullptr) {
     SiteTimer t(c, FV_SITE_UPDATE);
-    fvk::launch_update(stage, Un, Us, Ud, c->R, c->dt, c->g, P(c, FV_SITE_UPDATE, 0), P(c, FV_SITE_UPDATE, 1),
-                       c->stream);
+    fvk::launch_update(stage, Un, Us, Ud, c->R, dtp ? dtp : c->dt, c->g, P(c, FV_SITE_UPDATE, 0),
+                       P(c, FV_SITE_UPDATE, 1), c->stream);
+}
+
+// mu = (dR/dU)^T w into c->R; the ghosts of Us must be filled.
+void enqueue_vjp(fv_ctx* c, const double* Us, const double* w) {
+    for (int ax = 0; ax < c->g.ndim; ++ax) fvk::launch_adj_flux(ax, Us, w, c->G[ax], c->g, c->stream);
+    fvk::launch_adj_gather(c->G[0], c->G[1], c->G[2], c->R, c->g, c->stream);
 }
 
 void enqueue_cfl(fv_ctx* c, const double* U, const double* dt_in, double* dt_out) {
@@ -345,6 +357,7 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
     c->R = (double*)(base + L.off_R);
     c->lamA = (double*)(base + L.off_lamA);
     c->lamB = (double*)(base + L.off_lamB);
+    for (int d = 0; d < 3; ++d) c->G[d] = (double*)(base + L.off_G[d]);
     fvk::launch_set_u32(c->status, 0u, c->stream);
     if (check_launch_error(c) != FV_OK) {
         snprintf(g_err, 256, "%s", c->err);
@@ -405,10 +418,29 @@ int fv_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* d
 
 int fv_adjoint_step(fv_ctx* c, double* U_n, const double* dt, double* lam) {
     if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
-    (void)U_n;
-    (void)dt;
-    (void)lam;
-    return fail(c, FV_ENOTSUP, "adjoint step not available in this build%s");
+    if (!U_n || !dt || !lam) return fail(c, FV_EINVAL, "null state, dt or adjoint pointer%s");
+    // recompute the stage states with the frozen dt: U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1))
+    enqueue_bc(c, U_n);
+    enqueue_fluxes(c, U_n);
+    enqueue_residual(c, c->R);
+    enqueue_update(c, 0, U_n, U_n, c->U1, dt);
+    enqueue_bc(c, c->U1);
+    enqueue_fluxes(c, c->U1);
+    enqueue_residual(c, c->R);
+    enqueue_update(c, 1, U_n, c->U1, c->U2, dt);
+    enqueue_bc(c, c->U2);
+    // stage 3: U' = 1/3 U + 2/3 (U2 + dt L(U2))
+    enqueue_vjp(c, c->U2, lam);
+    fvk::launch_adj_comb(3, lam, c->lamA, c->lamB, c->R, dt, c->g, c->stream);
+    // stage 2 (ghosts of U1 are still valid)
+    enqueue_vjp(c, c->U1, c->lamA);
+    fvk::launch_adj_comb(2, lam, c->lamA, c->lamB, c->R, dt, c->g, c->stream);
+    // stage 1 (ghosts of U still valid)
+    enqueue_vjp(c, U_n, lam);
+    fvk::launch_adj_comb(1, lam, c->lamA, c->lamB, c->R, dt, c->g, c->stream);
+    int rc = check_launch_error(c);
+    if (rc != FV_OK) return rc;
+    return drain_timing(c);
 }
 
 int fv_set_launch(fv_ctx* c, const fv_launch* l) {

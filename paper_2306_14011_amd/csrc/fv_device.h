@@ -53,7 +53,7 @@ struct Geo {
 
 // minmod(a, b): zero unless a and b share a strict sign, else the one of smaller
 // magnitude. Sign tests, not a*b > 0, so tiny slopes do not underflow to a tie.
-__device__ __forceinline__ double minmod(double a, double b) {
+__host__ __device__ __forceinline__ double minmod(double a, double b) {
     const bool pos = (a > 0.0) & (b > 0.0);
     const bool neg = (a < 0.0) & (b < 0.0);
     const double m = fabs(a) <= fabs(b) ? a : b;
@@ -62,7 +62,7 @@ __device__ __forceinline__ double minmod(double a, double b) {
 
 // MUSCL face states (epsilon = 1, kappa = -1, minmod) at face k+1/2 of the
 // cells q0 = k-1, q1 = k, q2 = k+1, q3 = k+2.
-__device__ __forceinline__ void muscl_minmod(double q0, double q1, double q2, double q3,
+__host__ __device__ __forceinline__ void muscl_minmod(double q0, double q1, double q2, double q3,
                                              double& qL, double& qR) {
     const double dm = q1 - q0, dc = q2 - q1, dp = q3 - q2;
     qL = q1 + 0.5 * minmod(dm, dc);
@@ -72,7 +72,7 @@ __device__ __forceinline__ void muscl_minmod(double q0, double q1, double q2, do
 // Roe flux along axis AX for NDIM dimensions, conserved face states in, flux out.
 // F = (F(qL) + F(qR))/2 - sum_k |lambda_k| alpha_k r_k / 2, no entropy fix.
 template <int NDIM, int AX>
-__device__ __forceinline__ void roe_flux(const double* qL, const double* qR, double gm1, double* F) {
+__host__ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, double gm1, double* F) {
     constexpr int IE = NDIM + 1;
     // left / right primitive states
     const double rL = qL[0], rR = qR[0];
@@ -153,6 +153,265 @@ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, dou
         F[1 + d] = 0.5 * (fl + fr - D[1 + d]);
     }
     F[IE] = 0.5 * ((qL[IE] + pL) * vnL + (qR[IE] + pR) * vnR - D[IE]);
+}
+
+// ---------------------------------------------------------------------------
+// Reverse (adjoint) of the face computation, hand-derived from the forward
+// sequence above: given Fb = dJ/dF, accumulate dJ/dq of the four stencil
+// cells. Branches (minmod selection, |lambda| signs) follow the forward
+// evaluation; |x| has derivative 0 at x = 0.
+
+// MUSCL-minmod reverse for one variable: qLb = dJ/dQL, qRb = dJ/dQR.
+// g0..g3 receive dJ/dq of cells k-1, k, k+1, k+2 (accumulated).
+__host__ __device__ __forceinline__ void muscl_minmod_vjp(double q0, double q1, double q2, double q3, double qLb,
+                                                          double qRb, double& g0, double& g1, double& g2,
+                                                          double& g3) {
+    const double dm = q1 - q0, dc = q2 - q1, dp = q3 - q2;
+    // QL = q1 + minmod(dm, dc) / 2
+    if (((dm > 0.0) & (dc > 0.0)) | ((dm < 0.0) & (dc < 0.0))) {
+        if (fabs(dm) <= fabs(dc)) {  // q1 + (q1 - q0)/2
+            g1 += 1.5 * qLb;
+            g0 -= 0.5 * qLb;
+        } else {  // (q1 + q2)/2
+            g1 += 0.5 * qLb;
+            g2 += 0.5 * qLb;
+        }
+    } else {
+        g1 += qLb;
+    }
+    // QR = q2 - minmod(dp, dc) / 2
+    if (((dp > 0.0) & (dc > 0.0)) | ((dp < 0.0) & (dc < 0.0))) {
+        if (fabs(dp) <= fabs(dc)) {  // 3/2 q2 - q3/2
+            g2 += 1.5 * qRb;
+            g3 -= 0.5 * qRb;
+        } else {  // (q1 + q2)/2
+            g1 += 0.5 * qRb;
+            g2 += 0.5 * qRb;
+        }
+    } else {
+        g2 += qRb;
+    }
+}
+
+__host__ __device__ __forceinline__ double sgn0(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// Reverse of roe_flux<NDIM, AX>: Fb[NV] in, qLb[NV] and qRb[NV] out (overwritten).
+template <int NDIM, int AX>
+__host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const double* qR, double gm1, const double* Fb,
+                                                      double* qLb, double* qRb) {
+    constexpr int IE = NDIM + 1;
+    // ---- forward recomputation (as in roe_flux) ----
+    const double rL = qL[0], rR = qR[0];
+    const double irL = 1.0 / rL, irR = 1.0 / rR;
+    double uL[NDIM], uR[NDIM];
+    double qqL = 0.0, qqR = 0.0;
+    for (int d = 0; d < NDIM; ++d) {
+        uL[d] = qL[1 + d] * irL;
+        uR[d] = qR[1 + d] * irR;
+        qqL += uL[d] * uL[d];
+        qqR += uR[d] * uR[d];
+    }
+    const double EL = qL[IE], ER = qR[IE];
+    const double pL = gm1 * (EL - 0.5 * rL * qqL);
+    const double pR = gm1 * (ER - 0.5 * rR * qqR);
+    const double HL = (EL + pL) * irL;
+    const double HR = (ER + pR) * irR;
+    const double vnL = uL[AX], vnR = uR[AX];
+    const double sL = sqrt(rL), sR = sqrt(rR);
+    const double iw = 1.0 / (sL + sR);
+    const double wL = sL * iw, wR = sR * iw;
+    double ut[NDIM];
+    double qqt = 0.0;
+    for (int d = 0; d < NDIM; ++d) {
+        ut[d] = wL * uL[d] + wR * uR[d];
+        qqt += ut[d] * ut[d];
+    }
+    const double Ht = wL * HL + wR * HR;
+    const double rt = sL * sR;
+    const double c2 = gm1 * (Ht - 0.5 * qqt);
+    const double c = sqrt(c2);
+    const double ic2 = 1.0 / c2;
+    const double un = ut[AX];
+    const double dp = pR - pL;
+    const double dun = vnR - vnL;
+    const double rcdu = rt * c * dun;
+    const double a1 = 0.5 * (dp - rcdu) * ic2;
+    const double a2 = (rR - rL) - dp * ic2;
+    const double a5 = 0.5 * (dp + rcdu) * ic2;
+    const double l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
+    const double w1 = l1 * a1, w2 = l2 * a2, w5 = l5 * a5;
+    const double aun = l2 * rt;
+    const double w15 = w1 + w5;
+    const double fmL = rL * vnL, fmR = rR * vnR;  // mass fluxes
+
+    // ---- reverse ----
+    double rLb = 0.0, rRb = 0.0, ELb = 0.0, ERb = 0.0, pLb = 0.0, pRb = 0.0;
+    double vnLb = 0.0, vnRb = 0.0, fmLb = 0.0, fmRb = 0.0;
+    double uLb[NDIM], uRb[NDIM], utb[NDIM];
+    for (int d = 0; d < NDIM; ++d) uLb[d] = uRb[d] = utb[d] = 0.0;
+    // F0 = (fmL + fmR - D0)/2; F[1+d] = (fmL uL + fmR uR + [d==AX](pL + pR) - D[1+d])/2;
+    // F[IE] = ((EL + pL) vnL + (ER + pR) vnR - De)/2
+    const double D0b = -0.5 * Fb[0];
+    fmLb += 0.5 * Fb[0];
+    fmRb += 0.5 * Fb[0];
+    double Db[NDIM];
+    for (int d = 0; d < NDIM; ++d) {
+        const double f = 0.5 * Fb[1 + d];
+        fmLb += f * uL[d];
+        uLb[d] += f * fmL;
+        fmRb += f * uR[d];
+        uRb[d] += f * fmR;
+        if (d == AX) {
+            pLb += f;
+            pRb += f;
+        }
+        Db[d] = -f;
+    }
+    {
+        const double f = 0.5 * Fb[IE];
+        ELb += f * vnL;
+        pLb += f * vnL;
+        vnLb += f * (EL + pL);
+        ERb += f * vnR;
+        pRb += f * vnR;
+        vnRb += f * (ER + pR);
+    }
+    const double Deb = -0.5 * Fb[IE];
+    // mass fluxes fm = r vn
+    rLb += fmLb * vnL;
+    vnLb += fmLb * rL;
+    rRb += fmRb * vnR;
+    vnRb += fmRb * rR;
+    // De = w15 Ht + (w5 - w1) un c + w2 qqt/2 + sum_{d != AX} aun (uR - uL)_d ut_d
+    double w15b = 0.0, w1b = 0.0, w2b = 0.0, w5b = 0.0, Htb = 0.0, unb = 0.0, cb = 0.0, qqtb = 0.0, aunb = 0.0;
+    w15b += Deb * Ht;
+    Htb += Deb * w15;
+    w5b += Deb * un * c;
+    w1b -= Deb * un * c;
+    unb += Deb * (w5 - w1) * c;
+    cb += Deb * (w5 - w1) * un;
+    w2b += Deb * 0.5 * qqt;
+    qqtb += Deb * 0.5 * w2;
+    for (int d = 0; d < NDIM; ++d) {
+        if (d == AX) continue;
+        const double du = uR[d] - uL[d];
+        aunb += Deb * du * ut[d];
+        uRb[d] += Deb * aun * ut[d];
+        uLb[d] -= Deb * aun * ut[d];
+        utb[d] += Deb * aun * du;
+    }
+    // D[1+d]
+    for (int d = 0; d < NDIM; ++d) {
+        if (d == AX) {
+            // w15 ut + (w5 - w1) c + w2 ut
+            w15b += Db[d] * ut[d];
+            w2b += Db[d] * ut[d];
+            utb[d] += Db[d] * (w15 + w2);
+            w5b += Db[d] * c;
+            w1b -= Db[d] * c;
+            cb += Db[d] * (w5 - w1);
+        } else {
+            // (w15 + w2) ut + aun (uR - uL)
+            w15b += Db[d] * ut[d];
+            w2b += Db[d] * ut[d];
+            utb[d] += Db[d] * (w15 + w2);
+            aunb += Db[d] * (uR[d] - uL[d]);
+            uRb[d] += Db[d] * aun;
+            uLb[d] -= Db[d] * aun;
+        }
+    }
+    // D0 = w15 + w2
+    w15b += D0b;
+    w2b += D0b;
+    // w15 = w1 + w5
+    w1b += w15b;
+    w5b += w15b;
+    // aun = l2 rt; w_k = l_k a_k
+    double l1b = w1b * a1, l2b = w2b * a2 + aunb * rt, l5b = w5b * a5;
+    double rtb = aunb * l2;
+    const double a1b = w1b * l1, a2b = w2b * l2, a5b = w5b * l5;
+    // l1 = |un - c|, l2 = |un|, l5 = |un + c|
+    {
+        const double s1 = sgn0(un - c), s2 = sgn0(un), s5 = sgn0(un + c);
+        unb += l1b * s1 + l2b * s2 + l5b * s5;
+        cb += -l1b * s1 + l5b * s5;
+    }
+    // a5 = (dp + rcdu) ic2 / 2; a2 = dr - dp ic2; a1 = (dp - rcdu) ic2 / 2
+    double dpb = 0.5 * a5b * ic2 + 0.5 * a1b * ic2 - a2b * ic2;
+    const double rcdub = 0.5 * a5b * ic2 - 0.5 * a1b * ic2;
+    double ic2b = a5b * 0.5 * (dp + rcdu) + a1b * 0.5 * (dp - rcdu) - a2b * dp;
+    rRb += a2b;
+    rLb -= a2b;
+    // rcdu = rt c dun
+    rtb += rcdub * c * dun;
+    cb += rcdub * rt * dun;
+    const double dunb = rcdub * rt * c;
+    vnRb += dunb;
+    vnLb -= dunb;
+    pRb += dpb;
+    pLb -= dpb;
+    // ic2 = 1/c2; c = sqrt(c2); c2 = gm1 (Ht - qqt/2)
+    double c2b = -ic2b * ic2 * ic2 + cb * 0.5 / c;
+    Htb += gm1 * c2b;
+    qqtb -= 0.5 * gm1 * c2b;
+    // rt = sL sR
+    double sLb = rtb * sR, sRb = rtb * sL;
+    // Ht = wL HL + wR HR
+    double wLb = Htb * HL, wRb = Htb * HR;
+    const double HLb = Htb * wL, HRb = Htb * wR;
+    // un is ut[AX]; qqt = sum ut^2; ut = wL uL + wR uR
+    utb[AX] += unb;
+    for (int d = 0; d < NDIM; ++d) {
+        utb[d] += 2.0 * ut[d] * qqtb;
+        wLb += utb[d] * uL[d];
+        uLb[d] += utb[d] * wL;
+        wRb += utb[d] * uR[d];
+        uRb[d] += utb[d] * wR;
+    }
+    // wL = sL iw, wR = sR iw, iw = 1/(sL + sR)
+    const double iwb = wLb * sL + wRb * sR;
+    sLb += wLb * iw;
+    sRb += wRb * iw;
+    const double sumb = -iwb * iw * iw;
+    sLb += sumb;
+    sRb += sumb;
+    rLb += sLb * 0.5 / sL;
+    rRb += sRb * 0.5 / sR;
+    // per side: H = (E + p) ir; p = gm1 (E - r qq / 2); qq = sum u^2; u = m ir; ir = 1/r
+    {
+        double irb = HLb * (EL + pL);
+        ELb += HLb * irL;
+        pLb += HLb * irL;
+        ELb += gm1 * pLb;
+        rLb -= 0.5 * gm1 * qqL * pLb;
+        const double qqb = -0.5 * gm1 * rL * pLb;
+        uLb[AX] += vnLb;
+        for (int d = 0; d < NDIM; ++d) {
+            uLb[d] += 2.0 * uL[d] * qqb;
+            qLb[1 + d] = uLb[d] * irL;
+            irb += uLb[d] * qL[1 + d];
+        }
+        rLb -= irb * irL * irL;
+        qLb[0] = rLb;
+        qLb[IE] = ELb;
+    }
+    {
+        double irb = HRb * (ER + pR);
+        ERb += HRb * irR;
+        pRb += HRb * irR;
+        ERb += gm1 * pRb;
+        rRb -= 0.5 * gm1 * qqR * pRb;
+        const double qqb = -0.5 * gm1 * rR * pRb;
+        uRb[AX] += vnRb;
+        for (int d = 0; d < NDIM; ++d) {
+            uRb[d] += 2.0 * uR[d] * qqb;
+            qRb[1 + d] = uRb[d] * irR;
+            irb += uRb[d] * qR[1 + d];
+        }
+        rRb -= irb * irR * irR;
+        qRb[0] = rRb;
+        qRb[IE] = ERb;
+    }
 }
 
 }  // namespace fvk

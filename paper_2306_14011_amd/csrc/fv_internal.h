@@ -16,4 +16,11 @@ void launch_cfl(const double* U, double* partial, uint32_t* status, const double
                 double* dt_out, const Geo& g, int gang, int threads, hipStream_t s);
 void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 
+// adjoint
+void launch_adj_flux(int ax, const double* U, const double* w, double* G, const Geo& g, hipStream_t s);
+void launch_adj_gather(const double* Gx, const double* Gy, const double* Gz, double* mu, const Geo& g,
+                       hipStream_t s);
+void launch_adj_comb(int mode, double* lam, double* lamA, double* lamB, const double* mu, const double* dt,
+                     const Geo& g, hipStream_t s);
+
 }  // namespace fvk
