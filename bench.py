@@ -5,23 +5,33 @@ Workload: 2D Euler, 2048 x 2048 periodic grid on [0,10]^2, isentropic vortex
 1e-2), MUSCL-minmod + Roe, SSP-RK3, CFL 0.5. One "step" is one full SSP-RK3
 time step (3 stages + the CFL reduction) through ``fv_step``.
 
-Prints ONE JSON line: cell-updates/s over K timed steps (inputs resident in
-HBM), the dominant kernel's achieved bandwidth against the 8 TB/s HBM peak
-(per-kernel durations from HIP events recorded by the library on its own
-stream), and the FP64 CPU oracle timed on the host on a bounded sample.
+Sequence:
+  1. K timed steps with the default launch table;
+  2. the autotuner (the paper's method): ~300 sampled launch vectors timed,
+     network trained on 75 %, whole space predicted on the GPU, top 8
+     re-measured; default / tuned / best-of-random compared interleaved;
+  3. K timed steps with the tuned launch table -> `value`;
+  4. per-kernel durations of the tuned step from HIP events the library
+     records around each launch on its own stream -> `roofline`;
+  5. adjoint vs primal cost on the 512^2 / 60-step adjoint workload;
+  6. the FP64 CPU oracle on the host cores for a bounded sample.
+Prints ONE JSON line on stdout; progress goes to stderr.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--launch JSON]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--samples N] [--no-cpu] [--no-tune]
 """
 from __future__ import annotations
 
 import argparse
 import json
-import os
 import sys
 import time
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "cell-updates/s + HBM GB/s vs peak, tuned vs default launch; adjoint/primal"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -31,11 +41,113 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048, help="cells per side")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--samples", type=int, default=300, help="timed launch vectors for the tuner")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--launch", type=str, default=None, help="14 launch parameters as a JSON list")
+    ap.add_argument("--launch", type=str, default=None, help="14 launch parameters as a JSON list (skips tuning)")
     ap.add_argument("--timing-steps", type=int, default=20)
     return ap.parse_args()
+
+
+def timed_steps(torch, solver, U0, launch, steps, warmup):
+    """ms per step over `steps` steps from U0 (inputs resident in HBM)."""
+    solver.set_launch(launch)
+    solver.set_state(U0)
+    solver.step(warmup)
+    solver.set_state(U0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rc, flags = solver.status()
+    if flags:
+        log(f"non-physical flags {flags}")
+        sys.exit(3)
+    return e0.elapsed_time(e1) / steps
+
+
+def kernel_table(solver, g, launch, steps, fv, traffic):
+    solver.set_launch(launch)
+    solver.set_timing(True)
+    solver.step(steps)
+    ms, cnt = solver.get_timing()
+    solver.set_timing(False)
+    sb = traffic.site_bytes(g)
+    total = sum(ms)
+    kernels = {}
+    for i, name in enumerate(fv.SITES):
+        if cnt[i] == 0:
+            continue
+        avg_ms = ms[i] / cnt[i]
+        kernels[name] = {
+            "avg_us": round(avg_ms * 1e3, 3),
+            "launches_per_step": cnt[i] / steps,
+            "share": round(ms[i] / total, 4),
+            "alg_bytes": sb[name],
+            "achieved_GBps": round(sb[name] / (avg_ms * 1e-3) / 1e9, 1),
+        }
+    return kernels
+
+
+def adjoint_ratio(torch, fv, inputs):
+    """fv_adjoint_step / fv_step per step, and the checkpointed reverse / forward,
+    on the 512^2 vortex, 60 steps, checkpoints every 10."""
+    from paper_2306_14011_amd.rollout import pressure_integral, rollout
+    g, U0 = inputs.vortex_case(512, seed=0)
+    s = fv.Solver(g)
+    s.set_state(U0)
+    dts = torch.zeros(60, dtype=torch.float64, device="cuda")
+    s.step(60, dt_out=dts)
+    torch.cuda.synchronize()
+    lam = torch.ones(g.shape, dtype=torch.float64, device="cuda")
+    Ustate = s.U.clone()
+    stream = torch.cuda.current_stream()
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    s.U.copy_(Ustate)
+    t_primal = timeit(lambda: s.step(1, dt_in=dts[:1]), 50)
+    t_adj = timeit(lambda: fv.fv_adjoint_step(s.ctx, Ustate.data_ptr(), dts[:1].data_ptr(), lam.data_ptr()), 50)
+    x = torch.as_tensor(U0).cuda()
+    window = inputs.adjoint_window(512, 64)
+
+    def fwd():
+        with torch.no_grad():
+            rollout(x, s, 60, every=10)
+
+    def fwd_bwd():
+        xr = x.clone().requires_grad_(True)
+        out, _ = rollout(xr, s, 60, every=10)
+        pressure_integral(out, g, window).backward()
+
+    t_fwd = timeit(fwd, 3)
+    t_fb = timeit(fwd_bwd, 3)
+    s.close()
+    return {
+        "workload": "512x512 vortex, 60 steps, checkpoints every 10, J = pressure over cells [224,288)^2",
+        "primal_step_ms": round(t_primal, 4),
+        "adjoint_step_ms": round(t_adj, 4),
+        "adjoint_over_primal_step": round(t_adj / t_primal, 3),
+        "forward_60_ms": round(t_fwd, 3),
+        "reverse_60_ms_incl_recompute": round(t_fb - t_fwd, 3),
+        "reverse_over_forward": round((t_fb - t_fwd) / t_fwd, 3),
+    }
 
 
 def cpu_baseline(g, U0, seconds):
@@ -55,7 +167,7 @@ def cpu_baseline(g, U0, seconds):
         "unit": "cell-updates/s",
         "cores": oracle.omp_threads(),
         "kind": "oracle",
-        "sample": f"{steps} SSP-RK3 steps of the {g.n[0]}x{g.n[1]} workload (FP64, OpenMP), {el:.1f} s",
+        "sample": f"{steps} SSP-RK3 steps of the {g.n[0]}x{g.n[1]} workload (FP64, OpenMP over cells), {el:.1f} s",
     }
 
 
@@ -66,61 +178,37 @@ def main():
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2306_14011_amd import fv, inputs, traffic
 
     g, U0 = inputs.vortex_bumps_case(a.n, seed=a.seed)
-    print(f"[bench] workload {a.n}x{a.n} vortex+bumps, steps {a.steps}, warmup {a.warmup}", file=sys.stderr,
-          flush=True)
+    log(f"workload {a.n}x{a.n} vortex+bumps, steps {a.steps}, warmup {a.warmup}")
+    default = fv.fv_default_launch()
     s = fv.Solver(g)
+    ms_default = timed_steps(torch, s, U0, default, a.steps, a.warmup)
+    log(f"default launch: {ms_default:.4f} ms/step")
+
+    tune = None
+    launch = default
     if a.launch:
-        s.set_launch(json.loads(a.launch))
-    launch = s.get_launch()
-    s.set_state(U0)
-    dev = torch.device("cuda")
-    stream = torch.cuda.current_stream(dev)
+        launch = json.loads(a.launch)
+    elif not a.no_tune:
+        from paper_2306_14011_amd.autotune import Autotuner
+        t0 = time.perf_counter()
+        at = Autotuner(g, U0, seed=a.seed, repeats=3, warmup=3, min_ms=20.0)
+        tune = at.run(count=a.samples, k=8, rounds=5)
+        at.close()
+        tune["tuning_seconds"] = round(time.perf_counter() - t0, 1)
+        launch = tune["tuned_launch"]
+        log(f"tuned in {tune['tuning_seconds']} s: R2(test) {tune['r2_test']:.3f}, "
+            f"default/tuned {tune['factor_vs_default']:.3f}, best-random/tuned {tune['factor_vs_best_random']:.3f}")
 
-    s.step(a.warmup)
-    torch.cuda.synchronize()
-    s.set_state(U0)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(a.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    rc, flags = s.status()
-    if flags:
-        print(f"[bench] non-physical flags {flags}", file=sys.stderr)
-        sys.exit(3)
-    ms_per_step = gpu_ms / a.steps
-    value = g.ncells * a.steps / (gpu_ms * 1e-3)
-    print(f"[bench] timed {a.steps} steps: {gpu_ms:.1f} ms (wall {wall * 1e3:.1f} ms)", file=sys.stderr, flush=True)
+    ms_tuned = timed_steps(torch, s, U0, launch, a.steps, a.warmup)
+    value = g.ncells / (ms_tuned * 1e-3)
+    log(f"tuned launch {launch}: {ms_tuned:.4f} ms/step")
 
-    # per-kernel durations: HIP events recorded by the library around each launch
-    s.set_timing(True)
-    s.step(a.timing_steps)
-    ms, cnt = s.get_timing()
-    s.set_timing(False)
-    sb = traffic.site_bytes(g)
-    kernels = {}
-    for i, name in enumerate(fv.SITES):
-        if cnt[i] == 0:
-            continue
-        avg_ms = ms[i] / cnt[i]
-        kernels[name] = {
-            "avg_us": round(avg_ms * 1e3, 3),
-            "launches_per_step": cnt[i] / a.timing_steps,
-            "share": ms[i] / sum(ms),
-            "alg_bytes": sb[name],
-            "achieved_GBps": round(sb[name] / (avg_ms * 1e-3) / 1e9, 1),
-        }
+    kernels = kernel_table(s, g, launch, a.timing_steps, fv, traffic)
     dom = max(kernels, key=lambda k: kernels[k]["share"])
     ach = kernels[dom]["achieved_GBps"]
     roofline = {
@@ -140,26 +228,34 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms_tuned,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"2D Euler {a.n}x{a.n} periodic vortex+32 Gaussian bumps, MUSCL-minmod/Roe/SSP-RK3, CFL 0.5",
+            "workload": f"2D Euler {a.n}x{a.n} periodic vortex + 32 Gaussian bumps, MUSCL-minmod/Roe/SSP-RK3, CFL 0.5",
             "cells": g.ncells,
-            "path": "split 7-kernel step",
+            "path": "split 7-kernel step, MLP-tuned launch" if tune else "split 7-kernel step",
             "launch": launch,
         },
         "roofline": roofline,
+        "default_launch": {"launch": default, "ms_per_step": ms_default,
+                           "value": g.ncells / (ms_default * 1e-3)},
+        "tuned_over_default": round(ms_default / ms_tuned, 4),
         "step_effective_GBps": round(step_b * value / g.ncells / 1e9, 1),
         "alg_bytes_per_cell_update": step_b / g.ncells,
         "kernels": kernels,
     }
+    if tune:
+        out["autotune"] = {k: v for k, v in tune.items() if k not in ("top_pred",)}
+    s.close()
+    if not a.no_adjoint:
+        out["adjoint"] = adjoint_ratio(torch, fv, inputs)
+        log(f"adjoint/primal per step {out['adjoint']['adjoint_over_primal_step']}")
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, U0, a.cpu_seconds)
-    s.close()
     print(json.dumps(out), flush=True)
 
 

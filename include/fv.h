@@ -73,12 +73,18 @@ enum {
     FV_NSITES = 7
 };
 
+/* Scheme flags of fv_grid_desc.scheme. */
+enum {
+    FV_SCHEME_MINMOD = 0,      /* MUSCL with the minmod limiter (the default) */
+    FV_SCHEME_UNLIMITED = 1    /* Psi = 1: unlimited fully upwind (kappa = -1) states */
+};
+
 /* Grid description. ndim is 2 or 3; n[2] must be 1 in 2D. The box is
  * [lo, hi] per axis with n cells each. bc[d][0] / bc[d][1] is the low / high
  * face kind of axis d; periodic must be set on both faces of an axis. */
 typedef struct fv_grid_desc {
     int32_t ndim;
-    int32_t reserved;   /* must be 0 */
+    int32_t scheme;     /* FV_SCHEME_MINMOD or FV_SCHEME_UNLIMITED */
     int64_t n[3];
     double lo[3];
     double hi[3];

@@ -224,6 +224,8 @@ class Autotuner:
         F = LaunchSpace.raw_features([s.launch for s in good])
         t = np.array([s.ms for s in good])
         scale = float(np.median(t[tr]))
+        # runtime relative to the training median (O(1) targets, as the
+        # paper's 0.8 - 2.0 s runtimes are)
         y = t / scale
         mean = F[tr].mean(axis=0)
         std = F[tr].std(axis=0)

@@ -72,8 +72,8 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
         snprintf(why, 256, "ndim must be 2 or 3");
         return FV_EINVAL;
     }
-    if (g->reserved != 0) {
-        snprintf(why, 256, "reserved field must be 0");
+    if (g->scheme != FV_SCHEME_MINMOD && g->scheme != FV_SCHEME_UNLIMITED) {
+        snprintf(why, 256, "unknown scheme");
         return FV_EINVAL;
     }
     for (int d = 0; d < 3; ++d) {
@@ -206,6 +206,7 @@ Geo make_geo(const fv_grid_desc* d, const Layout& L) {
         g.bc[a][0] = d->bc[a][0];
         g.bc[a][1] = d->bc[a][1];
     }
+    g.unlimited = d->scheme == FV_SCHEME_UNLIMITED ? 1 : 0;
     return g;
 }
 

@@ -49,6 +49,7 @@ struct Geo {
     double gamma, gm1;  // gamma, gamma - 1
     double cfl;
     int bc[3][2];
+    int unlimited;      // 1: Psi = 1 (no limiter)
 };
 
 // minmod(a, b): zero unless a and b share a strict sign, else the one of smaller
@@ -67,6 +68,17 @@ __host__ __device__ __forceinline__ void muscl_minmod(double q0, double q1, doub
     const double dm = q1 - q0, dc = q2 - q1, dp = q3 - q2;
     qL = q1 + 0.5 * minmod(dm, dc);
     qR = q2 - 0.5 * minmod(dp, dc);
+}
+
+// The same with Psi = 1 when `unlimited` (a uniform run-time switch).
+__host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, double q3, int unlimited,
+                                              double& qL, double& qR) {
+    if (unlimited) {
+        qL = q1 + 0.5 * (q1 - q0);
+        qR = q2 - 0.5 * (q3 - q2);
+    } else {
+        muscl_minmod(q0, q1, q2, q3, qL, qR);
+    }
 }
 
 // Roe flux along axis AX for NDIM dimensions, conserved face states in, flux out.
@@ -167,7 +179,7 @@ __host__ __device__ __forceinline__ void muscl_minmod_vjp(double q0, double q1, 
                                                           double qRb, double& g0, double& g1, double& g2,
                                                           double& g3) {
     const double dm = q1 - q0, dc = q2 - q1, dp = q3 - q2;
-    // QL = q1 + minmod(dm, dc) / 2
+    // QL = q1 + minmod(dm, dc) / 2 (Psi(dc/dm) dm: the dm branch at a tie)
     if (((dm > 0.0) & (dc > 0.0)) | ((dm < 0.0) & (dc < 0.0))) {
         if (fabs(dm) <= fabs(dc)) {  // q1 + (q1 - q0)/2
             g1 += 1.5 * qLb;
@@ -179,9 +191,11 @@ __host__ __device__ __forceinline__ void muscl_minmod_vjp(double q0, double q1, 
     } else {
         g1 += qLb;
     }
-    // QR = q2 - minmod(dp, dc) / 2
+    // QR = q2 - minmod(dp, dc) / 2; at a tie |dp| = |dc| both branches give the
+    // same value, and the derivative follows the limiter written as
+    // Psi(dp/dc) dc with Psi saturating at ratio >= 1, i.e. the dc branch
     if (((dp > 0.0) & (dc > 0.0)) | ((dp < 0.0) & (dc < 0.0))) {
-        if (fabs(dp) <= fabs(dc)) {  // 3/2 q2 - q3/2
+        if (fabs(dp) < fabs(dc)) {  // 3/2 q2 - q3/2
             g2 += 1.5 * qRb;
             g3 -= 0.5 * qRb;
         } else {  // (q1 + q2)/2
@@ -190,6 +204,20 @@ __host__ __device__ __forceinline__ void muscl_minmod_vjp(double q0, double q1, 
         }
     } else {
         g2 += qRb;
+    }
+}
+
+// Reverse of muscl(): the unlimited states are linear in the stencil.
+__host__ __device__ __forceinline__ void muscl_vjp(double q0, double q1, double q2, double q3, int unlimited,
+                                                   double qLb, double qRb, double& g0, double& g1, double& g2,
+                                                   double& g3) {
+    if (unlimited) {
+        g1 += 1.5 * qLb;
+        g0 -= 0.5 * qLb;
+        g2 += 1.5 * qRb;
+        g3 -= 0.5 * qRb;
+    } else {
+        muscl_minmod_vjp(q0, q1, q2, q3, qLb, qRb, g0, g1, g2, g3);
     }
 }
 

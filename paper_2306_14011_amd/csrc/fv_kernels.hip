@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(MAXT) k_flux(const double* __restrict__ U, dou
         for (int v = 0; v < NV; ++v) {
             const double* Uv = U + v * g.sv;
             const double q0 = Uv[c - 2 * st], q1 = Uv[c - st], q2 = Uv[c], q3 = Uv[c + st];
-            muscl_minmod(q0, q1, q2, q3, qL[v], qR[v]);
+            muscl(q0, q1, q2, q3, g.unlimited, qL[v], qR[v]);
         }
         double Fl[NV];
         roe_flux<NDIM, AX>(qL, qR, g.gm1, Fl);

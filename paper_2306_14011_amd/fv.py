@@ -26,6 +26,9 @@ FV_ENONPHYS = -3
 FV_ENOTSUP = -4
 FV_EWORKSPACE = -5
 
+FV_SCHEME_MINMOD = 0
+FV_SCHEME_UNLIMITED = 1
+
 FV_BC_PERIODIC = 0
 FV_BC_TRANSMISSIVE = 1
 
@@ -41,7 +44,7 @@ NSITES = 7
 class fv_grid_desc(ctypes.Structure):
     _fields_ = [
         ("ndim", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
         ("n", ctypes.c_int64 * 3),
         ("lo", ctypes.c_double * 3),
         ("hi", ctypes.c_double * 3),
@@ -149,10 +152,11 @@ def _check(rc, ctx=None):
 
 
 def make_desc(spec) -> fv_grid_desc:
-    """fv_grid_desc from any object with ndim, n, lo, hi, bc, gamma, cfl."""
+    """fv_grid_desc from any object with ndim, n, lo, hi, bc, gamma, cfl (and
+    optionally limiter: False selects the unlimited scheme)."""
     d = fv_grid_desc()
     d.ndim = spec.ndim
-    d.reserved = 0
+    d.scheme = FV_SCHEME_UNLIMITED if not getattr(spec, "limiter", True) else FV_SCHEME_MINMOD
     for a in range(3):
         d.n[a] = int(spec.n[a])
         d.lo[a] = float(spec.lo[a])

@@ -39,6 +39,7 @@ class GridSpec:
     bc: tuple
     gamma: float = GAMMA
     cfl: float = 0.5
+    limiter: bool = True   # False: unlimited MUSCL (Psi = 1)
 
     @property
     def nvar(self) -> int:

@@ -57,7 +57,7 @@ def test_query_strides_and_workspace():
     lambda d: d.bc[1].__setitem__(1, 7),        # unknown kind
     lambda d: setattr(d, "gamma", 1.0),
     lambda d: setattr(d, "cfl", 0.0),
-    lambda d: setattr(d, "reserved", 1),
+    lambda d: setattr(d, "scheme", 2),
     lambda d: d.hi.__setitem__(0, d.lo[0]),
 ])
 def test_query_rejects_invalid_descriptions(mutate):
