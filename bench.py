@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--samples", type=int, default=300, help="timed launch vectors for the tuner")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-fused", action="store_true", help="skip the fused single-grid and batch measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--launch", type=str, default=None, help="14 launch parameters as a JSON list (skips tuning)")
@@ -150,6 +151,92 @@ def adjoint_ratio(torch, fv, inputs):
     }
 
 
+def fused_single(torch, fv, traffic, g, U0, steps, warmup):
+    """The fused path on the same grid: segment heights swept, best kept."""
+    s = fv.Solver(g)
+    res = {}
+    for seg in (8, 16, 32, 64):
+        s.set_path(fv.FV_PATH_FUSED, seg, 0)
+        res[seg] = timed_steps(torch, s, U0, fv.fv_default_launch(), steps, warmup)
+    seg = min(res, key=res.get)
+    s.set_path(fv.FV_PATH_FUSED, seg, 0)
+    s.set_timing(True)
+    s.step(20)
+    ms, cnt = s.get_timing()
+    s.set_timing(False)
+    s.close()
+    avg_ms = ms[7] / cnt[7]
+    alg = traffic.fused_step_bytes(g) / 3.0   # per stage launch, averaged over the three
+    return {
+        "ms_per_step": res[seg],
+        "value": g.ncells / (res[seg] * 1e-3),
+        "seg": seg,
+        "ms_per_step_by_seg": {str(k): round(v, 4) for k, v in res.items()},
+        "stage_avg_us": round(avg_ms * 1e3, 2),
+        "stage_alg_bytes": alg,
+        "stage_achieved_GBps": round(alg / (avg_ms * 1e-3) / 1e9, 1),
+        "alg_bytes_per_cell_update": traffic.fused_step_bytes(g) / g.ncells,
+    }
+
+
+def batch_bench(torch, fv, inputs, steps):
+    """96 uneven periodic vortex grids (sides 128..1024), fused stages in a HIP graph."""
+    spec = inputs.batch_case(count=96, seed=0)
+    cells = sum(gg.ncells for gg in spec.grids)
+    best = None
+    for seg, order in ((16, 1), (32, 1), (16, 0)):
+        B = fv.Batch(spec.grids, seg=seg, order=order)
+        B.set_states(spec.states)
+        B.step(3)
+        torch.cuda.synchronize()
+        B.set_states(spec.states)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        B.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rc, flags = B.status()
+        if flags:
+            log(f"batch flags {flags}")
+        if best is None or ms < best[0]:
+            best = (ms, seg, order, B)
+        else:
+            B.close()
+    ms, seg, order, B = best
+    # device-clock record of 20 steps: per-grid step time = sum over stages of (last end - first start)
+    B.set_states(spec.states)
+    tpu = B.set_timing(20)
+    B.step(20)
+    torch.cuda.synchronize()
+    clk = B.clocks()
+    B.close()
+    per = (clk[..., 1] - clk[..., 0]).sum(axis=2) / tpu   # (steps, grids) microseconds
+    import numpy as np
+    # sequential baseline: each grid alone through the single-grid fused path
+    seq = 0.0
+    for gg, st in zip(spec.grids, spec.states):
+        s = fv.Solver(gg)
+        s.set_path(fv.FV_PATH_FUSED, 16, 0)
+        seq += timed_steps(torch, s, st, fv.fv_default_launch(), 5, 1)
+        s.close()
+    return {
+        "workload": "96 periodic 2D vortex grids, sides U{128..1024}, beta U[1,5], FP64, 3 fused stages per step in a HIP graph",
+        "cells": cells,
+        "ms_per_step": round(ms, 4),
+        "value": cells / (ms * 1e-3),
+        "unit": "cell-updates/s",
+        "seg": seg,
+        "order": "largest_first" if order == 1 else "given",
+        "per_grid_step_us_p50": round(float(np.percentile(per, 50)), 2),
+        "per_grid_step_us_p99": round(float(np.percentile(per, 99)), 2),
+        "sequential_single_grid_ms_per_step": round(seq, 4),
+        "batch_speedup_vs_sequential": round(seq / ms, 3),
+    }
+
+
 def cpu_baseline(g, U0, seconds):
     """The oracle as it stands, on the host cores, for about `seconds`."""
     import oracle
@@ -251,6 +338,11 @@ def main():
     if tune:
         out["autotune"] = {k: v for k, v in tune.items() if k not in ("top_pred",)}
     s.close()
+    if not a.no_fused:
+        out["fused"] = fused_single(torch, fv, traffic, g, U0, a.steps, a.warmup)
+        log(f"fused path: {out['fused']['ms_per_step']:.4f} ms/step (seg {out['fused']['seg']})")
+        out["batch"] = batch_bench(torch, fv, inputs, 100)
+        log(f"batch: {out['batch']['value']:.3e} cell-updates/s")
     if not a.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, fv, inputs)
         log(f"adjoint/primal per step {out['adjoint']['adjoint_over_primal_step']}")

@@ -165,19 +165,80 @@ int fv_status(fv_ctx* ctx, uint32_t* flags);
 /* Enqueues a reset of the status word to 0. */
 int fv_clear_status(fv_ctx* ctx);
 
+/* Step paths. FV_PATH_SPLIT runs the seven tunable kernels (the launch
+ * table applies). FV_PATH_FUSED (2D only) runs one kernel per Runge-Kutta
+ * stage that does the ghost mapping, both flux axes, the residual and the
+ * stage update, and the last stage also the CFL max of the new state; the
+ * state then moves through HBM 8 times per step instead of ~33. `seg` is the
+ * segment height of a work item (8, 16, 32 or 64 rows; a work item is a
+ * 60-column strip of it, one wavefront each) and `waves` the number of
+ * wavefronts launched (0 = one per work item, else a grid-stride loop over
+ * the items). Both paths compute the same cell arithmetic; fv_residual and
+ * fv_adjoint_step always use the split kernels. Returns FV_ENOTSUP for 3D. */
+enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
+int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
+
 /* Per-site kernel timing, a diagnostic for profiling and the autotuner's
  * measurements. When enabled, every kernel launch of fv_step / fv_residual /
  * fv_adjoint_step is bracketed by two HIP events on the context's stream and
  * each call waits for its last event, so enabling it serialises the host with
  * the stream; kernel durations themselves are unaffected. fv_get_timing
- * writes, per FV_SITE_*, the accumulated milliseconds and number of launches
- * since the last read, then resets them. Either output may be NULL. */
+ * writes, per timer (FV_SITE_* and FV_TIMER_FUSED for the fused stages), the
+ * accumulated milliseconds and number of launches since the last read, then
+ * resets them. Either output may be NULL. */
+enum { FV_TIMER_FUSED = 7, FV_NTIMERS = 8 };
 int fv_set_timing(fv_ctx* ctx, int enable);
-int fv_get_timing(fv_ctx* ctx, double ms_out[7], int64_t launches_out[7]);
+int fv_get_timing(fv_ctx* ctx, double ms_out[8], int64_t launches_out[8]);
 
 /* Message of the last failing call on ctx (or of fv_query / fv_create when
  * ctx is NULL). Never NULL. */
 const char* fv_last_error(const fv_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches of uneven 2D grids advanced together by the fused stage kernels.
+ *
+ * Grid g of a batch is stored dense, variables outermost:
+ *   U[offsets[g] + v * nx_g * ny_g + j * nx_g + i],
+ * grids back to back (offsets from fv_batch_query). Every grid has its own
+ * CFL dt. A step is three fused stage launches that cover all work items of
+ * all grids (a work item is a 60-column x seg-row piece of one grid, one
+ * wavefront each); the three launches are captured once in a HIP graph and
+ * replayed per step on the caller's stream.
+ * ------------------------------------------------------------------------ */
+typedef struct fv_batch fv_batch;
+
+enum { FV_ORDER_GIVEN = 0, FV_ORDER_LARGEST_FIRST = 1 };
+
+/* Validates the grids (2D each) and reports the element offsets of every
+ * grid (offsets[0..ngrids], host array, may be NULL) and the workspace size. */
+int fv_batch_query(int32_t ngrids, const fv_grid_desc* grids, int64_t* offsets, size_t* workspace_bytes);
+
+/* Creates a batch. seg: 8, 16, 32 or 64; waves: wavefronts per stage launch
+ * (0 = one per work item, else a grid-stride loop); order: FV_ORDER_* of the
+ * grids in the work list. The workspace (queried size, 256-byte aligned) is
+ * owned by the caller. */
+int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int32_t waves, int32_t order,
+                    void* workspace, size_t workspace_bytes, void* stream, fv_batch** out);
+
+/* Advances every grid of the batch state U (device) by nsteps steps, each
+ * grid with its own CFL dt. */
+int fv_batch_step(fv_batch* b, double* U, int32_t nsteps);
+
+/* Device-clock record of each step: when history (device, max_steps *
+ * ngrids * 6 uint64) is non-NULL, step n of the following fv_batch_step calls
+ * writes, per grid and stage, the earliest work-item start and the latest
+ * work-item end (wall_clock64 ticks) to history[((n * ngrids + g) * 3 + stage) * 2 + {0,1}]
+ * for n < max_steps. NULL turns recording off. *ticks_per_us receives the
+ * clock rate. */
+int fv_batch_set_timing(fv_batch* b, uint64_t* history, int32_t max_steps, double* ticks_per_us);
+
+/* Copies the dt of the last step of every grid to dt (device, ngrids doubles). */
+int fv_batch_dt(fv_batch* b, double* dt);
+
+/* Synchronises the stream and reads the batch status word (FV_FLAG_*). */
+int fv_batch_status(fv_batch* b, uint32_t* flags);
+
+int fv_batch_destroy(fv_batch* b);
 
 /* ------------------------------------------------------------------------
  * Launch-parameter autotuner: the paper's runtime-regression network

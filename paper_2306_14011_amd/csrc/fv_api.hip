@@ -28,6 +28,12 @@ struct fv_ctx {
     double* lamA;
     double* lamB;
     double* G[3];   // face adjoint contributions [4][nvar][faces] per axis
+    // fused path
+    int path, fseg, fwaves, fitems;
+    fvk::FGrid fgrid_host;
+    fvk::FGrid* fgrid;
+    unsigned long long* flam;
+    double* fdt;
     // per-site event timing (diagnostic)
     static const int kMaxEv = 64;
     bool timing;
@@ -35,8 +41,8 @@ struct fv_ctx {
     hipEvent_t ev[2 * kMaxEv];
     int ev_site[kMaxEv];
     int nev;
-    double acc_ms[FV_NSITES];
-    int64_t acc_n[FV_NSITES];
+    double acc_ms[FV_NTIMERS];
+    int64_t acc_n[FV_NTIMERS];
     char err[256];
 };
 
@@ -58,7 +64,7 @@ struct Layout {
     int64_t faces[3];
     int64_t ncell;
     int max_partial;
-    size_t off_status, off_dt, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_G[3], total;
+    size_t off_status, off_dt, off_fused, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_G[3], total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -127,6 +133,8 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     L->off_status = o;
     o += 256;
     L->off_dt = o;
+    o += 256;
+    L->off_fused = o;   // FGrid (128 B), lambda slot, dt slot
     o += 256;
     L->off_partial = o;
     o = align256(o + (size_t)L->max_partial * 8);
@@ -359,6 +367,10 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
     c->lamA = (double*)(base + L.off_lamA);
     c->lamB = (double*)(base + L.off_lamB);
     for (int d = 0; d < 3; ++d) c->G[d] = (double*)(base + L.off_G[d]);
+    c->fgrid = (fvk::FGrid*)(base + L.off_fused);
+    c->flam = (unsigned long long*)(base + L.off_fused + 160);
+    c->fdt = (double*)(base + L.off_fused + 168);
+    c->path = FV_PATH_SPLIT;
     fvk::launch_set_u32(c->status, 0u, c->stream);
     if (check_launch_error(c) != FV_OK) {
         snprintf(g_err, 256, "%s", c->err);
@@ -394,10 +406,81 @@ int fv_residual(fv_ctx* c, double* U, double* R) {
     return drain_timing(c);
 }
 
+static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
+    if (nsteps == 0) return FV_OK;
+    fvk::launch_fused_init(c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, nullptr, c->stream);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        {
+            SiteTimer t(c, FV_TIMER_FUSED);
+            fvk::launch_fused_stage(0, c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, U, c->U1, c->flam, c->fdt,
+                                    dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status, nullptr,
+                                    c->stream);
+        }
+        {
+            SiteTimer t(c, FV_TIMER_FUSED);
+            fvk::launch_fused_stage(1, c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, c->U1, c->U2, c->flam, c->fdt,
+                                    nullptr, nullptr, c->status, nullptr, c->stream);
+        }
+        {
+            SiteTimer t(c, FV_TIMER_FUSED);
+            fvk::launch_fused_stage(2, c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, c->U2, U, c->flam, c->fdt,
+                                    nullptr, nullptr, c->status, nullptr, c->stream);
+        }
+        int rc = check_launch_error(c);
+        if (rc != FV_OK) return rc;
+        rc = drain_timing(c);
+        if (rc != FV_OK) return rc;
+    }
+    return FV_OK;
+}
+
+int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (path == FV_PATH_SPLIT) {
+        c->path = FV_PATH_SPLIT;
+        return FV_OK;
+    }
+    if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
+    if (c->g.ndim != 2) return fail(c, FV_ENOTSUP, "the fused path is 2D only%s");
+    if (seg != 8 && seg != 16 && seg != 32 && seg != 64) return fail(c, FV_EINVAL, "seg must be 8, 16, 32 or 64%s");
+    if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");
+    fvk::FGrid& G = c->fgrid_host;
+    memset(&G, 0, sizeof(G));
+    G.nx = c->g.n[0];
+    G.ny = c->g.n[1];
+    G.pitch = c->g.sy;
+    G.strips = fvk::fused_strips(G.nx);
+    G.work0 = 0;
+    G.unlimited = c->g.unlimited;
+    G.bcx0 = c->g.bc[0][0];
+    G.bcx1 = c->g.bc[0][1];
+    G.bcy0 = c->g.bc[1][0];
+    G.bcy1 = c->g.bc[1][1];
+    G.base = c->g.off0;
+    G.sv = c->g.sv;
+    G.ax = c->g.area[0];
+    G.ay = c->g.area[1];
+    G.inv_vol = c->g.inv_vol;
+    G.inv_dx = c->g.inv_dx[0];
+    G.inv_dy = c->g.inv_dx[1];
+    G.cfl = c->g.cfl;
+    G.gamma = c->g.gamma;
+    G.gm1 = c->g.gm1;
+    hipError_t e = hipMemcpyAsync(c->fgrid, &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
+    c->fseg = seg;
+    c->fwaves = waves;
+    c->fitems = fvk::fused_items(G, seg);
+    c->path = FV_PATH_FUSED;
+    return FV_OK;
+}
+
 int fv_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
     if (!U) return fail(c, FV_EINVAL, "null state pointer%s");
     if (nsteps < 0) return fail(c, FV_EINVAL, "negative step count%s");
+    if (c->path == FV_PATH_FUSED) return fused_step(c, U, nsteps, dt_in, dt_out);
     for (int32_t s = 0; s < nsteps; ++s) {
         enqueue_bc(c, U);
         enqueue_cfl(c, U, dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr);
@@ -499,11 +582,11 @@ int fv_set_timing(fv_ctx* c, int enable) {
     return FV_OK;
 }
 
-int fv_get_timing(fv_ctx* c, double ms_out[7], int64_t launches_out[7]) {
+int fv_get_timing(fv_ctx* c, double ms_out[8], int64_t launches_out[8]) {
     if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
     int rc = drain_timing(c);
     if (rc != FV_OK) return rc;
-    for (int s = 0; s < FV_NSITES; ++s) {
+    for (int s = 0; s < FV_NTIMERS; ++s) {
         if (ms_out) ms_out[s] = c->acc_ms[s];
         if (launches_out) launches_out[s] = c->acc_n[s];
         c->acc_ms[s] = 0.0;

@@ -167,6 +167,30 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
     F[IE] = 0.5 * ((qL[IE] + pL) * vnL + (qR[IE] + pR) * vnR - D[IE]);
 }
 
+// Wave-speed bound of one cell, sum_d (|u_d| + c) * inv_dx[d], and the
+// non-physical flags (1 NaN, 2 rho <= 0, 4 p <= 0) it raises.
+template <int NDIM>
+__host__ __device__ __forceinline__ double cell_lambda(const double* q, double gamma, double gm1, const double* inv_dx,
+                                                       uint32_t& fl) {
+    constexpr int IE = NDIM + 1;
+    const double rho = q[0];
+    const double ir = 1.0 / rho;
+    double u[NDIM];
+    double qq = 0.0;
+    for (int d = 0; d < NDIM; ++d) {
+        u[d] = q[1 + d] * ir;
+        qq += u[d] * u[d];
+    }
+    const double p = gm1 * (q[IE] - 0.5 * rho * qq);
+    const double c = sqrt(gamma * p * ir);
+    double lam = 0.0;
+    for (int d = 0; d < NDIM; ++d) lam += (fabs(u[d]) + c) * inv_dx[d];
+    if (isnan(lam) || isnan(rho) || isnan(p)) fl |= 1u;
+    if (!(rho > 0.0)) fl |= 2u;
+    if (!(p > 0.0)) fl |= 4u;
+    return lam;
+}
+
 // ---------------------------------------------------------------------------
 // Reverse (adjoint) of the face computation, hand-derived from the forward
 // sequence above: given Fb = dJ/dF, accumulate dJ/dq of the four stencil

@@ -5,6 +5,16 @@
 
 namespace fvk {
 
+// One 2D grid of the fused path (device memory, read uniformly).
+struct FGrid {
+    int nx, ny, pitch, strips, work0, unlimited;
+    int bcx0, bcx1, bcy0, bcy1, gid, pad1;  // gid: the caller's grid index (slots of lam, dt, clocks)
+    long long base;     // element offset of cell (0,0), variable 0
+    long long sv;       // per-variable stride
+    double ax, ay;      // face areas of x faces (dy) and y faces (dx)
+    double inv_vol, inv_dx, inv_dy, cfl, gamma, gm1;
+};
+
 void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t s);
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, double* R, const Geo& g, int gang,
@@ -15,6 +25,15 @@ int cfl_blocks(const Geo& g, int gang, int threads);
 void launch_cfl(const double* U, double* partial, uint32_t* status, const double* dt_in, double* dt,
                 double* dt_out, const Geo& g, int gang, int threads, hipStream_t s);
 void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+
+// fused 2D stages
+int fused_items(const FGrid& G, int seg);
+int fused_strips(int nx);
+void launch_fused_stage(int stage, int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
+                        const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
+                        double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s);
+void launch_fused_init(int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
+                       unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s);
 
 // adjoint
 void launch_adj_flux(int ax, const double* U, const double* w, double* G, const Geo& g, hipStream_t s);

@@ -179,7 +179,6 @@ __device__ __forceinline__ double wave_max(double v) {
 template <int NDIM, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_cfl_partial(const double* __restrict__ U, double* __restrict__ partial,
                                                       uint32_t* __restrict__ status, Geo g, int stride_all) {
-    constexpr int IE = NDIM + 1;
     __shared__ double sm[MAXT / 64];
     double lmax = 0.0;
     uint32_t fl = 0;
@@ -187,23 +186,10 @@ __global__ void __launch_bounds__(MAXT) k_cfl_partial(const double* __restrict__
         int i, j, k;
         decode_cell(e, g, i, j, k);
         const int o = g.off0 + i + j * g.sy + k * g.sz;
-        const double rho = U[o];
-        const double ir = 1.0 / rho;
-        double u[NDIM];
-        double qq = 0.0;
+        double q[NDIM + 2];
 #pragma unroll
-        for (int d = 0; d < NDIM; ++d) {
-            u[d] = U[(1 + d) * g.sv + o] * ir;
-            qq += u[d] * u[d];
-        }
-        const double p = g.gm1 * (U[IE * g.sv + o] - 0.5 * rho * qq);
-        const double c = sqrt(g.gamma * p * ir);
-        double lam = 0.0;
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d) lam += (fabs(u[d]) + c) * g.inv_dx[d];
-        if (isnan(lam) || isnan(rho) || isnan(p)) fl |= 1u;
-        if (!(rho > 0.0)) fl |= 2u;
-        if (!(p > 0.0)) fl |= 4u;
+        for (int v = 0; v < NDIM + 2; ++v) q[v] = U[v * g.sv + o];
+        const double lam = cell_lambda<NDIM>(q, g.gamma, g.gm1, g.inv_dx, fl);
         lmax = fmax(lmax, lam);
     }
     if (fl) atomicOr(status, fl);

@@ -39,6 +39,10 @@ FV_FLAG_DT = 8
 
 SITES = ("flux_x", "flux_y", "flux_z", "residual", "update", "bc", "cfl")
 NSITES = 7
+TIMERS = SITES + ("fused",)
+NTIMERS = 8
+FV_PATH_SPLIT = 0
+FV_PATH_FUSED = 1
 
 
 class fv_grid_desc(ctypes.Structure):
@@ -123,9 +127,19 @@ def lib():
         L.fv_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
         L.fv_clear_status.argtypes = [_vp]
         L.fv_set_timing.argtypes = [_vp, ctypes.c_int]
+        L.fv_set_path.argtypes = [_vp, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]
         L.fv_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fv_last_error.argtypes = [_vp]
         L.fv_last_error.restype = ctypes.c_char_p
+        L.fv_batch_query.argtypes = [ctypes.c_int32, ctypes.POINTER(fv_grid_desc), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_size_t)]
+        L.fv_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(fv_grid_desc), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+        L.fv_batch_step.argtypes = [_vp, _vp, ctypes.c_int32]
+        L.fv_batch_set_timing.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.fv_batch_dt.argtypes = [_vp, _vp]
+        L.fv_batch_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.fv_batch_destroy.argtypes = [_vp]
         L.fv_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_sweep_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp, _vp,
@@ -137,7 +151,9 @@ def lib():
                                    ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
                      "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
-                     "fv_set_timing", "fv_get_timing", "fv_mlp_workspace", "fv_mlp_sweep_workspace",
+                     "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_batch_query", "fv_batch_create",
+                     "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_destroy",
+                     "fv_mlp_workspace", "fv_mlp_sweep_workspace",
                      "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -236,20 +252,84 @@ def fv_clear_status(ctx):
     return _check(lib().fv_clear_status(_vp(ctx)), ctx)
 
 
+def fv_set_path(ctx, path, seg=16, waves=0):
+    return _check(lib().fv_set_path(_vp(ctx), int(path), int(seg), int(waves)), ctx)
+
+
 def fv_set_timing(ctx, enable):
     return _check(lib().fv_set_timing(_vp(ctx), 1 if enable else 0), ctx)
 
 
 def fv_get_timing(ctx):
-    """(ms per site, launches per site) accumulated since the last read."""
-    ms = (ctypes.c_double * NSITES)()
-    n = (ctypes.c_int64 * NSITES)()
+    """(ms per timer, launches per timer) accumulated since the last read; timers
+    are the seven sites then the fused stage."""
+    ms = (ctypes.c_double * NTIMERS)()
+    n = (ctypes.c_int64 * NTIMERS)()
     _check(lib().fv_get_timing(_vp(ctx), ms, n), ctx)
     return list(ms), list(n)
 
 
 def fv_last_error(ctx=None):
     return lib().fv_last_error(_vp(ctx)).decode()
+
+
+FV_ORDER_GIVEN = 0
+FV_ORDER_LARGEST_FIRST = 1
+
+
+def _desc_array(specs):
+    arr = (fv_grid_desc * len(specs))()
+    for i, s in enumerate(specs):
+        arr[i] = make_desc(s)
+    return arr
+
+
+def fv_batch_query(specs):
+    arr = _desc_array(specs)
+    offs = (ctypes.c_int64 * (len(specs) + 1))()
+    ws = ctypes.c_size_t()
+    _batch_check(lib().fv_batch_query(len(specs), arr, offs, ctypes.byref(ws)))
+    return list(offs), ws.value
+
+
+def _batch_check(rc, b=None):
+    if rc not in (FV_OK,):
+        raise FvError(rc, "batch call failed")
+    return rc
+
+
+def fv_batch_create(specs, seg, waves, order, ws_ptr, ws_bytes, stream_ptr):
+    arr = _desc_array(specs)
+    out = _vp()
+    _batch_check(lib().fv_batch_create(len(specs), arr, int(seg), int(waves), int(order), _vp(ws_ptr), ws_bytes,
+                                       _vp(stream_ptr), ctypes.byref(out)))
+    return out.value
+
+
+def fv_batch_step(b, U_ptr, nsteps):
+    return _batch_check(lib().fv_batch_step(_vp(b), _vp(U_ptr), int(nsteps)))
+
+
+def fv_batch_set_timing(b, history_ptr, max_steps):
+    tpu = ctypes.c_double()
+    _batch_check(lib().fv_batch_set_timing(_vp(b), _vp(history_ptr), int(max_steps), ctypes.byref(tpu)))
+    return tpu.value
+
+
+def fv_batch_dt(b, dt_ptr):
+    return _batch_check(lib().fv_batch_dt(_vp(b), _vp(dt_ptr)))
+
+
+def fv_batch_status(b):
+    fl = ctypes.c_uint32()
+    rc = lib().fv_batch_status(_vp(b), ctypes.byref(fl))
+    if rc not in (FV_OK, FV_ENONPHYS):
+        _batch_check(rc)
+    return rc, fl.value
+
+
+def fv_batch_destroy(b):
+    return _batch_check(lib().fv_batch_destroy(_vp(b)))
 
 
 def fv_mlp_workspace(n):
@@ -382,6 +462,9 @@ class Solver:
     def status(self):
         return fv_status(self.ctx)
 
+    def set_path(self, path, seg=16, waves=0):
+        fv_set_path(self.ctx, path, seg, waves)
+
     def set_timing(self, enable):
         fv_set_timing(self.ctx, enable)
 
@@ -390,3 +473,71 @@ class Solver:
 
     def clear_status(self):
         fv_clear_status(self.ctx)
+
+
+class Batch:
+    """Device buffers of a batch of 2D grids advanced by the fused stage kernels.
+
+    ``U`` holds grid g's dense (4, ny, nx) state at [offsets[g], offsets[g+1]).
+    """
+
+    def __init__(self, specs, seg=16, waves=0, order=FV_ORDER_GIVEN, device="cuda"):
+        torch = _torch()
+        self.specs = list(specs)
+        self.device = torch.device(device)
+        self.offsets, self.ws_bytes = fv_batch_query(self.specs)
+        self.U = torch.zeros(self.offsets[-1], dtype=torch.float64, device=self.device)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.b = fv_batch_create(self.specs, seg, waves, order, self.workspace.data_ptr(), self.ws_bytes,
+                                 self.stream.cuda_stream)
+        self.history = None
+
+    def view(self, g):
+        s = self.specs[g]
+        return self.U[self.offsets[g]:self.offsets[g + 1]].view(4, 1, int(s.n[1]), int(s.n[0]))
+
+    def set_states(self, states):
+        torch = _torch()
+        for g, st in enumerate(states):
+            self.view(g).copy_(torch.as_tensor(np.ascontiguousarray(st), dtype=torch.float64))
+
+    def get_states(self):
+        return [self.view(g).cpu().numpy().copy() for g in range(len(self.specs))]
+
+    def step(self, nsteps):
+        fv_batch_step(self.b, self.U.data_ptr(), nsteps)
+
+    def set_timing(self, max_steps):
+        """Record per-step device clocks; returns ticks per microsecond."""
+        torch = _torch()
+        if max_steps <= 0:
+            self.history = None
+            return fv_batch_set_timing(self.b, None, 0)
+        self.history = torch.zeros(max_steps * len(self.specs) * 6, dtype=torch.int64, device=self.device)
+        return fv_batch_set_timing(self.b, self.history.data_ptr(), max_steps)
+
+    def clocks(self):
+        """(steps, grids, 3 stages, 2) int64 array of (first start, last end)."""
+        h = self.history.cpu().numpy()
+        return h.reshape(-1, len(self.specs), 3, 2)
+
+    def dt(self):
+        torch = _torch()
+        out = torch.zeros(len(self.specs), dtype=torch.float64, device=self.device)
+        fv_batch_dt(self.b, out.data_ptr())
+        return out.cpu().numpy()
+
+    def status(self):
+        return fv_batch_status(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            fv_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

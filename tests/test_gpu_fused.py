@@ -1,0 +1,200 @@
+"""The fused 2D stage kernels (single grid through fv_step's fused path, and
+batches of uneven grids through fv_batch_*) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_14011_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _fv():
+    from paper_2306_14011_amd import fv
+    return fv
+
+
+def close(got, ref, tol=TOL, what=""):
+    for v in range(ref.shape[0]):
+        scale = np.abs(ref[v]).max()
+        err = np.abs(got[v] - ref[v]).max()
+        assert err <= tol * scale, f"{what} var {v}: {err:.3e} vs {scale:.3e}"
+
+
+def run_fused(g, U0, nsteps, seg=16, waves=0, dt_in=None, path=1):
+    import torch
+    fv = _fv()
+    s = fv.Solver(g)
+    s.set_path(path, seg, waves)
+    s.set_state(U0)
+    dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device="cuda")
+    dti = torch.as_tensor(np.asarray(dt_in, dtype=np.float64)).cuda() if dt_in is not None else None
+    s.step(nsteps, dt_in=dti, dt_out=dts)
+    rc, flags = s.status()
+    out = s.get_state()
+    s.close()
+    return out, dts.cpu().numpy()[:nsteps], flags
+
+
+CASES = [
+    ("vortex64", lambda: inputs.vortex_case(64, seed=0)),
+    ("ragged_bumps", lambda: (lambda g: (g, inputs.gaussian_bumps(g, inputs.vortex_state(g, (4.2, 5.7)), 1, amp=0.05)))(inputs.grid2d(133, 45))),
+    ("transmissive_sod_x", lambda: (lambda g: (g, inputs.sod_axis_state(g, 0)))(inputs.grid2d(131, 3, bc=((1, 1), (0, 0))))),
+    ("transmissive_sod_y", lambda: (lambda g: (g, inputs.sod_axis_state(g, 1)))(inputs.grid2d(2, 70, bc=((1, 1), (1, 1))))),
+    ("tilted_sod", lambda: (lambda g: (g, inputs.sod_state(g, (0.8, 0.6, 0.0), (0.5, 0.5, 0.0))))(inputs.grid2d(50, 41, hi=(1.0, 1.0), bc=((1, 1), (0, 0))))),
+    ("single_row", lambda: (lambda g: (g, inputs.sod_axis_state(g, 0)))(inputs.grid2d(66, 1, bc=((1, 1), (0, 0))))),
+    ("single_column", lambda: (lambda g: (g, inputs.sod_axis_state(g, 1)))(inputs.grid2d(1, 57, bc=((0, 0), (1, 1))))),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_fused_one_step_matches_oracle(name, make):
+    g, U0 = make()
+    got, dts, flags = run_fused(g, U0, 1)
+    ref, rdts, _ = oracle.run(g, U0, 1)
+    assert flags == 0
+    assert abs(dts[0] - rdts[0]) <= 1e-14 * rdts[0]
+    close(got, ref, what=name)
+
+
+def test_fused_equals_split():
+    g, U0 = inputs.vortex_bumps_case(150, seed=4)
+    a, da, _ = run_fused(g, U0, 5, path=1)
+    b, db, _ = run_fused(g, U0, 5, path=0)
+    assert np.array_equal(da, db)
+    close(a, b, tol=1e-14, what="fused vs split")
+    print("fused == split bitwise:", np.array_equal(a, b))
+
+
+def test_fused_100_steps():
+    g, U0 = inputs.vortex_case(64, seed=0)
+    got, dts, flags = run_fused(g, U0, 100)
+    ref, rdts, _ = oracle.run(g, U0, 100)
+    assert flags == 0 and np.allclose(dts, rdts, rtol=1e-12, atol=0)
+    close(got, ref, tol=1e-11, what="100 steps")
+
+
+def test_fused_frozen_dt_and_unlimited():
+    g, U0 = inputs.vortex_case(48, seed=6)
+    dt_in = [0.01, 0.015, 0.02]
+    got, dts, _ = run_fused(g, U0, 3, dt_in=dt_in)
+    assert np.array_equal(dts, dt_in)
+    close(got, oracle.run(g, U0, 3, dt_in=np.array(dt_in))[0], what="frozen dt")
+    g.limiter = False
+    got, _, _ = run_fused(g, U0, 3, dt_in=dt_in)
+    close(got, oracle.run(g, U0, 3, dt_in=np.array(dt_in), limiter=False)[0], what="unlimited")
+
+
+def test_fused_schedules_bitwise_equal():
+    g, U0 = inputs.vortex_bumps_case(190, seed=5)
+    base, _, _ = run_fused(g, U0, 3, seg=16, waves=0)
+    for seg, waves in ((8, 0), (32, 0), (64, 0), (16, 7), (8, 64), (32, 1000)):
+        got, _, _ = run_fused(g, U0, 3, seg=seg, waves=waves)
+        assert np.array_equal(got, base), (seg, waves)
+
+
+def test_fused_full_size_one_step():
+    g, U0 = inputs.vortex_bumps_case(2048, seed=0)
+    got, dts, flags = run_fused(g, U0, 1)
+    ref, rdts, _ = oracle.run(g, U0, 1)
+    assert flags == 0 and abs(dts[0] - rdts[0]) <= 1e-14 * rdts[0]
+    close(got, ref, what="2048^2 fused")
+
+
+def test_fused_rejects_3d():
+    fv = _fv()
+    s = fv.Solver(inputs.grid3d(8, 8, 8))
+    with pytest.raises(fv.FvError) as e:
+        s.set_path(1, 16, 0)
+    assert e.value.code == fv.FV_ENOTSUP
+    s.close()
+
+
+def small_batch(seed=3, count=7):
+    spec = inputs.batch_case(count=count, seed=seed, smin=20, smax=140)
+    # mix in boundary kinds
+    spec.grids[1] = inputs.grid2d(spec.grids[1].n[0], spec.grids[1].n[1], bc=((1, 1), (0, 0)))
+    spec.states[1] = inputs.vortex_state(spec.grids[1], (5.1, 4.3), 2.0)
+    return spec
+
+
+def test_batch_matches_per_grid_oracle():
+    fv = _fv()
+    spec = small_batch()
+    B = fv.Batch(spec.grids, seg=16)
+    B.set_states(spec.states)
+    B.step(3)
+    rc, flags = B.status()
+    got = B.get_states()
+    dts = B.dt()
+    B.close()
+    assert flags == 0
+    for g, (gs, U0) in enumerate(zip(spec.grids, spec.states)):
+        ref, rdts, _ = oracle.run(gs, U0, 3)
+        assert abs(dts[g] - rdts[-1]) <= 1e-14 * rdts[-1], g
+        close(got[g], ref, what=f"grid {g}")
+
+
+def test_batch_schedules_and_graph_replays_bitwise_equal():
+    fv = _fv()
+    spec = small_batch(seed=4, count=9)
+
+    def run(seg, waves, order, chunks):
+        B = fv.Batch(spec.grids, seg=seg, waves=waves, order=order)
+        B.set_states(spec.states)
+        for c in chunks:
+            B.step(c)
+        out = B.get_states()
+        B.close()
+        return out
+
+    base = run(16, 0, 0, [4])
+    for args in ((8, 0, 1, [4]), (64, 0, 0, [4]), (16, 40, 1, [4]), (32, 3, 0, [1, 1, 2]), (16, 0, 0, [2, 2])):
+        got = run(*args)
+        for g in range(len(base)):
+            assert np.array_equal(got[g], base[g]), (args, g)
+
+
+def test_batch_equals_single_grid_fused_path():
+    # eager single-grid launches vs the graph-replayed batch: same kernels, same bits
+    fv = _fv()
+    spec = small_batch(seed=5, count=5)
+    B = fv.Batch(spec.grids, seg=16)
+    B.set_states(spec.states)
+    B.step(3)
+    got = B.get_states()
+    B.close()
+    for g, (gs, U0) in enumerate(zip(spec.grids, spec.states)):
+        single, _, _ = run_fused(gs, U0, 3)
+        assert np.array_equal(got[g], single), g
+
+
+def test_batch_clock_history():
+    fv = _fv()
+    spec = small_batch(seed=6, count=6)
+    B = fv.Batch(spec.grids, seg=16)
+    B.set_states(spec.states)
+    tpu = B.set_timing(5)
+    B.step(5)
+    clk = B.clocks()
+    B.close()
+    assert tpu > 0
+    assert clk.shape == (5, 6, 3, 2)
+    assert np.all(clk[..., 1] >= clk[..., 0]) and np.all(clk[..., 0] > 0)
+    # stages of a grid run in order
+    assert np.all(clk[:, :, 1, 0] >= clk[:, :, 0, 0])
+
+
+def test_batch_flags_nonphysical():
+    fv = _fv()
+    spec = small_batch(seed=7, count=3)
+    spec.states[2] = spec.states[2].copy()
+    spec.states[2][3, 0, 3, 4] = -1.0
+    B = fv.Batch(spec.grids, seg=16)
+    B.set_states(spec.states)
+    B.step(1)
+    rc, flags = B.status()
+    B.close()
+    assert rc == fv.FV_ENONPHYS and flags & fv.FV_FLAG_P
