@@ -1,23 +1,27 @@
 """Benchmark of the FP64 finite-volume Euler step on one MI355X.
 
-Workload: 2D Euler, 2048 x 2048 periodic grid on [0,10]^2, isentropic vortex
-(beta 5, Mach 0.5 diagonal) plus 32 seeded Gaussian density bumps (amplitude
-1e-2), MUSCL-minmod + Roe, SSP-RK3, CFL 0.5. One "step" is one full SSP-RK3
-time step (3 stages + the CFL reduction) through ``fv_step``.
+Headline workload: 2D Euler, 2048 x 2048 periodic grid on [0,10]^2,
+isentropic vortex (beta 5, Mach 0.5 diagonal) plus 32 seeded Gaussian density
+bumps (amplitude 1e-2), MUSCL-minmod + Roe, SSP-RK3, CFL 0.5, 200 steps.
+One "step" is one full SSP-RK3 time step (3 stages + the CFL reduction).
 
-Sequence:
-  1. K timed steps with the default launch table;
-  2. the autotuner (the paper's method): ~300 sampled launch vectors timed,
-     network trained on 75 %, whole space predicted on the GPU, top 8
-     re-measured; default / tuned / best-of-random compared interleaved;
-  3. K timed steps with the tuned launch table -> `value`;
-  4. per-kernel durations of the tuned step from HIP events the library
-     records around each launch on its own stream -> `roofline`;
-  5. adjoint vs primal cost on the 512^2 / 60-step adjoint workload;
-  6. the FP64 CPU oracle on the host cores for a bounded sample.
+`value` is the throughput of the fused path (one kernel per RK stage), which
+computes the same FP64 step as the tunable seven-kernel split path (both
+match the FP64 oracle to 1e-12 per step). The split path is reported beside
+it with the paper's method applied: default launch table vs the table chosen
+by the MLP autotuner (~300 timed samples, network trained on the GPU, whole
+space predicted, top 8 re-measured).
+
+Other legs (each reported in its own field):
+  split_3d  256^3 rotated Sod, split path, default vs tuned (x/y/z fluxes separately)
+  small     64^2 vortex: fused by direct launches vs graph-replayed batch of one
+  batch     96 uneven 2D grids, fused stages in a HIP graph, p50/p99 per-grid step time
+  adjoint   512^2 vortex, 60 steps, checkpoints every 10: adjoint / primal
+  copy      device-to-device copy bandwidth of a 2 GiB buffer (reference)
+  cpu_baseline  the FP64 oracle on the host cores, bounded sample
+
 Prints ONE JSON line on stdout; progress goes to stderr.
-
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--samples N] [--no-cpu] [--no-tune]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--samples N] [--quick] [--no-cpu] ...
 """
 from __future__ import annotations
 
@@ -27,6 +31,7 @@ import sys
 import time
 
 HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 METRIC = "cell-updates/s + HBM GB/s vs peak, tuned vs default launch; adjoint/primal"
 
 
@@ -39,22 +44,28 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=2048, help="cells per side")
+    ap.add_argument("--n", type=int, default=2048, help="cells per side of the headline grid")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--samples", type=int, default=300, help="timed launch vectors for the tuner")
+    ap.add_argument("--samples", type=int, default=300, help="timed launch vectors for the 2D tuner")
+    ap.add_argument("--samples-3d", type=int, default=150, help="timed launch vectors for the 3D tuner")
+    ap.add_argument("--quick", action="store_true", help="headline and split default only")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-fused", action="store_true", help="skip the fused single-grid and batch measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--launch", type=str, default=None, help="14 launch parameters as a JSON list (skips tuning)")
     ap.add_argument("--timing-steps", type=int, default=20)
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.quick:
+        a.no_tune = a.no_3d = a.no_batch = a.no_adjoint = a.no_cpu = True
+    return a
 
 
-def timed_steps(torch, solver, U0, launch, steps, warmup):
+def timed_steps(torch, solver, U0, steps, warmup, launch=None):
     """ms per step over `steps` steps from U0 (inputs resident in HBM)."""
-    solver.set_launch(launch)
+    if launch is not None:
+        solver.set_launch(launch)
     solver.set_state(U0)
     solver.step(warmup)
     solver.set_state(U0)
@@ -73,8 +84,8 @@ def timed_steps(torch, solver, U0, launch, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def kernel_table(solver, g, launch, steps, fv, traffic):
-    solver.set_launch(launch)
+def site_table(solver, g, steps, fv, traffic):
+    """Per-kernel durations from the library's HIP events (its own stream)."""
     solver.set_timing(True)
     solver.step(steps)
     ms, cnt = solver.get_timing()
@@ -82,21 +93,184 @@ def kernel_table(solver, g, launch, steps, fv, traffic):
     sb = traffic.site_bytes(g)
     total = sum(ms)
     kernels = {}
-    for i, name in enumerate(fv.SITES):
+    for i, name in enumerate(fv.TIMERS):
         if cnt[i] == 0:
             continue
         avg_ms = ms[i] / cnt[i]
-        kernels[name] = {
-            "avg_us": round(avg_ms * 1e3, 3),
-            "launches_per_step": cnt[i] / steps,
-            "share": round(ms[i] / total, 4),
-            "alg_bytes": sb[name],
-            "achieved_GBps": round(sb[name] / (avg_ms * 1e-3) / 1e9, 1),
-        }
+        row = {"avg_us": round(avg_ms * 1e3, 3), "launches_per_step": cnt[i] / steps,
+               "share": round(ms[i] / total, 4)}
+        if name in sb:
+            row["alg_bytes"] = sb[name]
+            row["achieved_GBps"] = round(sb[name] / (avg_ms * 1e-3) / 1e9, 1)
+        kernels[name] = row
     return kernels
 
 
-def adjoint_ratio(torch, fv, inputs):
+def split_leg(torch, fv, traffic, g, U0, a, samples, tune_it):
+    """Split path: default launch, then the MLP-tuned launch (the paper's method)."""
+    s = fv.Solver(g)
+    default = fv.fv_default_launch()
+    ms_default = timed_steps(torch, s, U0, a.steps, a.warmup, default)
+    log(f"split {g.n[:g.ndim]} default launch: {ms_default:.4f} ms/step")
+    out = {"cells": g.ncells, "default_launch": default, "default_ms_per_step": ms_default,
+           "default_value": g.ncells / (ms_default * 1e-3)}
+    launch = default
+    if tune_it:
+        from paper_2306_14011_amd.autotune import Autotuner
+        t0 = time.perf_counter()
+        at = Autotuner(g, U0, seed=a.seed, repeats=3, warmup=3, min_ms=20.0)
+        tune = at.run(count=samples, k=8, rounds=5)
+        at.close()
+        tune["tuning_seconds"] = round(time.perf_counter() - t0, 1)
+        launch = tune["tuned_launch"]
+        ms_tuned = timed_steps(torch, s, U0, a.steps, a.warmup, launch)
+        out.update({"tuned_launch": launch, "tuned_ms_per_step": ms_tuned,
+                    "tuned_value": g.ncells / (ms_tuned * 1e-3),
+                    "tuned_over_default": round(ms_default / ms_tuned, 4),
+                    "autotune": {k: v for k, v in tune.items() if k != "top_pred"}})
+        log(f"split tuned in {tune['tuning_seconds']} s: {ms_tuned:.4f} ms/step, R2(test) {tune['r2_test']:.3f}, "
+            f"interleaved default/tuned {tune['factor_vs_default']:.3f}, best-random/tuned "
+            f"{tune['factor_vs_best_random']:.3f}")
+    s.set_launch(launch)
+    kernels = site_table(s, g, a.timing_steps, fv, traffic)
+    s.close()
+    dom = max(kernels, key=lambda k: kernels[k]["share"])
+    step_b = traffic.step_bytes(g)
+    best_ms = out.get("tuned_ms_per_step", ms_default)
+    out.update({
+        "kernels": kernels,
+        "alg_bytes_per_cell_update": step_b / g.ncells,
+        "step_effective_GBps": round(step_b / (best_ms * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": kernels[dom]["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(kernels[dom]["achieved_GBps"] / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": dom},
+    })
+    return out
+
+
+def fused_leg(torch, fv, traffic, g, U0, a):
+    """The fused path: segment heights swept, the fastest kept and timed."""
+    s = fv.Solver(g)
+    res = {}
+    for seg in (8, 16, 32):
+        s.set_path(fv.FV_PATH_FUSED, seg, 0)
+        res[seg] = timed_steps(torch, s, U0, max(a.steps // 4, 20), a.warmup)
+    seg = min(res, key=res.get)
+    s.set_path(fv.FV_PATH_FUSED, seg, 0)
+    ms = timed_steps(torch, s, U0, a.steps, a.warmup)
+    kernels = site_table(s, g, a.timing_steps, fv, traffic)
+    s.close()
+    k = kernels["fused"]
+    avg_s = k["avg_us"] * 1e-6
+    flops = traffic.fused_stage_flops(g)
+    stage_bytes = traffic.fused_step_bytes(g) / 3.0
+    k["alg_flops"] = flops
+    k["achieved_TFLOPs"] = round(flops / avg_s / 1e12, 2)
+    k["alg_bytes"] = stage_bytes
+    k["achieved_GBps"] = round(stage_bytes / avg_s / 1e9, 1)
+    return {
+        "ms_per_step": ms,
+        "value": g.ncells / (ms * 1e-3),
+        "seg": seg,
+        "ms_per_step_by_seg": {str(q): round(v, 4) for q, v in res.items()},
+        "kernels": kernels,
+        "alg_bytes_per_cell_update": traffic.fused_step_bytes(g) / g.ncells,
+        "roofline": {"bound": "alu", "achieved": k["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(k["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None, "kernel": "fused stage (k_fused2d)",
+                     "hbm_achieved_GBps": k["achieved_GBps"],
+                     "hbm_frac": round(k["achieved_GBps"] / HBM_PEAK_GBPS, 4)},
+    }
+
+
+def small_leg(torch, fv, inputs):
+    """64^2 vortex (launch-bound): split and fused by direct launches, fused as a
+    graph-replayed batch of one."""
+    g, U0 = inputs.vortex_case(64, seed=0)
+    out = {"workload": "64x64 periodic vortex, beta 5, CFL 0.5", "cells": g.ncells}
+    s = fv.Solver(g)
+    out["split_ms_per_step"] = timed_steps(torch, s, U0, 100, 10)
+    s.set_path(fv.FV_PATH_FUSED, 8, 0)
+    out["fused_ms_per_step"] = timed_steps(torch, s, U0, 100, 10)
+    s.close()
+    B = fv.Batch([g], seg=8)
+    B.set_states([U0])
+    B.step(10)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    B.step(100)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    B.close()
+    out["graph_ms_per_step"] = e0.elapsed_time(e1) / 100
+    for k in ("split", "fused", "graph"):
+        out[f"{k}_value"] = g.ncells / (out[f"{k}_ms_per_step"] * 1e-3)
+    return out
+
+
+def batch_leg(torch, fv, inputs, steps):
+    """96 uneven periodic vortex grids (sides 128..1024), fused stages in a HIP graph."""
+    import numpy as np
+    spec = inputs.batch_case(count=96, seed=0)
+    cells = sum(gg.ncells for gg in spec.grids)
+    best = None
+    stream = torch.cuda.current_stream()
+    for seg, order in ((8, 1), (16, 1), (16, 0)):
+        B = fv.Batch(spec.grids, seg=seg, order=order)
+        B.set_states(spec.states)
+        B.step(3)
+        torch.cuda.synchronize()
+        B.set_states(spec.states)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rc, flags = B.status()
+        if flags:
+            log(f"batch flags {flags}")
+        if best is None or ms < best[0]:
+            if best is not None:
+                best[3].close()
+            best = (ms, seg, order, B)
+        else:
+            B.close()
+    ms, seg, order, B = best
+    # device-clock record of 20 steps: per-grid step time = sum over stages of (last end - first start)
+    B.set_states(spec.states)
+    tpu = B.set_timing(20)
+    B.step(20)
+    torch.cuda.synchronize()
+    clk = B.clocks()
+    B.close()
+    per = (clk[..., 1] - clk[..., 0]).sum(axis=2) / tpu   # (steps, grids) microseconds
+    seq = 0.0
+    for gg, st in zip(spec.grids, spec.states):
+        s = fv.Solver(gg)
+        s.set_path(fv.FV_PATH_FUSED, seg, 0)
+        seq += timed_steps(torch, s, st, 5, 1)
+        s.close()
+    return {
+        "workload": "96 periodic 2D vortex grids, sides U{128..1024}, beta U[1,5], FP64, 3 fused stages per step in a HIP graph",
+        "cells": cells,
+        "ms_per_step": round(ms, 4),
+        "value": cells / (ms * 1e-3),
+        "unit": "cell-updates/s",
+        "seg": seg,
+        "order": "largest_first" if order == 1 else "given",
+        "per_grid_step_us_p50": round(float(np.percentile(per, 50)), 2),
+        "per_grid_step_us_p99": round(float(np.percentile(per, 99)), 2),
+        "sequential_single_grid_ms_per_step": round(seq, 4),
+        "batch_speedup_vs_sequential": round(seq / ms, 3),
+    }
+
+
+def adjoint_leg(torch, fv, inputs):
     """fv_adjoint_step / fv_step per step, and the checkpointed reverse / forward,
     on the 512^2 vortex, 60 steps, checkpoints every 10."""
     from paper_2306_14011_amd.rollout import pressure_integral, rollout
@@ -151,90 +325,24 @@ def adjoint_ratio(torch, fv, inputs):
     }
 
 
-def fused_single(torch, fv, traffic, g, U0, steps, warmup):
-    """The fused path on the same grid: segment heights swept, best kept."""
-    s = fv.Solver(g)
-    res = {}
-    for seg in (8, 16, 32, 64):
-        s.set_path(fv.FV_PATH_FUSED, seg, 0)
-        res[seg] = timed_steps(torch, s, U0, fv.fv_default_launch(), steps, warmup)
-    seg = min(res, key=res.get)
-    s.set_path(fv.FV_PATH_FUSED, seg, 0)
-    s.set_timing(True)
-    s.step(20)
-    ms, cnt = s.get_timing()
-    s.set_timing(False)
-    s.close()
-    avg_ms = ms[7] / cnt[7]
-    alg = traffic.fused_step_bytes(g) / 3.0   # per stage launch, averaged over the three
-    return {
-        "ms_per_step": res[seg],
-        "value": g.ncells / (res[seg] * 1e-3),
-        "seg": seg,
-        "ms_per_step_by_seg": {str(k): round(v, 4) for k, v in res.items()},
-        "stage_avg_us": round(avg_ms * 1e3, 2),
-        "stage_alg_bytes": alg,
-        "stage_achieved_GBps": round(alg / (avg_ms * 1e-3) / 1e9, 1),
-        "alg_bytes_per_cell_update": traffic.fused_step_bytes(g) / g.ncells,
-    }
-
-
-def batch_bench(torch, fv, inputs, steps):
-    """96 uneven periodic vortex grids (sides 128..1024), fused stages in a HIP graph."""
-    spec = inputs.batch_case(count=96, seed=0)
-    cells = sum(gg.ncells for gg in spec.grids)
-    best = None
-    for seg, order in ((16, 1), (32, 1), (16, 0)):
-        B = fv.Batch(spec.grids, seg=seg, order=order)
-        B.set_states(spec.states)
-        B.step(3)
-        torch.cuda.synchronize()
-        B.set_states(spec.states)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        stream = torch.cuda.current_stream()
-        e0.record(stream)
-        B.step(steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        rc, flags = B.status()
-        if flags:
-            log(f"batch flags {flags}")
-        if best is None or ms < best[0]:
-            best = (ms, seg, order, B)
-        else:
-            B.close()
-    ms, seg, order, B = best
-    # device-clock record of 20 steps: per-grid step time = sum over stages of (last end - first start)
-    B.set_states(spec.states)
-    tpu = B.set_timing(20)
-    B.step(20)
+def copy_leg(torch):
+    """Device-to-device copy of a 2 GiB buffer: bytes read + written per second."""
+    n = (2 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
     torch.cuda.synchronize()
-    clk = B.clocks()
-    B.close()
-    per = (clk[..., 1] - clk[..., 0]).sum(axis=2) / tpu   # (steps, grids) microseconds
-    import numpy as np
-    # sequential baseline: each grid alone through the single-grid fused path
-    seq = 0.0
-    for gg, st in zip(spec.grids, spec.states):
-        s = fv.Solver(gg)
-        s.set_path(fv.FV_PATH_FUSED, 16, 0)
-        seq += timed_steps(torch, s, st, fv.fv_default_launch(), 5, 1)
-        s.close()
-    return {
-        "workload": "96 periodic 2D vortex grids, sides U{128..1024}, beta U[1,5], FP64, 3 fused stages per step in a HIP graph",
-        "cells": cells,
-        "ms_per_step": round(ms, 4),
-        "value": cells / (ms * 1e-3),
-        "unit": "cell-updates/s",
-        "seg": seg,
-        "order": "largest_first" if order == 1 else "given",
-        "per_grid_step_us_p50": round(float(np.percentile(per, 50)), 2),
-        "per_grid_step_us_p99": round(float(np.percentile(per, 99)), 2),
-        "sequential_single_grid_ms_per_step": round(seq, 4),
-        "batch_speedup_vs_sequential": round(seq / ms, 3),
-    }
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        y.copy_(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del x, y
+    return {"bytes": 2 * n * 8, "ms": round(ms, 4), "GBps": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(g, U0, seconds):
@@ -271,80 +379,48 @@ def main():
 
     g, U0 = inputs.vortex_bumps_case(a.n, seed=a.seed)
     log(f"workload {a.n}x{a.n} vortex+bumps, steps {a.steps}, warmup {a.warmup}")
-    default = fv.fv_default_launch()
-    s = fv.Solver(g)
-    ms_default = timed_steps(torch, s, U0, default, a.steps, a.warmup)
-    log(f"default launch: {ms_default:.4f} ms/step")
+    fused = fused_leg(torch, fv, traffic, g, U0, a)
+    log(f"fused path: {fused['ms_per_step']:.4f} ms/step (seg {fused['seg']}), "
+        f"{fused['value']:.3e} cell-updates/s")
+    split = split_leg(torch, fv, traffic, g, U0, a, a.samples, not a.no_tune)
 
-    tune = None
-    launch = default
-    if a.launch:
-        launch = json.loads(a.launch)
-    elif not a.no_tune:
-        from paper_2306_14011_amd.autotune import Autotuner
-        t0 = time.perf_counter()
-        at = Autotuner(g, U0, seed=a.seed, repeats=3, warmup=3, min_ms=20.0)
-        tune = at.run(count=a.samples, k=8, rounds=5)
-        at.close()
-        tune["tuning_seconds"] = round(time.perf_counter() - t0, 1)
-        launch = tune["tuned_launch"]
-        log(f"tuned in {tune['tuning_seconds']} s: R2(test) {tune['r2_test']:.3f}, "
-            f"default/tuned {tune['factor_vs_default']:.3f}, best-random/tuned {tune['factor_vs_best_random']:.3f}")
-
-    ms_tuned = timed_steps(torch, s, U0, launch, a.steps, a.warmup)
-    value = g.ncells / (ms_tuned * 1e-3)
-    log(f"tuned launch {launch}: {ms_tuned:.4f} ms/step")
-
-    kernels = kernel_table(s, g, launch, a.timing_steps, fv, traffic)
-    dom = max(kernels, key=lambda k: kernels[k]["share"])
-    ach = kernels[dom]["achieved_GBps"]
-    roofline = {
-        "bound": "hbm",
-        "achieved": ach,
-        "peak": HBM_PEAK_GBPS,
-        "unit": "GB/s",
-        "frac": round(ach / HBM_PEAK_GBPS, 4),
-        "traffic": None,
-        "kernel": dom,
-    }
-    step_b = traffic.step_bytes(g)
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": fused["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_tuned,
+        "ms_per_step": fused["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"2D Euler {a.n}x{a.n} periodic vortex + 32 Gaussian bumps, MUSCL-minmod/Roe/SSP-RK3, CFL 0.5",
+            "workload": f"2D Euler {a.n}x{a.n} periodic vortex + 32 Gaussian bumps, MUSCL-minmod/Roe/SSP-RK3, "
+                        f"CFL 0.5, {a.steps} steps",
             "cells": g.ncells,
-            "path": "split 7-kernel step, MLP-tuned launch" if tune else "split 7-kernel step",
-            "launch": launch,
+            "path": f"fused (one kernel per RK stage, seg {fused['seg']})",
         },
-        "roofline": roofline,
-        "default_launch": {"launch": default, "ms_per_step": ms_default,
-                           "value": g.ncells / (ms_default * 1e-3)},
-        "tuned_over_default": round(ms_default / ms_tuned, 4),
-        "step_effective_GBps": round(step_b * value / g.ncells / 1e9, 1),
-        "alg_bytes_per_cell_update": step_b / g.ncells,
-        "kernels": kernels,
+        "roofline": fused["roofline"],
+        "fused": fused,
+        "split": split,
+        "tuned_over_default": split.get("tuned_over_default"),
     }
-    if tune:
-        out["autotune"] = {k: v for k, v in tune.items() if k not in ("top_pred",)}
-    s.close()
-    if not a.no_fused:
-        out["fused"] = fused_single(torch, fv, traffic, g, U0, a.steps, a.warmup)
-        log(f"fused path: {out['fused']['ms_per_step']:.4f} ms/step (seg {out['fused']['seg']})")
-        out["batch"] = batch_bench(torch, fv, inputs, 100)
+    if not a.no_3d:
+        g3, U3 = inputs.sod3d_case(256, seed=a.seed)
+        out["split_3d"] = split_leg(torch, fv, traffic, g3, U3, argparse.Namespace(
+            steps=20, warmup=2, timing_steps=5, seed=a.seed), a.samples_3d, not a.no_tune)
+        del U3
+    out["copy"] = copy_leg(torch)
+    if not a.quick:
+        out["small"] = small_leg(torch, fv, inputs)
+    if not a.no_batch:
+        out["batch"] = batch_leg(torch, fv, inputs, 100)
         log(f"batch: {out['batch']['value']:.3e} cell-updates/s")
     if not a.no_adjoint:
-        out["adjoint"] = adjoint_ratio(torch, fv, inputs)
+        out["adjoint"] = adjoint_leg(torch, fv, inputs)
         log(f"adjoint/primal per step {out['adjoint']['adjoint_over_primal_step']}")
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, U0, a.cpu_seconds)

@@ -52,6 +52,34 @@ struct Geo {
     int unlimited;      // 1: Psi = 1 (no limiter)
 };
 
+// 1/a and 1/sqrt(a) for the flux arithmetic: the hardware estimates
+// (v_rcp_f64, v_rsq_f64) refined by two Newton-Raphson steps each, which
+// brings them to within about one ulp of the correctly rounded results for
+// the normal, positive arguments the Euler fluxes produce.
+__host__ __device__ __forceinline__ double rcp_nr(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double x = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-a, x, 1.0);
+    return fma(x, e, x);
+#else
+    return 1.0 / a;
+#endif
+}
+
+__host__ __device__ __forceinline__ double rsqrt_nr(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(a);
+    double e = fma(-a * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+#else
+    return 1.0 / sqrt(a);
+#endif
+}
+
 // minmod(a, b): zero unless a and b share a strict sign, else the one of smaller
 // magnitude. Sign tests, not a*b > 0, so tiny slopes do not underflow to a tie.
 __host__ __device__ __forceinline__ double minmod(double a, double b) {
@@ -86,9 +114,10 @@ __host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, 
 template <int NDIM, int AX>
 __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, double gm1, double* F) {
     constexpr int IE = NDIM + 1;
-    // left / right primitive states
+    // left / right primitive states; rho^(-1/2) gives both sqrt(rho) and 1/rho
     const double rL = qL[0], rR = qR[0];
-    const double irL = 1.0 / rL, irR = 1.0 / rR;
+    const double rsL = rsqrt_nr(rL), rsR = rsqrt_nr(rR);
+    const double irL = rsL * rsL, irR = rsR * rsR;
     double uL[NDIM], uR[NDIM];
     double qqL = 0.0, qqR = 0.0;
 #pragma unroll
@@ -105,8 +134,8 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
     const double vnL = uL[AX], vnR = uR[AX];
 
     // Roe averages with weights sqrt(rho) / (sqrt(rhoL) + sqrt(rhoR))
-    const double sL = sqrt(rL), sR = sqrt(rR);
-    const double iw = 1.0 / (sL + sR);
+    const double sL = rL * rsL, sR = rR * rsR;
+    const double iw = rcp_nr(sL + sR);
     const double wL = sL * iw, wR = sR * iw;
     double ut[NDIM];
     double qqt = 0.0;
@@ -118,8 +147,9 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
     const double Ht = wL * HL + wR * HR;
     const double rt = sL * sR;
     const double c2 = gm1 * (Ht - 0.5 * qqt);
-    const double c = sqrt(c2);
-    const double ic2 = 1.0 / c2;
+    const double rc = rsqrt_nr(c2);
+    const double c = c2 * rc;
+    const double ic2 = rc * rc;
     const double un = ut[AX];
 
     // wave strengths
@@ -254,7 +284,8 @@ __host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const do
     constexpr int IE = NDIM + 1;
     // ---- forward recomputation (as in roe_flux) ----
     const double rL = qL[0], rR = qR[0];
-    const double irL = 1.0 / rL, irR = 1.0 / rR;
+    const double rsL = rsqrt_nr(rL), rsR = rsqrt_nr(rR);
+    const double irL = rsL * rsL, irR = rsR * rsR;
     double uL[NDIM], uR[NDIM];
     double qqL = 0.0, qqR = 0.0;
     for (int d = 0; d < NDIM; ++d) {
@@ -269,8 +300,8 @@ __host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const do
     const double HL = (EL + pL) * irL;
     const double HR = (ER + pR) * irR;
     const double vnL = uL[AX], vnR = uR[AX];
-    const double sL = sqrt(rL), sR = sqrt(rR);
-    const double iw = 1.0 / (sL + sR);
+    const double sL = rL * rsL, sR = rR * rsR;
+    const double iw = rcp_nr(sL + sR);
     const double wL = sL * iw, wR = sR * iw;
     double ut[NDIM];
     double qqt = 0.0;
@@ -281,8 +312,9 @@ __host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const do
     const double Ht = wL * HL + wR * HR;
     const double rt = sL * sR;
     const double c2 = gm1 * (Ht - 0.5 * qqt);
-    const double c = sqrt(c2);
-    const double ic2 = 1.0 / c2;
+    const double rc = rsqrt_nr(c2);
+    const double c = c2 * rc;
+    const double ic2 = rc * rc;
     const double un = ut[AX];
     const double dp = pR - pL;
     const double dun = vnR - vnL;
@@ -403,7 +435,7 @@ __host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const do
     pRb += dpb;
     pLb -= dpb;
     // ic2 = 1/c2; c = sqrt(c2); c2 = gm1 (Ht - qqt/2)
-    double c2b = -ic2b * ic2 * ic2 + cb * 0.5 / c;
+    double c2b = -ic2b * ic2 * ic2 + cb * 0.5 * rc;
     Htb += gm1 * c2b;
     qqtb -= 0.5 * gm1 * c2b;
     // rt = sL sR
@@ -427,8 +459,8 @@ __host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const do
     const double sumb = -iwb * iw * iw;
     sLb += sumb;
     sRb += sumb;
-    rLb += sLb * 0.5 / sL;
-    rRb += sRb * 0.5 / sR;
+    rLb += sLb * 0.5 * rsL;
+    rRb += sRb * 0.5 * rsR;
     // per side: H = (E + p) ir; p = gm1 (E - r qq / 2); qq = sum u^2; u = m ir; ir = 1/r
     {
         double irb = HLb * (EL + pL);

@@ -95,16 +95,39 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         double Fyb[NV];
         double lmax = 0.0;
         uint32_t fl = 0;
+        // software pipeline: the next row of U_s and the U^n value of the next
+        // finalised row are requested one iteration ahead of their use
+        double Wn[NV], Unc[NV], Unn[NV];
+        {
+            const int rmap = map_index(r0 - 2, G.ny, G.bcy0, G.bcy1);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Wn[v] = Usg[v * G.sv + (long long)rmap * G.pitch];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Unc[v] = Unn[v] = 0.0;
 #pragma unroll 1
         for (int t = 0; t < SEG + 4; ++t) {
             const int row = r0 - 2 + t;
-            const int rmap = map_index(row < G.ny + 2 ? row : G.ny - 1, G.ny, G.bcy0, G.bcy1);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 W[0][v] = W[1][v];
                 W[1][v] = W[2][v];
                 W[2][v] = W[3][v];
-                W[3][v] = Usg[v * G.sv + (long long)rmap * G.pitch];
+                W[3][v] = Wn[v];
+                Unc[v] = Unn[v];
+            }
+            if (t + 1 < SEG + 4) {
+                const int nrow = row + 1;
+                const int rmap = map_index(nrow < G.ny + 2 ? nrow : G.ny - 1, G.ny, G.bcy0, G.bcy1);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Wn[v] = Usg[v * G.sv + (long long)rmap * G.pitch];
+            }
+            if (STAGE > 0 && t >= 3 && t + 1 < SEG + 4) {
+                // U^n of the row finalised in the next iteration (row - 1), clamped inside the grid
+                const int fr = row - 1 < G.ny ? row - 1 : G.ny - 1;
+                const long long pn = G.base + (long long)fr * G.pitch + (out_lane ? col : 0);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Unn[v] = Un[v * G.sv + pn];
             }
             if (t < 3) continue;
             // y face between rows row-2 and row-1 (stencil rows row-3 .. row)
@@ -138,9 +161,9 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
                         if (STAGE == 0) {
                             out[v] = W[1][v] + s * r;
                         } else if (STAGE == 1) {
-                            out[v] = 0.75 * Un[v * G.sv + p] + 0.25 * (W[1][v] + s * r);
+                            out[v] = 0.75 * Unc[v] + 0.25 * (W[1][v] + s * r);
                         } else {
-                            out[v] = (1.0 / 3.0) * Un[v * G.sv + p] + (2.0 / 3.0) * (W[1][v] + s * r);
+                            out[v] = (1.0 / 3.0) * Unc[v] + (2.0 / 3.0) * (W[1][v] + s * r);
                         }
                         Ud[v * G.sv + p] = out[v];
                     }

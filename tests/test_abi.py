@@ -101,3 +101,19 @@ def test_oracle_and_product_share_nothing():
         text = open(path).read()
         assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), path
         assert "liboracle" not in text and "fv_oracle" not in text, path
+
+
+def test_batch_query_offsets_and_validation():
+    grids = [inputs.grid2d(30, 20), inputs.grid2d(7, 1, bc=((1, 1), (0, 0))), inputs.grid2d(128, 64)]
+    offs, ws = fv.fv_batch_query(grids)
+    assert offs == [0, 4 * 600, 4 * 600 + 4 * 7, 4 * 600 + 28 + 4 * 128 * 64]
+    assert ws > 2 * 8 * offs[-1]   # two stage states plus tables
+    with pytest.raises(fv.FvError) as e:
+        fv.fv_batch_query([inputs.grid2d(8, 8), inputs.grid3d(4, 4, 4)])
+    assert e.value.code == fv.FV_ENOTSUP
+    bad = inputs.grid2d(8, 8)
+    bad.cfl = -1.0
+    with pytest.raises(fv.FvError) as e:
+        fv.fv_batch_query([bad])
+    assert e.value.code == fv.FV_EINVAL
+
