@@ -123,6 +123,7 @@ struct fv_batch {
     hipGraphExec_t exec;
     double* graph_U;
     bool graph_timed;
+    unsigned long long* graph_history;  // history buffer baked into the captured graph
     unsigned long long* history;
     int max_steps;
     char err[256];
@@ -141,6 +142,7 @@ static void drop_graph(fv_batch* b) {
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_U = nullptr;
+    b->graph_history = nullptr;
 }
 
 // Enqueues one step (three stages, plus the clock record when timing) on s.
@@ -256,7 +258,7 @@ int fv_batch_step(fv_batch* b, double* U, int32_t nsteps) {
     if (!U || nsteps < 0) return bfail(b, FV_EINVAL, "null state or negative step count");
     if (nsteps == 0) return FV_OK;
     const bool timed = b->history != nullptr;
-    if (b->graph_U != U || !b->exec || b->graph_timed != timed) {
+    if (b->graph_U != U || !b->exec || b->graph_timed != timed || b->graph_history != b->history) {
         drop_graph(b);
         hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
@@ -270,6 +272,7 @@ int fv_batch_step(fv_batch* b, double* U, int32_t nsteps) {
         }
         b->graph_U = U;
         b->graph_timed = timed;
+        b->graph_history = b->history;
     }
     fvk::launch_fused_init(b->seg, b->waves, b->grids, b->ngrids, b->nitems, U, b->lam, b->status, nullptr, b->stream);
     for (int32_t s = 0; s < nsteps; ++s) {

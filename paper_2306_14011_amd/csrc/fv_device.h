@@ -204,7 +204,7 @@ __host__ __device__ __forceinline__ double cell_lambda(const double* q, double g
                                                        uint32_t& fl) {
     constexpr int IE = NDIM + 1;
     const double rho = q[0];
-    const double ir = 1.0 / rho;
+    const double ir = rcp_nr(rho);
     double u[NDIM];
     double qq = 0.0;
     for (int d = 0; d < NDIM; ++d) {
@@ -212,7 +212,9 @@ __host__ __device__ __forceinline__ double cell_lambda(const double* q, double g
         qq += u[d] * u[d];
     }
     const double p = gm1 * (q[IE] - 0.5 * rho * qq);
-    const double c = sqrt(gamma * p * ir);
+    // c = sqrt(c^2) as c^2 * (c^2)^(-1/2); a negative c^2 gives NaN, as sqrt does
+    const double c2 = gamma * p * ir;
+    const double c = c2 * rsqrt_nr(c2);
     double lam = 0.0;
     for (int d = 0; d < NDIM; ++d) lam += (fabs(u[d]) + c) * inv_dx[d];
     if (isnan(lam) || isnan(rho) || isnan(p)) fl |= 1u;

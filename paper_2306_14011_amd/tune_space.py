@@ -7,11 +7,17 @@ take two CDNA launch parameters:
   * stencil sites (flux x/y/z): block width along x in {16, ..., 256} and
     threads per block in {64, ..., 1024}, width <= threads: 22 pairs;
   * one-dimensional sites (residual, update, bc, cfl): gang (blocks of a
-    grid-stride loop) in {256, 512, 1024, 2048} and threads per block in
-    {64, ..., 1024}: 20 pairs.
+    grid-stride loop) in {512, 2048, 8192, 32768} or 0 (one thread per
+    element, as many blocks as that takes) and threads per block in
+    {64, ..., 1024}: 25 pairs.
 In 2D the z-flux site is pinned to one pair, so the space has
-22^2 * 20^4 = 7.74e7 points; in 3D 22^3 * 20^4 = 1.70e9.
+22^2 * 25^4 = 1.89e8 points; in 3D 22^3 * 25^4 = 4.16e9. The default launch
+table (stencil (64, 256), one-dimensional (0, 256)) is a point of the space.
 Indices are mixed radix with site 0 fastest.
+
+Network features are log2 of the 14 parameters; a gang of 0 (one thread per
+element: more blocks than any finite choice) is encoded as 2^17, one octave
+above the largest finite gang.
 """
 from __future__ import annotations
 
@@ -21,7 +27,8 @@ import numpy as np
 
 THREADS = (64, 128, 256, 512, 1024)
 STENCIL_WIDTHS = (16, 32, 64, 128, 256)
-GANGS = (256, 512, 1024, 2048)
+GANGS = (512, 2048, 8192, 32768, 0)
+GANG_AUTO_FEATURE = 2 ** 17
 STENCIL_PAIRS = tuple((w, t) for w in STENCIL_WIDTHS for t in THREADS if w <= t)
 GANG_PAIRS = tuple((g, t) for g in GANGS for t in THREADS)
 PINNED_FLUX_Z = ((64, 256),)
@@ -69,15 +76,23 @@ class LaunchSpace:
         return out
 
     @staticmethod
+    def encode_params(vecs):
+        """Launch vectors with gang 0 replaced by its feature value 2^17."""
+        P = np.asarray(vecs, dtype=np.float64).copy()
+        P[P == 0] = GANG_AUTO_FEATURE
+        return P
+
+    @staticmethod
     def raw_features(vecs):
-        """log2 of the 14 launch parameters (all powers of two), one row per vector."""
-        return np.log2(np.asarray(vecs, dtype=np.float64))
+        """log2 of the 14 (encoded) launch parameters, one row per vector."""
+        return np.log2(LaunchSpace.encode_params(vecs))
 
     def tables(self, mean, std):
         """Standardised feature value of every choice: (f1, f2) per site, lists."""
         f1, f2 = [], []
         for s in range(NSITES):
-            f1.append([(math.log2(a) - mean[2 * s]) / std[2 * s] for a, _ in self.choices[s]])
+            f1.append([(math.log2(a if a else GANG_AUTO_FEATURE) - mean[2 * s]) / std[2 * s]
+                       for a, _ in self.choices[s]])
             f2.append([(math.log2(b) - mean[2 * s + 1]) / std[2 * s + 1] for _, b in self.choices[s]])
         return f1, f2
 

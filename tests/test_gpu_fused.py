@@ -182,6 +182,16 @@ def test_batch_clock_history():
     B.close()
     assert tpu > 0
     assert clk.shape == (5, 6, 3, 2)
+    # a new history buffer is honoured (the captured graph is rebuilt)
+    B2 = fv.Batch(spec.grids, seg=16)
+    B2.set_states(spec.states)
+    B2.set_timing(2)
+    B2.step(2)
+    first = B2.history
+    B2.set_timing(3)
+    B2.step(3)
+    assert B2.history is not first and np.all(B2.clocks()[:, :, :, 1] > 0)
+    B2.close()
     assert np.all(clk[..., 1] >= clk[..., 0]) and np.all(clk[..., 0] > 0)
     # stages of a grid run in order
     assert np.all(clk[:, :, 1, 0] >= clk[:, :, 0, 0])

@@ -81,7 +81,7 @@ def test_sweep_topk_matches_brute_force():
     sp = LaunchSpace(2)
     rng = np.random.default_rng(8)
     train_idx = sp.sample(200, 3)
-    F = np.log2(np.asarray([sp.decode(i) for i in train_idx], dtype=float))
+    F = LaunchSpace.raw_features([sp.decode(i) for i in train_idx])
     mean, std = mlp.standard_scaler(F)
     N = net(9)
     theta = N.params.cpu().numpy().astype(np.float64)
@@ -114,7 +114,7 @@ def test_sweep_topk_matches_brute_force():
 
 def synthetic_cost(sp, vecs, rng=None, noise=0.02):
     """Separable quadratic in log2 P plus two pairwise terms (sites 3-4 and 5-6)."""
-    L = np.log2(np.asarray(vecs, dtype=float))
+    L = LaunchSpace.raw_features(vecs)
     opt = np.array([5, 8, 6, 8, 6, 8, 11, 9, 9, 7, 10, 8, 8, 9], dtype=float)
     w = np.array([0.3, 0.2, 0.25, 0.15, 0.0, 0.0, 0.1, 0.2, 0.15, 0.1, 0.05, 0.05, 0.1, 0.1])
     c = 1.0 + (w * (L - opt) ** 2).sum(axis=1)
@@ -131,7 +131,7 @@ def test_tuner_finds_known_optimum_and_beats_random():
     vecs = [sp.decode(i) for i in idx]
     t = synthetic_cost(sp, vecs, rng)
     tr = np.arange(225)
-    F = np.log2(np.asarray(vecs, dtype=float))
+    F = LaunchSpace.raw_features(vecs)
     mean, std = mlp.standard_scaler(F[tr])
     scale = np.median(t[tr])
     X = (F - mean) / std
@@ -189,5 +189,5 @@ def test_end_to_end_tuning_on_a_small_grid():
     at.close()
     assert res["n_samples"] == 40 and res["n_valid"] == 40
     assert res["n_train"] == 30 and res["n_test"] == 10
-    assert res["space_size"] == 77_440_000
+    assert res["space_size"] == 189_062_500
     assert res["tuned_ms"] > 0 and res["default_ms"] > 0

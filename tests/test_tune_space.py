@@ -7,10 +7,18 @@ from paper_2306_14011_amd.tune_space import GANG_PAIRS, STENCIL_PAIRS, LaunchSpa
 
 
 def test_pair_counts_and_space_sizes():
-    assert len(STENCIL_PAIRS) == 22 and len(GANG_PAIRS) == 20
+    assert len(STENCIL_PAIRS) == 22 and len(GANG_PAIRS) == 25
     assert all(w <= t for w, t in STENCIL_PAIRS)
-    assert LaunchSpace(2).size == 22 ** 2 * 20 ** 4 == 77_440_000
-    assert LaunchSpace(3).size == 22 ** 3 * 20 ** 4 == 1_703_680_000
+    assert LaunchSpace(2).size == 22 ** 2 * 25 ** 4 == 189_062_500
+    assert LaunchSpace(3).size == 22 ** 3 * 25 ** 4 == 4_159_375_000
+
+
+def test_default_launch_is_in_the_space():
+    from paper_2306_14011_amd import fv
+    d = fv.fv_default_launch()
+    for nd in (2, 3):
+        sp = LaunchSpace(nd)
+        assert sp.decode(sp.encode(d)) == d
 
 
 @pytest.mark.parametrize("ndim", [2, 3])
@@ -33,9 +41,12 @@ def test_feature_tables_match_direct_features():
     rng = np.random.default_rng(1)
     idx = [int(i) for i in rng.integers(0, sp.size, 200)]
     vecs = [sp.decode(i) for i in idx]
-    mean, std = mlp.standard_scaler(np.log2(np.asarray(vecs, dtype=float)))
+    # gang 0 (one thread per element) is encoded as 2^17 before the log
+    enc = np.asarray(vecs, dtype=float)
+    enc[enc == 0] = 2.0 ** 17
+    mean, std = mlp.standard_scaler(np.log2(enc))
     f1, f2 = sp.tables(mean, std)
-    direct = mlp.features(vecs, mean, std)
+    direct = mlp.features(enc, mean, std)
     for row, i in zip(direct, idx):
         d = mlp.decode(i, sp.radix)
         tab = []
