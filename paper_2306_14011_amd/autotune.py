@@ -137,7 +137,7 @@ class Autotuner:
         import torch
         self.torch = torch
         self.spec = spec
-        self.space = LaunchSpace(spec.ndim)
+        self.space = LaunchSpace.for_grid(spec)
         self.solver = fv.Solver(spec)
         self.U0 = U0
         self.seed = seed
@@ -221,7 +221,7 @@ class Autotuner:
     def fit(self, samples):
         good = [s for s in samples if s.valid and np.isfinite(s.ms)]
         tr, te = split_indices(len(good), self.seed)
-        F = LaunchSpace.raw_features([s.launch for s in good])
+        F = self.space.features([s.index for s in good])
         t = np.array([s.ms for s in good])
         scale = float(np.median(t[tr]))
         # runtime relative to the training median (O(1) targets, as the

@@ -6,18 +6,20 @@ kernels (Sec. "Tuning Parameters", Table tuning-parameters: 10 gang values x
 take two CDNA launch parameters:
   * stencil sites (flux x/y/z): block width along x in {16, ..., 256} and
     threads per block in {64, ..., 1024}, width <= threads: 22 pairs;
-  * one-dimensional sites (residual, update, bc, cfl): gang (blocks of a
-    grid-stride loop) in {512, 2048, 8192, 32768} or 0 (one thread per
-    element, as many blocks as that takes) and threads per block in
-    {64, ..., 1024}: 25 pairs.
+  * one-dimensional sites (residual, update, bc, cfl): threads per block t in
+    {64, ..., 1024} and elements per thread e in {1, 2, 4, 8, 16}: 25 pairs.
+    e = 1 is the launch with one thread per element (gang 0); otherwise the
+    gang is the power of two nearest to N / (t e) for the site's element
+    count N (cells, or ghost cells for the fill), clamped to [1, 65536], and
+    the kernel runs a grid-stride loop. The gang is thus relative to the
+    problem size, as the paper's gang range was relative to its grid.
 In 2D the z-flux site is pinned to one pair, so the space has
 22^2 * 25^4 = 1.89e8 points; in 3D 22^3 * 25^4 = 4.16e9. The default launch
 table (stencil (64, 256), one-dimensional (0, 256)) is a point of the space.
 Indices are mixed radix with site 0 fastest.
 
-Network features are log2 of the 14 parameters; a gang of 0 (one thread per
-element: more blocks than any finite choice) is encoded as 2^17, one octave
-above the largest finite gang.
+Network features per site: log2 of (block width, threads) for stencil sites
+and log2 of (elements per thread, threads) for one-dimensional sites.
 """
 from __future__ import annotations
 
@@ -27,34 +29,73 @@ import numpy as np
 
 THREADS = (64, 128, 256, 512, 1024)
 STENCIL_WIDTHS = (16, 32, 64, 128, 256)
-GANGS = (512, 2048, 8192, 32768, 0)
-GANG_AUTO_FEATURE = 2 ** 17
+ELEMS_PER_THREAD = (1, 2, 4, 8, 16)
 STENCIL_PAIRS = tuple((w, t) for w in STENCIL_WIDTHS for t in THREADS if w <= t)
-GANG_PAIRS = tuple((g, t) for g in GANGS for t in THREADS)
 PINNED_FLUX_Z = ((64, 256),)
 NSITES = 7
+ONE_D_SITES = (3, 4, 5, 6)   # residual, update, bc, cfl
+
+
+def gang_for(n_elements: int, threads: int, e: int) -> int:
+    """Blocks of a grid-stride launch giving about e elements per thread (0 for e = 1)."""
+    if e == 1:
+        return 0
+    g = max(1.0, n_elements / float(threads * e))
+    return int(min(65536, max(1, 2 ** int(round(math.log2(g))))))
+
+
+def site_elements(spec):
+    """Element counts of the one-dimensional sites: residual, update, bc, cfl."""
+    nx, ny, nz = (int(v) for v in spec.n)
+    ncell = nx * ny * nz
+    ghosts = 4 * ny * nz + 4 * nx * nz + (4 * nx * ny if spec.ndim == 3 else 0)
+    return {3: ncell, 4: ncell, 5: ghosts, 6: ncell}
 
 
 class LaunchSpace:
-    def __init__(self, ndim: int):
+    def __init__(self, ndim: int, counts=None):
+        """counts: element count per one-dimensional site (defaults to a 2048^2 grid)."""
         self.ndim = ndim
-        self.choices = [STENCIL_PAIRS, STENCIL_PAIRS, STENCIL_PAIRS if ndim == 3 else PINNED_FLUX_Z,
-                        GANG_PAIRS, GANG_PAIRS, GANG_PAIRS, GANG_PAIRS]
+        if counts is None:
+            counts = {3: 2048 * 2048, 4: 2048 * 2048, 5: 8 * 2048, 6: 2048 * 2048}
+        self.counts = dict(counts)
+        self.choices = []   # (p1, p2) launch parameters per choice
+        self.feats = []     # (f1, f2) raw network features per choice
+        for s in range(NSITES):
+            if s in ONE_D_SITES:
+                ch = [(gang_for(self.counts[s], t, e), t) for e in ELEMS_PER_THREAD for t in THREADS]
+                ft = [(math.log2(e), math.log2(t)) for e in ELEMS_PER_THREAD for t in THREADS]
+            else:
+                pairs = STENCIL_PAIRS if (s < 2 or ndim == 3) else PINNED_FLUX_Z
+                ch = list(pairs)
+                ft = [(math.log2(a), math.log2(b)) for a, b in pairs]
+            self.choices.append(ch)
+            self.feats.append(ft)
         self.radix = [len(c) for c in self.choices]
         self.size = int(np.prod([int(r) for r in self.radix], dtype=object))
 
-    def decode(self, idx: int):
-        """14-vector of launch parameters of index idx."""
+    @classmethod
+    def for_grid(cls, spec):
+        return cls(spec.ndim, site_elements(spec))
+
+    def digits(self, idx: int):
         if not 0 <= idx < self.size:
             raise ValueError("index outside the space")
         out = []
         for s in range(NSITES):
-            c = idx % self.radix[s]
+            out.append(idx % self.radix[s])
             idx //= self.radix[s]
+        return out
+
+    def decode(self, idx: int):
+        """14-vector of launch parameters of index idx."""
+        out = []
+        for s, c in enumerate(self.digits(idx)):
             out += list(self.choices[s][c])
         return out
 
     def encode(self, vec):
+        """Index of a launch vector (the first choice matching each pair)."""
         idx = 0
         mul = 1
         for s in range(NSITES):
@@ -75,25 +116,20 @@ class LaunchSpace:
                 out.append(i)
         return out
 
-    @staticmethod
-    def encode_params(vecs):
-        """Launch vectors with gang 0 replaced by its feature value 2^17."""
-        P = np.asarray(vecs, dtype=np.float64).copy()
-        P[P == 0] = GANG_AUTO_FEATURE
-        return P
-
-    @staticmethod
-    def raw_features(vecs):
-        """log2 of the 14 (encoded) launch parameters, one row per vector."""
-        return np.log2(LaunchSpace.encode_params(vecs))
+    def features(self, indices):
+        """Raw (unscaled) network features of the given indices, one row each."""
+        X = np.zeros((len(indices), 2 * NSITES))
+        for r, idx in enumerate(indices):
+            for s, c in enumerate(self.digits(int(idx))):
+                X[r, 2 * s], X[r, 2 * s + 1] = self.feats[s][c]
+        return X
 
     def tables(self, mean, std):
         """Standardised feature value of every choice: (f1, f2) per site, lists."""
         f1, f2 = [], []
         for s in range(NSITES):
-            f1.append([(math.log2(a if a else GANG_AUTO_FEATURE) - mean[2 * s]) / std[2 * s]
-                       for a, _ in self.choices[s]])
-            f2.append([(math.log2(b) - mean[2 * s + 1]) / std[2 * s + 1] for _, b in self.choices[s]])
+            f1.append([(a - mean[2 * s]) / std[2 * s] for a, _ in self.feats[s]])
+            f2.append([(b - mean[2 * s + 1]) / std[2 * s + 1] for _, b in self.feats[s]])
         return f1, f2
 
     def struct(self, mean, std):

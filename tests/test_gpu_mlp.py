@@ -81,7 +81,7 @@ def test_sweep_topk_matches_brute_force():
     sp = LaunchSpace(2)
     rng = np.random.default_rng(8)
     train_idx = sp.sample(200, 3)
-    F = LaunchSpace.raw_features([sp.decode(i) for i in train_idx])
+    F = sp.features(train_idx)
     mean, std = mlp.standard_scaler(F)
     N = net(9)
     theta = N.params.cpu().numpy().astype(np.float64)
@@ -112,10 +112,10 @@ def test_sweep_topk_matches_brute_force():
     assert abs(pred[ti[0] - begin] - pred[order[0]]) <= 2e-5 * scale
 
 
-def synthetic_cost(sp, vecs, rng=None, noise=0.02):
-    """Separable quadratic in log2 P plus two pairwise terms (sites 3-4 and 5-6)."""
-    L = LaunchSpace.raw_features(vecs)
-    opt = np.array([5, 8, 6, 8, 6, 8, 11, 9, 9, 7, 10, 8, 8, 9], dtype=float)
+def synthetic_cost(sp, idx, rng=None, noise=0.02):
+    """Separable quadratic in the raw features plus two pairwise terms (sites 3-4 and 5-6)."""
+    L = sp.features(idx)
+    opt = np.array([5, 8, 6, 8, 6, 8, 1, 9, 2, 7, 0, 8, 3, 9], dtype=float)
     w = np.array([0.3, 0.2, 0.25, 0.15, 0.0, 0.0, 0.1, 0.2, 0.15, 0.1, 0.05, 0.05, 0.1, 0.1])
     c = 1.0 + (w * (L - opt) ** 2).sum(axis=1)
     c += 0.05 * (L[:, 6] - L[:, 8]) ** 2 + 0.04 * (L[:, 11] - L[:, 13]) ** 2
@@ -128,10 +128,9 @@ def test_tuner_finds_known_optimum_and_beats_random():
     sp = LaunchSpace(2)
     rng = np.random.default_rng(11)
     idx = sp.sample(300, 21)
-    vecs = [sp.decode(i) for i in idx]
-    t = synthetic_cost(sp, vecs, rng)
+    t = synthetic_cost(sp, idx, rng)
     tr = np.arange(225)
-    F = LaunchSpace.raw_features(vecs)
+    F = sp.features(idx)
     mean, std = mlp.standard_scaler(F[tr])
     scale = np.median(t[tr])
     X = (F - mean) / std
@@ -141,16 +140,18 @@ def test_tuner_finds_known_optimum_and_beats_random():
     from paper_2306_14011_amd.autotune import r2_score
     r2 = r2_score(y[225:], N.predict(X[225:]))
     ti, tv = N.sweep(sp.struct(mean, std), 0, sp.size, 8)
-    cand = synthetic_cost(sp, [sp.decode(i) for i in ti])
+    cand = synthetic_cost(sp, ti)
     best_tuned = cand.min()
-    best_random = synthetic_cost(sp, vecs).min()
+    best_random = synthetic_cost(sp, idx).min()
     # true optimum: sites 0 and 1 are independent, sites (3, 4) and (5, 6) are
     # coupled pairwise and searched jointly, site 2 is pinned
     def cost_of(choice):
-        v = []
+        idx_ = 0
+        mul = 1
         for s in range(7):
-            v += list(sp.choices[s][choice[s]])
-        return v
+            idx_ += choice[s] * mul
+            mul *= sp.radix[s]
+        return idx_
     # independent sites: minimise one at a time from a fixed base
     choice = [0] * 7
     for s in (0, 1):

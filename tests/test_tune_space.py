@@ -3,14 +3,35 @@ import numpy as np
 import pytest
 
 from oracle import mlp
-from paper_2306_14011_amd.tune_space import GANG_PAIRS, STENCIL_PAIRS, LaunchSpace
+from paper_2306_14011_amd import inputs
+from paper_2306_14011_amd.tune_space import STENCIL_PAIRS, LaunchSpace, gang_for, site_elements
 
 
 def test_pair_counts_and_space_sizes():
-    assert len(STENCIL_PAIRS) == 22 and len(GANG_PAIRS) == 25
+    assert len(STENCIL_PAIRS) == 22
     assert all(w <= t for w, t in STENCIL_PAIRS)
     assert LaunchSpace(2).size == 22 ** 2 * 25 ** 4 == 189_062_500
     assert LaunchSpace(3).size == 22 ** 3 * 25 ** 4 == 4_159_375_000
+
+
+def test_gang_is_relative_to_the_problem_size():
+    # about e elements per thread: gang * threads * e ~ N, rounded to a power of two
+    assert gang_for(2048 * 2048, 256, 1) == 0
+    assert gang_for(2048 * 2048, 256, 4) == 4096
+    assert gang_for(256 ** 3, 1024, 2) == 8192
+    assert gang_for(10, 1024, 16) == 1
+    assert gang_for(1 << 30, 64, 2) == 65536
+    g = inputs.grid3d(256, 256, 256)
+    counts = site_elements(g)
+    assert counts[3] == 256 ** 3 and counts[5] == 3 * 4 * 256 * 256
+    sp = LaunchSpace.for_grid(g)
+    for s in (3, 4, 5, 6):
+        for (gang, t), (le, lt) in zip(sp.choices[s], sp.feats[s]):
+            assert 2 ** lt == t
+            if le == 0:
+                assert gang == 0
+            else:
+                assert 0.5 <= counts[s] / (gang * t * 2 ** le) <= 2.0 or gang in (1, 65536)
 
 
 def test_default_launch_is_in_the_space():
@@ -40,13 +61,23 @@ def test_feature_tables_match_direct_features():
     sp = LaunchSpace(2)
     rng = np.random.default_rng(1)
     idx = [int(i) for i in rng.integers(0, sp.size, 200)]
-    vecs = [sp.decode(i) for i in idx]
-    # gang 0 (one thread per element) is encoded as 2^17 before the log
-    enc = np.asarray(vecs, dtype=float)
-    enc[enc == 0] = 2.0 ** 17
-    mean, std = mlp.standard_scaler(np.log2(enc))
+    # raw features are log2 of (width, threads) / (elements per thread, threads)
+    F = sp.features(idx)
+    raw = []
+    for i in idx:
+        d = mlp.decode(i, sp.radix)
+        row = []
+        for s in range(7):
+            a, b = sp.choices[s][d[s]]
+            if s >= 3:
+                e = 2 ** sp.feats[s][d[s]][0]
+                row += [e, b]
+            else:
+                row += [a, b]
+        raw.append(row)
+    mean, std = mlp.standard_scaler(F)
     f1, f2 = sp.tables(mean, std)
-    direct = mlp.features(enc, mean, std)
+    direct = mlp.features(raw, mean, std)
     for row, i in zip(direct, idx):
         d = mlp.decode(i, sp.radix)
         tab = []
