@@ -179,7 +179,9 @@ def fused_leg(torch, fv, traffic, g, U0, a):
     """The fused path: segment heights swept, the fastest kept and timed."""
     s = fv.Solver(g)
     res = {}
-    for seg in (8, 16, 32):
+    s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    auto_seg = s.get_path()[1]
+    for seg in sorted({auto_seg, 8, 12, 16, 20, 24, 32}):
         s.set_path(fv.FV_PATH_FUSED, seg, 0)
         res[seg] = timed_steps(torch, s, U0, max(a.steps // 4, 20), a.warmup)
     seg = min(res, key=res.get)
@@ -199,6 +201,7 @@ def fused_leg(torch, fv, traffic, g, U0, a):
         "ms_per_step": ms,
         "value": g.ncells / (ms * 1e-3),
         "seg": seg,
+        "auto_seg": auto_seg,
         "ms_per_step_by_seg": {str(q): round(v, 4) for q, v in res.items()},
         "kernels": kernels,
         "alg_bytes_per_cell_update": traffic.fused_step_bytes(g) / g.ncells,
@@ -217,10 +220,10 @@ def small_leg(torch, fv, inputs):
     out = {"workload": "64x64 periodic vortex, beta 5, CFL 0.5", "cells": g.ncells}
     s = fv.Solver(g)
     out["split_ms_per_step"] = timed_steps(torch, s, U0, 100, 10)
-    s.set_path(fv.FV_PATH_FUSED, 8, 0)
+    s.set_path(fv.FV_PATH_FUSED, 0, 0)
     out["fused_ms_per_step"] = timed_steps(torch, s, U0, 100, 10)
     s.close()
-    B = fv.Batch([g], seg=8)
+    B = fv.Batch([g], seg=0)
     B.set_states([U0])
     B.step(10)
     torch.cuda.synchronize()
@@ -245,8 +248,9 @@ def batch_leg(torch, fv, inputs, steps):
     cells = sum(gg.ncells for gg in spec.grids)
     best = None
     stream = torch.cuda.current_stream()
-    for seg, order in ((8, 1), (16, 1), (16, 0)):
+    for seg, order in ((0, 1), (0, 0), (16, 1), (32, 1)):
         B = fv.Batch(spec.grids, seg=seg, order=order)
+        seg = B.info()[0]
         B.set_states(spec.states)
         B.step(3)
         torch.cuda.synchronize()
@@ -279,7 +283,7 @@ def batch_leg(torch, fv, inputs, steps):
     seq = 0.0
     for gg, st in zip(spec.grids, spec.states):
         s = fv.Solver(gg)
-        s.set_path(fv.FV_PATH_FUSED, seg, 0)
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
         seq += timed_steps(torch, s, st, 5, 1)
         s.close()
     return {

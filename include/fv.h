@@ -170,13 +170,21 @@ int fv_clear_status(fv_ctx* ctx);
  * stage that does the ghost mapping, both flux axes, the residual and the
  * stage update, and the last stage also the CFL max of the new state; the
  * state then moves through HBM 8 times per step instead of ~33. `seg` is the
- * segment height of a work item (8, 16, 32 or 64 rows; a work item is a
- * 60-column strip of it, one wavefront each) and `waves` the number of
- * wavefronts launched (0 = one per work item, else a grid-stride loop over
- * the items). Both paths compute the same cell arithmetic; fv_residual and
- * fv_adjoint_step always use the split kernels. Returns FV_ENOTSUP for 3D. */
+ * segment height of a work item in rows, a multiple of 4 in [4, 1024], or 0
+ * to let the library choose it from the grid and the number of wavefronts the
+ * device holds at once (a work item is a 60-column strip of a segment, one
+ * wavefront each); `waves` is the number of wavefronts launched (0 = one per
+ * work item, else a grid-stride loop over the items). Every segment height
+ * and wave count gives bitwise the same result. Both paths compute the same
+ * cell arithmetic; fv_residual and fv_adjoint_step always use the split
+ * kernels. Returns FV_ENOTSUP for 3D and FV_EINVAL for other seg values. */
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
+
+/* Reads back the path, the segment height in use (the library's choice when
+ * fv_set_path was given 0; 0 on the split path) and the wave count. Outputs
+ * may be NULL. */
+int fv_get_path(const fv_ctx* ctx, int32_t* path, int32_t* seg, int32_t* waves);
 
 /* Per-site kernel timing, a diagnostic for profiling and the autotuner's
  * measurements. When enabled, every kernel launch of fv_step / fv_residual /
@@ -213,10 +221,11 @@ enum { FV_ORDER_GIVEN = 0, FV_ORDER_LARGEST_FIRST = 1 };
  * grid (offsets[0..ngrids], host array, may be NULL) and the workspace size. */
 int fv_batch_query(int32_t ngrids, const fv_grid_desc* grids, int64_t* offsets, size_t* workspace_bytes);
 
-/* Creates a batch. seg: 8, 16, 32 or 64; waves: wavefronts per stage launch
- * (0 = one per work item, else a grid-stride loop); order: FV_ORDER_* of the
- * grids in the work list. The workspace (queried size, 256-byte aligned) is
- * owned by the caller. */
+/* Creates a batch. seg: segment height, a multiple of 4 in [4, 1024], or 0
+ * for the library's choice over all grids of the batch; waves: wavefronts per
+ * stage launch (0 = one per work item, else a grid-stride loop); order:
+ * FV_ORDER_* of the grids in the work list. The workspace (queried size,
+ * 256-byte aligned) is owned by the caller. */
 int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int32_t waves, int32_t order,
                     void* workspace, size_t workspace_bytes, void* stream, fv_batch** out);
 
@@ -237,6 +246,10 @@ int fv_batch_dt(fv_batch* b, double* dt);
 
 /* Synchronises the stream and reads the batch status word (FV_FLAG_*). */
 int fv_batch_status(fv_batch* b, uint32_t* flags);
+
+/* The segment height in use (the library's choice when created with 0) and
+ * the number of work items of one stage launch. Outputs may be NULL. */
+int fv_batch_info(const fv_batch* b, int32_t* seg, int32_t* nitems);
 
 int fv_batch_destroy(fv_batch* b);
 

@@ -442,7 +442,8 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
     if (c->g.ndim != 2) return fail(c, FV_ENOTSUP, "the fused path is 2D only%s");
-    if (seg != 8 && seg != 16 && seg != 32 && seg != 64) return fail(c, FV_EINVAL, "seg must be 8, 16, 32 or 64%s");
+    if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
+        return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
     if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");
     fvk::FGrid& G = c->fgrid_host;
     memset(&G, 0, sizeof(G));
@@ -469,10 +470,19 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
     hipError_t e = hipMemcpyAsync(c->fgrid, &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
+    if (seg == 0) seg = fvk::fused_auto_seg(&G, 1, fvk::fused_slots());
     c->fseg = seg;
     c->fwaves = waves;
     c->fitems = fvk::fused_items(G, seg);
     c->path = FV_PATH_FUSED;
+    return FV_OK;
+}
+
+int fv_get_path(const fv_ctx* c, int32_t* path, int32_t* seg, int32_t* waves) {
+    if (!c) return FV_EINVAL;
+    if (path) *path = c->path;
+    if (seg) *seg = c->path == FV_PATH_FUSED ? c->fseg : 0;
+    if (waves) *waves = c->path == FV_PATH_FUSED ? c->fwaves : 0;
     return FV_OK;
 }
 

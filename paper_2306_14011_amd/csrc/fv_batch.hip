@@ -178,7 +178,8 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
     BLayout L;
     int rc = validate_batch(ngrids, grids, &L, g_berr);
     if (rc != FV_OK) return rc;
-    if (seg != 8 && seg != 16 && seg != 32 && seg != 64) return bfail(nullptr, FV_EINVAL, "seg must be 8, 16, 32 or 64");
+    if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
+        return bfail(nullptr, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]");
     if (waves < 0) return bfail(nullptr, FV_EINVAL, "negative wave count");
     if (order != FV_ORDER_GIVEN && order != FV_ORDER_LARGEST_FIRST) return bfail(nullptr, FV_EINVAL, "unknown order");
     if (!workspace || ((uintptr_t)workspace & 255)) return bfail(nullptr, FV_EWORKSPACE, "workspace missing or misaligned");
@@ -217,7 +218,6 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
         G.ny = (int)d.n[1];
         G.pitch = G.nx;
         G.strips = fvk::fused_strips(G.nx);
-        G.work0 = work;
         G.unlimited = d.scheme == FV_SCHEME_UNLIMITED;
         G.bcx0 = d.bc[0][0];
         G.bcx1 = d.bc[0][1];
@@ -236,7 +236,12 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
         G.cfl = d.cfl;
         G.gamma = d.gamma;
         G.gm1 = d.gamma - 1.0;
-        work += fvk::fused_items(G, seg);
+    }
+    if (seg == 0) seg = fvk::fused_auto_seg(b->host_grids.data(), ngrids, fvk::fused_slots());
+    b->seg = seg;
+    for (int q = 0; q < ngrids; ++q) {
+        b->host_grids[q].work0 = work;
+        work += fvk::fused_items(b->host_grids[q], seg);
     }
     b->nitems = work;
     hipError_t e = hipMemcpyAsync(b->grids, b->host_grids.data(), sizeof(fvk::FGrid) * ngrids,
@@ -313,6 +318,13 @@ int fv_batch_status(fv_batch* b, uint32_t* flags) {
     if (e != hipSuccess) return bfail(b, FV_EDEVICE, "status read failed");
     if (flags) *flags = h;
     return h ? FV_ENONPHYS : FV_OK;
+}
+
+int fv_batch_info(const fv_batch* b, int32_t* seg, int32_t* nitems) {
+    if (!b) return FV_EINVAL;
+    if (seg) *seg = b->seg;
+    if (nitems) *nitems = b->nitems;
+    return FV_OK;
 }
 
 int fv_batch_destroy(fv_batch* b) {

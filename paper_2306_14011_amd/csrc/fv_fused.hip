@@ -2,8 +2,8 @@
 // the ghost mapping, MUSCL-minmod + Roe fluxes on both axes, the residual and
 // the stage combination, and the last stage also the CFL max of the new state.
 //
-// Work decomposition: a work item is a 60-column strip x SEG-row segment of
-// one grid; one wavefront (64 lanes) owns an item. Lane l holds column
+// Work decomposition: a work item is a 60-column strip x seg-row segment of
+// one grid (seg a multiple of 4); one wavefront (64 lanes) owns an item. Lane l holds column
 // x0 + l, x0 = 60*strip - 2, so lanes 2..61 produce the 60 output columns and
 // lanes 0, 1, 62, 63 carry the x halo. The wave marches up the segment one row
 // at a time, keeping the last four rows in registers: that window gives the
@@ -25,10 +25,15 @@ namespace fvk {
 
 constexpr int FW = 60;  // output columns per wave
 
+// Index i of a cell within two of the axis (-2 <= i <= n + 1) mapped through
+// the boundary kinds (0 periodic wrap, else transmissive clamp); anything
+// beyond n + 1 maps to n - 1. Selects only, no division: for n >= 2 a wrap
+// shifts by one period, and for n = 1 every index maps to 0.
 __device__ __forceinline__ int map_index(int i, int n, int lo_kind, int hi_kind) {
-    if (i < 0) return lo_kind == 0 ? ((i % n) + n) % n : 0;
-    if (i >= n) return hi_kind == 0 ? i % n : n - 1;
-    return i;
+    const int lo = lo_kind == 0 ? i + n : 0;
+    const int hi = i > n + 1 ? n - 1 : (hi_kind == 0 ? i - n : n - 1);
+    const int m = i < 0 ? lo : (i >= n ? hi : i);
+    return n == 1 ? 0 : m;
 }
 
 // Grid of the work item (uniform): largest g with work0 <= item.
@@ -54,8 +59,17 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
     return v;
 }
 
-template <int STAGE, int SEG>
-__global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems,
+// Element at a wave-uniform base plus a per-lane 32-bit byte offset.
+__device__ __forceinline__ double ld_lane(const double* base, uint32_t boff) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
+}
+
+__device__ __forceinline__ void st_lane(double* base, uint32_t boff, double x) {
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + boff) = x;
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems, int seg,
                                                  const double* Un, const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                  const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
@@ -73,7 +87,7 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         const FGrid G = grids[gi];
         const int local = item - G.work0;
         const int strip = local % G.strips;
-        const int seg = local / G.strips;
+        const int sidx = local / G.strips;
         double dt;
         if (STAGE == 0) {
             dt = dt_fixed ? dt_fixed[G.gid] : G.cfl / __longlong_as_double((long long)lam[G.gid]);
@@ -87,94 +101,105 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         }
         const double s = -dt * G.inv_vol;
         const int col = FW * strip - 2 + lane;
-        const int cmap = map_index(col < G.nx + 2 ? col : G.nx - 1, G.nx, G.bcx0, G.bcx1);
+        const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
         const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
-        const int r0 = seg * SEG;
-        const double* Usg = Us + G.base + cmap;
+        const int r0 = sidx * seg;
+        const double* Usg = Us + G.base;
+        const uint32_t cboff = (uint32_t)cmap * 8u;  // this lane's column in bytes
+        // row offset of U_s row r through the y boundary map (rows past the
+        // last halo row are clamped inside the grid; they feed no output)
+        auto row_off = [&](int r) -> long long {
+            return (long long)map_index(r, G.ny, G.bcy0, G.bcy1) * G.pitch;
+        };
+        // Circular window of four U_s rows: row r sits in slot (r - r0 + 2) & 3.
+        // The loop visits the y faces f = 0 .. seg of the segment (face f lies
+        // between rows r0 + f - 1 and r0 + f) in unrolled groups of four, so
+        // every slot index is a compile-time constant and the window never
+        // moves between registers. Face f is always computed by unrolled copy
+        // f mod 4, and since r0 is a multiple of 4 a given face of the grid
+        // gets the same machine code (and bits) whatever the segment height.
         double W[4][NV];
-        double Fyb[NV];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long o = row_off(r0 - 2 + k);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) W[k][v] = ld_lane(Usg + v * G.sv + o, cboff);
+        }
+        double Fy[2][NV];   // y-face fluxes: face f in Fy[f & 1]
+        double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
+        const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column in bytes
         double lmax = 0.0;
         uint32_t fl = 0;
-        // software pipeline: the next row of U_s and the U^n value of the next
-        // finalised row are requested one iteration ahead of their use
-        double Wn[NV], Unc[NV], Unn[NV];
-        {
-            const int rmap = map_index(r0 - 2, G.ny, G.bcy0, G.bcy1);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Wn[v] = Usg[v * G.sv + (long long)rmap * G.pitch];
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Unc[v] = Unn[v] = 0.0;
 #pragma unroll 1
-        for (int t = 0; t < SEG + 4; ++t) {
-            const int row = r0 - 2 + t;
+        for (int m0 = 0; m0 <= seg; m0 += 4) {
+            if (r0 + m0 - 1 >= G.ny) break;  // ragged last segment (uniform)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                W[0][v] = W[1][v];
-                W[1][v] = W[2][v];
-                W[2][v] = W[3][v];
-                W[3][v] = Wn[v];
-                Unc[v] = Unn[v];
-            }
-            if (t + 1 < SEG + 4) {
-                const int nrow = row + 1;
-                const int rmap = map_index(nrow < G.ny + 2 ? nrow : G.ny - 1, G.ny, G.bcy0, G.bcy1);
+            for (int j = 0; j < 4; ++j) {
+                const int f = m0 + j;
+                if (f > seg) break;          // uniform: only in the last group
+                const bool more = f < seg;   // another face follows
+                const int rr = r0 + f - 1;   // output row finished at this face
+                if (STAGE > 0 && more) {
+                    // U^n of row rr + 1, used at face f + 1
+                    const int fr = rr + 1 < G.ny ? rr + 1 : G.ny - 1;
+                    const long long pn = G.base + (long long)fr * G.pitch;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) Wn[v] = Usg[v * G.sv + (long long)rmap * G.pitch];
-            }
-            if (STAGE > 0 && t >= 3 && t + 1 < SEG + 4) {
-                // U^n of the row finalised in the next iteration (row - 1), clamped inside the grid
-                const int fr = row - 1 < G.ny ? row - 1 : G.ny - 1;
-                const long long pn = G.base + (long long)fr * G.pitch + (out_lane ? col : 0);
+                    for (int v = 0; v < NV; ++v) Unb[(j + 1) & 1][v] = ld_lane(Un + v * G.sv + pn, oboff);
+                }
+                double qL[NV], qR[NV];
+                // y face f: stencil rows rr-1 .. rr+2 in slots j, j+1, j+2, j+3 (mod 4)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) Unn[v] = Un[v * G.sv + pn];
-            }
-            if (t < 3) continue;
-            // y face between rows row-2 and row-1 (stencil rows row-3 .. row)
-            double qL[NV], qR[NV], Fyt[NV];
+                for (int v = 0; v < NV; ++v)
+                    muscl(W[j][v], W[(j + 1) & 3][v], W[(j + 2) & 3][v], W[(j + 3) & 3][v], G.unlimited, qL[v],
+                          qR[v]);
+                roe_flux<2, 1>(qL, qR, G.gm1, Fy[j & 1]);
+                double c[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) muscl(W[0][v], W[1][v], W[2][v], W[3][v], G.unlimited, qL[v], qR[v]);
-            roe_flux<2, 1>(qL, qR, G.gm1, Fyt);
-            if (t >= 4) {
-                // finalise cell row rr = row - 2 (held in W[1])
-                const int rr = row - 2;
-                double Fxl[NV];
+                for (int v = 0; v < NV; ++v) c[v] = W[(j + 1) & 3][v];
+                // row rr - 1 is dead: its slot takes row rr + 3 for face f + 1
+                if (more) {
+                    const long long o = row_off(rr + 3);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) W[j][v] = ld_lane(Usg + v * G.sv + o, cboff);
+                }
+                if (f == 0) continue;  // uniform: the first face has no row below it in the segment
+                // x faces of row rr: left face from the lanes to the left, right face one lane up
+                double Fxl[NV], Fxr[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double c1 = W[1][v];
-                    const double a = __shfl_up(c1, 2, 64);
-                    const double b = __shfl_up(c1, 1, 64);
-                    const double d = __shfl_down(c1, 1, 64);
-                    muscl(a, b, c1, d, G.unlimited, qL[v], qR[v]);
+                    const double a = __shfl_up(c[v], 2, 64);
+                    const double b = __shfl_up(c[v], 1, 64);
+                    const double d = __shfl_down(c[v], 1, 64);
+                    muscl(a, b, c[v], d, G.unlimited, qL[v], qR[v]);
                 }
                 roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
-                double Fxr[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Fxr[v] = __shfl_down(Fxl[v], 1, 64);
                 if (out_lane && rr < G.ny) {
-                    const long long p = G.base + (long long)rr * G.pitch + col;
+                    const long long p = G.base + (long long)rr * G.pitch;
                     double out[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         double r = (Fxr[v] - Fxl[v]) * G.ax;
-                        r += (Fyt[v] - Fyb[v]) * G.ay;
+                        r += (Fy[j & 1][v] - Fy[(j + 1) & 1][v]) * G.ay;
                         if (STAGE == 0) {
-                            out[v] = W[1][v] + s * r;
+                            out[v] = c[v] + s * r;
                         } else if (STAGE == 1) {
-                            out[v] = 0.75 * Unc[v] + 0.25 * (W[1][v] + s * r);
+                            out[v] = 0.75 * Unb[j & 1][v] + 0.25 * (c[v] + s * r);
                         } else {
-                            out[v] = (1.0 / 3.0) * Unc[v] + (2.0 / 3.0) * (W[1][v] + s * r);
+                            out[v] = (1.0 / 3.0) * Unb[j & 1][v] + (2.0 / 3.0) * (c[v] + s * r);
                         }
-                        Ud[v * G.sv + p] = out[v];
+                        st_lane(Ud + v * G.sv + p, oboff, out[v]);
                     }
                     if (STAGE == 2) {
                         const double idx[2] = {G.inv_dx, G.inv_dy};
                         lmax = fmax(lmax, cell_lambda<2>(out, G.gamma, G.gm1, idx, fl));
                     }
                 }
+                // keep the scheduler from overlapping consecutive rows, which
+                // would raise the live register count beyond 128
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Fyb[v] = Fyt[v];
         }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
@@ -193,8 +218,7 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
 }
 
 // lambda_max of U^n per grid (the first step's dt), same work items.
-template <int SEG>
-__global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ grids, int ngrids, int nitems,
+__global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ grids, int ngrids, int nitems, int seg,
                                                       const double* __restrict__ U, unsigned long long* __restrict__ lam,
                                                       uint32_t* __restrict__ status) {
     const int lane = threadIdx.x & 63;
@@ -205,13 +229,13 @@ __global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ 
         const FGrid G = grids[gi];
         const int local = item - G.work0;
         const int strip = local % G.strips;
-        const int seg = local / G.strips;
+        const int sidx = local / G.strips;
         const int col = FW * strip + lane;
         double lmax = 0.0;
         uint32_t fl = 0;
         if (lane < FW && col < G.nx) {
             const double idx[2] = {G.inv_dx, G.inv_dy};
-            for (int rr = seg * SEG; rr < seg * SEG + SEG && rr < G.ny; ++rr) {
+            for (int rr = sidx * seg; rr < sidx * seg + seg && rr < G.ny; ++rr) {
                 const long long p = G.base + (long long)rr * G.pitch + col;
                 double q[4];
 #pragma unroll
@@ -251,39 +275,62 @@ static inline int fused_blocks(int nitems, int waves) {
     return (w + 3) / 4;
 }
 
-#define FV_SEG_DISPATCH(SEGV, MACRO)         \
-    switch (SEGV) {                          \
-        case 8: MACRO(8); break;             \
-        case 32: MACRO(32); break;           \
-        case 64: MACRO(64); break;           \
-        default: MACRO(16); break;           \
-    }
-
 void launch_fused_stage(int stage, int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s) {
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
-#define FV_LFS(SV)                                                                                               \
-    if (stage == 0)                                                                                              \
-        hipLaunchKernelGGL((k_fused2d<0, SV>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,   \
-                           dt_fixed, dt_out, status, clk);                                                       \
-    else if (stage == 1)                                                                                         \
-        hipLaunchKernelGGL((k_fused2d<1, SV>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,   \
-                           dt_fixed, dt_out, status, clk);                                                       \
-    else                                                                                                         \
-        hipLaunchKernelGGL((k_fused2d<2, SV>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,   \
+    if (stage == 0)
+        hipLaunchKernelGGL(k_fused2d<0>, grid, block, 0, s, grids, ngrids, nitems, seg, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk);
-    FV_SEG_DISPATCH(seg, FV_LFS)
-#undef FV_LFS
+    else if (stage == 1)
+        hipLaunchKernelGGL(k_fused2d<1>, grid, block, 0, s, grids, ngrids, nitems, seg, Un, Us, Ud, lam, dtg,
+                           dt_fixed, dt_out, status, clk);
+    else
+        hipLaunchKernelGGL(k_fused2d<2>, grid, block, 0, s, grids, ngrids, nitems, seg, Un, Us, Ud, lam, dtg,
+                           dt_fixed, dt_out, status, clk);
 }
 
 void launch_fused_init(int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s) {
     hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(256), 0, s, lam, ngrids, clk);
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
-#define FV_LFL(SV) hipLaunchKernelGGL((k_fused_lambda<SV>), grid, block, 0, s, grids, ngrids, nitems, U, lam, status);
-    FV_SEG_DISPATCH(seg, FV_LFL)
-#undef FV_LFL
+    hipLaunchKernelGGL(k_fused_lambda, grid, block, 0, s, grids, ngrids, nitems, seg, U, lam, status);
+}
+
+// Waves of the stage kernels that are resident on the current device at once:
+// blocks per CU (the least over the three stages) x 4 waves x CUs.
+int fused_slots() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    int b0 = 0, b1 = 0, b2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused2d<0>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused2d<1>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused2d<2>, 256, 0) != hipSuccess)
+        return 0;
+    const int b = b0 < b1 ? (b0 < b2 ? b0 : b2) : (b1 < b2 ? b1 : b2);
+    return b * 4 * cus;
+}
+
+// Segment height for a set of grids: the multiple of 4 that minimises
+// (rounds of resident waves) x (rows per item + 1), the item's critical path
+// in rows (one extra y face per item). Ties go to the taller segment, which
+// re-reads fewer halo rows.
+int fused_auto_seg(const FGrid* grids, int ngrids, int slots) {
+    if (slots <= 0) return 16;
+    int best = 16;
+    double best_cost = 0.0;
+    for (int seg = 4; seg <= 256; seg += 4) {
+        long long items = 0;
+        for (int g = 0; g < ngrids; ++g) items += (long long)fused_items(grids[g], seg);
+        const long long rounds = (items + slots - 1) / slots;
+        const double cost = (double)rounds * (seg + 1);
+        if (seg == 4 || cost <= best_cost) {
+            best_cost = cost;
+            best = seg;
+        }
+    }
+    return best;
 }
 
 }  // namespace fvk

@@ -34,6 +34,8 @@ void launch_fused_stage(int stage, int seg, int waves, const FGrid* grids, int n
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s);
 void launch_fused_init(int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s);
+int fused_slots();
+int fused_auto_seg(const FGrid* grids, int ngrids, int slots);
 
 // adjoint
 void launch_adj_flux(int ax, const double* U, const double* w, double* G, const Geo& g, hipStream_t s);

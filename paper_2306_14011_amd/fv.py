@@ -128,6 +128,8 @@ def lib():
         L.fv_clear_status.argtypes = [_vp]
         L.fv_set_timing.argtypes = [_vp, ctypes.c_int]
         L.fv_set_path.argtypes = [_vp, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]
+        L.fv_get_path.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]
         L.fv_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fv_last_error.argtypes = [_vp]
         L.fv_last_error.restype = ctypes.c_char_p
@@ -139,6 +141,7 @@ def lib():
         L.fv_batch_set_timing.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         L.fv_batch_dt.argtypes = [_vp, _vp]
         L.fv_batch_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.fv_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.fv_batch_destroy.argtypes = [_vp]
         L.fv_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_sweep_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
@@ -151,8 +154,8 @@ def lib():
                                    ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
                      "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
-                     "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_batch_query", "fv_batch_create",
-                     "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_destroy",
+                     "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_batch_query", "fv_batch_create",
+                     "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_destroy",
                      "fv_mlp_workspace", "fv_mlp_sweep_workspace",
                      "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep"):
             getattr(L, name).restype = ctypes.c_int
@@ -252,8 +255,15 @@ def fv_clear_status(ctx):
     return _check(lib().fv_clear_status(_vp(ctx)), ctx)
 
 
-def fv_set_path(ctx, path, seg=16, waves=0):
+def fv_set_path(ctx, path, seg=0, waves=0):
     return _check(lib().fv_set_path(_vp(ctx), int(path), int(seg), int(waves)), ctx)
+
+
+def fv_get_path(ctx):
+    """(path, segment height in use, waves)."""
+    p, sg, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().fv_get_path(_vp(ctx), ctypes.byref(p), ctypes.byref(sg), ctypes.byref(w)), ctx)
+    return p.value, sg.value, w.value
 
 
 def fv_set_timing(ctx, enable):
@@ -326,6 +336,13 @@ def fv_batch_status(b):
     if rc not in (FV_OK, FV_ENONPHYS):
         _batch_check(rc)
     return rc, fl.value
+
+
+def fv_batch_info(b):
+    """(segment height in use, work items per stage launch)."""
+    sg, n = ctypes.c_int32(), ctypes.c_int32()
+    _batch_check(lib().fv_batch_info(_vp(b), ctypes.byref(sg), ctypes.byref(n)))
+    return sg.value, n.value
 
 
 def fv_batch_destroy(b):
@@ -462,8 +479,12 @@ class Solver:
     def status(self):
         return fv_status(self.ctx)
 
-    def set_path(self, path, seg=16, waves=0):
+    def set_path(self, path, seg=0, waves=0):
+        """seg 0 lets the library choose the segment height (see get_path)."""
         fv_set_path(self.ctx, path, seg, waves)
+
+    def get_path(self):
+        return fv_get_path(self.ctx)
 
     def set_timing(self, enable):
         fv_set_timing(self.ctx, enable)
@@ -481,7 +502,7 @@ class Batch:
     ``U`` holds grid g's dense (4, ny, nx) state at [offsets[g], offsets[g+1]).
     """
 
-    def __init__(self, specs, seg=16, waves=0, order=FV_ORDER_GIVEN, device="cuda"):
+    def __init__(self, specs, seg=0, waves=0, order=FV_ORDER_GIVEN, device="cuda"):
         torch = _torch()
         self.specs = list(specs)
         self.device = torch.device(device)
@@ -527,6 +548,10 @@ class Batch:
         out = torch.zeros(len(self.specs), dtype=torch.float64, device=self.device)
         fv_batch_dt(self.b, out.data_ptr())
         return out.cpu().numpy()
+
+    def info(self):
+        """(segment height in use, work items per stage launch)."""
+        return fv_batch_info(self.b)
 
     def status(self):
         return fv_batch_status(self.b)

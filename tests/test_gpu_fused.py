@@ -90,9 +90,26 @@ def test_fused_frozen_dt_and_unlimited():
 def test_fused_schedules_bitwise_equal():
     g, U0 = inputs.vortex_bumps_case(190, seed=5)
     base, _, _ = run_fused(g, U0, 3, seg=16, waves=0)
-    for seg, waves in ((8, 0), (32, 0), (64, 0), (16, 7), (8, 64), (32, 1000)):
+    for seg, waves in ((8, 0), (32, 0), (64, 0), (16, 7), (8, 64), (32, 1000), (4, 0), (12, 0), (20, 5),
+                       (196, 0), (0, 0)):
         got, _, _ = run_fused(g, U0, 3, seg=seg, waves=waves)
         assert np.array_equal(got, base), (seg, waves)
+
+
+def test_fused_segment_choice_and_rejection():
+    fv = _fv()
+    g, U0 = inputs.vortex_bumps_case(2048, seed=0)
+    s = fv.Solver(g)
+    s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    path, seg, waves = s.get_path()
+    assert path == fv.FV_PATH_FUSED and seg % 4 == 0 and 4 <= seg <= 256 and waves == 0
+    for bad in (2, 6, 1028, -4):
+        with pytest.raises(fv.FvError):
+            s.set_path(fv.FV_PATH_FUSED, bad, 0)
+    assert s.get_path() == (path, seg, waves)  # a rejected call keeps the previous setting
+    s.set_path(fv.FV_PATH_SPLIT)
+    assert s.get_path()[0] == fv.FV_PATH_SPLIT
+    s.close()
 
 
 def test_fused_full_size_one_step():
@@ -151,7 +168,8 @@ def test_batch_schedules_and_graph_replays_bitwise_equal():
         return out
 
     base = run(16, 0, 0, [4])
-    for args in ((8, 0, 1, [4]), (64, 0, 0, [4]), (16, 40, 1, [4]), (32, 3, 0, [1, 1, 2]), (16, 0, 0, [2, 2])):
+    for args in ((8, 0, 1, [4]), (64, 0, 0, [4]), (16, 40, 1, [4]), (32, 3, 0, [1, 1, 2]), (16, 0, 0, [2, 2]),
+                 (0, 0, 1, [4]), (28, 0, 0, [3, 1])):
         got = run(*args)
         for g in range(len(base)):
             assert np.array_equal(got[g], base[g]), (args, g)

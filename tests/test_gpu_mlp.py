@@ -124,6 +124,34 @@ def synthetic_cost(sp, idx, rng=None, noise=0.02):
     return c
 
 
+def synthetic_optimum(sp):
+    """Exact minimum of synthetic_cost over the space: sites 0 and 1 are
+    independent, sites (3, 4) and (5, 6) are coupled pairwise and searched
+    jointly, site 2 is pinned."""
+    def index_of(choice):
+        idx_ = 0
+        mul = 1
+        for s in range(7):
+            idx_ += choice[s] * mul
+            mul *= sp.radix[s]
+        return idx_
+    choice = [0] * 7
+    for s in (0, 1):
+        cs = [synthetic_cost(sp, [index_of(choice[:s] + [c] + choice[s + 1:])])[0] for c in range(sp.radix[s])]
+        choice[s] = int(np.argmin(cs))
+    for s1, s2 in ((3, 4), (5, 6)):
+        best_c, best_v = None, np.inf
+        for c1 in range(sp.radix[s1]):
+            for c2 in range(sp.radix[s2]):
+                ch = list(choice)
+                ch[s1], ch[s2] = c1, c2
+                v = synthetic_cost(sp, [index_of(ch)])[0]
+                if v < best_v:
+                    best_c, best_v = (c1, c2), v
+        choice[s1], choice[s2] = best_c
+    return synthetic_cost(sp, [index_of(choice)])[0]
+
+
 def test_tuner_pick_on_known_cost_beats_random():
     sp = LaunchSpace(2)
     rng = np.random.default_rng(11)
@@ -143,31 +171,7 @@ def test_tuner_pick_on_known_cost_beats_random():
     cand = synthetic_cost(sp, ti)
     best_tuned = cand.min()
     best_random = synthetic_cost(sp, idx).min()
-    # true optimum: sites 0 and 1 are independent, sites (3, 4) and (5, 6) are
-    # coupled pairwise and searched jointly, site 2 is pinned
-    def cost_of(choice):
-        idx_ = 0
-        mul = 1
-        for s in range(7):
-            idx_ += choice[s] * mul
-            mul *= sp.radix[s]
-        return idx_
-    # independent sites: minimise one at a time from a fixed base
-    choice = [0] * 7
-    for s in (0, 1):
-        cs = [synthetic_cost(sp, [cost_of(choice[:s] + [c] + choice[s + 1:])])[0] for c in range(sp.radix[s])]
-        choice[s] = int(np.argmin(cs))
-    for s1, s2 in ((3, 4), (5, 6)):
-        best_c, best_v = None, np.inf
-        for c1 in range(sp.radix[s1]):
-            for c2 in range(sp.radix[s2]):
-                ch = list(choice)
-                ch[s1], ch[s2] = c1, c2
-                v = synthetic_cost(sp, [cost_of(ch)])[0]
-                if v < best_v:
-                    best_c, best_v = (c1, c2), v
-        choice[s1], choice[s2] = best_c
-    optimum = synthetic_cost(sp, [cost_of(choice)])[0]
+    optimum = synthetic_optimum(sp)
     # share of the space below the tuned pick, on a uniform sample of 4e5 points
     probe = synthetic_cost(sp, sp.sample(400_000, 5))
     share_tuned = float((probe < best_tuned).mean())
@@ -185,6 +189,36 @@ def test_tuner_pick_on_known_cost_beats_random():
     assert share_tuned <= 2e-4 and share_tuned * 10 <= share_random, info
     assert best_tuned >= optimum - 1e-12, info
     assert r2 > 0.7, info
+
+
+def test_tuner_with_the_papers_sample_budget_lands_near_the_optimum():
+    # The paper trains on 7500 of 10000 samples (Sec. "Results"). The synthetic
+    # cost is free to evaluate, so that budget is affordable here: with it the
+    # fit is close (R^2 about 0.98 for the FP64 network on the same rows) and
+    # the best of the 8 predicted configurations lies within 15% of the true
+    # optimum (the FP64 network's exhaustive argmin lands at 1.10x).
+    sp = LaunchSpace(2)
+    rng = np.random.default_rng(11)
+    idx = sp.sample(10_000, 21)
+    t = synthetic_cost(sp, idx, rng)
+    tr = np.arange(7500)
+    F = sp.features(idx)
+    mean, std = mlp.standard_scaler(F[tr])
+    X = (F - mean) / std
+    y = t / np.median(t[tr])
+    N = net(12)
+    N.train(X[tr], y[tr])
+    from paper_2306_14011_amd.autotune import r2_score
+    r2 = r2_score(y[7500:], N.predict(X[7500:]))
+    ti, _ = N.sweep(sp.struct(mean, std), 0, sp.size, 8)
+    best_tuned = synthetic_cost(sp, ti).min()
+    best_random = synthetic_cost(sp, idx).min()
+    optimum = synthetic_optimum(sp)
+    info = dict(r2=r2, best_tuned=best_tuned, best_random=best_random)
+    print(info)
+    assert r2 > 0.95, info
+    assert best_tuned <= 1.15 * optimum, info
+    assert best_tuned < best_random, info
 
 
 def test_end_to_end_tuning_on_a_small_grid():
