@@ -221,11 +221,12 @@ enum { FV_ORDER_GIVEN = 0, FV_ORDER_LARGEST_FIRST = 1 };
  * grid (offsets[0..ngrids], host array, may be NULL) and the workspace size. */
 int fv_batch_query(int32_t ngrids, const fv_grid_desc* grids, int64_t* offsets, size_t* workspace_bytes);
 
-/* Creates a batch. seg: segment height, a multiple of 4 in [4, 1024], or 0
- * for the library's choice over all grids of the batch; waves: wavefronts per
- * stage launch (0 = one per work item, else a grid-stride loop); order:
- * FV_ORDER_* of the grids in the work list. The workspace (queried size,
- * 256-byte aligned) is owned by the caller. */
+/* Creates a batch. seg: segment height of every grid, a multiple of 4 in
+ * [4, 1024], or 0 for the library's choice over all grids of the batch
+ * (fv_batch_set_schedule sets one per grid); waves: wavefronts per stage
+ * launch (0 = one per work item, else a grid-stride loop); order: FV_ORDER_*
+ * of the grids in the work list. The workspace (queried size, 256-byte
+ * aligned) is owned by the caller. */
 int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int32_t waves, int32_t order,
                     void* workspace, size_t workspace_bytes, void* stream, fv_batch** out);
 
@@ -247,9 +248,17 @@ int fv_batch_dt(fv_batch* b, double* dt);
 /* Synchronises the stream and reads the batch status word (FV_FLAG_*). */
 int fv_batch_status(fv_batch* b, uint32_t* flags);
 
-/* The segment height in use (the library's choice when created with 0) and
- * the number of work items of one stage launch. Outputs may be NULL. */
-int fv_batch_info(const fv_batch* b, int32_t* seg, int32_t* nitems);
+/* Sets the schedule: the segment height of every grid (segs[g] for the
+ * caller's grid g, each a multiple of 4 in [4, 1024]; NULL keeps the current
+ * ones) and the work-list order (FV_ORDER_*). Results are bitwise the same
+ * under every schedule; the step's graph is rebuilt on the next
+ * fv_batch_step. Synchronises the batch's stream. */
+int fv_batch_set_schedule(fv_batch* b, const int32_t* segs, int32_t order);
+
+/* The schedule in use: segment height per grid (segs, ngrids entries), the
+ * work-list order and the number of work items of one stage launch. Outputs
+ * may be NULL. */
+int fv_batch_info(const fv_batch* b, int32_t* segs, int32_t* order, int32_t* nitems);
 
 int fv_batch_destroy(fv_batch* b);
 

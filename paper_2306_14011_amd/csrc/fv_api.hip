@@ -408,22 +408,22 @@ int fv_residual(fv_ctx* c, double* U, double* R) {
 
 static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (nsteps == 0) return FV_OK;
-    fvk::launch_fused_init(c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, nullptr, c->stream);
+    fvk::launch_fused_init(c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, nullptr, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused_stage(0, c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, U, c->U1, c->flam, c->fdt,
+            fvk::launch_fused_stage(0, c->fwaves, c->fgrid, 1, c->fitems, U, U, c->U1, c->flam, c->fdt,
                                     dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status, nullptr,
                                     c->stream);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused_stage(1, c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, c->U1, c->U2, c->flam, c->fdt,
+            fvk::launch_fused_stage(1, c->fwaves, c->fgrid, 1, c->fitems, U, c->U1, c->U2, c->flam, c->fdt,
                                     nullptr, nullptr, c->status, nullptr, c->stream);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused_stage(2, c->fseg, c->fwaves, c->fgrid, 1, c->fitems, U, c->U2, U, c->flam, c->fdt,
+            fvk::launch_fused_stage(2, c->fwaves, c->fgrid, 1, c->fitems, U, c->U2, U, c->flam, c->fdt,
                                     nullptr, nullptr, c->status, nullptr, c->stream);
         }
         int rc = check_launch_error(c);
@@ -467,10 +467,11 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
     G.cfl = c->g.cfl;
     G.gamma = c->g.gamma;
     G.gm1 = c->g.gm1;
+    if (seg == 0) seg = fvk::fused_auto_seg(&G, 1, fvk::fused_slots());
+    G.seg = seg;
     hipError_t e = hipMemcpyAsync(c->fgrid, &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
-    if (seg == 0) seg = fvk::fused_auto_seg(&G, 1, fvk::fused_slots());
     c->fseg = seg;
     c->fwaves = waves;
     c->fitems = fvk::fused_items(G, seg);

@@ -108,7 +108,7 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
 }  // namespace
 
 struct fv_batch {
-    int ngrids, seg, waves, nitems;
+    int ngrids, waves, nitems, order;
     hipStream_t stream, cap;
     fvk::FGrid* grids;
     unsigned long long* lam;
@@ -118,7 +118,8 @@ struct fv_batch {
     int* counter;
     double* U1;
     double* U2;
-    std::vector<fvk::FGrid> host_grids;
+    std::vector<fvk::FGrid> by_grid;     // table entry of each grid, in the caller's order
+    std::vector<fvk::FGrid> host_grids;  // the uploaded table, in work-list order
     hipGraph_t graph;
     hipGraphExec_t exec;
     double* graph_U;
@@ -150,13 +151,45 @@ static void enqueue_step(fv_batch* b, double* U, hipStream_t s) {
     const int nclk = 6 * b->ngrids;
     unsigned long long* clk = b->history ? b->clk : nullptr;
     if (clk) hipLaunchKernelGGL(k_clk_reset, dim3(1), dim3(256), 0, s, b->clk, nclk);
-    fvk::launch_fused_stage(0, b->seg, b->waves, b->grids, b->ngrids, b->nitems, U, U, b->U1, b->lam, b->dt, nullptr,
+    fvk::launch_fused_stage(0, b->waves, b->grids, b->ngrids, b->nitems, U, U, b->U1, b->lam, b->dt, nullptr,
                             nullptr, b->status, clk, s);
-    fvk::launch_fused_stage(1, b->seg, b->waves, b->grids, b->ngrids, b->nitems, U, b->U1, b->U2, b->lam, b->dt,
+    fvk::launch_fused_stage(1, b->waves, b->grids, b->ngrids, b->nitems, U, b->U1, b->U2, b->lam, b->dt,
                             nullptr, nullptr, b->status, clk, s);
-    fvk::launch_fused_stage(2, b->seg, b->waves, b->grids, b->ngrids, b->nitems, U, b->U2, U, b->lam, b->dt, nullptr,
+    fvk::launch_fused_stage(2, b->waves, b->grids, b->ngrids, b->nitems, U, b->U2, U, b->lam, b->dt, nullptr,
                             nullptr, b->status, clk, s);
     if (clk) hipLaunchKernelGGL(k_clk_store, dim3(1), dim3(256), 0, s, b->clk, nclk, b->history, b->max_steps, b->counter);
+}
+
+static bool valid_seg(int32_t seg) { return seg >= 4 && seg <= 1024 && seg % 4 == 0; }
+
+// Orders the table by the work-list order, assigns each grid its segment
+// height and first work item, and uploads it. Work items of a grid are
+// contiguous; the step's graph is rebuilt on the next step.
+static int apply_schedule(fv_batch* b, int32_t order) {
+    const int n = b->ngrids;
+    std::vector<int> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    if (order == FV_ORDER_LARGEST_FIRST)
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) {
+            return (long long)b->by_grid[a].nx * b->by_grid[a].ny > (long long)b->by_grid[c].nx * b->by_grid[c].ny;
+        });
+    b->host_grids.resize(n);
+    long long work = 0;
+    for (int q = 0; q < n; ++q) {
+        fvk::FGrid G = b->by_grid[perm[q]];
+        G.work0 = (int)work;
+        work += fvk::fused_items(G, G.seg);
+        b->host_grids[q] = G;
+    }
+    if (work > 0x7fffffff) return bfail(b, FV_EINVAL, "too many work items");
+    b->nitems = (int)work;
+    b->order = order;
+    hipError_t e = hipMemcpyAsync(b->grids, b->host_grids.data(), sizeof(fvk::FGrid) * n, hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, FV_EDEVICE, "grid table upload failed");
+    drop_graph(b);
+    return FV_OK;
 }
 
 extern "C" {
@@ -178,7 +211,7 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
     BLayout L;
     int rc = validate_batch(ngrids, grids, &L, g_berr);
     if (rc != FV_OK) return rc;
-    if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
+    if (seg != 0 && !valid_seg(seg))
         return bfail(nullptr, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]");
     if (waves < 0) return bfail(nullptr, FV_EINVAL, "negative wave count");
     if (order != FV_ORDER_GIVEN && order != FV_ORDER_LARGEST_FIRST) return bfail(nullptr, FV_EINVAL, "unknown order");
@@ -187,7 +220,6 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
     fv_batch* b = new (std::nothrow) fv_batch();
     if (!b) return bfail(nullptr, FV_EDEVICE, "host allocation failed");
     b->ngrids = ngrids;
-    b->seg = seg;
     b->waves = waves;
     b->stream = (hipStream_t)stream;
     char* base = (char*)workspace;
@@ -199,20 +231,11 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
     b->counter = (int*)(base + L.off_counter);
     b->U1 = (double*)(base + L.off_U1);
     b->U2 = (double*)(base + L.off_U2);
-    // work-list order: grid table entries are in work order; each keeps the
-    // element offset of its own slot of the state
-    std::vector<int> perm(ngrids);
-    std::iota(perm.begin(), perm.end(), 0);
-    if (order == FV_ORDER_LARGEST_FIRST)
-        std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) {
-            return grids[a].n[0] * grids[a].n[1] > grids[c].n[0] * grids[c].n[1];
-        });
-    b->host_grids.resize(ngrids);
-    int work = 0;
-    for (int q = 0; q < ngrids; ++q) {
-        const int g = perm[q];
+    // table entries by grid; each keeps the element offset of its own slot of the state
+    b->by_grid.resize(ngrids);
+    for (int g = 0; g < ngrids; ++g) {
         const fv_grid_desc& d = grids[g];
-        fvk::FGrid& G = b->host_grids[q];
+        fvk::FGrid& G = b->by_grid[g];
         memset(&G, 0, sizeof(G));
         G.nx = (int)d.n[0];
         G.ny = (int)d.n[1];
@@ -237,21 +260,20 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
         G.gamma = d.gamma;
         G.gm1 = d.gamma - 1.0;
     }
-    if (seg == 0) seg = fvk::fused_auto_seg(b->host_grids.data(), ngrids, fvk::fused_slots());
-    b->seg = seg;
-    for (int q = 0; q < ngrids; ++q) {
-        b->host_grids[q].work0 = work;
-        work += fvk::fused_items(b->host_grids[q], seg);
-    }
-    b->nitems = work;
-    hipError_t e = hipMemcpyAsync(b->grids, b->host_grids.data(), sizeof(fvk::FGrid) * ngrids,
-                                  hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (seg == 0) seg = fvk::fused_auto_seg(b->by_grid.data(), ngrids, fvk::fused_slots());
+    for (int g = 0; g < ngrids; ++g) b->by_grid[g].seg = seg;
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         snprintf(g_berr, 256, "batch set-up failed: %s", hipGetErrorString(e));
         delete b;
         return FV_EDEVICE;
+    }
+    rc = apply_schedule(b, order);
+    if (rc != FV_OK) {
+        snprintf(g_berr, 256, "%s", b->err);
+        (void)hipStreamDestroy(b->cap);
+        delete b;
+        return rc;
     }
     fvk::launch_set_u32(b->status, 0u, b->stream);
     *out = b;
@@ -279,7 +301,7 @@ int fv_batch_step(fv_batch* b, double* U, int32_t nsteps) {
         b->graph_timed = timed;
         b->graph_history = b->history;
     }
-    fvk::launch_fused_init(b->seg, b->waves, b->grids, b->ngrids, b->nitems, U, b->lam, b->status, nullptr, b->stream);
+    fvk::launch_fused_init(b->waves, b->grids, b->ngrids, b->nitems, U, b->lam, b->status, nullptr, b->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         hipError_t e = hipGraphLaunch(b->exec, b->stream);
         if (e != hipSuccess) return bfail(b, FV_EDEVICE, "graph launch failed");
@@ -320,9 +342,22 @@ int fv_batch_status(fv_batch* b, uint32_t* flags) {
     return h ? FV_ENONPHYS : FV_OK;
 }
 
-int fv_batch_info(const fv_batch* b, int32_t* seg, int32_t* nitems) {
+int fv_batch_set_schedule(fv_batch* b, const int32_t* segs, int32_t order) {
+    if (!b) return bfail(nullptr, FV_EINVAL, "null batch");
+    if (order != FV_ORDER_GIVEN && order != FV_ORDER_LARGEST_FIRST) return bfail(b, FV_EINVAL, "unknown order");
+    if (segs)
+        for (int g = 0; g < b->ngrids; ++g)
+            if (!valid_seg(segs[g])) return bfail(b, FV_EINVAL, "seg must be a multiple of 4 in [4, 1024]");
+    if (segs)
+        for (int g = 0; g < b->ngrids; ++g) b->by_grid[g].seg = segs[g];
+    return apply_schedule(b, order);
+}
+
+int fv_batch_info(const fv_batch* b, int32_t* segs, int32_t* order, int32_t* nitems) {
     if (!b) return FV_EINVAL;
-    if (seg) *seg = b->seg;
+    if (segs)
+        for (int g = 0; g < b->ngrids; ++g) segs[g] = b->by_grid[g].seg;
+    if (order) *order = b->order;
     if (nitems) *nitems = b->nitems;
     return FV_OK;
 }

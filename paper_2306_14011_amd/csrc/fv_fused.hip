@@ -3,7 +3,8 @@
 // the stage combination, and the last stage also the CFL max of the new state.
 //
 // Work decomposition: a work item is a 60-column strip x seg-row segment of
-// one grid (seg a multiple of 4); one wavefront (64 lanes) owns an item. Lane l holds column
+// one grid (seg a multiple of 4, per grid in the table); one wavefront (64
+// lanes) owns an item. Lane l holds column
 // x0 + l, x0 = 60*strip - 2, so lanes 2..61 produce the 60 output columns and
 // lanes 0, 1, 62, 63 carry the x halo. The wave marches up the segment one row
 // at a time, keeping the last four rows in registers: that window gives the
@@ -69,7 +70,7 @@ __device__ __forceinline__ void st_lane(double* base, uint32_t boff, double x) {
 }
 
 template <int STAGE>
-__global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems, int seg,
+__global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems,
                                                  const double* Un, const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                  const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
@@ -88,6 +89,7 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         const int local = item - G.work0;
         const int strip = local % G.strips;
         const int sidx = local / G.strips;
+        const int seg = G.seg;
         double dt;
         if (STAGE == 0) {
             dt = dt_fixed ? dt_fixed[G.gid] : G.cfl / __longlong_as_double((long long)lam[G.gid]);
@@ -218,7 +220,7 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
 }
 
 // lambda_max of U^n per grid (the first step's dt), same work items.
-__global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ grids, int ngrids, int nitems, int seg,
+__global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ grids, int ngrids, int nitems,
                                                       const double* __restrict__ U, unsigned long long* __restrict__ lam,
                                                       uint32_t* __restrict__ status) {
     const int lane = threadIdx.x & 63;
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ 
         uint32_t fl = 0;
         if (lane < FW && col < G.nx) {
             const double idx[2] = {G.inv_dx, G.inv_dy};
-            for (int rr = sidx * seg; rr < sidx * seg + seg && rr < G.ny; ++rr) {
+            for (int rr = sidx * G.seg; rr < sidx * G.seg + G.seg && rr < G.ny; ++rr) {
                 const long long p = G.base + (long long)rr * G.pitch + col;
                 double q[4];
 #pragma unroll
@@ -275,26 +277,26 @@ static inline int fused_blocks(int nitems, int waves) {
     return (w + 3) / 4;
 }
 
-void launch_fused_stage(int stage, int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
+void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s) {
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
     if (stage == 0)
-        hipLaunchKernelGGL(k_fused2d<0>, grid, block, 0, s, grids, ngrids, nitems, seg, Un, Us, Ud, lam, dtg,
+        hipLaunchKernelGGL(k_fused2d<0>, grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk);
     else if (stage == 1)
-        hipLaunchKernelGGL(k_fused2d<1>, grid, block, 0, s, grids, ngrids, nitems, seg, Un, Us, Ud, lam, dtg,
+        hipLaunchKernelGGL(k_fused2d<1>, grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk);
     else
-        hipLaunchKernelGGL(k_fused2d<2>, grid, block, 0, s, grids, ngrids, nitems, seg, Un, Us, Ud, lam, dtg,
+        hipLaunchKernelGGL(k_fused2d<2>, grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk);
 }
 
-void launch_fused_init(int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
+void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s) {
     hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(256), 0, s, lam, ngrids, clk);
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
-    hipLaunchKernelGGL(k_fused_lambda, grid, block, 0, s, grids, ngrids, nitems, seg, U, lam, status);
+    hipLaunchKernelGGL(k_fused_lambda, grid, block, 0, s, grids, ngrids, nitems, U, lam, status);
 }
 
 // Waves of the stage kernels that are resident on the current device at once:

@@ -8,7 +8,8 @@ namespace fvk {
 // One 2D grid of the fused path (device memory, read uniformly).
 struct FGrid {
     int nx, ny, pitch, strips, work0, unlimited;
-    int bcx0, bcx1, bcy0, bcy1, gid, pad1;  // gid: the caller's grid index (slots of lam, dt, clocks)
+    int bcx0, bcx1, bcy0, bcy1, gid, seg;   // gid: the caller's grid index (slots of lam, dt, clocks);
+                                            // seg: rows per work item (a multiple of 4)
     long long base;     // element offset of cell (0,0), variable 0
     long long sv;       // per-variable stride
     double ax, ay;      // face areas of x faces (dy) and y faces (dx)
@@ -27,12 +28,12 @@ void launch_cfl(const double* U, double* partial, uint32_t* status, const double
 void launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 
 // fused 2D stages
-int fused_items(const FGrid& G, int seg);
+int fused_items(const FGrid& G, int seg);  // work items of G at segment height seg
 int fused_strips(int nx);
-void launch_fused_stage(int stage, int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
+void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s);
-void launch_fused_init(int seg, int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
+void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s);
 int fused_slots();
 int fused_auto_seg(const FGrid* grids, int ngrids, int slots);

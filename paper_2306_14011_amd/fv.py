@@ -141,7 +141,9 @@ def lib():
         L.fv_batch_set_timing.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
         L.fv_batch_dt.argtypes = [_vp, _vp]
         L.fv_batch_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
-        L.fv_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.fv_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
+        L.fv_batch_set_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.fv_batch_destroy.argtypes = [_vp]
         L.fv_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_sweep_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
@@ -155,7 +157,7 @@ def lib():
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
                      "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
                      "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_batch_query", "fv_batch_create",
-                     "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_destroy",
+                     "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_set_schedule", "fv_batch_destroy",
                      "fv_mlp_workspace", "fv_mlp_sweep_workspace",
                      "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep"):
             getattr(L, name).restype = ctypes.c_int
@@ -338,11 +340,19 @@ def fv_batch_status(b):
     return rc, fl.value
 
 
-def fv_batch_info(b):
-    """(segment height in use, work items per stage launch)."""
-    sg, n = ctypes.c_int32(), ctypes.c_int32()
-    _batch_check(lib().fv_batch_info(_vp(b), ctypes.byref(sg), ctypes.byref(n)))
-    return sg.value, n.value
+def fv_batch_info(b, ngrids):
+    """(segment height per grid, work-list order, work items per stage launch)."""
+    segs = (ctypes.c_int32 * ngrids)()
+    order, n = ctypes.c_int32(), ctypes.c_int32()
+    _batch_check(lib().fv_batch_info(_vp(b), segs, ctypes.byref(order), ctypes.byref(n)))
+    return list(segs), order.value, n.value
+
+
+def fv_batch_set_schedule(b, segs, order):
+    arr = None
+    if segs is not None:
+        arr = (ctypes.c_int32 * len(segs))(*[int(x) for x in segs])
+    _batch_check(lib().fv_batch_set_schedule(_vp(b), arr, int(order)), b)
 
 
 def fv_batch_destroy(b):
@@ -550,8 +560,14 @@ class Batch:
         return out.cpu().numpy()
 
     def info(self):
-        """(segment height in use, work items per stage launch)."""
-        return fv_batch_info(self.b)
+        """(segment height per grid, work-list order, work items per stage launch)."""
+        return fv_batch_info(self.b, len(self.specs))
+
+    def set_schedule(self, segs=None, order=FV_ORDER_GIVEN):
+        """Segment height per grid (None keeps them) and work-list order."""
+        if segs is not None and len(segs) != len(self.specs):
+            raise ValueError("one segment height per grid")
+        fv_batch_set_schedule(self.b, segs, order)
 
     def status(self):
         return fv_batch_status(self.b)

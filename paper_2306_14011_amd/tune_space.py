@@ -52,31 +52,15 @@ def site_elements(spec):
     return {3: ncell, 4: ncell, 5: ghosts, 6: ncell}
 
 
-class LaunchSpace:
-    def __init__(self, ndim: int, counts=None):
-        """counts: element count per one-dimensional site (defaults to a 2048^2 grid)."""
-        self.ndim = ndim
-        if counts is None:
-            counts = {3: 2048 * 2048, 4: 2048 * 2048, 5: 8 * 2048, 6: 2048 * 2048}
-        self.counts = dict(counts)
-        self.choices = []   # (p1, p2) launch parameters per choice
-        self.feats = []     # (f1, f2) raw network features per choice
-        for s in range(NSITES):
-            if s in ONE_D_SITES:
-                ch = [(gang_for(self.counts[s], t, e), t) for e in ELEMS_PER_THREAD for t in THREADS]
-                ft = [(math.log2(e), math.log2(t)) for e in ELEMS_PER_THREAD for t in THREADS]
-            else:
-                pairs = STENCIL_PAIRS if (s < 2 or ndim == 3) else PINNED_FLUX_Z
-                ch = list(pairs)
-                ft = [(math.log2(a), math.log2(b)) for a, b in pairs]
-            self.choices.append(ch)
-            self.feats.append(ft)
-        self.radix = [len(c) for c in self.choices]
-        self.size = int(np.prod([int(r) for r in self.radix], dtype=object))
+class MixedRadixSpace:
+    """Choices per site (at most 7 sites, 2 parameters and 2 raw network
+    features each); an index is the mixed-radix number of the per-site choice
+    digits, site 0 fastest."""
 
-    @classmethod
-    def for_grid(cls, spec):
-        return cls(spec.ndim, site_elements(spec))
+    choices: list
+    feats: list
+    radix: list
+    size: int
 
     def digits(self, idx: int):
         if not 0 <= idx < self.size:
@@ -145,3 +129,69 @@ class LaunchSpace:
                 sp.f1[s][c] = f1[s][c]
                 sp.f2[s][c] = f2[s][c]
         return sp
+
+
+class LaunchSpace(MixedRadixSpace):
+    def __init__(self, ndim: int, counts=None):
+        """counts: element count per one-dimensional site (defaults to a 2048^2 grid)."""
+        self.ndim = ndim
+        if counts is None:
+            counts = {3: 2048 * 2048, 4: 2048 * 2048, 5: 8 * 2048, 6: 2048 * 2048}
+        self.counts = dict(counts)
+        self.choices = []   # (p1, p2) launch parameters per choice
+        self.feats = []     # (f1, f2) raw network features per choice
+        for s in range(NSITES):
+            if s in ONE_D_SITES:
+                ch = [(gang_for(self.counts[s], t, e), t) for e in ELEMS_PER_THREAD for t in THREADS]
+                ft = [(math.log2(e), math.log2(t)) for e in ELEMS_PER_THREAD for t in THREADS]
+            else:
+                pairs = STENCIL_PAIRS if (s < 2 or ndim == 3) else PINNED_FLUX_Z
+                ch = list(pairs)
+                ft = [(math.log2(a), math.log2(b)) for a, b in pairs]
+            self.choices.append(ch)
+            self.feats.append(ft)
+        self.radix = [len(c) for c in self.choices]
+        self.size = int(np.prod([int(r) for r in self.radix], dtype=object))
+
+    @classmethod
+    def for_grid(cls, spec):
+        return cls(spec.ndim, site_elements(spec))
+
+
+
+BATCH_SEGS = (4, 8, 12, 16, 20, 24, 32, 40, 48, 64)
+BATCH_BUCKET_EDGES = (352, 576, 800)   # grid size buckets by sqrt(cells)
+
+
+def batch_bucket(spec) -> int:
+    side = math.sqrt(float(spec.n[0]) * float(spec.n[1]))
+    return sum(side >= e for e in BATCH_BUCKET_EDGES)
+
+
+class BatchSpace(MixedRadixSpace):
+    """Schedule space of a batch of 2D grids: the segment height of each of
+    four grid-size buckets (sites 0-3; a bucket with no grid is pinned) and
+    the work-list order (site 4: given, largest first); sites 5 and 6 are
+    pinned. Features: log2 of the segment height, the order flag."""
+
+    def __init__(self, grids):
+        self.bucket = [batch_bucket(g) for g in grids]
+        used = set(self.bucket)
+        self.choices, self.feats = [], []
+        for b in range(4):
+            segs = BATCH_SEGS if b in used else (16,)
+            self.choices.append([(sg, 0) for sg in segs])
+            self.feats.append([(math.log2(sg), 0.0) for sg in segs])
+        self.choices.append([(0, 0), (1, 0)])
+        self.feats.append([(0.0, 0.0), (1.0, 0.0)])
+        for _ in range(2):
+            self.choices.append([(0, 0)])
+            self.feats.append([(0.0, 0.0)])
+        self.radix = [len(c) for c in self.choices]
+        self.size = int(np.prod([int(r) for r in self.radix], dtype=object))
+
+    def schedule(self, idx: int):
+        """(segment height per grid, order) of index idx."""
+        d = self.digits(idx)
+        segs = [self.choices[b][d[b]][0] for b in self.bucket]
+        return segs, self.choices[4][d[4]][0]

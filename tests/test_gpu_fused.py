@@ -175,6 +175,34 @@ def test_batch_schedules_and_graph_replays_bitwise_equal():
             assert np.array_equal(got[g], base[g]), (args, g)
 
 
+def test_batch_per_grid_schedules_bitwise_equal_and_validated():
+    fv = _fv()
+    spec = small_batch(seed=6, count=7)
+    B = fv.Batch(spec.grids, seg=16)
+    B.set_states(spec.states)
+    B.step(3)
+    base = B.get_states()
+    rng = np.random.default_rng(3)
+    for order in (0, 1, 1):
+        segs = [int(4 * rng.integers(1, 17)) for _ in spec.grids]
+        B.set_schedule(segs, order)
+        got_segs, got_order, nitems = B.info()
+        assert got_segs == segs and got_order == order
+        assert nitems == sum(((gg.n[0] + 59) // 60) * ((gg.n[1] + sg - 1) // sg) for gg, sg in zip(spec.grids, segs))
+        B.set_states(spec.states)
+        B.step(3)
+        for g, st in enumerate(B.get_states()):
+            assert np.array_equal(st, base[g]), (segs, order, g)
+    keep = B.info()
+    for bad in ([3] * len(spec.grids), [1028] * len(spec.grids), [0] * len(spec.grids)):
+        with pytest.raises(fv.FvError):
+            B.set_schedule(bad, 0)
+    with pytest.raises(fv.FvError):
+        B.set_schedule(None, 2)
+    assert B.info() == keep  # rejected calls keep the schedule
+    B.close()
+
+
 def test_batch_equals_single_grid_fused_path():
     # eager single-grid launches vs the graph-replayed batch: same kernels, same bits
     fv = _fv()

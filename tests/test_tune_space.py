@@ -1,4 +1,6 @@
 """Host-side checks of the 14-parameter launch space."""
+import math
+
 import numpy as np
 import pytest
 
@@ -90,3 +92,28 @@ def test_sampling_is_distinct_and_seeded():
     sp = LaunchSpace(2)
     a = sp.sample(300, 5)
     assert len(set(a)) == 300 and a == sp.sample(300, 5) and a != sp.sample(300, 6)
+
+
+def test_target_scaler():
+    from paper_2306_14011_amd.autotune import target_scaler
+    m, s = target_scaler([1.0, 2.0, 3.0, 4.0])
+    assert m == 2.5 and abs(s - math.sqrt(1.25)) < 1e-15   # population sigma
+    assert target_scaler([2.0, 2.0]) == (2.0, 1.0)           # zero spread leaves the target centred only
+
+
+def test_batch_space_buckets_and_schedules():
+    from paper_2306_14011_amd.tune_space import BATCH_SEGS, BatchSpace, batch_bucket
+    g = [inputs.grid2d(n, n) for n in (128, 351, 352, 575, 576, 799, 800, 1024)]
+    assert [batch_bucket(x) for x in g] == [0, 0, 1, 1, 2, 2, 3, 3]
+    sp = BatchSpace(g)
+    assert sp.radix == [len(BATCH_SEGS)] * 4 + [2, 1, 1] and sp.size == len(BATCH_SEGS) ** 4 * 2
+    rng = np.random.default_rng(0)
+    for idx in rng.integers(0, sp.size, 50):
+        segs, order = sp.schedule(int(idx))
+        d = sp.digits(int(idx))
+        assert segs == [BATCH_SEGS[d[b]] for b in sp.bucket] and order == d[4]
+    # buckets without a grid are pinned
+    sp2 = BatchSpace([inputs.grid2d(200, 200), inputs.grid2d(900, 900)])
+    assert sp2.radix == [len(BATCH_SEGS), 1, 1, len(BATCH_SEGS), 2, 1, 1]
+    X = sp2.features(sp2.sample(20, 1))
+    assert X.shape == (20, 14) and np.all(X[:, 1::2] == 0.0)
