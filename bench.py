@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--samples-3d", type=int, default=2000, help="timed launch vectors for the 3D tuner")
     ap.add_argument("--samples-batch", type=int, default=300, help="timed schedules for the batch tuner")
     ap.add_argument("--quick", action="store_true", help="headline and split default only")
+    ap.add_argument("--seg", type=int, default=-1,
+                    help="fused segment height: -1 sweeps a few and keeps the fastest, 0 is the library's choice")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -186,7 +188,8 @@ def fused_leg(torch, fv, traffic, g, U0, a):
     res = {}
     s.set_path(fv.FV_PATH_FUSED, 0, 0)
     auto_seg = s.get_path()[1]
-    for seg in sorted({auto_seg, 8, 12, 16, 20, 24, 32}):
+    segs = sorted({auto_seg, 8, 12, 16, 20, 24, 32}) if a.seg < 0 else [a.seg or auto_seg]
+    for seg in segs:
         s.set_path(fv.FV_PATH_FUSED, seg, 0)
         res[seg] = timed_steps(torch, s, U0, max(a.steps // 4, 20), a.warmup)
     seg = min(res, key=res.get)
