@@ -68,9 +68,19 @@ def fused_step_bytes(spec):
     return 8 * (spec.ndim + 2) * spec.ncells * 8
 
 
-FLOPS_FACE_2D = 28 + 161
+# Algorithmic FP64 flops, counted from the device source with an FMA as 2
+# and min / max / abs as 0:
+#   MUSCL-minmod per face: 4 variables x (3 differences + 2 minmod adds + 2 fma)
+#   Roe flux per face (2D): primitive states, Roe averages, wave strengths and
+#     dissipation, central fluxes; each 1/x is 6 flops and each 1/sqrt(x) 8
+#     (hardware estimate plus one third-order correction), 3 and 1 of them
+#   cell update: residual of 4 faces x 4 variables, scaled, and the RK combination
+#   CFL wave speed of a cell: 1/rho, velocities, pressure, c, sum over axes
+FLOPS_MUSCL_FACE = 4 * 9
+FLOPS_ROE_FACE_2D = 147
+FLOPS_FACE_2D = FLOPS_MUSCL_FACE + FLOPS_ROE_FACE_2D
 FLOPS_CELL_UPDATE_2D = 44
-FLOPS_CELL_LAMBDA = 20
+FLOPS_CELL_LAMBDA = 30
 
 
 def fused_stage_flops(spec):
