@@ -177,7 +177,9 @@ int fv_clear_status(fv_ctx* ctx);
  * work item, else a grid-stride loop over the items). Every segment height
  * and wave count gives bitwise the same result. Both paths compute the same
  * cell arithmetic; fv_residual and fv_adjoint_step always use the split
- * kernels. Returns FV_ENOTSUP for 3D and FV_EINVAL for other seg values. */
+ * kernels. Returns FV_ENOTSUP for 3D grids and for states of 4 GiB or more
+ * (the fused kernels address a grid through 32-bit buffer offsets), and
+ * FV_EINVAL for other seg values. */
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
 
@@ -217,8 +219,9 @@ typedef struct fv_batch fv_batch;
 
 enum { FV_ORDER_GIVEN = 0, FV_ORDER_LARGEST_FIRST = 1 };
 
-/* Validates the grids (2D each) and reports the element offsets of every
- * grid (offsets[0..ngrids], host array, may be NULL) and the workspace size. */
+/* Validates the grids (2D each, each state below 4 GiB, i.e. under 2^27
+ * cells) and reports the element offsets of every grid (offsets[0..ngrids],
+ * host array, may be NULL) and the workspace size. */
 int fv_batch_query(int32_t ngrids, const fv_grid_desc* grids, int64_t* offsets, size_t* workspace_bytes);
 
 /* Creates a batch. seg: segment height of every grid, a multiple of 4 in

@@ -442,6 +442,8 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
     if (c->g.ndim != 2) return fail(c, FV_ENOTSUP, "the fused path is 2D only%s");
+    if (4 * c->g.sv * 8 >= (1ll << 32))
+        return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
     if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
         return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
     if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");

@@ -54,8 +54,8 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
             snprintf(why, 256, "grid %d: cell counts must be in [1, 65534]", g);
             return FV_EINVAL;
         }
-        if ((int64_t)d.n[0] * d.n[1] * 4 >= ((int64_t)1 << 31)) {
-            snprintf(why, 256, "grid %d: too large", g);
+        if ((int64_t)d.n[0] * d.n[1] * 4 * 8 >= ((int64_t)1 << 32)) {
+            snprintf(why, 256, "grid %d: a state of 4 GiB or more (buffer offsets are 32-bit)", g);
             return FV_EINVAL;
         }
         if (d.scheme != FV_SCHEME_MINMOD && d.scheme != FV_SCHEME_UNLIMITED) {

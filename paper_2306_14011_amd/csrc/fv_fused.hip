@@ -9,7 +9,9 @@
 // lanes 0, 1, 62, 63 carry the x halo. The wave marches up the segment one row
 // at a time, keeping the last four rows in registers: that window gives the
 // y-face flux, and the x-stencil and the right-face flux come from
-// neighbouring lanes by wave shuffles. No LDS and no block barriers.
+// neighbouring lanes by DPP lane shifts. No LDS and no block barriers. Loads
+// and stores go through buffer descriptors of the grid's arrays, so one
+// grid's state (4 variables) must stay below 4 GiB (checked on the host).
 //
 // Halo cells outside a grid are read through the boundary map (periodic
 // wrap, transmissive clamp), so no ghost layers are needed. A grid table
@@ -61,12 +63,36 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 }
 
 // Element at a wave-uniform base plus a per-lane 32-bit byte offset.
-__device__ __forceinline__ double ld_lane(const double* base, uint32_t boff) {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
+// Buffer access with a wave-uniform descriptor (the grid's array), a per-lane
+// 32-bit byte offset (the column) and a wave-uniform 32-bit byte offset (the
+// variable and row): no per-lane 64-bit address arithmetic.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+__device__ __forceinline__ Rsrc grid_rsrc(const double* base, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(unsigned int)bytes, 0x00020000);
 }
 
-__device__ __forceinline__ void st_lane(double* base, uint32_t boff, double x) {
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + boff) = x;
+__device__ __forceinline__ double ld_buf(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ void st_buf(Rsrc r, uint32_t voff, uint32_t soff, double x) {
+    using T = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(T, x), r, (int)voff, (int)soff, 0);
+}
+
+// Value of lane l - 1 (UP) or l + 1 (down) of a double, by the whole-wave
+// DPP shifts wave_shr:1 / wave_shl:1 on both halves (two VALU moves, no LDS
+// round trip). The lane without a source (0 for UP, 63 otherwise) gets 0;
+// only halo lanes see it, and their faces feed no output.
+template <bool UP>
+__device__ __forceinline__ double lane_shift1(double x) {
+    const long long b = __double_as_longlong(x);
+    int lo = (int)b, hi = (int)(b >> 32);
+    constexpr int ctrl = UP ? 0x138 : 0x130;
+    lo = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xf, 0xf, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 template <int STAGE>
@@ -106,13 +132,16 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
         const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
         const int r0 = sidx * seg;
-        const double* Usg = Us + G.base;
+        const long long gbytes = 4 * G.sv * 8;  // one grid's state, below 4 GiB
+        const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes),
+                   rd = grid_rsrc(Ud + G.base, gbytes);
         const uint32_t cboff = (uint32_t)cmap * 8u;  // this lane's column in bytes
-        // row offset of U_s row r through the y boundary map (rows past the
-        // last halo row are clamped inside the grid; they feed no output)
-        auto row_off = [&](int r) -> long long {
-            return (long long)map_index(r, G.ny, G.bcy0, G.bcy1) * G.pitch;
+        // byte offset of variable v, U_s row r through the y boundary map
+        // (rows past the last halo row are clamped inside the grid; they feed no output)
+        auto row_off = [&](int r) -> uint32_t {
+            return (uint32_t)((long long)map_index(r, G.ny, G.bcy0, G.bcy1) * G.pitch * 8);
         };
+        const uint32_t vstride = (uint32_t)(G.sv * 8);
         // Circular window of four U_s rows: row r sits in slot (r - r0 + 2) & 3.
         // The loop visits the y faces f = 0 .. seg of the segment (face f lies
         // between rows r0 + f - 1 and r0 + f) in unrolled groups of four, so
@@ -123,9 +152,9 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         double W[4][NV];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const long long o = row_off(r0 - 2 + k);
+            const uint32_t o = row_off(r0 - 2 + k);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) W[k][v] = ld_lane(Usg + v * G.sv + o, cboff);
+            for (int v = 0; v < NV; ++v) W[k][v] = ld_buf(rs, cboff, o + v * vstride);
         }
         double Fy[2][NV];   // y-face fluxes: face f in Fy[f & 1]
         double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
@@ -144,9 +173,9 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
                 if (STAGE > 0 && more) {
                     // U^n of row rr + 1, used at face f + 1
                     const int fr = rr + 1 < G.ny ? rr + 1 : G.ny - 1;
-                    const long long pn = G.base + (long long)fr * G.pitch;
+                    const uint32_t pn = (uint32_t)((long long)fr * G.pitch * 8);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Unb[(j + 1) & 1][v] = ld_lane(Un + v * G.sv + pn, oboff);
+                    for (int v = 0; v < NV; ++v) Unb[(j + 1) & 1][v] = ld_buf(rn, oboff, pn + v * vstride);
                 }
                 double qL[NV], qR[NV];
                 // y face f: stencil rows rr-1 .. rr+2 in slots j, j+1, j+2, j+3 (mod 4)
@@ -160,25 +189,25 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
                 for (int v = 0; v < NV; ++v) c[v] = W[(j + 1) & 3][v];
                 // row rr - 1 is dead: its slot takes row rr + 3 for face f + 1
                 if (more) {
-                    const long long o = row_off(rr + 3);
+                    const uint32_t o = row_off(rr + 3);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) W[j][v] = ld_lane(Usg + v * G.sv + o, cboff);
+                    for (int v = 0; v < NV; ++v) W[j][v] = ld_buf(rs, cboff, o + v * vstride);
                 }
                 if (f == 0) continue;  // uniform: the first face has no row below it in the segment
                 // x faces of row rr: left face from the lanes to the left, right face one lane up
                 double Fxl[NV], Fxr[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double a = __shfl_up(c[v], 2, 64);
-                    const double b = __shfl_up(c[v], 1, 64);
-                    const double d = __shfl_down(c[v], 1, 64);
+                    const double b = lane_shift1<true>(c[v]);
+                    const double a = lane_shift1<true>(b);
+                    const double d = lane_shift1<false>(c[v]);
                     muscl(a, b, c[v], d, G.unlimited, qL[v], qR[v]);
                 }
                 roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) Fxr[v] = __shfl_down(Fxl[v], 1, 64);
+                for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
                 if (out_lane && rr < G.ny) {
-                    const long long p = G.base + (long long)rr * G.pitch;
+                    const uint32_t p = (uint32_t)((long long)rr * G.pitch * 8);
                     double out[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
@@ -191,7 +220,7 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
                         } else {
                             out[v] = (1.0 / 3.0) * Unb[j & 1][v] + (2.0 / 3.0) * (c[v] + s * r);
                         }
-                        st_lane(Ud + v * G.sv + p, oboff, out[v]);
+                        st_buf(rd, oboff, p + v * vstride, out[v]);
                     }
                     if (STAGE == 2) {
                         const double idx[2] = {G.inv_dx, G.inv_dy};

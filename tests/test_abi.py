@@ -116,4 +116,9 @@ def test_batch_query_offsets_and_validation():
     with pytest.raises(fv.FvError) as e:
         fv.fv_batch_query([bad])
     assert e.value.code == fv.FV_EINVAL
+    # one grid's state must stay below 4 GiB: 2^27 cells is the first size refused
+    fv.fv_batch_query([inputs.grid2d(8192, 16383)])
+    with pytest.raises(fv.FvError) as e:
+        fv.fv_batch_query([inputs.grid2d(8192, 16384)])
+    assert e.value.code == fv.FV_EINVAL
 
