@@ -95,6 +95,15 @@ __device__ __forceinline__ double lane_shift1(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Block index with the hardware's round-robin spread over the 8 XCDs undone:
+// block b runs on XCD b % 8, and the blocks of one XCD get a contiguous range
+// of logical indices, so vertically adjacent segments (which share halo rows)
+// are processed by the same XCD and its L2. A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 template <int STAGE>
 __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems,
                                                  const double* Un, const double* __restrict__ Us, double* Ud,
@@ -104,7 +113,8 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
     constexpr int NV = 4;
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    const int wave0 = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int wave0 = __builtin_amdgcn_readfirstlane(
+        (int)((xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6));
     if (STAGE == 1 && blockIdx.x == 0)
         for (int g = threadIdx.x; g < ngrids; g += blockDim.x) lam[g] = 0ull;  // stage 1 has read it
     for (int item = wave0; item < nitems; item += nwaves) {
