@@ -166,20 +166,20 @@ int fv_status(fv_ctx* ctx, uint32_t* flags);
 int fv_clear_status(fv_ctx* ctx);
 
 /* Step paths. FV_PATH_SPLIT runs the seven tunable kernels (the launch
- * table applies). FV_PATH_FUSED (2D only) runs one kernel per Runge-Kutta
- * stage that does the ghost mapping, both flux axes, the residual and the
+ * table applies). FV_PATH_FUSED runs one kernel per Runge-Kutta stage that
+ * does the ghost mapping, the fluxes of every axis, the residual and the
  * stage update, and the last stage also the CFL max of the new state; the
- * state then moves through HBM 8 times per step instead of ~33. `seg` is the
- * segment height of a work item in rows, a multiple of 4 in [4, 1024], or 0
- * to let the library choose it from the grid and the number of wavefronts the
- * device holds at once (a work item is a 60-column strip of a segment, one
- * wavefront each); `waves` is the number of wavefronts launched (0 = one per
- * work item, else a grid-stride loop over the items). Every segment height
- * and wave count gives bitwise the same result. Both paths compute the same
- * cell arithmetic; fv_residual and fv_adjoint_step always use the split
- * kernels. Returns FV_ENOTSUP for 3D grids and for states of 4 GiB or more
- * (the fused kernels address a grid through 32-bit buffer offsets), and
- * FV_EINVAL for other seg values. */
+ * state then moves through HBM 8 times per step instead of ~33 (2D) or ~42
+ * (3D). `seg` is the segment height of a work item (rows in 2D, planes in
+ * 3D), a multiple of 4 in [4, 1024], or 0 to let the library choose it from
+ * the grid and the number of wavefronts the device holds at once (a work item
+ * is a 60-column strip of a segment, one wavefront each); `waves` is the
+ * number of wavefronts launched (0 = one per work item, else a grid-stride
+ * loop over the items). Every segment height and wave count gives bitwise the
+ * same result. Both paths compute the same cell arithmetic; fv_residual and
+ * fv_adjoint_step always use the split kernels. Returns FV_ENOTSUP for states
+ * of 4 GiB or more (the fused kernels address a grid through 32-bit buffer
+ * offsets) and FV_EINVAL for other seg values. */
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
 

@@ -31,7 +31,8 @@ struct fv_ctx {
     // fused path
     int path, fseg, fwaves, fitems;
     fvk::FGrid fgrid_host;
-    fvk::FGrid* fgrid;
+    fvk::FGrid3 fgrid3_host;
+    fvk::FGrid* fgrid;  // the fused path's grid description (an FGrid3 in 3D)
     unsigned long long* flam;
     double* fdt;
     // per-site event timing (diagnostic)
@@ -134,7 +135,7 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     o += 256;
     L->off_dt = o;
     o += 256;
-    L->off_fused = o;   // FGrid (128 B), lambda slot, dt slot
+    L->off_fused = o;   // FGrid (128 B) or FGrid3 (160 B), lambda slot at +160, dt slot at +168
     o += 256;
     L->off_partial = o;
     o = align256(o + (size_t)L->max_partial * 8);
@@ -406,8 +407,39 @@ int fv_residual(fv_ctx* c, double* U, double* R) {
     return drain_timing(c);
 }
 
+static_assert(sizeof(fvk::FGrid) <= 160 && sizeof(fvk::FGrid3) <= 160, "fused grid slot is 160 bytes");
+
+static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
+    const fvk::FGrid3* G = (const fvk::FGrid3*)c->fgrid;
+    fvk::launch_fused3d_init(c->fwaves, G, c->fitems, U, c->flam, c->status, c->stream);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        {
+            SiteTimer t(c, FV_TIMER_FUSED);
+            fvk::launch_fused3d_stage(0, c->fwaves, G, c->fitems, U, U, c->U1, c->flam, c->fdt,
+                                      dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status,
+                                      c->stream);
+        }
+        {
+            SiteTimer t(c, FV_TIMER_FUSED);
+            fvk::launch_fused3d_stage(1, c->fwaves, G, c->fitems, U, c->U1, c->U2, c->flam, c->fdt, nullptr,
+                                      nullptr, c->status, c->stream);
+        }
+        {
+            SiteTimer t(c, FV_TIMER_FUSED);
+            fvk::launch_fused3d_stage(2, c->fwaves, G, c->fitems, U, c->U2, U, c->flam, c->fdt, nullptr, nullptr,
+                                      c->status, c->stream);
+        }
+        int rc = check_launch_error(c);
+        if (rc != FV_OK) return rc;
+        rc = drain_timing(c);
+        if (rc != FV_OK) return rc;
+    }
+    return FV_OK;
+}
+
 static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (nsteps == 0) return FV_OK;
+    if (c->g.ndim == 3) return fused_step3(c, U, nsteps, dt_in, dt_out);
     fvk::launch_fused_init(c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, nullptr, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
@@ -441,12 +473,50 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         return FV_OK;
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
-    if (c->g.ndim != 2) return fail(c, FV_ENOTSUP, "the fused path is 2D only%s");
-    if (4 * c->g.sv * 8 >= (1ll << 32))
+    if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
         return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
     if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
         return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
     if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");
+    if (c->g.ndim == 3) {
+        fvk::FGrid3& G = c->fgrid3_host;
+        memset(&G, 0, sizeof(G));
+        G.nx = c->g.n[0];
+        G.ny = c->g.n[1];
+        G.nz = c->g.n[2];
+        G.strips = fvk::fused_strips(G.nx);
+        G.unlimited = c->g.unlimited;
+        G.bcx0 = c->g.bc[0][0];
+        G.bcx1 = c->g.bc[0][1];
+        G.bcy0 = c->g.bc[1][0];
+        G.bcy1 = c->g.bc[1][1];
+        G.bcz0 = c->g.bc[2][0];
+        G.bcz1 = c->g.bc[2][1];
+        G.base = c->g.off0;
+        G.sv = c->g.sv;
+        G.py = c->g.sy;
+        G.pz = c->g.sz;
+        G.ax = c->g.area[0];
+        G.ay = c->g.area[1];
+        G.az = c->g.area[2];
+        G.inv_vol = c->g.inv_vol;
+        G.inv_dx = c->g.inv_dx[0];
+        G.inv_dy = c->g.inv_dx[1];
+        G.inv_dz = c->g.inv_dx[2];
+        G.cfl = c->g.cfl;
+        G.gamma = c->g.gamma;
+        G.gm1 = c->g.gm1;
+        if (seg == 0) seg = fvk::fused3d_auto_seg(G, fvk::fused3d_slots());
+        G.seg = seg;
+        hipError_t e = hipMemcpyAsync(c->fgrid, &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
+        c->fseg = seg;
+        c->fwaves = waves;
+        c->fitems = fvk::fused3d_items(G, seg);
+        c->path = FV_PATH_FUSED;
+        return FV_OK;
+    }
     fvk::FGrid& G = c->fgrid_host;
     memset(&G, 0, sizeof(G));
     G.nx = c->g.n[0];

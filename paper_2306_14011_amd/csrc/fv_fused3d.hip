@@ -1,0 +1,287 @@
+// Fused SSP-RK3 stage for 3D grids (FP64, gfx950): one kernel per stage does
+// the ghost mapping, MUSCL-minmod + Roe fluxes on the three axes, the residual
+// and the stage combination, and the last stage also the CFL max of the new
+// state.
+//
+// Work decomposition: a work item is a 60-column x strip of one grid row j
+// over a segment of seg planes (seg a multiple of 4); one wavefront owns an
+// item, lane l holding column 60*strip - 2 + l (lanes 2..61 produce outputs,
+// lanes 0, 1, 62, 63 are the x halo). The wave marches along z with a window
+// of four planes of its own row in registers, walking the segment's seg + 1
+// z faces in unrolled groups of four so that every window slot is a
+// compile-time constant (and each z face of the grid is computed by the same
+// unrolled copy whatever seg is). At each plane it reads the rows j-2, j-1,
+// j+1, j+2 of that plane and computes both y faces of its row; the x stencil
+// comes from DPP lane shifts. A y face is thus computed by the two waves of
+// the rows it separates (no block barriers, no LDS), which costs one flux in
+// four extra against a shared-tile scheme.
+//
+// Halo cells outside the grid are read through the boundary maps; the state
+// may keep ghost layers but they are not read. Per-grid dt and the CFL max
+// follow the 2D kernel: stage 1 computes dt from the max that the previous
+// step's stage 3 (or the init kernel) accumulated, stage 2 resets it, stage 3
+// accumulates the max of the new state.
+#include "fv_fused_common.h"
+
+namespace fvk {
+
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
+                                                 const double* __restrict__ Us, double* Ud,
+                                                 unsigned long long* __restrict__ lam, double* __restrict__ dtg,
+                                                 const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
+                                                 uint32_t* __restrict__ status) {
+    constexpr int NV = 5;
+    const int lane = threadIdx.x & 63;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int wave0 = __builtin_amdgcn_readfirstlane(
+        (int)((xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6));
+    if (STAGE == 1 && blockIdx.x == 0 && threadIdx.x == 0) lam[0] = 0ull;  // stage 1 has read it
+    const FGrid3 G = *grid;
+    for (int item = wave0; item < nitems; item += nwaves) {
+        const int strip = item % G.strips;
+        const int t = item / G.strips;
+        const int j = t % G.ny;
+        const int zs = t / G.ny;
+        double dt;
+        if (STAGE == 0) {
+            dt = dt_fixed ? dt_fixed[0] : G.cfl / __longlong_as_double((long long)lam[0]);
+            if (item == 0 && lane == 0) {
+                dtg[0] = dt;
+                if (dt_out) dt_out[0] = dt;
+                if (!(dt > 0.0) || isinf(dt)) atomicOr(status, 8u);
+            }
+        } else {
+            dt = dtg[0];
+        }
+        const double s = -dt * G.inv_vol;
+        const int col = FW * strip - 2 + lane;
+        const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
+        const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
+        const int k0 = zs * G.seg;
+        const int seg = G.seg;
+        const long long gbytes = NV * G.sv * 8;  // one grid's state, below 4 GiB
+        const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes),
+                   rd = grid_rsrc(Ud + G.base, gbytes);
+        const uint32_t cboff = (uint32_t)cmap * 8u;                         // stencil column in bytes
+        const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;          // output column in bytes
+        const uint32_t vstride = (uint32_t)(G.sv * 8);
+        // byte offsets of rows j-2 .. j+2 and of plane kk through the boundary maps
+        uint32_t ro[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) ro[d] = (uint32_t)((long long)map_index(j - 2 + d, G.ny, G.bcy0, G.bcy1) * G.py * 8);
+        auto plane_off = [&](int kk) -> uint32_t {
+            return (uint32_t)((long long)map_index(kk, G.nz, G.bcz0, G.bcz1) * G.pz * 8);
+        };
+        // window of the own row: plane kk in slot (kk - k0 + 2) & 3
+        double W[4][NV];
+#pragma unroll
+        for (int kz = 0; kz < 4; ++kz) {
+            const uint32_t o = plane_off(k0 - 2 + kz) + ro[2];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) W[kz][v] = ld_buf(rs, cboff, o + v * vstride);
+        }
+        double Fz[2][NV];  // z-face fluxes: face f in Fz[f & 1]
+        double lmax = 0.0;
+        uint32_t fl = 0;
+#pragma unroll 1
+        for (int m0 = 0; m0 <= seg; m0 += 4) {
+            if (k0 + m0 - 1 >= G.nz) break;  // ragged last segment (uniform)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int f = m0 + jj;
+                if (f > seg) break;          // uniform: only in the last group
+                const bool more = f < seg;   // another face follows
+                const int kk = k0 + f - 1;   // output plane finished at this face
+                // rows j-2, j-1, j+1, j+2 of plane kk, requested before the z face
+                double Y[4][NV];
+                double Unc[NV];
+                if (f > 0) {
+                    const uint32_t po = plane_off(kk);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const uint32_t o = po + ro[d < 2 ? d : d + 1];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) Y[d][v] = ld_buf(rs, cboff, o + v * vstride);
+                    }
+                    if (STAGE > 0) {
+                        const int kc = kk < G.nz ? kk : G.nz - 1;
+                        const uint32_t o = (uint32_t)((long long)kc * G.pz * 8) + (uint32_t)((long long)j * G.py * 8);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) Unc[v] = ld_buf(rn, oboff, o + v * vstride);
+                    }
+                }
+                double qL[NV], qR[NV];
+                // z face f: stencil planes kk-1 .. kk+2 in slots jj, jj+1, jj+2, jj+3 (mod 4)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    muscl(W[jj][v], W[(jj + 1) & 3][v], W[(jj + 2) & 3][v], W[(jj + 3) & 3][v], G.unlimited, qL[v],
+                          qR[v]);
+                roe_flux<3, 2>(qL, qR, G.gm1, Fz[jj & 1]);
+                double c[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) c[v] = W[(jj + 1) & 3][v];
+                // plane kk - 1 is dead: its slot takes plane kk + 3 for face f + 1
+                if (more) {
+                    const uint32_t o = plane_off(kk + 3) + ro[2];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) W[jj][v] = ld_buf(rs, cboff, o + v * vstride);
+                }
+                if (f == 0) continue;  // uniform: face 0 has no plane below it in the segment
+                // y faces of row j at plane kk: below (rows j-2 .. j+1) and above (rows j-1 .. j+2)
+                double Fyb[NV], Fyt[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) muscl(Y[0][v], Y[1][v], c[v], Y[2][v], G.unlimited, qL[v], qR[v]);
+                roe_flux<3, 1>(qL, qR, G.gm1, Fyb);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) muscl(Y[1][v], c[v], Y[2][v], Y[3][v], G.unlimited, qL[v], qR[v]);
+                roe_flux<3, 1>(qL, qR, G.gm1, Fyt);
+                // x faces: left face from the lanes to the left, right face one lane up
+                double Fxl[NV], Fxr[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double b = lane_shift1<true>(c[v]);
+                    const double a = lane_shift1<true>(b);
+                    const double d = lane_shift1<false>(c[v]);
+                    muscl(a, b, c[v], d, G.unlimited, qL[v], qR[v]);
+                }
+                roe_flux<3, 0>(qL, qR, G.gm1, Fxl);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
+                if (out_lane && kk < G.nz) {
+                    const uint32_t p = (uint32_t)((long long)kk * G.pz * 8) + (uint32_t)((long long)j * G.py * 8);
+                    double out[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        double r = (Fxr[v] - Fxl[v]) * G.ax;
+                        r += (Fyt[v] - Fyb[v]) * G.ay;
+                        r += (Fz[jj & 1][v] - Fz[(jj + 1) & 1][v]) * G.az;
+                        if (STAGE == 0) {
+                            out[v] = c[v] + s * r;
+                        } else if (STAGE == 1) {
+                            out[v] = 0.75 * Unc[v] + 0.25 * (c[v] + s * r);
+                        } else {
+                            out[v] = (1.0 / 3.0) * Unc[v] + (2.0 / 3.0) * (c[v] + s * r);
+                        }
+                        st_buf(rd, oboff, p + v * vstride, out[v]);
+                    }
+                    if (STAGE == 2) {
+                        const double idx[3] = {G.inv_dx, G.inv_dy, G.inv_dz};
+                        lmax = fmax(lmax, cell_lambda<3>(out, G.gamma, G.gm1, idx, fl));
+                    }
+                }
+                // keep the scheduler from overlapping consecutive planes (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (STAGE == 2) {
+            lmax = wave_max_d(lmax);
+            fl = wave_or(fl);
+            if (lane == 0) {
+                atomicMax(&lam[0], (unsigned long long)__double_as_longlong(lmax));
+                if (fl) atomicOr(status, fl);
+            }
+        }
+    }
+}
+
+// lambda_max of U^n (the first step's dt), same work items.
+__global__ void __launch_bounds__(256) k_fused3d_lambda(const FGrid3* __restrict__ grid, int nitems,
+                                                        const double* __restrict__ U,
+                                                        unsigned long long* __restrict__ lam,
+                                                        uint32_t* __restrict__ status) {
+    const int lane = threadIdx.x & 63;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int wave0 = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const FGrid3 G = *grid;
+    for (int item = wave0; item < nitems; item += nwaves) {
+        const int strip = item % G.strips;
+        const int t = item / G.strips;
+        const int j = t % G.ny;
+        const int zs = t / G.ny;
+        const int col = FW * strip + lane;
+        double lmax = 0.0;
+        uint32_t fl = 0;
+        if (lane < FW && col < G.nx) {
+            const double idx[3] = {G.inv_dx, G.inv_dy, G.inv_dz};
+            for (int kk = zs * G.seg; kk < zs * G.seg + G.seg && kk < G.nz; ++kk) {
+                const long long p = G.base + (long long)kk * G.pz + (long long)j * G.py + col;
+                double q[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) q[v] = U[v * G.sv + p];
+                lmax = fmax(lmax, cell_lambda<3>(q, G.gamma, G.gm1, idx, fl));
+            }
+        }
+        lmax = wave_max_d(lmax);
+        fl = wave_or(fl);
+        if (lane == 0) {
+            atomicMax(&lam[0], (unsigned long long)__double_as_longlong(lmax));
+            if (fl) atomicOr(status, fl);
+        }
+    }
+}
+
+__global__ void k_fused3d_reset(unsigned long long* lam) { lam[0] = 0ull; }
+
+// ---------------------------------------------------------------------------
+
+int fused3d_items(const FGrid3& G, int seg) {
+    return fused_strips(G.nx) * G.ny * ((G.nz + seg - 1) / seg);
+}
+
+static inline int blocks_for(int nitems, int waves) {
+    const int w = waves > 0 ? (waves < nitems ? waves : nitems) : nitems;
+    return (w + 3) / 4;
+}
+
+void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
+                          double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed, double* dt_out,
+                          uint32_t* status, hipStream_t s) {
+    const dim3 g(blocks_for(nitems, waves)), b(256);
+    if (stage == 0)
+        hipLaunchKernelGGL(k_fused3d<0>, g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status);
+    else if (stage == 1)
+        hipLaunchKernelGGL(k_fused3d<1>, g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status);
+    else
+        hipLaunchKernelGGL(k_fused3d<2>, g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status);
+}
+
+void launch_fused3d_init(int waves, const FGrid3* grid, int nitems, const double* U, unsigned long long* lam,
+                         uint32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_fused3d_reset, dim3(1), dim3(1), 0, s, lam);
+    hipLaunchKernelGGL(k_fused3d_lambda, dim3(blocks_for(nitems, waves)), dim3(256), 0, s, grid, nitems, U, lam,
+                       status);
+}
+
+int fused3d_slots() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    int b0 = 0, b1 = 0, b2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused3d<0>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused3d<1>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused3d<2>, 256, 0) != hipSuccess)
+        return 0;
+    const int bmin = b0 < b1 ? (b0 < b2 ? b0 : b2) : (b1 < b2 ? b1 : b2);
+    return bmin * 4 * cus;
+}
+
+// Segment height (a multiple of 4): as in 2D, the one minimising (rounds of
+// resident waves) x (planes per item + 1); ties go to the taller segment.
+int fused3d_auto_seg(const FGrid3& G, int slots) {
+    if (slots <= 0) return 16;
+    int best = 16;
+    double best_cost = 0.0;
+    for (int seg = 4; seg <= 256; seg += 4) {
+        const long long items = fused3d_items(G, seg);
+        const long long rounds = (items + slots - 1) / slots;
+        const double cost = (double)rounds * (seg + 1);
+        if (seg == 4 || cost <= best_cost) {
+            best_cost = cost;
+            best = seg;
+        }
+    }
+    return best;
+}
+
+}  // namespace fvk

@@ -16,6 +16,16 @@ struct FGrid {
     double inv_vol, inv_dx, inv_dy, cfl, gamma, gm1;
 };
 
+// The 3D grid of the fused path (device memory, read uniformly).
+struct FGrid3 {
+    int nx, ny, nz, strips, seg, unlimited;       // seg: planes per work item (a multiple of 4)
+    int bcx0, bcx1, bcy0, bcy1, bcz0, bcz1;
+    long long base;                                // element offset of cell (0,0,0), variable 0
+    long long sv, py, pz;                          // strides: variable, row (y), plane (z)
+    double ax, ay, az;                             // face areas: dy dz, dx dz, dx dy
+    double inv_vol, inv_dx, inv_dy, inv_dz, cfl, gamma, gm1;
+};
+
 void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t s);
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, double* R, const Geo& g, int gang,
@@ -36,6 +46,14 @@ void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, in
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s);
 int fused_slots();
+int fused3d_items(const FGrid3& G, int seg);
+void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
+                          double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed, double* dt_out,
+                          uint32_t* status, hipStream_t s);
+void launch_fused3d_init(int waves, const FGrid3* grid, int nitems, const double* U, unsigned long long* lam,
+                         uint32_t* status, hipStream_t s);
+int fused3d_slots();
+int fused3d_auto_seg(const FGrid3& G, int slots);
 int fused_auto_seg(const FGrid* grids, int ngrids, int slots);
 
 // adjoint

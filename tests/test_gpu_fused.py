@@ -1,5 +1,6 @@
-"""The fused 2D stage kernels (single grid through fv_step's fused path, and
-batches of uneven grids through fv_batch_*) against the FP64 oracle."""
+"""The fused stage kernels (2D and 3D single grids through fv_step's fused
+path, and batches of uneven 2D grids through fv_batch_*) against the FP64
+oracle."""
 import numpy as np
 import pytest
 
@@ -120,13 +121,86 @@ def test_fused_full_size_one_step():
     close(got, ref, what="2048^2 fused")
 
 
-def test_fused_rejects_3d():
-    fv = _fv()
-    s = fv.Solver(inputs.grid3d(8, 8, 8))
-    with pytest.raises(fv.FvError) as e:
-        s.set_path(1, 16, 0)
-    assert e.value.code == fv.FV_ENOTSUP
-    s.close()
+def smooth_3d(g, seed=0):
+    """A smooth periodic 3D state with all velocity components non-zero."""
+    x, y, z = g.centres()
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 6)
+    L = [g.hi[a] - g.lo[a] for a in range(3)]
+    X, Y, Z = (2 * np.pi * x / L[0], 2 * np.pi * y / L[1], 2 * np.pi * z / L[2])
+    rho = 1.0 + 0.2 * np.sin(X + ph[0]) * np.sin(Y + ph[1]) * np.cos(Z + ph[2])
+    u = 0.3 + 0.1 * np.sin(Y + ph[3])
+    v = -0.2 + 0.1 * np.cos(Z + ph[4])
+    w = 0.25 + 0.1 * np.sin(X + ph[5])
+    p = 1.0 + 0.1 * np.cos(X + Y + Z)
+    return inputs.primitive_to_conserved(g, rho, (u, v, w), p)
+
+
+CASES_3D = [
+    ("tilted_sod", lambda: (lambda g: (g, inputs.sod_state(g, inputs.sod_rotated_normal(3), (0.5, 0.5, 0.5))))(inputs.grid3d(20, 17, 13))),
+    ("smooth_periodic", lambda: (lambda g: (g, smooth_3d(g, 1)))(inputs.grid3d(22, 19, 17, bc=((0, 0), (0, 0), (0, 0))))),
+    ("transmissive_z", lambda: (lambda g: (g, inputs.sod_state(g, (0.0, 0.3, 0.95), (0.5, 0.5, 0.5))))(inputs.grid3d(12, 9, 23, bc=((0, 0), (1, 1), (1, 1))))),
+    ("thin_planes", lambda: (lambda g: (g, smooth_3d(g, 2)))(inputs.grid3d(70, 3, 1, bc=((0, 0), (1, 1), (0, 0))))),
+    ("single_cell_y", lambda: (lambda g: (g, inputs.sod_state(g, (0.6, 0.0, 0.8), (0.5, 0.5, 0.5))))(inputs.grid3d(9, 1, 30))),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES_3D, ids=[c[0] for c in CASES_3D])
+def test_fused3d_one_step_matches_oracle(name, make):
+    g, U0 = make()
+    got, dts, flags = run_fused(g, U0, 1)
+    ref, rdts, _ = oracle.run(g, U0, 1)
+    assert flags == 0
+    assert abs(dts[0] - rdts[0]) <= 1e-14 * rdts[0]
+    close(got, ref, what=name)
+
+
+def test_fused3d_steps_frozen_dt_and_split_agreement():
+    g, U0 = CASES_3D[1][1]()
+    got, dts, flags = run_fused(g, U0, 5)
+    ref, rdts, _ = oracle.run(g, U0, 5)
+    assert flags == 0 and np.allclose(dts, rdts, rtol=1e-13, atol=0)
+    close(got, ref, tol=1e-11, what="3d 5 steps")
+    dt_in = [0.9 * rdts[0], 0.7 * rdts[0]]
+    got, dts, _ = run_fused(g, U0, 2, dt_in=dt_in)
+    assert np.array_equal(dts, dt_in)
+    close(got, oracle.run(g, U0, 2, dt_in=np.array(dt_in))[0], what="3d frozen dt")
+    split, _, _ = run_fused(g, U0, 5, path=0)
+    fused, _, _ = run_fused(g, U0, 5)
+    close(fused, split, tol=1e-13, what="3d fused vs split")
+
+
+def test_fused3d_schedules_bitwise_equal():
+    g, U0 = CASES_3D[0][1]()
+    base, _, _ = run_fused(g, U0, 3, seg=16, waves=0)
+    for seg, waves in ((4, 0), (8, 0), (12, 3), (20, 0), (0, 0), (16, 50)):
+        got, _, _ = run_fused(g, U0, 3, seg=seg, waves=waves)
+        assert np.array_equal(got, base), (seg, waves)
+
+
+def test_fused3d_full_size_sampled_patches():
+    # 256^3 rotated Sod, one fused step; the oracle recomputes sampled 20^3
+    # patches with the same dt (a cell depends on cells at most 6 away)
+    g, U0 = inputs.sod3d_case(256, seed=0)
+    got, dts, flags = run_fused(g, U0, 1, seg=0)
+    dt_ref, _ = oracle.dt(g, U0)
+    assert flags == 0 and abs(dts[0] - dt_ref) <= 1e-14 * dt_ref
+    rng = np.random.default_rng(9)
+    P, H = 20, 6
+    checked = 0
+    for _ in range(8):
+        o = rng.integers(0, 256, size=3)
+        if o[0] + P > 256:
+            continue   # the x faces are transmissive: a wrapped patch is not periodic there
+        idx = [(o[a] + np.arange(P)) % 256 for a in range(3)]
+        patch = U0[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+        pg = inputs.grid3d(P, P, P, hi=(P / 256.0,) * 3, bc=((1, 1), (1, 1), (1, 1)))
+        ref = oracle.rk3_step(pg, patch, dts[0])[:, H:-H, H:-H, H:-H]
+        gp = got[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]][:, H:-H, H:-H, H:-H]
+        scale = np.abs(ref).max()
+        assert np.abs(gp - ref).max() <= 1e-12 * scale, o
+        checked += 1
+    assert checked >= 3
 
 
 def small_batch(seed=3, count=7):
