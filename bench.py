@@ -13,7 +13,8 @@ by the MLP autotuner (~300 timed samples, network trained on the GPU, whole
 space predicted, top 8 re-measured).
 
 Other legs (each reported in its own field):
-  split_3d  256^3 rotated Sod, split path, default vs tuned (x/y/z fluxes separately)
+  split_3d  256^3 rotated Sod, split path, default vs tuned (x/y/z fluxes separately),
+            and the same workload on the fused path
   small     64^2 vortex: fused by direct launches vs graph-replayed batch of one
   batch     96 uneven 2D grids, fused stages in a HIP graph, schedule (segment height per
             grid-size bucket, work-list order) chosen by the MLP autotuner; p50/p99 per-grid step time
@@ -472,6 +473,18 @@ def main():
         out["split_3d"] = split_leg(torch, fv, traffic, g3, U3, argparse.Namespace(
             steps=20, warmup=2, timing_steps=5, seed=a.seed), a.samples_3d, not a.no_tune,
             sample_timing=(1, 1, 10.0, 1))
+        # the same 3D workload on the fused path (one kernel per stage)
+        s3 = fv.Solver(g3)
+        s3.set_path(fv.FV_PATH_FUSED, 0, 0)
+        ms3 = timed_steps(torch, s3, U3, 20, 2)
+        k3 = site_table(s3, g3, 5, fv, traffic)["fused"]
+        out["split_3d"]["fused"] = {
+            "seg": s3.get_path()[1], "ms_per_step": ms3, "value": g3.ncells / (ms3 * 1e-3),
+            "stage_avg_us": k3["avg_us"], "over_split_default": round(out["split_3d"]["default_ms_per_step"] / ms3, 3),
+            "alg_bytes_per_cell_update": traffic.fused_step_bytes(g3) / g3.ncells,
+            "hbm_achieved_GBps": round(traffic.fused_step_bytes(g3) / 3.0 / (k3["avg_us"] * 1e-6) / 1e9, 1)}
+        s3.close()
+        log(f"fused 3D: {ms3:.4f} ms/step, {out['split_3d']['fused']['value']:.3e} cell-updates/s")
         del U3
     out["copy"] = copy_leg(torch)
     if not a.quick:
