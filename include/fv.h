@@ -263,6 +263,10 @@ int fv_batch_set_schedule(fv_batch* b, const int32_t* segs, int32_t order);
  * may be NULL. */
 int fv_batch_info(const fv_batch* b, int32_t* segs, int32_t* order, int32_t* nitems);
 
+/* Message of the last failing call on b (or of fv_batch_query /
+ * fv_batch_create when b is NULL). Never NULL. */
+const char* fv_batch_last_error(const fv_batch* b);
+
 int fv_batch_destroy(fv_batch* b);
 
 /* ------------------------------------------------------------------------

@@ -362,6 +362,8 @@ int fv_batch_info(const fv_batch* b, int32_t* segs, int32_t* order, int32_t* nit
     return FV_OK;
 }
 
+const char* fv_batch_last_error(const fv_batch* b) { return b ? b->err : g_berr; }
+
 int fv_batch_destroy(fv_batch* b) {
     if (!b) return FV_EINVAL;
     drop_graph(b);

@@ -145,6 +145,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int32)]
         L.fv_batch_set_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.fv_batch_destroy.argtypes = [_vp]
+        L.fv_batch_last_error.argtypes = [_vp]
+        L.fv_batch_last_error.restype = ctypes.c_char_p
         L.fv_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_sweep_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp, _vp,
@@ -305,8 +307,8 @@ def fv_batch_query(specs):
 
 
 def _batch_check(rc, b=None):
-    if rc not in (FV_OK,):
-        raise FvError(rc, "batch call failed")
+    if rc != FV_OK:
+        raise FvError(rc, lib().fv_batch_last_error(b).decode())
     return rc
 
 
@@ -319,24 +321,24 @@ def fv_batch_create(specs, seg, waves, order, ws_ptr, ws_bytes, stream_ptr):
 
 
 def fv_batch_step(b, U_ptr, nsteps):
-    return _batch_check(lib().fv_batch_step(_vp(b), _vp(U_ptr), int(nsteps)))
+    return _batch_check(lib().fv_batch_step(_vp(b), _vp(U_ptr), int(nsteps)), b)
 
 
 def fv_batch_set_timing(b, history_ptr, max_steps):
     tpu = ctypes.c_double()
-    _batch_check(lib().fv_batch_set_timing(_vp(b), _vp(history_ptr), int(max_steps), ctypes.byref(tpu)))
+    _batch_check(lib().fv_batch_set_timing(_vp(b), _vp(history_ptr), int(max_steps), ctypes.byref(tpu)), b)
     return tpu.value
 
 
 def fv_batch_dt(b, dt_ptr):
-    return _batch_check(lib().fv_batch_dt(_vp(b), _vp(dt_ptr)))
+    return _batch_check(lib().fv_batch_dt(_vp(b), _vp(dt_ptr)), b)
 
 
 def fv_batch_status(b):
     fl = ctypes.c_uint32()
     rc = lib().fv_batch_status(_vp(b), ctypes.byref(fl))
     if rc not in (FV_OK, FV_ENONPHYS):
-        _batch_check(rc)
+        _batch_check(rc, b)
     return rc, fl.value
 
 
@@ -344,7 +346,7 @@ def fv_batch_info(b, ngrids):
     """(segment height per grid, work-list order, work items per stage launch)."""
     segs = (ctypes.c_int32 * ngrids)()
     order, n = ctypes.c_int32(), ctypes.c_int32()
-    _batch_check(lib().fv_batch_info(_vp(b), segs, ctypes.byref(order), ctypes.byref(n)))
+    _batch_check(lib().fv_batch_info(_vp(b), segs, ctypes.byref(order), ctypes.byref(n)), b)
     return list(segs), order.value, n.value
 
 
