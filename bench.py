@@ -51,7 +51,8 @@ def parse():
     ap.add_argument("--samples", type=int, default=300, help="timed launch vectors for the 2D tuner")
     ap.add_argument("--samples-3d", type=int, default=2000, help="timed launch vectors for the 3D tuner")
     ap.add_argument("--samples-batch", type=int, default=300, help="timed schedules for the batch tuner")
-    ap.add_argument("--quick", action="store_true", help="headline and split default only")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline, split default and the 3D workload untuned only")
     ap.add_argument("--seg", type=int, default=-1,
                     help="fused segment height: -1 sweeps a few and keeps the fastest, 0 is the library's choice")
     ap.add_argument("--no-tune", action="store_true")
@@ -63,7 +64,7 @@ def parse():
     ap.add_argument("--timing-steps", type=int, default=20)
     a = ap.parse_args()
     if a.quick:
-        a.no_tune = a.no_3d = a.no_batch = a.no_adjoint = a.no_cpu = True
+        a.no_tune = a.no_batch = a.no_adjoint = a.no_cpu = True
     return a
 
 
