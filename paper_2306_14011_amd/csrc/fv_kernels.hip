@@ -101,6 +101,58 @@ __global__ void __launch_bounds__(MAXT) k_flux(const double* __restrict__ U, dou
     }
 }
 
+// Faces along y or z (AX = 1, 2): each thread walks a run of RUN consecutive
+// faces of its column with a window of four cells in registers, so each cell
+// is loaded once per run instead of four times. Same face arithmetic.
+template <int NDIM, int AX, int MAXT, int RUN>
+__global__ void __launch_bounds__(MAXT) k_flux_run(const double* __restrict__ U, double* __restrict__ F, Geo g) {
+    constexpr int NV = NDIM + 2;
+    static_assert(AX >= 1 && RUN % 4 == 0, "runs march along y or z in groups of four");
+    const int cols = g.n[0];
+    const int rows_j = g.n[1] + (AX == 1 ? 1 : 0);
+    const int rows_k = NDIM == 3 ? g.n[2] + (AX == 2 ? 1 : 0) : 1;
+    const int nax = AX == 1 ? rows_j : rows_k;   // faces along the axis
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cols) return;
+    const int st = AX == 1 ? g.sy : g.sz;
+    const long long fsv = g.fsv[AX];
+    // the other (non-marching) index: k for AX = 1 (grid z), j for AX = 2 (grid y)
+    const int other = AX == 1 ? (int)blockIdx.z : (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    if (AX == 2 && other >= rows_j) return;
+    const int r0 = AX == 1 ? (int)(blockIdx.y * blockDim.y + threadIdx.y) : (int)blockIdx.z;
+    const int rstride = AX == 1 ? (int)(gridDim.y * blockDim.y) : (int)gridDim.z;
+    for (int run = r0; run * RUN < nax; run += rstride) {
+        const int a0 = run * RUN;   // first face of the run
+        const int j = AX == 1 ? a0 : other, k = AX == 1 ? other : a0;
+        const int c0 = g.off0 + i + j * g.sy + k * g.sz;  // right cell of face a0
+        double W[4][NV];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) W[q][v] = U[v * g.sv + c0 + (q - 2) * st];
+#pragma unroll
+        for (int t = 0; t < RUN; ++t) {
+            const int a = a0 + t;
+            if (a >= nax) break;
+            // face a: cells a-2 .. a+1 in slots t, t+1, t+2, t+3 (mod 4)
+            double qL[NV], qR[NV], Fl[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                muscl(W[t & 3][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], g.unlimited, qL[v],
+                      qR[v]);
+            roe_flux<NDIM, AX>(qL, qR, g.gm1, Fl);
+            const int fj = AX == 1 ? a : j, fk = AX == 1 ? k : a;
+            const long long f = (long long)(fk * rows_j + fj) * cols + i;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v * fsv + f] = Fl[v];
+            if (t + 1 < RUN && a + 1 < nax) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) W[t & 3][v] = U[v * g.sv + c0 + (t + 2) * st];  // cell a + 2
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Interior cell e -> (i, j, k) and its offset in the ghosted layout.
 __device__ __forceinline__ void decode_cell(int e, const Geo& g, int& i, int& j, int& k) {
@@ -267,19 +319,40 @@ void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t 
         hipLaunchKernelGGL(k_bc_fill<5>, dim3(blocks), dim3(threads), 0, s, U, g, total, seg0, seg1, stride_all);
 }
 
+constexpr int FLUX_RUN = 8;  // faces per thread of the y / z flux kernels
+
 template <int NDIM, int AX>
 static void launch_flux_t(const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s) {
     const int by = threads / bx;
     const int cols = g.n[0] + (AX == 0 ? 1 : 0);
     const int rows_j = g.n[1] + (AX == 1 ? 1 : 0);
     const int rows_k = NDIM == 3 ? g.n[2] + (AX == 2 ? 1 : 0) : 1;
-    int gy = blocks_for(rows_j, by);
-    if (gy > 65535) gy = 65535;
-    dim3 grid(blocks_for(cols, bx), gy, rows_k);
-    dim3 block(bx, by);
+    // 3D blocks of 1024 threads leave 128 registers per lane, too few for the
+    // five-variable window: those keep one face per thread
+    if (AX == 0 || (NDIM == 3 && threads == 1024)) {
+        int gy = blocks_for(rows_j, by);
+        if (gy > 65535) gy = 65535;
+        dim3 grid(blocks_for(cols, bx), gy, rows_k);
+        dim3 block(bx, by);
 #define FV_LF(T) hipLaunchKernelGGL((k_flux<NDIM, AX, T>), grid, block, 0, s, U, F, g)
-    FV_DISPATCH_THREADS(threads, FV_LF)
+        FV_DISPATCH_THREADS(threads, FV_LF)
 #undef FV_LF
+        return;
+    }
+    const int runs = AX == 1 ? blocks_for(rows_j, FLUX_RUN) : blocks_for(rows_k, FLUX_RUN);
+    dim3 grid, block(bx, by);
+    if (AX == 1) {
+        int gy = blocks_for(runs, by);
+        if (gy > 65535) gy = 65535;
+        grid = dim3(blocks_for(cols, bx), gy, rows_k);
+    } else {
+        int gy = blocks_for(rows_j, by);
+        if (gy > 65535) gy = 65535;  // rows_j <= 65535 * by for every valid grid
+        grid = dim3(blocks_for(cols, bx), gy, runs);
+    }
+#define FV_LFR(T) hipLaunchKernelGGL((k_flux_run<NDIM, (AX > 0 ? AX : 1), T, FLUX_RUN>), grid, block, 0, s, U, F, g)
+    FV_DISPATCH_THREADS(threads, FV_LFR)
+#undef FV_LFR
 }
 
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s) {
