@@ -120,5 +120,5 @@ def test_batch_query_offsets_and_validation():
     fv.fv_batch_query([inputs.grid2d(8192, 16383)])
     with pytest.raises(fv.FvError) as e:
         fv.fv_batch_query([inputs.grid2d(8192, 16384)])
-    assert e.value.code == fv.FV_EINVAL
+    assert e.value.code == fv.FV_EINVAL and "4 GiB" in str(e.value)   # the library's own message
 
