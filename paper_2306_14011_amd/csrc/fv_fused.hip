@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
                         } else {
                             out[v] = (1.0 / 3.0) * Unb[j & 1][v] + (2.0 / 3.0) * (c[v] + s * r);
                         }
-                        st_buf(rd, oboff, p + v * vstride, out[v]);
+                        st_buf<true>(rd, oboff, p + v * vstride, out[v]);
                     }
                     if (STAGE == 2) {
                         const double idx[2] = {G.inv_dx, G.inv_dy};

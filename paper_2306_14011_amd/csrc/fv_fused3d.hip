@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256) k_fused3d(const FGrid3* __restrict__ grid
                         } else {
                             out[v] = (1.0 / 3.0) * Unc[v] + (2.0 / 3.0) * (c[v] + s * r);
                         }
-                        st_buf(rd, oboff, p + v * vstride, out[v]);
+                        st_buf<false>(rd, oboff, p + v * vstride, out[v]);
                     }
                     if (STAGE == 2) {
                         const double idx[3] = {G.inv_dx, G.inv_dy, G.inv_dz};
