@@ -100,6 +100,19 @@ __host__ __device__ __forceinline__ void muscl_minmod(double q0, double q1, doub
     qR = q2 - 0.5 * minmod(dp, dc);
 }
 
+// The same with the choice fixed at compile time (UNL: Psi = 1), for loops
+// that must stay free of branches.
+template <bool UNL>
+__host__ __device__ __forceinline__ void muscl_fixed(double q0, double q1, double q2, double q3, double& qL,
+                                                    double& qR) {
+    if (UNL) {
+        qL = q1 + 0.5 * (q1 - q0);
+        qR = q2 - 0.5 * (q3 - q2);
+    } else {
+        muscl_minmod(q0, q1, q2, q3, qL, qR);
+    }
+}
+
 // The same with Psi = 1 when `unlimited` (a uniform run-time switch).
 __host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, double q3, int unlimited,
                                               double& qL, double& qR) {

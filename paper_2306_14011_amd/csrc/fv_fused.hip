@@ -26,13 +26,145 @@
 
 namespace fvk {
 
+// The rows of one work item (strip, rows r0 .. r0 + seg - 1) for stage STAGE
+// with the limiter fixed at compile time (UNL: Psi = 1). The loop body has
+// no branch around a memory access: every load is issued whatever the row
+// (indices past the grid are clamped), and the stores of lanes or rows with
+// no output go to an offset past the end of the buffer, where the hardware
+// drops them. A conditional load or store would make the compiler's wait
+// counting assume the shortest path and wait for every outstanding access
+// (the prefetches included) at the top of each row.
+template <int STAGE, bool UNL>
+__device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip, int r0, double s, const double* Un,
+                                             const double* Us, double* Ud, double& lmax, uint32_t& fl) {
+    constexpr int NV = 4;
+    const int seg = G.seg;
+    const int col = FW * strip - 2 + lane;
+    const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
+    const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
+    const long long gbytes = 4 * G.sv * 8;  // one grid's state, below 4 GiB
+    const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes);
+    // one descriptor per output variable: the plane is below 1 GiB, so the
+    // drop offset plus any row offset stays past the end without wrapping
+    Rsrc rd[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rd[v] = grid_rsrc(Ud + G.base + v * G.sv, G.sv * 8);
+    const uint32_t cboff = (uint32_t)cmap * 8u;                // this lane's (mapped) column in bytes
+    const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column for U^n reads
+    const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
+    const uint32_t vstride = (uint32_t)(G.sv * 8);
+    // byte offset of U_s row r through the y boundary map (rows past the
+    // last halo row are clamped inside the grid; they feed no output)
+    auto row_off = [&](int r) -> uint32_t {
+        return (uint32_t)((long long)map_index(r, G.ny, G.bcy0, G.bcy1) * G.pitch * 8);
+    };
+    auto out_row = [&](int r) -> uint32_t { return (uint32_t)((long long)(r < G.ny ? r : G.ny - 1) * G.pitch * 8); };
+    // Circular window of four U_s rows: row r sits in slot (r - r0 + 2) & 3.
+    // Face f of the segment (f = 0 .. seg) lies between rows r0 + f - 1 and
+    // r0 + f, and its stencil rows are in slots f, f + 1, f + 2, f + 3
+    // (mod 4). Face 0 is computed first; faces 1 .. seg follow in unrolled
+    // groups of four, so each slot index is a compile-time constant and the
+    // window never moves between registers. Since r0 is a multiple of 4, a
+    // given face of the grid is computed by the same instructions whatever
+    // the segment height (face 0 of a segment repeats the loop's sequence).
+    double W[4][NV];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t o = row_off(r0 - 2 + k);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[k][v] = ld_buf(rs, cboff, o + v * vstride);
+    }
+    double Fy[2][NV];   // y-face fluxes: face f in Fy[f & 1]
+    double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
+    double qL[NV], qR[NV];
+    if (STAGE > 0) {
+        const uint32_t pn = out_row(r0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Unb[1][v] = ld_buf(rn, oboff, pn + v * vstride);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(W[0][v], W[1][v], W[2][v], W[3][v], qL[v], qR[v]);
+    roe_flux<2, 1>(qL, qR, G.gm1, Fy[0]);
+    {
+        const uint32_t o = row_off(r0 + 2);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[0][v] = ld_buf(rs, cboff, o + v * vstride);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll 1
+    for (int m0 = 1; m0 <= seg; m0 += 4) {
+        if (r0 + m0 - 1 >= G.ny) break;  // ragged last segment (uniform)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int f = m0 + j;
+            const int t = (j + 1) & 3;  // f mod 4, a compile-time constant
+            const int rr = r0 + f - 1;  // output row finished at this face
+            if (STAGE > 0) {
+                // U^n of row rr + 1, used at face f + 1
+                const uint32_t pn = out_row(rr + 1);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Unb[(t + 1) & 1][v] = ld_buf(rn, oboff, pn + v * vstride);
+            }
+            // y face f: stencil rows rr-1 .. rr+2
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                muscl_fixed<UNL>(W[t][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], qL[v], qR[v]);
+            roe_flux<2, 1>(qL, qR, G.gm1, Fy[t & 1]);
+            double c[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) c[v] = W[(t + 1) & 3][v];
+            // row rr - 1 is dead: its slot takes row rr + 3 for face f + 1
+            {
+                const uint32_t o = row_off(rr + 3);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
+            }
+            // x faces of row rr: left face from the lanes to the left, right face one lane up
+            double Fxl[NV], Fxr[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double b = lane_shift1<true>(c[v]);
+                const double a = lane_shift1<true>(b);
+                const double d = lane_shift1<false>(c[v]);
+                muscl_fixed<UNL>(a, b, c[v], d, qL[v], qR[v]);
+            }
+            roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
+            const bool row_ok = rr < G.ny;  // uniform
+            const uint32_t p = out_row(rr);
+            const uint32_t so = row_ok ? sboff : DROP_OFFSET;
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double r = (Fxr[v] - Fxl[v]) * G.ax;
+                r += (Fy[t & 1][v] - Fy[(t + 1) & 1][v]) * G.ay;
+                if (STAGE == 0) {
+                    out[v] = c[v] + s * r;
+                } else if (STAGE == 1) {
+                    out[v] = 0.75 * Unb[t & 1][v] + 0.25 * (c[v] + s * r);
+                } else {
+                    out[v] = (1.0 / 3.0) * Unb[t & 1][v] + (2.0 / 3.0) * (c[v] + s * r);
+                }
+                st_buf<true>(rd[v], so, p, out[v]);
+            }
+            if (STAGE == 2 && out_lane && row_ok) {
+                const double idx[2] = {G.inv_dx, G.inv_dy};
+                lmax = fmax(lmax, cell_lambda<2>(out, G.gamma, G.gm1, idx, fl));
+            }
+            // keep the scheduler from overlapping consecutive rows, which
+            // would raise the live register count beyond 128
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 template <int STAGE>
 __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems,
                                                  const double* Un, const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                  const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
                                                  uint32_t* __restrict__ status, unsigned long long* __restrict__ clk) {
-    constexpr int NV = 4;
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int wave0 = __builtin_amdgcn_readfirstlane(
@@ -47,7 +179,6 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         const int local = item - G.work0;
         const int strip = local % G.strips;
         const int sidx = local / G.strips;
-        const int seg = G.seg;
         double dt;
         if (STAGE == 0) {
             dt = dt_fixed ? dt_fixed[G.gid] : G.cfl / __longlong_as_double((long long)lam[G.gid]);
@@ -60,110 +191,12 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
             dt = dtg[G.gid];
         }
         const double s = -dt * G.inv_vol;
-        const int col = FW * strip - 2 + lane;
-        const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
-        const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
-        const int r0 = sidx * seg;
-        const long long gbytes = 4 * G.sv * 8;  // one grid's state, below 4 GiB
-        const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes),
-                   rd = grid_rsrc(Ud + G.base, gbytes);
-        const uint32_t cboff = (uint32_t)cmap * 8u;  // this lane's column in bytes
-        // byte offset of variable v, U_s row r through the y boundary map
-        // (rows past the last halo row are clamped inside the grid; they feed no output)
-        auto row_off = [&](int r) -> uint32_t {
-            return (uint32_t)((long long)map_index(r, G.ny, G.bcy0, G.bcy1) * G.pitch * 8);
-        };
-        const uint32_t vstride = (uint32_t)(G.sv * 8);
-        // Circular window of four U_s rows: row r sits in slot (r - r0 + 2) & 3.
-        // The loop visits the y faces f = 0 .. seg of the segment (face f lies
-        // between rows r0 + f - 1 and r0 + f) in unrolled groups of four, so
-        // every slot index is a compile-time constant and the window never
-        // moves between registers. Face f is always computed by unrolled copy
-        // f mod 4, and since r0 is a multiple of 4 a given face of the grid
-        // gets the same machine code (and bits) whatever the segment height.
-        double W[4][NV];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t o = row_off(r0 - 2 + k);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) W[k][v] = ld_buf(rs, cboff, o + v * vstride);
-        }
-        double Fy[2][NV];   // y-face fluxes: face f in Fy[f & 1]
-        double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
-        const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column in bytes
         double lmax = 0.0;
         uint32_t fl = 0;
-#pragma unroll 1
-        for (int m0 = 0; m0 <= seg; m0 += 4) {
-            if (r0 + m0 - 1 >= G.ny) break;  // ragged last segment (uniform)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int f = m0 + j;
-                if (f > seg) break;          // uniform: only in the last group
-                const bool more = f < seg;   // another face follows
-                const int rr = r0 + f - 1;   // output row finished at this face
-                if (STAGE > 0 && more) {
-                    // U^n of row rr + 1, used at face f + 1
-                    const int fr = rr + 1 < G.ny ? rr + 1 : G.ny - 1;
-                    const uint32_t pn = (uint32_t)((long long)fr * G.pitch * 8);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Unb[(j + 1) & 1][v] = ld_buf(rn, oboff, pn + v * vstride);
-                }
-                double qL[NV], qR[NV];
-                // y face f: stencil rows rr-1 .. rr+2 in slots j, j+1, j+2, j+3 (mod 4)
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    muscl(W[j][v], W[(j + 1) & 3][v], W[(j + 2) & 3][v], W[(j + 3) & 3][v], G.unlimited, qL[v],
-                          qR[v]);
-                roe_flux<2, 1>(qL, qR, G.gm1, Fy[j & 1]);
-                double c[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) c[v] = W[(j + 1) & 3][v];
-                // row rr - 1 is dead: its slot takes row rr + 3 for face f + 1
-                if (more) {
-                    const uint32_t o = row_off(rr + 3);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) W[j][v] = ld_buf(rs, cboff, o + v * vstride);
-                }
-                if (f == 0) continue;  // uniform: the first face has no row below it in the segment
-                // x faces of row rr: left face from the lanes to the left, right face one lane up
-                double Fxl[NV], Fxr[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double b = lane_shift1<true>(c[v]);
-                    const double a = lane_shift1<true>(b);
-                    const double d = lane_shift1<false>(c[v]);
-                    muscl(a, b, c[v], d, G.unlimited, qL[v], qR[v]);
-                }
-                roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
-                if (out_lane && rr < G.ny) {
-                    const uint32_t p = (uint32_t)((long long)rr * G.pitch * 8);
-                    double out[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        double r = (Fxr[v] - Fxl[v]) * G.ax;
-                        r += (Fy[j & 1][v] - Fy[(j + 1) & 1][v]) * G.ay;
-                        if (STAGE == 0) {
-                            out[v] = c[v] + s * r;
-                        } else if (STAGE == 1) {
-                            out[v] = 0.75 * Unb[j & 1][v] + 0.25 * (c[v] + s * r);
-                        } else {
-                            out[v] = (1.0 / 3.0) * Unb[j & 1][v] + (2.0 / 3.0) * (c[v] + s * r);
-                        }
-                        st_buf<true>(rd, oboff, p + v * vstride, out[v]);
-                    }
-                    if (STAGE == 2) {
-                        const double idx[2] = {G.inv_dx, G.inv_dy};
-                        lmax = fmax(lmax, cell_lambda<2>(out, G.gamma, G.gm1, idx, fl));
-                    }
-                }
-                // keep the scheduler from overlapping consecutive rows, which
-                // would raise the live register count beyond 128
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
+        if (G.unlimited)
+            fused2d_rows<STAGE, true>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl);
+        else
+            fused2d_rows<STAGE, false>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl);
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
             fl = wave_or(fl);

@@ -56,6 +56,12 @@ __device__ __forceinline__ double ld_buf(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
+// Per-lane store offset for lanes with nothing to write: past the end of any
+// buffer these kernels address (at most 2^31 bytes per descriptor used for
+// stores, with scalar offsets below 2^31), so the buffer range check drops
+// the store. Keeps lane-masked stores out of conditional blocks.
+constexpr uint32_t DROP_OFFSET = 0x80000000u;
+
 // NT: the store carries the non-temporal hint (cache policy bit 1). The 2D
 // stage kernel's outputs are read a whole launch later, and keeping them out
 // of L2's working set leaves room for the halo rows that neighbouring work

@@ -64,7 +64,9 @@ def test_fused_equals_split():
     g, U0 = inputs.vortex_bumps_case(150, seed=4)
     a, da, _ = run_fused(g, U0, 5, path=1)
     b, db, _ = run_fused(g, U0, 5, path=0)
-    assert np.array_equal(da, db)
+    # the two paths round the same arithmetic in different orders (states
+    # agree to a few ulps), so dt = cfl / lambda_max agrees to rounding
+    assert np.allclose(da, db, rtol=1e-14, atol=0)
     close(a, b, tol=1e-14, what="fused vs split")
     print("fused == split bitwise:", np.array_equal(a, b))
 
