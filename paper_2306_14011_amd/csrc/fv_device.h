@@ -82,22 +82,36 @@ __host__ __device__ __forceinline__ double rsqrt_nr(double a) {
 }
 
 // minmod(a, b): zero unless a and b share a strict sign, else the one of smaller
-// magnitude. Written as max(0, min(a, b)) + min(0, max(a, b)): for two positive
-// slopes the first term is the smaller and the second 0, for two negative ones
-// the reverse, and for mixed signs or a zero both terms vanish. No product, so
-// tiny slopes do not underflow, and no compares or selects (four min/max and
-// one add).
+// magnitude, i.e. the median of a, b and 0, written as
+// max(min(a, b), min(max(a, b), 0)): for two positive slopes the inner min
+// with 0 gives 0 and the outer max the smaller slope, for two negative ones
+// the inner min gives the one nearer 0, and for mixed signs or a zero the
+// result is 0. No product, so tiny slopes do not underflow, and no compares
+// or selects (four min/max).
 __host__ __device__ __forceinline__ double minmod(double a, double b) {
-    return fmax(0.0, fmin(a, b)) + fmin(0.0, fmax(a, b));
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// MUSCL face states from the three differences of the stencil,
+// dm = q1 - q0, dc = q2 - q1, dp = q3 - q2 (for callers that share them
+// between neighbouring faces); UNL selects Psi = 1.
+template <bool UNL>
+__host__ __device__ __forceinline__ void muscl_from_diffs(double q1, double q2, double dm, double dc, double dp,
+                                                         double& qL, double& qR) {
+    if (UNL) {
+        qL = q1 + 0.5 * dm;
+        qR = q2 - 0.5 * dp;
+    } else {
+        qL = q1 + 0.5 * minmod(dm, dc);
+        qR = q2 - 0.5 * minmod(dp, dc);
+    }
 }
 
 // MUSCL face states (epsilon = 1, kappa = -1, minmod) at face k+1/2 of the
 // cells q0 = k-1, q1 = k, q2 = k+1, q3 = k+2.
 __host__ __device__ __forceinline__ void muscl_minmod(double q0, double q1, double q2, double q3,
                                              double& qL, double& qR) {
-    const double dm = q1 - q0, dc = q2 - q1, dp = q3 - q2;
-    qL = q1 + 0.5 * minmod(dm, dc);
-    qR = q2 - 0.5 * minmod(dp, dc);
+    muscl_from_diffs<false>(q1, q2, q1 - q0, q2 - q1, q3 - q2, qL, qR);
 }
 
 // The same with the choice fixed at compile time (UNL: Psi = 1), for loops
@@ -105,12 +119,7 @@ __host__ __device__ __forceinline__ void muscl_minmod(double q0, double q1, doub
 template <bool UNL>
 __host__ __device__ __forceinline__ void muscl_fixed(double q0, double q1, double q2, double q3, double& qL,
                                                     double& qR) {
-    if (UNL) {
-        qL = q1 + 0.5 * (q1 - q0);
-        qR = q2 - 0.5 * (q3 - q2);
-    } else {
-        muscl_minmod(q0, q1, q2, q3, qL, qR);
-    }
+    muscl_from_diffs<UNL>(q1, q2, q1 - q0, q2 - q1, q3 - q2, qL, qR);
 }
 
 // The same with Psi = 1 when `unlimited` (a uniform run-time switch).

@@ -119,14 +119,15 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
 #pragma unroll
                 for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
             }
-            // x faces of row rr: left face from the lanes to the left, right face one lane up
+            // x faces of row rr: left face from the lanes to the left, right
+            // face one lane up. Each lane forms its own backward difference
+            // once; the stencil's outer differences are its neighbours'.
             double Fxl[NV], Fxr[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const double b = lane_shift1<true>(c[v]);
-                const double a = lane_shift1<true>(b);
-                const double d = lane_shift1<false>(c[v]);
-                muscl_fixed<UNL>(a, b, c[v], d, qL[v], qR[v]);
+                const double dc = c[v] - b;
+                muscl_from_diffs<UNL>(b, c[v], lane_shift1<true>(dc), dc, lane_shift1<false>(dc), qL[v], qR[v]);
             }
             roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
 #pragma unroll
