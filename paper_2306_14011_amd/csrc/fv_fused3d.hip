@@ -25,13 +25,157 @@
 
 namespace fvk {
 
+// The planes of one work item (strip, row j, planes k0 .. k0 + seg - 1) for
+// stage STAGE with the limiter fixed at compile time (UNL: Psi = 1). As in
+// 2D, no memory access sits on a conditional path: loads are issued for
+// every face (clamped indices), and stores of lanes or planes without output
+// go past the end of a per-variable descriptor, where they are dropped.
+template <int STAGE, bool UNL>
+__device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int strip, int j, int k0, double s,
+                                               const double* Un, const double* Us, double* Ud, double& lmax,
+                                               uint32_t& fl) {
+    constexpr int NV = 5;
+    const int col = FW * strip - 2 + lane;
+    const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
+    const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
+    const int seg = G.seg;
+    const long long gbytes = NV * G.sv * 8;  // one grid's state, below 4 GiB
+    const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes);
+    // one descriptor per output variable (a plane of the state is below
+    // 1 GiB, so the drop offset plus any plane offset cannot wrap)
+    Rsrc rd[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rd[v] = grid_rsrc(Ud + G.base + v * G.sv, G.sv * 8);
+    const uint32_t cboff = (uint32_t)cmap * 8u;                 // stencil column in bytes
+    const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column for U^n reads
+    const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
+    const uint32_t vstride = (uint32_t)(G.sv * 8);
+    const uint32_t jo = (uint32_t)((long long)j * G.py * 8);
+    // byte offsets of rows j-2 .. j+2 and of plane kk through the boundary maps
+    uint32_t ro[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) ro[d] = (uint32_t)((long long)map_index(j - 2 + d, G.ny, G.bcy0, G.bcy1) * G.py * 8);
+    auto plane_off = [&](int kk) -> uint32_t {
+        return (uint32_t)((long long)map_index(kk, G.nz, G.bcz0, G.bcz1) * G.pz * 8);
+    };
+    auto out_plane = [&](int kk) -> uint32_t {
+        return (uint32_t)((long long)(kk < G.nz ? kk : G.nz - 1) * G.pz * 8) + jo;
+    };
+    // window of the own row: plane kk in slot (kk - k0 + 2) & 3; z face f
+    // (between planes k0 + f - 1 and k0 + f) uses slots f .. f + 3 (mod 4).
+    // Face 0 first, then faces 1 .. seg in unrolled groups of four, so every
+    // slot is a compile-time constant and a given z face of the grid is
+    // computed by the same instructions whatever seg is.
+    double W[4][NV];
+#pragma unroll
+    for (int kz = 0; kz < 4; ++kz) {
+        const uint32_t o = plane_off(k0 - 2 + kz) + ro[2];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[kz][v] = ld_buf(rs, cboff, o + v * vstride);
+    }
+    double Fz[2][NV];  // z-face fluxes: face f in Fz[f & 1]
+    double qL[NV], qR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(W[0][v], W[1][v], W[2][v], W[3][v], qL[v], qR[v]);
+    roe_flux<3, 2>(qL, qR, G.gm1, Fz[0]);
+    {
+        const uint32_t o = plane_off(k0 + 2) + ro[2];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W[0][v] = ld_buf(rs, cboff, o + v * vstride);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll 1
+    for (int m0 = 1; m0 <= seg; m0 += 4) {
+        if (k0 + m0 - 1 >= G.nz) break;  // ragged last segment (uniform)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int f = m0 + jj;
+            const int t = (jj + 1) & 3;  // f mod 4, a compile-time constant
+            const int kk = k0 + f - 1;   // output plane finished at this face
+            // rows j-2, j-1, j+1, j+2 of plane kk, requested before the z face
+            double Y[4][NV];
+            double Unc[NV];
+            {
+                const uint32_t po = plane_off(kk);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t o = po + ro[d < 2 ? d : d + 1];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Y[d][v] = ld_buf(rs, cboff, o + v * vstride);
+                }
+                if (STAGE > 0) {
+                    const uint32_t o = out_plane(kk);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Unc[v] = ld_buf(rn, oboff, o + v * vstride);
+                }
+            }
+            // z face f: stencil planes kk-1 .. kk+2
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                muscl_fixed<UNL>(W[t][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], qL[v], qR[v]);
+            roe_flux<3, 2>(qL, qR, G.gm1, Fz[t & 1]);
+            double c[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) c[v] = W[(t + 1) & 3][v];
+            // plane kk - 1 is dead: its slot takes plane kk + 3 for face f + 1
+            {
+                const uint32_t o = plane_off(kk + 3) + ro[2];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
+            }
+            // y faces of row j at plane kk: below (rows j-2 .. j+1) and above (rows j-1 .. j+2)
+            double Fyb[NV], Fyt[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(Y[0][v], Y[1][v], c[v], Y[2][v], qL[v], qR[v]);
+            roe_flux<3, 1>(qL, qR, G.gm1, Fyb);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(Y[1][v], c[v], Y[2][v], Y[3][v], qL[v], qR[v]);
+            roe_flux<3, 1>(qL, qR, G.gm1, Fyt);
+            // x faces: left face from the lanes to the left, right face one lane up
+            double Fxl[NV], Fxr[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double b = lane_shift1<true>(c[v]);
+                const double dc = c[v] - b;
+                muscl_from_diffs<UNL>(b, c[v], lane_shift1<true>(dc), dc, lane_shift1<false>(dc), qL[v], qR[v]);
+            }
+            roe_flux<3, 0>(qL, qR, G.gm1, Fxl);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
+            const bool plane_ok = kk < G.nz;  // uniform
+            const uint32_t p = out_plane(kk);
+            const uint32_t so = plane_ok ? sboff : DROP_OFFSET;
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double r = (Fxr[v] - Fxl[v]) * G.ax;
+                r += (Fyt[v] - Fyb[v]) * G.ay;
+                r += (Fz[t & 1][v] - Fz[(t + 1) & 1][v]) * G.az;
+                if (STAGE == 0) {
+                    out[v] = c[v] + s * r;
+                } else if (STAGE == 1) {
+                    out[v] = 0.75 * Unc[v] + 0.25 * (c[v] + s * r);
+                } else {
+                    out[v] = (1.0 / 3.0) * Unc[v] + (2.0 / 3.0) * (c[v] + s * r);
+                }
+                st_buf<false>(rd[v], so, p, out[v]);
+            }
+            if (STAGE == 2 && out_lane && plane_ok) {
+                const double idx[3] = {G.inv_dx, G.inv_dy, G.inv_dz};
+                lmax = fmax(lmax, cell_lambda<3>(out, G.gamma, G.gm1, idx, fl));
+            }
+            // keep the scheduler from overlapping consecutive planes (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 template <int STAGE>
-__global__ void __launch_bounds__(256) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
                                                  const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                  const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
                                                  uint32_t* __restrict__ status) {
-    constexpr int NV = 5;
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int wave0 = __builtin_amdgcn_readfirstlane(
@@ -55,125 +199,12 @@ __global__ void __launch_bounds__(256) k_fused3d(const FGrid3* __restrict__ grid
             dt = dtg[0];
         }
         const double s = -dt * G.inv_vol;
-        const int col = FW * strip - 2 + lane;
-        const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
-        const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
-        const int k0 = zs * G.seg;
-        const int seg = G.seg;
-        const long long gbytes = NV * G.sv * 8;  // one grid's state, below 4 GiB
-        const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes),
-                   rd = grid_rsrc(Ud + G.base, gbytes);
-        const uint32_t cboff = (uint32_t)cmap * 8u;                         // stencil column in bytes
-        const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;          // output column in bytes
-        const uint32_t vstride = (uint32_t)(G.sv * 8);
-        // byte offsets of rows j-2 .. j+2 and of plane kk through the boundary maps
-        uint32_t ro[5];
-#pragma unroll
-        for (int d = 0; d < 5; ++d) ro[d] = (uint32_t)((long long)map_index(j - 2 + d, G.ny, G.bcy0, G.bcy1) * G.py * 8);
-        auto plane_off = [&](int kk) -> uint32_t {
-            return (uint32_t)((long long)map_index(kk, G.nz, G.bcz0, G.bcz1) * G.pz * 8);
-        };
-        // window of the own row: plane kk in slot (kk - k0 + 2) & 3
-        double W[4][NV];
-#pragma unroll
-        for (int kz = 0; kz < 4; ++kz) {
-            const uint32_t o = plane_off(k0 - 2 + kz) + ro[2];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) W[kz][v] = ld_buf(rs, cboff, o + v * vstride);
-        }
-        double Fz[2][NV];  // z-face fluxes: face f in Fz[f & 1]
         double lmax = 0.0;
         uint32_t fl = 0;
-#pragma unroll 1
-        for (int m0 = 0; m0 <= seg; m0 += 4) {
-            if (k0 + m0 - 1 >= G.nz) break;  // ragged last segment (uniform)
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int f = m0 + jj;
-                if (f > seg) break;          // uniform: only in the last group
-                const bool more = f < seg;   // another face follows
-                const int kk = k0 + f - 1;   // output plane finished at this face
-                // rows j-2, j-1, j+1, j+2 of plane kk, requested before the z face
-                double Y[4][NV];
-                double Unc[NV];
-                if (f > 0) {
-                    const uint32_t po = plane_off(kk);
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        const uint32_t o = po + ro[d < 2 ? d : d + 1];
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) Y[d][v] = ld_buf(rs, cboff, o + v * vstride);
-                    }
-                    if (STAGE > 0) {
-                        const int kc = kk < G.nz ? kk : G.nz - 1;
-                        const uint32_t o = (uint32_t)((long long)kc * G.pz * 8) + (uint32_t)((long long)j * G.py * 8);
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) Unc[v] = ld_buf(rn, oboff, o + v * vstride);
-                    }
-                }
-                double qL[NV], qR[NV];
-                // z face f: stencil planes kk-1 .. kk+2 in slots jj, jj+1, jj+2, jj+3 (mod 4)
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    muscl(W[jj][v], W[(jj + 1) & 3][v], W[(jj + 2) & 3][v], W[(jj + 3) & 3][v], G.unlimited, qL[v],
-                          qR[v]);
-                roe_flux<3, 2>(qL, qR, G.gm1, Fz[jj & 1]);
-                double c[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) c[v] = W[(jj + 1) & 3][v];
-                // plane kk - 1 is dead: its slot takes plane kk + 3 for face f + 1
-                if (more) {
-                    const uint32_t o = plane_off(kk + 3) + ro[2];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) W[jj][v] = ld_buf(rs, cboff, o + v * vstride);
-                }
-                if (f == 0) continue;  // uniform: face 0 has no plane below it in the segment
-                // y faces of row j at plane kk: below (rows j-2 .. j+1) and above (rows j-1 .. j+2)
-                double Fyb[NV], Fyt[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) muscl(Y[0][v], Y[1][v], c[v], Y[2][v], G.unlimited, qL[v], qR[v]);
-                roe_flux<3, 1>(qL, qR, G.gm1, Fyb);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) muscl(Y[1][v], c[v], Y[2][v], Y[3][v], G.unlimited, qL[v], qR[v]);
-                roe_flux<3, 1>(qL, qR, G.gm1, Fyt);
-                // x faces: left face from the lanes to the left, right face one lane up
-                double Fxl[NV], Fxr[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double b = lane_shift1<true>(c[v]);
-                    const double a = lane_shift1<true>(b);
-                    const double d = lane_shift1<false>(c[v]);
-                    muscl(a, b, c[v], d, G.unlimited, qL[v], qR[v]);
-                }
-                roe_flux<3, 0>(qL, qR, G.gm1, Fxl);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
-                if (out_lane && kk < G.nz) {
-                    const uint32_t p = (uint32_t)((long long)kk * G.pz * 8) + (uint32_t)((long long)j * G.py * 8);
-                    double out[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        double r = (Fxr[v] - Fxl[v]) * G.ax;
-                        r += (Fyt[v] - Fyb[v]) * G.ay;
-                        r += (Fz[jj & 1][v] - Fz[(jj + 1) & 1][v]) * G.az;
-                        if (STAGE == 0) {
-                            out[v] = c[v] + s * r;
-                        } else if (STAGE == 1) {
-                            out[v] = 0.75 * Unc[v] + 0.25 * (c[v] + s * r);
-                        } else {
-                            out[v] = (1.0 / 3.0) * Unc[v] + (2.0 / 3.0) * (c[v] + s * r);
-                        }
-                        st_buf<false>(rd, oboff, p + v * vstride, out[v]);
-                    }
-                    if (STAGE == 2) {
-                        const double idx[3] = {G.inv_dx, G.inv_dy, G.inv_dz};
-                        lmax = fmax(lmax, cell_lambda<3>(out, G.gamma, G.gm1, idx, fl));
-                    }
-                }
-                // keep the scheduler from overlapping consecutive planes (register pressure)
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
+        if (G.unlimited)
+            fused3d_planes<STAGE, true>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl);
+        else
+            fused3d_planes<STAGE, false>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl);
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
             fl = wave_or(fl);
