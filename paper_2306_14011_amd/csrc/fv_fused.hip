@@ -61,12 +61,19 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     auto out_row = [&](int r) -> uint32_t { return (uint32_t)((long long)(r < G.ny ? r : G.ny - 1) * G.pitch * 8); };
     // Circular window of four U_s rows: row r sits in slot (r - r0 + 2) & 3.
     // Face f of the segment (f = 0 .. seg) lies between rows r0 + f - 1 and
-    // r0 + f, and its stencil rows are in slots f, f + 1, f + 2, f + 3
-    // (mod 4). Face 0 is computed first; faces 1 .. seg follow in unrolled
+    // r0 + f. Face 0 is computed first; faces 1 .. seg follow in unrolled
     // groups of four, so each slot index is a compile-time constant and the
-    // window never moves between registers. Since r0 is a multiple of 4, a
+    // window never moves between registers.
+    //
+    // MUSCL per cell rather than per face: with D[r] = U[r] - U[r-1], the
+    // left state of the face above row r is U[r] + minmod(D[r], D[r+1]) / 2
+    // and the right state of the face below it U[r] - minmod(D[r+1], D[r]) / 2
+    // (unlimited: D[r] / 2 and D[r+1] / 2), so each row needs one new
+    // difference and one minmod, and the face's left state is carried from
+    // the previous face. The same values as the face-wise formula, operation
+    // for operation (minmod is symmetric); since r0 is a multiple of 4, a
     // given face of the grid is computed by the same instructions whatever
-    // the segment height (face 0 of a segment repeats the loop's sequence).
+    // the segment height.
     double W[4][NV];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -77,19 +84,28 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     double Fy[2][NV];   // y-face fluxes: face f in Fy[f & 1]
     double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
     double qL[NV], qR[NV];
+    double qLy[NV], Dy[NV];  // left state of the next y face, and D of its upper row
     if (STAGE > 0) {
         const uint32_t pn = out_row(r0);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Unb[1][v] = ld_buf(rn, oboff, pn + v * vstride);
     }
+    // face 0: rows r0-2 .. r0+1 in slots 0 .. 3
 #pragma unroll
-    for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(W[0][v], W[1][v], W[2][v], W[3][v], qL[v], qR[v]);
-    roe_flux<2, 1>(qL, qR, G.gm1, Fy[0]);
+    for (int v = 0; v < NV; ++v) {
+        const double d0 = W[1][v] - W[0][v], d1 = W[2][v] - W[1][v], d2 = W[3][v] - W[2][v];
+        qL[v] = W[1][v] + 0.5 * (UNL ? d0 : minmod(d0, d1));
+        const double mr = UNL ? d2 : minmod(d1, d2);
+        qR[v] = W[2][v] - 0.5 * mr;
+        qLy[v] = W[2][v] + 0.5 * (UNL ? d1 : mr);
+        Dy[v] = d2;
+    }
     {
         const uint32_t o = row_off(r0 + 2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[0][v] = ld_buf(rs, cboff, o + v * vstride);
     }
+    roe_flux<2, 1>(qL, qR, G.gm1, Fy[0]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll 1
     for (int m0 = 1; m0 <= seg; m0 += 4) {
@@ -99,35 +115,46 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             const int f = m0 + j;
             const int t = (j + 1) & 3;  // f mod 4, a compile-time constant
             const int rr = r0 + f - 1;  // output row finished at this face
+            // rows rr-1 .. rr+2 sit in slots t .. t+3; row rr-1 is no longer
+            // needed, so its slot takes row rr + 3 (for face f + 1) right away
+            double c[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) c[v] = W[(t + 1) & 3][v];
+            {
+                const uint32_t o = row_off(rr + 3);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
+            }
             if (STAGE > 0) {
                 // U^n of row rr + 1, used at face f + 1
                 const uint32_t pn = out_row(rr + 1);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Unb[(t + 1) & 1][v] = ld_buf(rn, oboff, pn + v * vstride);
             }
-            // y face f: stencil rows rr-1 .. rr+2
+            // y face f between rows rr and rr+1
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                muscl_fixed<UNL>(W[t][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], qL[v], qR[v]);
-            roe_flux<2, 1>(qL, qR, G.gm1, Fy[t & 1]);
-            double c[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) c[v] = W[(t + 1) & 3][v];
-            // row rr - 1 is dead: its slot takes row rr + 3 for face f + 1
-            {
-                const uint32_t o = row_off(rr + 3);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
+            for (int v = 0; v < NV; ++v) {
+                const double u1 = W[(t + 2) & 3][v];
+                const double dn = W[(t + 3) & 3][v] - u1;  // D[rr+2]
+                const double mr = UNL ? dn : minmod(Dy[v], dn);
+                qL[v] = qLy[v];
+                qR[v] = u1 - 0.5 * mr;
+                qLy[v] = u1 + 0.5 * (UNL ? Dy[v] : mr);
+                Dy[v] = dn;
             }
-            // x faces of row rr: left face from the lanes to the left, right
-            // face one lane up. Each lane forms its own backward difference
-            // once; the stencil's outer differences are its neighbours'.
+            roe_flux<2, 1>(qL, qR, G.gm1, Fy[t & 1]);
+            // x faces of row rr: this lane computes its left face; its right
+            // face is the left face of the lane above. Each lane forms its
+            // backward difference once and its slope once, and takes the
+            // left state of its left face from the lane below.
             double Fxl[NV], Fxr[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double b = lane_shift1<true>(c[v]);
-                const double dc = c[v] - b;
-                muscl_from_diffs<UNL>(b, c[v], lane_shift1<true>(dc), dc, lane_shift1<false>(dc), qL[v], qR[v]);
+                const double d = c[v] - lane_shift1<true>(c[v]);  // D[i]
+                const double dn = lane_shift1<false>(d);           // D[i+1]
+                const double mr = UNL ? dn : minmod(d, dn);
+                qR[v] = c[v] - 0.5 * mr;
+                qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
             }
             roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
 #pragma unroll
@@ -154,7 +181,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                 lmax = fmax(lmax, cell_lambda<2>(out, G.gamma, G.gm1, idx, fl));
             }
             // keep the scheduler from overlapping consecutive rows, which
-            // would raise the live register count beyond 128
+            // would raise the live register count
             __builtin_amdgcn_sched_barrier(0);
         }
     }
