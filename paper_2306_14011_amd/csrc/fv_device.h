@@ -135,7 +135,9 @@ __host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, 
 
 // Roe flux along axis AX for NDIM dimensions, conserved face states in, flux out.
 // F = (F(qL) + F(qR))/2 - sum_k |lambda_k| alpha_k r_k / 2, no entropy fix.
-template <int NDIM, int AX>
+// TWICE returns 2F: callers that difference the fluxes fold the exact factor
+// 1/2 into their face areas and save a multiply per component.
+template <int NDIM, int AX, bool TWICE = false>
 __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, double gm1, double* F) {
     constexpr int IE = NDIM + 1;
     // left / right primitive states; rho^(-1/2) gives both sqrt(rho) and 1/rho
@@ -180,9 +182,10 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
     const double dp = pR - pL;
     const double dun = vnR - vnL;
     const double rcdu = rt * c * dun;
-    const double a1 = 0.5 * (dp - rcdu) * ic2;
+    const double hic2 = 0.5 * ic2;  // exact scaling: a1, a5 as (0.5 (dp -+ rcdu)) / c^2
+    const double a1 = (dp - rcdu) * hic2;
     const double a2 = (rR - rL) - dp * ic2;
-    const double a5 = 0.5 * (dp + rcdu) * ic2;
+    const double a5 = (dp + rcdu) * hic2;
     // |lambda| times strength
     const double w1 = fabs(un - c) * a1;
     const double w2 = fabs(un) * a2;
@@ -206,9 +209,11 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
         if (d != AX) De += aun * (uR[d] - uL[d]) * ut[d];
     D[IE] = De;
 
-    // central part: physical fluxes of both sides
-    const double mL = rL * vnL, mR = rR * vnR;
-    F[0] = 0.5 * (mL + mR - D[0]);
+    // central part: physical fluxes of both sides (the mass flux rho u_n is
+    // the normal momentum itself)
+    const double mL = qL[1 + AX], mR = qR[1 + AX];
+    constexpr double h = TWICE ? 1.0 : 0.5;
+    F[0] = h * (mL + mR - D[0]);
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
         double fl = mL * uL[d], fr = mR * uR[d];
@@ -216,9 +221,9 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
             fl += pL;
             fr += pR;
         }
-        F[1 + d] = 0.5 * (fl + fr - D[1 + d]);
+        F[1 + d] = h * (fl + fr - D[1 + d]);
     }
-    F[IE] = 0.5 * ((qL[IE] + pL) * vnL + (qR[IE] + pR) * vnR - D[IE]);
+    F[IE] = h * ((qL[IE] + pL) * vnL + (qR[IE] + pR) * vnR - D[IE]);
 }
 
 // Wave-speed bound of one cell, sum_d (|u_d| + c) * inv_dx[d], and the
@@ -345,9 +350,10 @@ __host__ __device__ __forceinline__ void roe_flux_vjp(const double* qL, const do
     const double dp = pR - pL;
     const double dun = vnR - vnL;
     const double rcdu = rt * c * dun;
-    const double a1 = 0.5 * (dp - rcdu) * ic2;
+    const double hic2 = 0.5 * ic2;  // exact scaling: a1, a5 as (0.5 (dp -+ rcdu)) / c^2
+    const double a1 = (dp - rcdu) * hic2;
     const double a2 = (rR - rL) - dp * ic2;
-    const double a5 = 0.5 * (dp + rcdu) * ic2;
+    const double a5 = (dp + rcdu) * hic2;
     const double l1 = fabs(un - c), l2 = fabs(un), l5 = fabs(un + c);
     const double w1 = l1 * a1, w2 = l2 * a2, w5 = l5 * a5;
     const double aun = l2 * rt;

@@ -53,6 +53,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column for U^n reads
     const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
     const uint32_t vstride = (uint32_t)(G.sv * 8);
+    const double hax = 0.5 * G.ax, hay = 0.5 * G.ay;
     // byte offset of U_s row r through the y boundary map (rows past the
     // last halo row are clamped inside the grid; they feed no output)
     auto row_off = [&](int r) -> uint32_t {
@@ -81,7 +82,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[k][v] = ld_buf(rs, cboff, o + v * vstride);
     }
-    double Fy[2][NV];   // y-face fluxes: face f in Fy[f & 1]
+    double Fy[2][NV];   // y-face fluxes (times 2): face f in Fy[f & 1]
     double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
     double qL[NV], qR[NV];
     double qLy[NV], Dy[NV];  // left state of the next y face, and D of its upper row
@@ -105,7 +106,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[0][v] = ld_buf(rs, cboff, o + v * vstride);
     }
-    roe_flux<2, 1>(qL, qR, G.gm1, Fy[0]);
+    roe_flux<2, 1, true>(qL, qR, G.gm1, Fy[0]);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll 1
     for (int m0 = 1; m0 <= seg; m0 += 4) {
@@ -142,12 +143,12 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                 qLy[v] = u1 + 0.5 * (UNL ? Dy[v] : mr);
                 Dy[v] = dn;
             }
-            roe_flux<2, 1>(qL, qR, G.gm1, Fy[t & 1]);
+            roe_flux<2, 1, true>(qL, qR, G.gm1, Fy[t & 1]);
             // x faces of row rr: this lane computes its left face; its right
             // face is the left face of the lane above. Each lane forms its
             // backward difference once and its slope once, and takes the
             // left state of its left face from the lane below.
-            double Fxl[NV], Fxr[NV];
+            double Fxl[NV], Fxr[NV];  // times 2, like Fy
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const double d = c[v] - lane_shift1<true>(c[v]);  // D[i]
@@ -156,7 +157,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                 qR[v] = c[v] - 0.5 * mr;
                 qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
             }
-            roe_flux<2, 0>(qL, qR, G.gm1, Fxl);
+            roe_flux<2, 0, true>(qL, qR, G.gm1, Fxl);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
             const bool row_ok = rr < G.ny;  // uniform
@@ -165,8 +166,9 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double r = (Fxr[v] - Fxl[v]) * G.ax;
-                r += (Fy[t & 1][v] - Fy[(t + 1) & 1][v]) * G.ay;
+                // the doubled fluxes against halved areas: the same products
+                double r = (Fxr[v] - Fxl[v]) * hax;
+                r += (Fy[t & 1][v] - Fy[(t + 1) & 1][v]) * hay;
                 if (STAGE == 0) {
                     out[v] = c[v] + s * r;
                 } else if (STAGE == 1) {
