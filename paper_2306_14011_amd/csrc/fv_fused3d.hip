@@ -51,6 +51,7 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
     const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
     const uint32_t vstride = (uint32_t)(G.sv * 8);
     const uint32_t jo = (uint32_t)((long long)j * G.py * 8);
+    const double hax = 0.5 * G.ax, hay = 0.5 * G.ay, haz = 0.5 * G.az;
     // byte offsets of rows j-2 .. j+2 and of plane kk through the boundary maps
     uint32_t ro[5];
 #pragma unroll
@@ -73,11 +74,11 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[kz][v] = ld_buf(rs, cboff, o + v * vstride);
     }
-    double Fz[2][NV];  // z-face fluxes: face f in Fz[f & 1]
+    double Fz[2][NV];  // z-face fluxes (times 2): face f in Fz[f & 1]
     double qL[NV], qR[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(W[0][v], W[1][v], W[2][v], W[3][v], qL[v], qR[v]);
-    roe_flux<3, 2>(qL, qR, G.gm1, Fz[0]);
+    roe_flux<3, 2, true>(qL, qR, G.gm1, Fz[0]);
     {
         const uint32_t o = plane_off(k0 + 2) + ro[2];
 #pragma unroll
@@ -113,7 +114,7 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 muscl_fixed<UNL>(W[t][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], qL[v], qR[v]);
-            roe_flux<3, 2>(qL, qR, G.gm1, Fz[t & 1]);
+            roe_flux<3, 2, true>(qL, qR, G.gm1, Fz[t & 1]);
             double c[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) c[v] = W[(t + 1) & 3][v];
@@ -123,23 +124,35 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
 #pragma unroll
                 for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
             }
-            // y faces of row j at plane kk: below (rows j-2 .. j+1) and above (rows j-1 .. j+2)
-            double Fyb[NV], Fyt[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(Y[0][v], Y[1][v], c[v], Y[2][v], qL[v], qR[v]);
-            roe_flux<3, 1>(qL, qR, G.gm1, Fyb);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(Y[1][v], c[v], Y[2][v], Y[3][v], qL[v], qR[v]);
-            roe_flux<3, 1>(qL, qR, G.gm1, Fyt);
-            // x faces: left face from the lanes to the left, right face one lane up
-            double Fxl[NV], Fxr[NV];
+            // y faces of row j at plane kk: below (rows j-2 .. j+1) and above
+            // (rows j-1 .. j+2). With D[r] = U[r] - U[r-1], the own row's
+            // slope minmod(D[j], D[j+1]) serves both faces (minmod is symmetric).
+            double Fyb[NV], Fyt[NV];  // times 2, like Fz
+            double qLt[NV], qRt[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double b = lane_shift1<true>(c[v]);
-                const double dc = c[v] - b;
-                muscl_from_diffs<UNL>(b, c[v], lane_shift1<true>(dc), dc, lane_shift1<false>(dc), qL[v], qR[v]);
+                const double d1 = Y[1][v] - Y[0][v], d2 = c[v] - Y[1][v];
+                const double d3 = Y[2][v] - c[v], d4 = Y[3][v] - Y[2][v];
+                const double m = UNL ? 0.0 : minmod(d2, d3);
+                qL[v] = Y[1][v] + 0.5 * (UNL ? d1 : minmod(d1, d2));
+                qR[v] = c[v] - 0.5 * (UNL ? d3 : m);
+                qLt[v] = c[v] + 0.5 * (UNL ? d2 : m);
+                qRt[v] = Y[2][v] - 0.5 * (UNL ? d4 : minmod(d4, d3));
             }
-            roe_flux<3, 0>(qL, qR, G.gm1, Fxl);
+            roe_flux<3, 1, true>(qL, qR, G.gm1, Fyb);
+            roe_flux<3, 1, true>(qLt, qRt, G.gm1, Fyt);
+            // x faces: this lane computes its left face, its right face is the
+            // lane above's left face; one difference and one slope per lane
+            double Fxl[NV], Fxr[NV];  // times 2
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double d = c[v] - lane_shift1<true>(c[v]);  // D[i]
+                const double dn = lane_shift1<false>(d);           // D[i+1]
+                const double mr = UNL ? dn : minmod(d, dn);
+                qR[v] = c[v] - 0.5 * mr;
+                qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
+            }
+            roe_flux<3, 0, true>(qL, qR, G.gm1, Fxl);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
             const bool plane_ok = kk < G.nz;  // uniform
@@ -148,9 +161,10 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double r = (Fxr[v] - Fxl[v]) * G.ax;
-                r += (Fyt[v] - Fyb[v]) * G.ay;
-                r += (Fz[t & 1][v] - Fz[(t + 1) & 1][v]) * G.az;
+                // the doubled fluxes against halved areas: the same products
+                double r = (Fxr[v] - Fxl[v]) * hax;
+                r += (Fyt[v] - Fyb[v]) * hay;
+                r += (Fz[t & 1][v] - Fz[(t + 1) & 1][v]) * haz;
                 if (STAGE == 0) {
                     out[v] = c[v] + s * r;
                 } else if (STAGE == 1) {
