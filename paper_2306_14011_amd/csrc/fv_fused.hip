@@ -40,7 +40,9 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     constexpr int NV = 4;
     const int seg = G.seg;
     const int col = FW * strip - 2 + lane;
-    const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
+    // lanes past the last halo column feed no output: they read that
+    // column again (the same cache line) instead of wrapped or clamped data
+    const int cmap = map_index(col < G.nx + 1 ? col : G.nx + 1, G.nx, G.bcx0, G.bcx1);
     const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
     const long long gbytes = 4 * G.sv * 8;  // one grid's state, below 4 GiB
     const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes);
@@ -50,7 +52,11 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
 #pragma unroll
     for (int v = 0; v < NV; ++v) rd[v] = grid_rsrc(Ud + G.base + v * G.sv, G.sv * 8);
     const uint32_t cboff = (uint32_t)cmap * 8u;                // this lane's (mapped) column in bytes
-    const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column for U^n reads
+    // U^n reads: lanes without output read a column of the strip's own
+    // output range (the same cache lines), clamped inside the grid
+    const int olast = FW * strip + FW - 1 < G.nx - 1 ? FW * strip + FW - 1 : G.nx - 1;
+    const int ocol = col < FW * strip ? FW * strip : (col < olast ? col : olast);
+    const uint32_t oboff = (uint32_t)ocol * 8u;
     const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
     const uint32_t vstride = (uint32_t)(G.sv * 8);
     const double hax = 0.5 * G.ax, hay = 0.5 * G.ay;

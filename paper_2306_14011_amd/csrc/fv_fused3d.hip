@@ -36,7 +36,9 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
                                                uint32_t& fl) {
     constexpr int NV = 5;
     const int col = FW * strip - 2 + lane;
-    const int cmap = map_index(col, G.nx, G.bcx0, G.bcx1);
+    // lanes past the last halo column feed no output: they read that
+    // column again (the same cache line) instead of wrapped or clamped data
+    const int cmap = map_index(col < G.nx + 1 ? col : G.nx + 1, G.nx, G.bcx0, G.bcx1);
     const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
     const int seg = G.seg;
     const long long gbytes = NV * G.sv * 8;  // one grid's state, below 4 GiB
@@ -47,7 +49,11 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
 #pragma unroll
     for (int v = 0; v < NV; ++v) rd[v] = grid_rsrc(Ud + G.base + v * G.sv, G.sv * 8);
     const uint32_t cboff = (uint32_t)cmap * 8u;                 // stencil column in bytes
-    const uint32_t oboff = out_lane ? (uint32_t)col * 8u : 0u;  // output column for U^n reads
+    // U^n reads: lanes without output read a column of the strip's own
+    // output range (the same cache lines), clamped inside the grid
+    const int olast = FW * strip + FW - 1 < G.nx - 1 ? FW * strip + FW - 1 : G.nx - 1;
+    const int ocol = col < FW * strip ? FW * strip : (col < olast ? col : olast);
+    const uint32_t oboff = (uint32_t)ocol * 8u;
     const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
     const uint32_t vstride = (uint32_t)(G.sv * 8);
     const uint32_t jo = (uint32_t)((long long)j * G.py * 8);
