@@ -215,14 +215,15 @@ def fused_leg(torch, fv, traffic, g, U0, a):
         "ms_per_step_by_seg": {str(q): round(v, 4) for q, v in res.items()},
         "kernels": kernels,
         "alg_bytes_per_cell_update": traffic.fused_step_bytes(g) / g.ncells,
-        # The stage is limited on the arithmetic side (dependent FP64 chains of
-        # the Roe flux; a variant moving a third less data ran no faster), so it
-        # is reported against the FP64 vector peak, with its HBM rate beside it.
-        "roofline": {"bound": "alu", "achieved": k["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(k["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4),
+        # Stages 2 and 3 also read U^n and move their bytes at about the rate
+        # of a plain device copy; stage 1 sits nearer its FP64 issue limit.
+        # Over the three stages the HBM fraction is the larger one, so the
+        # stage is reported against HBM, with its FP64 rate beside it.
+        "roofline": {"bound": "hbm", "achieved": k["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(k["achieved_GBps"] / HBM_PEAK_GBPS, 4),
                      "traffic": counted_traffic("fused", seg, g.n[0]), "kernel": "fused stage (k_fused2d)",
-                     "hbm_achieved_GBps": k["achieved_GBps"],
-                     "hbm_frac": round(k["achieved_GBps"] / HBM_PEAK_GBPS, 4)},
+                     "alu_achieved_TFLOPs": k["achieved_TFLOPs"],
+                     "alu_frac": round(k["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4)},
     }
 
 

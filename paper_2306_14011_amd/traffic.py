@@ -13,13 +13,10 @@ Per launch, with V = nvar, N = interior cells, F_d = faces on axis d:
 Per cell-update of the whole step (3 stages + one dt reduction), 2D: 1056 B,
 3D: 1694 B (plus the ghost fill).
 
-Algorithmic FP64 flops (an FMA counts 2), counted from the source:
-  MUSCL-minmod face states, 4 variables          28 per face
-  Roe flux incl. the Newton-refined rcp / rsqrt  161 per face (2D)
-  residual + stage combination                   44 per cell (2D)
-  CFL wave speed of a cell                       20
-A 2D cell-stage has two faces: 2 * 189 + 44 = 422 flops; the last stage of
-the fused step adds the wave speed of the new state.
+Algorithmic FP64 flops of the fused 2D stage (an FMA counts 2), counted
+from the source (constants below): per cell and axis one MUSCL difference
+and two face states, per face one Roe flux, per cell the residual and the
+stage combination, and in the last stage the CFL wave speed.
 """
 from __future__ import annotations
 
@@ -68,22 +65,24 @@ def fused_step_bytes(spec):
     return 8 * (spec.ndim + 2) * spec.ncells * 8
 
 
-# Algorithmic FP64 flops, counted from the device source with an FMA as 2
-# and min / max / abs as 0:
-#   MUSCL-minmod per face: 4 variables x (3 differences + 2 minmod adds + 2 fma)
-#   Roe flux per face (2D): primitive states, Roe averages, wave strengths and
-#     dissipation, central fluxes; each 1/x is 6 flops and each 1/sqrt(x) 8
-#     (hardware estimate plus one third-order correction), 3 and 1 of them
-#   cell update: residual of 4 faces x 4 variables, scaled, and the RK combination
+# Algorithmic FP64 flops, counted from the device source with an FMA as 2,
+# min / max / abs as 0 and each shared subexpression once:
+#   MUSCL per cell and axis: 4 variables x (the backward difference D[i] and
+#     the two face states U[i] +- minmod(D[i], D[i+1]) / 2)
+#   Roe flux per face (2D, returned as 2F): primitive states, Roe averages,
+#     wave strengths and dissipation, central fluxes; each 1/x is 6 flops and
+#     each 1/sqrt(x) 8 (hardware estimate plus one third-order correction),
+#     3 of the latter and 1 of the former
+#   cell update: residual of 4 faces x 4 variables (5 flops each) and the RK
+#     combination (2, 5, 5 flops in stages 1, 2, 3), averaged over the stages
 #   CFL wave speed of a cell: 1/rho, velocities, pressure, c, sum over axes
-FLOPS_MUSCL_FACE = 4 * 9
-FLOPS_ROE_FACE_2D = 147
-FLOPS_FACE_2D = FLOPS_MUSCL_FACE + FLOPS_ROE_FACE_2D
-FLOPS_CELL_UPDATE_2D = 44
-FLOPS_CELL_LAMBDA = 30
+FLOPS_MUSCL_CELL_AXIS = 4 * 5
+FLOPS_ROE_FACE_2D = 131
+FLOPS_CELL_UPDATE_2D = 4 * (5 + 4)
+FLOPS_CELL_LAMBDA = 31
 
 
 def fused_stage_flops(spec):
     """Algorithmic FP64 flops of one fused stage launch, averaged over the three stages."""
-    per_cell = 2 * FLOPS_FACE_2D + FLOPS_CELL_UPDATE_2D + FLOPS_CELL_LAMBDA / 3.0
+    per_cell = 2 * (FLOPS_MUSCL_CELL_AXIS + FLOPS_ROE_FACE_2D) + FLOPS_CELL_UPDATE_2D + FLOPS_CELL_LAMBDA / 3.0
     return per_cell * spec.ncells
