@@ -440,7 +440,7 @@ static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in
 static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (nsteps == 0) return FV_OK;
     if (c->g.ndim == 3) return fused_step3(c, U, nsteps, dt_in, dt_out);
-    fvk::launch_fused_init(c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, nullptr, c->stream);
+    fvk::launch_fused_init(c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);

@@ -13,16 +13,27 @@
 
 namespace {
 
+// Clock record of one step: n entries (even: earliest start, odd: latest
+// end), each over fvk::CLK_SLOTS slots.
 __global__ void k_clk_reset(unsigned long long* clk, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) clk[i] = (i & 1) ? 0ull : ~0ull;
+    for (int i = threadIdx.x; i < n * fvk::CLK_SLOTS; i += blockDim.x)
+        clk[fvk::clk_index(i / fvk::CLK_SLOTS, i % fvk::CLK_SLOTS)] = ((i / fvk::CLK_SLOTS) & 1) ? 0ull : ~0ull;
 }
 
-// Copies this step's clock record into history[counter] and advances the counter.
+// Folds the slots of this step's clock record into history[counter] and
+// advances the counter.
 __global__ void k_clk_store(const unsigned long long* clk, int n, unsigned long long* history, int max_steps,
                             int* counter) {
     const int step = *counter;
     if (step < max_steps)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) history[(long long)step * n + i] = clk[i];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            unsigned long long v = clk[fvk::clk_index(i, 0)];
+            for (int k = 1; k < fvk::CLK_SLOTS; ++k) {
+                const unsigned long long w = clk[fvk::clk_index(i, k)];
+                v = (i & 1) ? (w > v ? w : v) : (w < v ? w : v);
+            }
+            history[(long long)step * n + i] = v;
+        }
     __syncthreads();
     if (threadIdx.x == 0) *counter = step + 1;
 }
@@ -94,7 +105,7 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
     L->off_status = o;
     o = a256(o + 4);
     L->off_clk = o;
-    o = a256(o + 48 * (size_t)ngrids);
+    o = a256(o + 6 * sizeof(unsigned long long) * fvk::CLK_SLOTS * fvk::CLK_PAD * (size_t)ngrids);
     L->off_counter = o;
     o = a256(o + 4);
     L->off_U1 = o;
@@ -301,7 +312,7 @@ int fv_batch_step(fv_batch* b, double* U, int32_t nsteps) {
         b->graph_timed = timed;
         b->graph_history = b->history;
     }
-    fvk::launch_fused_init(b->waves, b->grids, b->ngrids, b->nitems, U, b->lam, b->status, nullptr, b->stream);
+    fvk::launch_fused_init(b->waves, b->grids, b->ngrids, b->nitems, U, b->lam, b->status, b->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         hipError_t e = hipGraphLaunch(b->exec, b->stream);
         if (e != hipSuccess) return bfail(b, FV_EDEVICE, "graph launch failed");

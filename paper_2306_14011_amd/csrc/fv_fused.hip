@@ -243,8 +243,9 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         }
         if (clk && lane == 0) {
             const unsigned long long t_end = wall_clock64();
-            atomicMin(&clk[(G.gid * 3 + STAGE) * 2 + 0], t_start);
-            atomicMax(&clk[(G.gid * 3 + STAGE) * 2 + 1], t_end);
+            const int slot = item & (CLK_SLOTS - 1);
+            atomicMin(&clk[clk_index((G.gid * 3 + STAGE) * 2 + 0, slot)], t_start);
+            atomicMax(&clk[clk_index((G.gid * 3 + STAGE) * 2 + 1, slot)], t_end);
         }
     }
 }
@@ -284,16 +285,9 @@ __global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ 
     }
 }
 
-// Zero the lambda accumulators; clocks to (max, 0) when present.
-__global__ void k_fused_reset(unsigned long long* lam, int ngrids, unsigned long long* clk) {
-    for (int g = threadIdx.x; g < ngrids; g += blockDim.x) {
-        lam[g] = 0ull;
-        if (clk)
-            for (int s = 0; s < 3; ++s) {
-                clk[(g * 3 + s) * 2 + 0] = ~0ull;
-                clk[(g * 3 + s) * 2 + 1] = 0ull;
-            }
-    }
+// Zero the lambda accumulators.
+__global__ void k_fused_reset(unsigned long long* lam, int ngrids) {
+    for (int g = threadIdx.x; g < ngrids; g += blockDim.x) lam[g] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -323,8 +317,8 @@ void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, in
 }
 
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
-                       unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s) {
-    hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(256), 0, s, lam, ngrids, clk);
+                       unsigned long long* lam, uint32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_fused_reset, dim3(1), dim3(256), 0, s, lam, ngrids);
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
     hipLaunchKernelGGL(k_fused_lambda, grid, block, 0, s, grids, ngrids, nitems, U, lam, status);
 }

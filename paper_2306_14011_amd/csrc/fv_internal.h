@@ -6,6 +6,15 @@
 namespace fvk {
 
 // One 2D grid of the fused path (device memory, read uniformly).
+// Stage clock record of the batch (per grid and stage, earliest work-item
+// start and latest end): each entry is spread over CLK_SLOTS slots, one
+// 128-byte line apart, that work items pick by their index, so the per-item
+// atomics do not all meet on one address; the slots are folded when the
+// step's record is stored.
+constexpr int CLK_SLOTS = 16;
+constexpr int CLK_PAD = 16;  // unsigned long longs per slot (one 128-byte line)
+__host__ __device__ inline int clk_index(int entry, int slot) { return (entry * CLK_SLOTS + slot) * CLK_PAD; }
+
 struct FGrid {
     int nx, ny, pitch, strips, work0, unlimited;
     int bcx0, bcx1, bcy0, bcy1, gid, seg;   // gid: the caller's grid index (slots of lam, dt, clocks);
@@ -44,7 +53,7 @@ void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, in
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s);
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
-                       unsigned long long* lam, uint32_t* status, unsigned long long* clk, hipStream_t s);
+                       unsigned long long* lam, uint32_t* status, hipStream_t s);
 int fused_slots();
 int fused3d_items(const FGrid3& G, int seg);
 void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
