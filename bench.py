@@ -227,6 +227,25 @@ def fused_leg(torch, fv, traffic, g, U0, a):
     }
 
 
+def schemes_leg(torch, fv, traffic, g, U0, steps):
+    """The fused 2D step on the headline workload for each member of the MUSCL
+    family: minmod (the headline) and Psi = 1 with kappa = -1, 0, 1/3, 1."""
+    import copy
+    out = {}
+    for name, lim, kappa in (("minmod", True, -1.0), ("kappa=-1", False, -1.0), ("kappa=0", False, 0.0),
+                             ("kappa=1/3", False, 1.0 / 3.0), ("kappa=1", False, 1.0)):
+        gg = copy.copy(g)
+        gg.limiter, gg.kappa = lim, kappa
+        s = fv.Solver(gg)
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+        ms = timed_steps(torch, s, U0, steps, 5)
+        k = site_table(s, gg, 10, fv, traffic)["fused"]
+        s.close()
+        out[name] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3), "stage_avg_us": k["avg_us"],
+                     "hbm_achieved_GBps": round(traffic.fused_step_bytes(g) / 3.0 / (k["avg_us"] * 1e-6) / 1e9, 1)}
+    return out
+
+
 def small_leg(torch, fv, inputs):
     """64^2 vortex (launch-bound): split and fused by direct launches, fused as a
     graph-replayed batch of one."""
@@ -492,6 +511,8 @@ def main():
     out["copy"] = copy_leg(torch)
     if not a.quick:
         out["small"] = small_leg(torch, fv, inputs)
+        out["schemes"] = schemes_leg(torch, fv, traffic, g, U0, 50)
+        log("schemes (fused 2D): " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in out["schemes"].items()))
     if not a.no_batch:
         out["batch"] = batch_leg(torch, fv, inputs, 100, 0 if a.no_tune else a.samples_batch)
         log(f"batch: {out['batch']['value']:.3e} cell-updates/s")

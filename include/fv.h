@@ -73,10 +73,17 @@ enum {
     FV_NSITES = 7
 };
 
-/* Scheme flags of fv_grid_desc.scheme. */
+/* Scheme of fv_grid_desc.scheme: the MUSCL face states of Eq. (flux) with
+ * epsilon = 1. With the minmod limiter the kappa terms collapse (minmod is
+ * symmetric, so Psi+ and Psi- give the same limited difference) and every
+ * kappa gives Q^L = Q_k + minmod(dQ_{k-1/2}, dQ_{k+1/2}) / 2. With Psi = 1,
+ * kappa selects the member of the family. */
 enum {
-    FV_SCHEME_MINMOD = 0,      /* MUSCL with the minmod limiter (the default) */
-    FV_SCHEME_UNLIMITED = 1    /* Psi = 1: unlimited fully upwind (kappa = -1) states */
+    FV_SCHEME_MINMOD = 0,      /* minmod limiter (the default)                          */
+    FV_SCHEME_UNLIMITED = 1,   /* Psi = 1, kappa = -1: fully upwind                     */
+    FV_SCHEME_FROMM = 2,       /* Psi = 1, kappa = 0: Fromm's upwind-biased scheme      */
+    FV_SCHEME_THIRD = 3,       /* Psi = 1, kappa = 1/3: third-order upwind-biased       */
+    FV_SCHEME_CENTRAL = 4      /* Psi = 1, kappa = 1: central                            */
 };
 
 /* Grid description. ndim is 2 or 3; n[2] must be 1 in 2D. The box is
@@ -84,7 +91,7 @@ enum {
  * face kind of axis d; periodic must be set on both faces of an axis. */
 typedef struct fv_grid_desc {
     int32_t ndim;
-    int32_t scheme;     /* FV_SCHEME_MINMOD or FV_SCHEME_UNLIMITED */
+    int32_t scheme;     /* FV_SCHEME_* */
     int64_t n[3];
     double lo[3];
     double hi[3];

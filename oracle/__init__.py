@@ -205,9 +205,9 @@ def residual_vjp(spec, U, w, limiter=True):
     return mu
 
 
-def rk3_step_vjp(spec, U, dt_, lam, limiter=True):
+def rk3_step_vjp(spec, U, dt_, lam, limiter=True, kappa=-1.0):
     """dJ/dU^n from dJ/dU^{n+1} = lam for one step at frozen dt."""
-    g = make_grid(spec, limiter)
+    g = make_grid(spec, limiter, kappa)
     U = _arr(U)
     lam = _arr(lam).copy()
     lib().or_rk3_step_vjp(ctypes.byref(g), _p(U), float(dt_), _p(lam))

@@ -24,6 +24,14 @@ HIP_FLAGS = [
 ]
 
 
+# Per-source extra flags. The split path's face kernels (one face per thread,
+# and the variant that walks runs of faces) must give the same bits for every
+# launch table; contracting multiply-adds only within one source expression
+# makes the fused multiply-adds independent of how the compiler shares
+# subexpressions between the faces a thread computes.
+FILE_FLAGS = {"fv_kernels.hip": ["-ffp-contract=on"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
@@ -36,7 +44,8 @@ def build(verbose=False, jobs=None):
     procs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+        cmd = [HIPCC, *HIP_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-I", os.path.join(ROOT, "include"),
+               "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd)))

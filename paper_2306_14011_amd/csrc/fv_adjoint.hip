@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(MAXT) k_adj_flux(const double* __restrict__ U,
             q[1][v] = Uv[c - st];
             q[2][v] = Uv[c];
             q[3][v] = Uv[c + st];
-            muscl(q[0][v], q[1][v], q[2][v], q[3][v], g.unlimited, qL[v], qR[v]);
+            muscl(q[0][v], q[1][v], q[2][v], q[3][v], g.scheme, qL[v], qR[v]);
         }
         // face adjoint: the face adds F*A to its left cell and -F*A to its right cell
         const int e = (k * g.n[1] + j) * g.n[0] + i;  // interior index of (i, j, k) when inside
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(MAXT) k_adj_flux(const double* __restrict__ U,
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-            muscl_vjp(q[0][v], q[1][v], q[2][v], q[3][v], g.unlimited, qLb[v], qRb[v], g0, g1, g2, g3);
+            muscl_vjp(q[0][v], q[1][v], q[2][v], q[3][v], g.scheme, qLb[v], qRb[v], g0, g1, g2, g3);
             G[0 * ms + v * fsv + f] = g0;
             G[1 * ms + v * fsv + f] = g1;
             G[2 * ms + v * fsv + f] = g2;

@@ -79,7 +79,7 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
         snprintf(why, 256, "ndim must be 2 or 3");
         return FV_EINVAL;
     }
-    if (g->scheme != FV_SCHEME_MINMOD && g->scheme != FV_SCHEME_UNLIMITED) {
+    if (g->scheme < FV_SCHEME_MINMOD || g->scheme > FV_SCHEME_CENTRAL) {
         snprintf(why, 256, "unknown scheme");
         return FV_EINVAL;
     }
@@ -215,7 +215,7 @@ Geo make_geo(const fv_grid_desc* d, const Layout& L) {
         g.bc[a][0] = d->bc[a][0];
         g.bc[a][1] = d->bc[a][1];
     }
-    g.unlimited = d->scheme == FV_SCHEME_UNLIMITED ? 1 : 0;
+    g.scheme = d->scheme;
     return g;
 }
 
@@ -485,7 +485,7 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         G.ny = c->g.n[1];
         G.nz = c->g.n[2];
         G.strips = fvk::fused_strips(G.nx);
-        G.unlimited = c->g.unlimited;
+        G.scheme = c->g.scheme;
         G.bcx0 = c->g.bc[0][0];
         G.bcx1 = c->g.bc[0][1];
         G.bcy0 = c->g.bc[1][0];
@@ -524,7 +524,7 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
     G.pitch = c->g.sy;
     G.strips = fvk::fused_strips(G.nx);
     G.work0 = 0;
-    G.unlimited = c->g.unlimited;
+    G.scheme = c->g.scheme;
     G.bcx0 = c->g.bc[0][0];
     G.bcx1 = c->g.bc[0][1];
     G.bcy0 = c->g.bc[1][0];

@@ -69,7 +69,7 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
             snprintf(why, 256, "grid %d: a state of 4 GiB or more (buffer offsets are 32-bit)", g);
             return FV_EINVAL;
         }
-        if (d.scheme != FV_SCHEME_MINMOD && d.scheme != FV_SCHEME_UNLIMITED) {
+        if (d.scheme < FV_SCHEME_MINMOD || d.scheme > FV_SCHEME_CENTRAL) {
             snprintf(why, 256, "grid %d: unknown scheme", g);
             return FV_EINVAL;
         }
@@ -252,7 +252,7 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
         G.ny = (int)d.n[1];
         G.pitch = G.nx;
         G.strips = fvk::fused_strips(G.nx);
-        G.unlimited = d.scheme == FV_SCHEME_UNLIMITED;
+        G.scheme = d.scheme;
         G.bcx0 = d.bc[0][0];
         G.bcx1 = d.bc[0][1];
         G.bcy0 = d.bc[1][0];

@@ -49,7 +49,7 @@ struct Geo {
     double gamma, gm1;  // gamma, gamma - 1
     double cfl;
     int bc[3][2];
-    int unlimited;      // 1: Psi = 1 (no limiter)
+    int scheme;         // 0 minmod; Psi = 1 with kappa = -1, 0, 1/3, 1 for 1 .. 4
 };
 
 // 1/a and 1/sqrt(a) for the flux arithmetic: the hardware estimates
@@ -122,14 +122,38 @@ __host__ __device__ __forceinline__ void muscl_fixed(double q0, double q1, doubl
     muscl_from_diffs<UNL>(q1, q2, q1 - q0, q2 - q1, q3 - q2, qL, qR);
 }
 
-// The same with Psi = 1 when `unlimited` (a uniform run-time switch).
-__host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, double q3, int unlimited,
+// Weights of the unlimited (Psi = 1) kappa family of Eq. (flux) with
+// epsilon = 1: Q^L = Q_k + a dQ_{k-1/2} + b dQ_{k+1/2} and
+// Q^R = Q_{k+1} - b dQ_{k+1/2} - a dQ_{k+3/2}, a = (1 - kappa)/4,
+// b = (1 + kappa)/4, for schemes 2 .. 4 (kappa = 0, 1/3, 1).
+__host__ __device__ __forceinline__ void kappa_weights(int scheme, double& a, double& b) {
+    const double kappa = scheme == 2 ? 0.0 : (scheme == 3 ? 1.0 / 3.0 : 1.0);
+    a = 0.25 * (1.0 - kappa);
+    b = 0.25 * (1.0 + kappa);
+}
+
+// Face states of the kappa family from the stencil's differences, with
+// explicit fused multiply-adds: the same bits whether the differences are
+// formed per face or shared per cell, whatever the compiler contracts.
+__host__ __device__ __forceinline__ void muscl_kappa_diffs(double q1, double q2, double dm, double dc, double dp,
+                                                          double a, double b, double& qL, double& qR) {
+    qL = fma(a, dm, fma(b, dc, q1));
+    qR = fma(-b, dc, fma(-a, dp, q2));
+}
+
+// The same with the scheme chosen at run time (uniform): 0 minmod, 1 Psi = 1
+// with kappa = -1, 2 .. 4 the other kappa members.
+__host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, double q3, int scheme,
                                               double& qL, double& qR) {
-    if (unlimited) {
+    if (scheme == 1) {
         qL = q1 + 0.5 * (q1 - q0);
         qR = q2 - 0.5 * (q3 - q2);
-    } else {
+    } else if (scheme == 0) {
         muscl_minmod(q0, q1, q2, q3, qL, qR);
+    } else {
+        double a, b;
+        kappa_weights(scheme, a, b);
+        muscl_kappa_diffs(q1, q2, q1 - q0, q2 - q1, q3 - q2, a, b, qL, qR);
     }
 }
 
@@ -292,17 +316,27 @@ __host__ __device__ __forceinline__ void muscl_minmod_vjp(double q0, double q1, 
     }
 }
 
-// Reverse of muscl(): the unlimited states are linear in the stencil.
-__host__ __device__ __forceinline__ void muscl_vjp(double q0, double q1, double q2, double q3, int unlimited,
+// Reverse of muscl(): the unlimited states are linear in the stencil,
+// Q^L = (1 - b + a) q1 - a q0 + b q2 and Q^R = (1 - b + a) q2 + b q1 - a q3
+// (a = 1/2, b = 0 for kappa = -1).
+__host__ __device__ __forceinline__ void muscl_vjp(double q0, double q1, double q2, double q3, int scheme,
                                                    double qLb, double qRb, double& g0, double& g1, double& g2,
                                                    double& g3) {
-    if (unlimited) {
+    if (scheme == 1) {
         g1 += 1.5 * qLb;
         g0 -= 0.5 * qLb;
         g2 += 1.5 * qRb;
         g3 -= 0.5 * qRb;
-    } else {
+    } else if (scheme == 0) {
         muscl_minmod_vjp(q0, q1, q2, q3, qLb, qRb, g0, g1, g2, g3);
+    } else {
+        double a, b;
+        kappa_weights(scheme, a, b);
+        const double c = 1.0 - b + a;
+        g0 -= a * qLb;
+        g1 += c * qLb + b * qRb;
+        g2 += b * qLb + c * qRb;
+        g3 -= a * qRb;
     }
 }
 

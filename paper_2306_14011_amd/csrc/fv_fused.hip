@@ -27,16 +27,19 @@
 namespace fvk {
 
 // The rows of one work item (strip, rows r0 .. r0 + seg - 1) for stage STAGE
-// with the limiter fixed at compile time (UNL: Psi = 1). The loop body has
+// with the face-state rule fixed at compile time (LIM: 0 minmod, 1 Psi = 1
+// with kappa = -1, 2 Psi = 1 with the kappa weights ka, kb). The loop body has
 // no branch around a memory access: every load is issued whatever the row
 // (indices past the grid are clamped), and the stores of lanes or rows with
 // no output go to an offset past the end of the buffer, where the hardware
 // drops them. A conditional load or store would make the compiler's wait
 // counting assume the shortest path and wait for every outstanding access
 // (the prefetches included) at the top of each row.
-template <int STAGE, bool UNL>
+template <int STAGE, int LIM>
 __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip, int r0, double s, const double* Un,
-                                             const double* Us, double* Ud, double& lmax, uint32_t& fl) {
+                                             const double* Us, double* Ud, double& lmax, uint32_t& fl, double ka,
+                                             double kb) {
+    constexpr bool UNL = LIM == 1;
     constexpr int NV = 4;
     const int seg = G.seg;
     const int col = FW * strip - 2 + lane;
@@ -75,7 +78,8 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     // MUSCL per cell rather than per face: with D[r] = U[r] - U[r-1], the
     // left state of the face above row r is U[r] + minmod(D[r], D[r+1]) / 2
     // and the right state of the face below it U[r] - minmod(D[r+1], D[r]) / 2
-    // (unlimited: D[r] / 2 and D[r+1] / 2), so each row needs one new
+    // (unlimited: D[r] / 2 and D[r+1] / 2; other kappa: the weighted sums
+    // ka D[r] + kb D[r+1] and kb D[r] + ka D[r+1]), so each row needs one new
     // difference and one minmod, and the face's left state is carried from
     // the previous face. The same values as the face-wise formula, operation
     // for operation (minmod is symmetric); since r0 is a multiple of 4, a
@@ -101,10 +105,16 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const double d0 = W[1][v] - W[0][v], d1 = W[2][v] - W[1][v], d2 = W[3][v] - W[2][v];
-        qL[v] = W[1][v] + 0.5 * (UNL ? d0 : minmod(d0, d1));
-        const double mr = UNL ? d2 : minmod(d1, d2);
-        qR[v] = W[2][v] - 0.5 * mr;
-        qLy[v] = W[2][v] + 0.5 * (UNL ? d1 : mr);
+        if (LIM == 2) {
+            qL[v] = fma(ka, d0, fma(kb, d1, W[1][v]));
+            qR[v] = fma(-kb, d1, fma(-ka, d2, W[2][v]));
+            qLy[v] = fma(ka, d1, fma(kb, d2, W[2][v]));
+        } else {
+            qL[v] = W[1][v] + 0.5 * (UNL ? d0 : minmod(d0, d1));
+            const double mr = UNL ? d2 : minmod(d1, d2);
+            qR[v] = W[2][v] - 0.5 * mr;
+            qLy[v] = W[2][v] + 0.5 * (UNL ? d1 : mr);
+        }
         Dy[v] = d2;
     }
     {
@@ -143,10 +153,15 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             for (int v = 0; v < NV; ++v) {
                 const double u1 = W[(t + 2) & 3][v];
                 const double dn = W[(t + 3) & 3][v] - u1;  // D[rr+2]
-                const double mr = UNL ? dn : minmod(Dy[v], dn);
                 qL[v] = qLy[v];
-                qR[v] = u1 - 0.5 * mr;
-                qLy[v] = u1 + 0.5 * (UNL ? Dy[v] : mr);
+                if (LIM == 2) {
+                    qR[v] = fma(-kb, Dy[v], fma(-ka, dn, u1));
+                    qLy[v] = fma(ka, Dy[v], fma(kb, dn, u1));
+                } else {
+                    const double mr = UNL ? dn : minmod(Dy[v], dn);
+                    qR[v] = u1 - 0.5 * mr;
+                    qLy[v] = u1 + 0.5 * (UNL ? Dy[v] : mr);
+                }
                 Dy[v] = dn;
             }
             roe_flux<2, 1, true>(qL, qR, G.gm1, Fy[t & 1]);
@@ -159,9 +174,14 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             for (int v = 0; v < NV; ++v) {
                 const double d = c[v] - lane_shift1<true>(c[v]);  // D[i]
                 const double dn = lane_shift1<false>(d);           // D[i+1]
-                const double mr = UNL ? dn : minmod(d, dn);
-                qR[v] = c[v] - 0.5 * mr;
-                qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
+                if (LIM == 2) {
+                    qR[v] = fma(-kb, d, fma(-ka, dn, c[v]));
+                    qL[v] = lane_shift1<true>(fma(ka, d, fma(kb, dn, c[v])));
+                } else {
+                    const double mr = UNL ? dn : minmod(d, dn);
+                    qR[v] = c[v] - 0.5 * mr;
+                    qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
+                }
             }
             roe_flux<2, 0, true>(qL, qR, G.gm1, Fxl);
 #pragma unroll
@@ -229,10 +249,15 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         const double s = -dt * G.inv_vol;
         double lmax = 0.0;
         uint32_t fl = 0;
-        if (G.unlimited)
-            fused2d_rows<STAGE, true>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl);
-        else
-            fused2d_rows<STAGE, false>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl);
+        if (G.scheme == 0) {
+            fused2d_rows<STAGE, 0>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+        } else if (G.scheme == 1) {
+            fused2d_rows<STAGE, 1>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+        } else {
+            double ka, kb;
+            kappa_weights(G.scheme, ka, kb);
+            fused2d_rows<STAGE, 2>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb);
+        }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
             fl = wave_or(fl);

@@ -25,15 +25,29 @@
 
 namespace fvk {
 
+// Face states of one face from its four stencil cells, face-wise, by the
+// compile-time rule LIM (0 minmod, 1 Psi = 1 with kappa = -1, 2 the kappa
+// weights ka, kb with explicit fused multiply-adds).
+template <int LIM>
+__device__ __forceinline__ void zface_states(double q0, double q1, double q2, double q3, double ka, double kb,
+                                             double& qL, double& qR) {
+    if (LIM == 2)
+        muscl_kappa_diffs(q1, q2, q1 - q0, q2 - q1, q3 - q2, ka, kb, qL, qR);
+    else
+        muscl_fixed<LIM == 1>(q0, q1, q2, q3, qL, qR);
+}
+
 // The planes of one work item (strip, row j, planes k0 .. k0 + seg - 1) for
-// stage STAGE with the limiter fixed at compile time (UNL: Psi = 1). As in
+// stage STAGE with the face-state rule fixed at compile time (LIM: 0 minmod,
+// 1 Psi = 1 with kappa = -1, 2 Psi = 1 with kappa weights ka, kb). As in
 // 2D, no memory access sits on a conditional path: loads are issued for
 // every face (clamped indices), and stores of lanes or planes without output
 // go past the end of a per-variable descriptor, where they are dropped.
-template <int STAGE, bool UNL>
+template <int STAGE, int LIM>
 __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int strip, int j, int k0, double s,
                                                const double* Un, const double* Us, double* Ud, double& lmax,
-                                               uint32_t& fl) {
+                                               uint32_t& fl, double ka, double kb) {
+    constexpr bool UNL = LIM == 1;
     constexpr int NV = 5;
     const int col = FW * strip - 2 + lane;
     // lanes past the last halo column feed no output: they read that
@@ -83,7 +97,7 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
     double Fz[2][NV];  // z-face fluxes (times 2): face f in Fz[f & 1]
     double qL[NV], qR[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) muscl_fixed<UNL>(W[0][v], W[1][v], W[2][v], W[3][v], qL[v], qR[v]);
+    for (int v = 0; v < NV; ++v) zface_states<LIM>(W[0][v], W[1][v], W[2][v], W[3][v], ka, kb, qL[v], qR[v]);
     roe_flux<3, 2, true>(qL, qR, G.gm1, Fz[0]);
     {
         const uint32_t o = plane_off(k0 + 2) + ro[2];
@@ -119,7 +133,8 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
             // z face f: stencil planes kk-1 .. kk+2
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                muscl_fixed<UNL>(W[t][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], qL[v], qR[v]);
+                zface_states<LIM>(W[t][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], ka, kb, qL[v],
+                                  qR[v]);
             roe_flux<3, 2, true>(qL, qR, G.gm1, Fz[t & 1]);
             double c[NV];
 #pragma unroll
@@ -139,11 +154,18 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
             for (int v = 0; v < NV; ++v) {
                 const double d1 = Y[1][v] - Y[0][v], d2 = c[v] - Y[1][v];
                 const double d3 = Y[2][v] - c[v], d4 = Y[3][v] - Y[2][v];
-                const double m = UNL ? 0.0 : minmod(d2, d3);
-                qL[v] = Y[1][v] + 0.5 * (UNL ? d1 : minmod(d1, d2));
-                qR[v] = c[v] - 0.5 * (UNL ? d3 : m);
-                qLt[v] = c[v] + 0.5 * (UNL ? d2 : m);
-                qRt[v] = Y[2][v] - 0.5 * (UNL ? d4 : minmod(d4, d3));
+                if (LIM == 2) {
+                    qL[v] = fma(ka, d1, fma(kb, d2, Y[1][v]));
+                    qR[v] = fma(-kb, d2, fma(-ka, d3, c[v]));
+                    qLt[v] = fma(ka, d2, fma(kb, d3, c[v]));
+                    qRt[v] = fma(-kb, d3, fma(-ka, d4, Y[2][v]));
+                } else {
+                    const double m = UNL ? 0.0 : minmod(d2, d3);
+                    qL[v] = Y[1][v] + 0.5 * (UNL ? d1 : minmod(d1, d2));
+                    qR[v] = c[v] - 0.5 * (UNL ? d3 : m);
+                    qLt[v] = c[v] + 0.5 * (UNL ? d2 : m);
+                    qRt[v] = Y[2][v] - 0.5 * (UNL ? d4 : minmod(d4, d3));
+                }
             }
             roe_flux<3, 1, true>(qL, qR, G.gm1, Fyb);
             roe_flux<3, 1, true>(qLt, qRt, G.gm1, Fyt);
@@ -154,9 +176,14 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
             for (int v = 0; v < NV; ++v) {
                 const double d = c[v] - lane_shift1<true>(c[v]);  // D[i]
                 const double dn = lane_shift1<false>(d);           // D[i+1]
-                const double mr = UNL ? dn : minmod(d, dn);
-                qR[v] = c[v] - 0.5 * mr;
-                qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
+                if (LIM == 2) {
+                    qR[v] = fma(-kb, d, fma(-ka, dn, c[v]));
+                    qL[v] = lane_shift1<true>(fma(ka, d, fma(kb, dn, c[v])));
+                } else {
+                    const double mr = UNL ? dn : minmod(d, dn);
+                    qR[v] = c[v] - 0.5 * mr;
+                    qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
+                }
             }
             roe_flux<3, 0, true>(qL, qR, G.gm1, Fxl);
 #pragma unroll
@@ -221,10 +248,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const double s = -dt * G.inv_vol;
         double lmax = 0.0;
         uint32_t fl = 0;
-        if (G.unlimited)
-            fused3d_planes<STAGE, true>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl);
-        else
-            fused3d_planes<STAGE, false>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl);
+        if (G.scheme == 0) {
+            fused3d_planes<STAGE, 0>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+        } else if (G.scheme == 1) {
+            fused3d_planes<STAGE, 1>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+        } else {
+            double ka, kb;
+            kappa_weights(G.scheme, ka, kb);
+            fused3d_planes<STAGE, 2>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb);
+        }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
             fl = wave_or(fl);

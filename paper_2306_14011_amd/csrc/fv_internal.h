@@ -16,7 +16,7 @@ constexpr int CLK_PAD = 16;  // unsigned long longs per slot (one 128-byte line)
 __host__ __device__ inline int clk_index(int entry, int slot) { return (entry * CLK_SLOTS + slot) * CLK_PAD; }
 
 struct FGrid {
-    int nx, ny, pitch, strips, work0, unlimited;
+    int nx, ny, pitch, strips, work0, scheme;  // scheme: FV_SCHEME_*
     int bcx0, bcx1, bcy0, bcy1, gid, seg;   // gid: the caller's grid index (slots of lam, dt, clocks);
                                             // seg: rows per work item (a multiple of 4)
     long long base;     // element offset of cell (0,0), variable 0
@@ -27,7 +27,7 @@ struct FGrid {
 
 // The 3D grid of the fused path (device memory, read uniformly).
 struct FGrid3 {
-    int nx, ny, nz, strips, seg, unlimited;       // seg: planes per work item (a multiple of 4)
+    int nx, ny, nz, strips, seg, scheme;       // seg: planes per work item (a multiple of 4)
     int bcx0, bcx1, bcy0, bcy1, bcz0, bcz1;
     long long base;                                // element offset of cell (0,0,0), variable 0
     long long sv, py, pz;                          // strides: variable, row (y), plane (z)

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(MAXT) k_flux(const double* __restrict__ U, dou
         for (int v = 0; v < NV; ++v) {
             const double* Uv = U + v * g.sv;
             const double q0 = Uv[c - 2 * st], q1 = Uv[c - st], q2 = Uv[c], q3 = Uv[c + st];
-            muscl(q0, q1, q2, q3, g.unlimited, qL[v], qR[v]);
+            muscl(q0, q1, q2, q3, g.scheme, qL[v], qR[v]);
         }
         double Fl[NV];
         roe_flux<NDIM, AX>(qL, qR, g.gm1, Fl);
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(MAXT) k_flux_run(const double* __restrict__ U,
             double qL[NV], qR[NV], Fl[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                muscl(W[t & 3][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], g.unlimited, qL[v],
+                muscl(W[t & 3][v], W[(t + 1) & 3][v], W[(t + 2) & 3][v], W[(t + 3) & 3][v], g.scheme, qL[v],
                       qR[v]);
             roe_flux<NDIM, AX>(qL, qR, g.gm1, Fl);
             const int fj = AX == 1 ? a : j, fk = AX == 1 ? k : a;

@@ -28,6 +28,24 @@ FV_EWORKSPACE = -5
 
 FV_SCHEME_MINMOD = 0
 FV_SCHEME_UNLIMITED = 1
+FV_SCHEME_FROMM = 2
+FV_SCHEME_THIRD = 3
+FV_SCHEME_CENTRAL = 4
+# kappa of the unlimited (Psi = 1) members of the MUSCL family
+_SCHEME_OF_KAPPA = ((-1.0, FV_SCHEME_UNLIMITED), (0.0, FV_SCHEME_FROMM), (1.0 / 3.0, FV_SCHEME_THIRD),
+                    (1.0, FV_SCHEME_CENTRAL))
+
+
+def scheme_of(spec):
+    """FV_SCHEME_* of a grid spec: minmod unless spec.limiter is False, then the
+    unlimited member for spec.kappa (-1 by default; 0, 1/3 and 1 also exist)."""
+    if getattr(spec, "limiter", True):
+        return FV_SCHEME_MINMOD
+    kappa = float(getattr(spec, "kappa", -1.0))
+    for k, code in _SCHEME_OF_KAPPA:
+        if abs(kappa - k) <= 1e-12:
+            return code
+    raise ValueError(f"unlimited MUSCL supports kappa in (-1, 0, 1/3, 1), got {kappa}")
 
 FV_BC_PERIODIC = 0
 FV_BC_TRANSMISSIVE = 1
@@ -176,10 +194,11 @@ def _check(rc, ctx=None):
 
 def make_desc(spec) -> fv_grid_desc:
     """fv_grid_desc from any object with ndim, n, lo, hi, bc, gamma, cfl (and
-    optionally limiter: False selects the unlimited scheme)."""
+    optionally limiter: False selects the unlimited scheme of kappa, see
+    scheme_of)."""
     d = fv_grid_desc()
     d.ndim = spec.ndim
-    d.scheme = FV_SCHEME_UNLIMITED if not getattr(spec, "limiter", True) else FV_SCHEME_MINMOD
+    d.scheme = scheme_of(spec)
     for a in range(3):
         d.n[a] = int(spec.n[a])
         d.lo[a] = float(spec.lo[a])

@@ -40,6 +40,7 @@ class GridSpec:
     gamma: float = GAMMA
     cfl: float = 0.5
     limiter: bool = True   # False: unlimited MUSCL (Psi = 1)
+    kappa: float = -1.0    # MUSCL kappa of the unlimited scheme: -1, 0, 1/3 or 1
 
     @property
     def nvar(self) -> int:

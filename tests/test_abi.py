@@ -57,7 +57,8 @@ def test_query_strides_and_workspace():
     lambda d: d.bc[1].__setitem__(1, 7),        # unknown kind
     lambda d: setattr(d, "gamma", 1.0),
     lambda d: setattr(d, "cfl", 0.0),
-    lambda d: setattr(d, "scheme", 2),
+    lambda d: setattr(d, "scheme", 5),
+    lambda d: setattr(d, "scheme", -1),
     lambda d: d.hi.__setitem__(0, d.lo[0]),
 ])
 def test_query_rejects_invalid_descriptions(mutate):
@@ -67,6 +68,28 @@ def test_query_rejects_invalid_descriptions(mutate):
         fv.fv_query(d)
     assert e.value.code == fv.FV_EINVAL
     assert fv.fv_last_error()
+
+
+def test_schemes_of_the_muscl_family():
+    """Every FV_SCHEME_* is accepted; a spec maps to the scheme of its limiter
+    and kappa (with the limiter on, kappa does not matter: minmod collapses
+    the kappa terms), and kappas outside the family are refused on the host."""
+    g = inputs.grid2d(16, 16)
+    for code in (fv.FV_SCHEME_MINMOD, fv.FV_SCHEME_UNLIMITED, fv.FV_SCHEME_FROMM, fv.FV_SCHEME_THIRD,
+                 fv.FV_SCHEME_CENTRAL):
+        d = fv.make_desc(g)
+        d.scheme = code
+        fv.fv_query(d)
+    assert fv.scheme_of(g) == fv.FV_SCHEME_MINMOD
+    for kappa, code in ((-1.0, fv.FV_SCHEME_UNLIMITED), (0.0, fv.FV_SCHEME_FROMM), (1.0 / 3.0, fv.FV_SCHEME_THIRD),
+                        (1.0, fv.FV_SCHEME_CENTRAL)):
+        g.limiter, g.kappa = False, kappa
+        assert fv.scheme_of(g) == code
+        g.limiter = True
+        assert fv.scheme_of(g) == fv.FV_SCHEME_MINMOD
+    g.limiter, g.kappa = False, 0.5
+    with pytest.raises(ValueError):
+        fv.make_desc(g)
 
 
 def test_query_rejects_oversized_grid():

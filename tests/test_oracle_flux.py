@@ -57,6 +57,31 @@ def test_muscl_hand_values():
     assert oracle.muscl(5.0, 1.0, 3.0, -7.0, limiter=False, kappa=1.0) == (2.0, 2.0)
 
 
+def test_muscl_kappa_family_pins():
+    """Eq. (flux) with epsilon = 1. (a) With the minmod limiter Psi+ and Psi-
+    give the same limited difference (minmod is symmetric), so kappa drops
+    out: every kappa gives Q_k + minmod / 2. (b) kappa = 1/3 without limiter
+    reproduces the face value of a quadratic from its cell averages (third
+    order): averages of x^2 over unit cells centred on -1, 0, 1, 2 are
+    k^2 + 1/12, and both states at x = 1/2 are 1/4. (c) kappa = 0 (Fromm)
+    uses the central difference (Q_{k+1} - Q_{k-1}) / 4."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        q = rng.normal(size=4)
+        base = oracle.muscl(*q, kappa=-1.0)
+        for kappa in (0.0, 1.0 / 3.0, 1.0):
+            got = oracle.muscl(*q, kappa=kappa)
+            assert np.allclose(got, base, rtol=1e-15, atol=1e-15), (q, kappa)
+    avg = [k * k + 1.0 / 12.0 for k in (-1, 0, 1, 2)]
+    qL, qR = oracle.muscl(*avg, limiter=False, kappa=1.0 / 3.0)
+    assert abs(qL - 0.25) < 1e-15 and abs(qR - 0.25) < 1e-15
+    # the other members are not exact for it: kappa = -1 gives 1/12 + 1/2 (1/12 - 13/12)
+    qL_up, _ = oracle.muscl(*avg, limiter=False, kappa=-1.0)
+    assert abs(qL_up - (1.0 / 12.0 - 0.5)) < 1e-15
+    qL0, qR0 = oracle.muscl(0.0, 1.0, 5.0, 2.0, limiter=False, kappa=0.0)
+    assert qL0 == 1.0 + (5.0 - 0.0) / 4.0 and qR0 == 5.0 - (2.0 - 1.0) / 4.0
+
+
 def test_physical_flux_hand_values():
     # rho = 1, u = (2, 0), p = 1 -> E = 1/0.4 + 0.5*4 = 4.5
     Q = [1.0, 2.0, 0.0, 4.5]
