@@ -93,23 +93,35 @@ def timed_steps(torch, solver, U0, steps, warmup, launch=None):
 TRAFFIC_FILE = "profiles/fused_and_split_vortex2048_traffic.json"
 
 
+def code_digest(root, sources):
+    """SHA-256 of the code of C/HIP sources: comments removed and whitespace
+    collapsed, so that an edit of comments alone keeps the digest."""
+    import hashlib
+    import os
+    import re
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(root, src)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def counted_traffic(path, key, n):
     """HBM bytes per launch counted by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled
     by a copy of known size) for the 2048^2 workload, or None when the grid
-    differs or the kernel sources changed since the counters were taken."""
-    import hashlib
+    differs or the kernels' code changed since the counters were taken."""
     import os
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         with open(os.path.join(root, TRAFFIC_FILE)) as f:
             rec = json.load(f)[path]
-        h = hashlib.sha256()
-        for src in rec["sources"]:
-            with open(os.path.join(root, src), "rb") as f:
-                h.update(f.read())
+        digest = code_digest(root, rec["sources"])
     except (OSError, KeyError, ValueError):
         return None
-    if n != 2048 or h.hexdigest() != rec["source_sha256"]:
+    if n != 2048 or digest != rec["code_sha256"]:
         return None
     table = rec.get("bytes_per_launch_by_seg") or rec.get("bytes_per_launch")
     return table.get(str(key))

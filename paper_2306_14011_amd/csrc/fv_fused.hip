@@ -1,6 +1,7 @@
 // Fused SSP-RK3 stage for 2D grids (FP64, gfx950): one kernel per stage does
-// the ghost mapping, MUSCL-minmod + Roe fluxes on both axes, the residual and
-// the stage combination, and the last stage also the CFL max of the new state.
+// the ghost mapping, MUSCL face states (minmod, or an unlimited kappa member)
+// and Roe fluxes on both axes, the residual and the stage combination, and
+// the last stage also the CFL max of the new state.
 //
 // Work decomposition: a work item is a 60-column strip x seg-row segment of
 // one grid (seg a multiple of 4, per grid in the table); one wavefront (64

@@ -1,7 +1,7 @@
 // Fused SSP-RK3 stage for 3D grids (FP64, gfx950): one kernel per stage does
-// the ghost mapping, MUSCL-minmod + Roe fluxes on the three axes, the residual
-// and the stage combination, and the last stage also the CFL max of the new
-// state.
+// the ghost mapping, MUSCL face states (minmod, or an unlimited kappa member)
+// and Roe fluxes on the three axes, the residual and the stage combination,
+// and the last stage also the CFL max of the new state.
 //
 // Work decomposition: a work item is a 60-column x strip of one grid row j
 // over a segment of seg planes (seg a multiple of 4); one wavefront owns an
