@@ -241,10 +241,12 @@ def fused_leg(torch, fv, traffic, g, U0, a):
 
 def schemes_leg(torch, fv, traffic, g, U0, steps):
     """The fused 2D step on the headline workload for each member of the MUSCL
-    family: minmod (the headline) and Psi = 1 with kappa = -1, 0, 1/3, 1."""
+    family: minmod (the headline), van Leer, and Psi = 1 with kappa = -1, 0,
+    1/3, 1."""
     import copy
     out = {}
-    for name, lim, kappa in (("minmod", True, -1.0), ("kappa=-1", False, -1.0), ("kappa=0", False, 0.0),
+    for name, lim, kappa in (("minmod", True, -1.0), ("vanleer", "vanleer", -1.0), ("kappa=-1", False, -1.0),
+                             ("kappa=0", False, 0.0),
                              ("kappa=1/3", False, 1.0 / 3.0), ("kappa=1", False, 1.0)):
         gg = copy.copy(g)
         gg.limiter, gg.kappa = lim, kappa

@@ -74,16 +74,18 @@ enum {
 };
 
 /* Scheme of fv_grid_desc.scheme: the MUSCL face states of Eq. (flux) with
- * epsilon = 1. With the minmod limiter the kappa terms collapse (minmod is
- * symmetric, so Psi+ and Psi- give the same limited difference) and every
- * kappa gives Q^L = Q_k + minmod(dQ_{k-1/2}, dQ_{k+1/2}) / 2. With Psi = 1,
- * kappa selects the member of the family. */
+ * epsilon = 1. With a symmetric limiter (minmod, van Leer) the kappa terms
+ * collapse (Psi+ and Psi- give the same limited difference) and every kappa
+ * gives Q^L = Q_k + Psi dQ / 2. With Psi = 1, kappa selects the member of
+ * the family. */
 enum {
     FV_SCHEME_MINMOD = 0,      /* minmod limiter (the default)                          */
     FV_SCHEME_UNLIMITED = 1,   /* Psi = 1, kappa = -1: fully upwind                     */
     FV_SCHEME_FROMM = 2,       /* Psi = 1, kappa = 0: Fromm's upwind-biased scheme      */
     FV_SCHEME_THIRD = 3,       /* Psi = 1, kappa = 1/3: third-order upwind-biased       */
-    FV_SCHEME_CENTRAL = 4      /* Psi = 1, kappa = 1: central                            */
+    FV_SCHEME_CENTRAL = 4,     /* Psi = 1, kappa = 1: central                            */
+    FV_SCHEME_VANLEER = 5      /* van Leer's limiter, Psi(r) = (r + |r|)/(1 + |r|) (symmetric,
+                                  so kappa drops out as with minmod)                      */
 };
 
 /* Grid description. ndim is 2 or 3; n[2] must be 1 in 2D. The box is

@@ -53,6 +53,8 @@ def lib():
         L = ctypes.CDLL(path)
         L.or_psi_minmod.restype = ctypes.c_double
         L.or_psi_minmod.argtypes = [ctypes.c_double]
+        L.or_psi_vanleer.restype = ctypes.c_double
+        L.or_psi_vanleer.argtypes = [ctypes.c_double]
         L.or_limited.restype = ctypes.c_double
         L.or_limited.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.or_muscl.restype = None
@@ -80,11 +82,23 @@ def _p(a):
     return a.ctypes.data_as(c_double_p)
 
 
+def limiter_code(limiter):
+    """OrGrid.limiter of a limiter choice: True or "minmod" -> 1, "vanleer" -> 2,
+    False or None -> 0 (Psi = 1)."""
+    if limiter == "vanleer":
+        return 2
+    if limiter is True or limiter == "minmod":
+        return 1
+    if limiter is False or limiter is None:
+        return 0
+    raise ValueError(f"unknown limiter {limiter!r}")
+
+
 def make_grid(spec, limiter=True, kappa=-1.0):
     """OrGrid from any object with ndim, n, lo, hi, bc, gamma, cfl attributes."""
     g = OrGrid()
     g.ndim = spec.ndim
-    g.limiter = 1 if limiter else 0
+    g.limiter = limiter_code(limiter)
     for d in range(3):
         g.n[d] = int(spec.n[d])
         g.dx[d] = (spec.hi[d] - spec.lo[d]) / spec.n[d]
@@ -104,14 +118,18 @@ def psi_minmod(r):
     return lib().or_psi_minmod(float(r))
 
 
+def psi_vanleer(r):
+    return lib().or_psi_vanleer(float(r))
+
+
 def limited(num, den, limiter=True):
-    return lib().or_limited(float(num), float(den), 1 if limiter else 0)
+    return lib().or_limited(float(num), float(den), limiter_code(limiter))
 
 
 def muscl(qm1, q0, qp1, qp2, limiter=True, kappa=-1.0):
     a = ctypes.c_double()
     b = ctypes.c_double()
-    lib().or_muscl(qm1, q0, qp1, qp2, 1 if limiter else 0, kappa, ctypes.byref(a), ctypes.byref(b))
+    lib().or_muscl(qm1, q0, qp1, qp2, limiter_code(limiter), kappa, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
 
 

@@ -44,7 +44,7 @@ extern "C" {
 // Grid description passed from Python (ctypes mirrors this struct).
 struct OrGrid {
     int32_t ndim;       // 2 or 3
-    int32_t limiter;    // 1 = minmod, 0 = unlimited (Psi = 1), test use only
+    int32_t limiter;    // 1 = minmod, 2 = van Leer, 0 = unlimited (Psi = 1)
     int64_t n[3];       // cells per axis (n[2] = 1 in 2D)
     double dx[3];       // cell widths
     int32_t bc[3][2];   // 0 = periodic, 1 = transmissive, per axis and side
@@ -85,11 +85,19 @@ template <class T> static inline T psi_minmod(const T& r) {
     return T(1.0);
 }
 
+// van Leer's limiter function Psi(r) = (r + |r|) / (1 + |r|) (van Leer 1974),
+// written for r > 0 as 2r / (1 + r); zero for r <= 0.
+template <class T> static inline T psi_vanleer(const T& r) {
+    if (!(re(r) > 0.0)) return T(0.0);
+    return 2.0 * r / (1.0 + r);
+}
+
 // Limited difference Psi(num/den) * den, with Psi * 0 := 0.
-// For Psi = minmod this equals minmod(den, num); with the limiter off Psi = 1.
+// limiter: 0 Psi = 1, 1 minmod (this equals minmod(den, num)), 2 van Leer.
 template <class T> static inline T limited(const T& num, const T& den, int limiter) {
     if (!limiter) return den;
     if (re(den) == 0.0) return T(0.0);
+    if (limiter == 2) return psi_vanleer(num / den) * den;
     // the branch of Psi is taken on the ratio of the real parts
     const double rr = re(num) / re(den);
     if (!(rr > 0.0)) return T(0.0);
@@ -307,6 +315,8 @@ static void rk3_step(const OrGrid* g, T* U, double dt) {
 extern "C" {
 
 double or_psi_minmod(double r) { return psi_minmod(r); }
+
+double or_psi_vanleer(double r) { return psi_vanleer(r); }
 
 double or_limited(double num, double den, int limiter) { return limited(num, den, limiter); }
 

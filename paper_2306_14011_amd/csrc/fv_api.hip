@@ -79,7 +79,7 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
         snprintf(why, 256, "ndim must be 2 or 3");
         return FV_EINVAL;
     }
-    if (g->scheme < FV_SCHEME_MINMOD || g->scheme > FV_SCHEME_CENTRAL) {
+    if (g->scheme < FV_SCHEME_MINMOD || g->scheme > FV_SCHEME_VANLEER) {
         snprintf(why, 256, "unknown scheme");
         return FV_EINVAL;
     }

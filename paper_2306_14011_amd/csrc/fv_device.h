@@ -49,7 +49,7 @@ struct Geo {
     double gamma, gm1;  // gamma, gamma - 1
     double cfl;
     int bc[3][2];
-    int scheme;         // 0 minmod; Psi = 1 with kappa = -1, 0, 1/3, 1 for 1 .. 4
+    int scheme;         // 0 minmod; Psi = 1 with kappa = -1, 0, 1/3, 1 for 1 .. 4; 5 van Leer
 };
 
 // 1/a and 1/sqrt(a) for the flux arithmetic: the hardware estimates
@@ -90,6 +90,14 @@ __host__ __device__ __forceinline__ double rsqrt_nr(double a) {
 // or selects (four min/max).
 __host__ __device__ __forceinline__ double minmod(double a, double b) {
     return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// van Leer's limited difference Psi(b/a) a with Psi(r) = (r + |r|)/(1 + |r|):
+// 2ab/(a + b) for slopes of one sign, else 0. Symmetric in a and b, bit for
+// bit (products and sums commute), so one value serves both faces of a cell.
+__host__ __device__ __forceinline__ double vanleer(double a, double b) {
+    const double ab = a * b;
+    return ab > 0.0 ? 2.0 * ab * rcp_nr(a + b) : 0.0;
 }
 
 // MUSCL face states from the three differences of the stencil,
@@ -150,6 +158,10 @@ __host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, 
         qR = q2 - 0.5 * (q3 - q2);
     } else if (scheme == 0) {
         muscl_minmod(q0, q1, q2, q3, qL, qR);
+    } else if (scheme == 5) {
+        const double dc = q2 - q1;
+        qL = q1 + 0.5 * vanleer(q1 - q0, dc);
+        qR = q2 - 0.5 * vanleer(dc, q3 - q2);
     } else {
         double a, b;
         kappa_weights(scheme, a, b);
@@ -329,6 +341,24 @@ __host__ __device__ __forceinline__ void muscl_vjp(double q0, double q1, double 
         g3 -= 0.5 * qRb;
     } else if (scheme == 0) {
         muscl_minmod_vjp(q0, q1, q2, q3, qLb, qRb, g0, g1, g2, g3);
+    } else if (scheme == 5) {
+        // d vl(a, b)/da = 2 b^2 / (a + b)^2 and symmetric, zero unless ab > 0
+        const double dm = q1 - q0, dc = q2 - q1, dp = q3 - q2;
+        double ga = 0.0, gb = 0.0, ha = 0.0, hb = 0.0;
+        if (dm * dc > 0.0) {
+            const double i2 = 2.0 / ((dm + dc) * (dm + dc));
+            ga = i2 * dc * dc;
+            gb = i2 * dm * dm;
+        }
+        if (dc * dp > 0.0) {
+            const double i2 = 2.0 / ((dc + dp) * (dc + dp));
+            ha = i2 * dp * dp;
+            hb = i2 * dc * dc;
+        }
+        g0 -= 0.5 * ga * qLb;
+        g1 += (1.0 + 0.5 * ga - 0.5 * gb) * qLb + 0.5 * ha * qRb;
+        g2 += 0.5 * gb * qLb + (1.0 - 0.5 * ha + 0.5 * hb) * qRb;
+        g3 -= 0.5 * hb * qRb;
     } else {
         double a, b;
         kappa_weights(scheme, a, b);

@@ -29,7 +29,8 @@ namespace fvk {
 
 // The rows of one work item (strip, rows r0 .. r0 + seg - 1) for stage STAGE
 // with the face-state rule fixed at compile time (LIM: 0 minmod, 1 Psi = 1
-// with kappa = -1, 2 Psi = 1 with the kappa weights ka, kb). The loop body has
+// with kappa = -1, 2 Psi = 1 with the kappa weights ka, kb, 3 van Leer). The
+// loop body has
 // no branch around a memory access: every load is issued whatever the row
 // (indices past the grid are clamped), and the stores of lanes or rows with
 // no output go to an offset past the end of the buffer, where the hardware
@@ -77,8 +78,9 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     // window never moves between registers.
     //
     // MUSCL per cell rather than per face: with D[r] = U[r] - U[r-1], the
-    // left state of the face above row r is U[r] + minmod(D[r], D[r+1]) / 2
-    // and the right state of the face below it U[r] - minmod(D[r+1], D[r]) / 2
+    // left state of the face above row r is U[r] + lim(D[r], D[r+1]) / 2 and
+    // the right state of the face below it U[r] - lim(D[r+1], D[r]) / 2 for a
+    // symmetric limited slope lim (minmod, van Leer)
     // (unlimited: D[r] / 2 and D[r+1] / 2; other kappa: the weighted sums
     // ka D[r] + kb D[r+1] and kb D[r] + ka D[r+1]), so each row needs one new
     // difference and one minmod, and the face's left state is carried from
@@ -111,8 +113,8 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             qR[v] = fma(-kb, d1, fma(-ka, d2, W[2][v]));
             qLy[v] = fma(ka, d1, fma(kb, d2, W[2][v]));
         } else {
-            qL[v] = W[1][v] + 0.5 * (UNL ? d0 : minmod(d0, d1));
-            const double mr = UNL ? d2 : minmod(d1, d2);
+            qL[v] = W[1][v] + 0.5 * (UNL ? d0 : limited_slope<LIM>(d0, d1));
+            const double mr = UNL ? d2 : limited_slope<LIM>(d1, d2);
             qR[v] = W[2][v] - 0.5 * mr;
             qLy[v] = W[2][v] + 0.5 * (UNL ? d1 : mr);
         }
@@ -159,7 +161,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                     qR[v] = fma(-kb, Dy[v], fma(-ka, dn, u1));
                     qLy[v] = fma(ka, Dy[v], fma(kb, dn, u1));
                 } else {
-                    const double mr = UNL ? dn : minmod(Dy[v], dn);
+                    const double mr = UNL ? dn : limited_slope<LIM>(Dy[v], dn);
                     qR[v] = u1 - 0.5 * mr;
                     qLy[v] = u1 + 0.5 * (UNL ? Dy[v] : mr);
                 }
@@ -179,7 +181,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                     qR[v] = fma(-kb, d, fma(-ka, dn, c[v]));
                     qL[v] = lane_shift1<true>(fma(ka, d, fma(kb, dn, c[v])));
                 } else {
-                    const double mr = UNL ? dn : minmod(d, dn);
+                    const double mr = UNL ? dn : limited_slope<LIM>(d, dn);
                     qR[v] = c[v] - 0.5 * mr;
                     qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
                 }
@@ -252,6 +254,8 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         uint32_t fl = 0;
         if (G.scheme == 0) {
             fused2d_rows<STAGE, 0>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+        } else if (G.scheme == 5) {
+            fused2d_rows<STAGE, 3>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
         } else if (G.scheme == 1) {
             fused2d_rows<STAGE, 1>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
         } else {

@@ -27,19 +27,25 @@ namespace fvk {
 
 // Face states of one face from its four stencil cells, face-wise, by the
 // compile-time rule LIM (0 minmod, 1 Psi = 1 with kappa = -1, 2 the kappa
-// weights ka, kb with explicit fused multiply-adds).
+// weights ka, kb with explicit fused multiply-adds, 3 van Leer).
 template <int LIM>
 __device__ __forceinline__ void zface_states(double q0, double q1, double q2, double q3, double ka, double kb,
                                              double& qL, double& qR) {
-    if (LIM == 2)
+    if (LIM == 2) {
         muscl_kappa_diffs(q1, q2, q1 - q0, q2 - q1, q3 - q2, ka, kb, qL, qR);
-    else
+    } else if (LIM == 3) {
+        const double dc = q2 - q1;
+        qL = q1 + 0.5 * vanleer(q1 - q0, dc);
+        qR = q2 - 0.5 * vanleer(dc, q3 - q2);
+    } else {
         muscl_fixed<LIM == 1>(q0, q1, q2, q3, qL, qR);
+    }
 }
 
 // The planes of one work item (strip, row j, planes k0 .. k0 + seg - 1) for
 // stage STAGE with the face-state rule fixed at compile time (LIM: 0 minmod,
-// 1 Psi = 1 with kappa = -1, 2 Psi = 1 with kappa weights ka, kb). As in
+// 1 Psi = 1 with kappa = -1, 2 Psi = 1 with kappa weights ka, kb, 3 van
+// Leer). As in
 // 2D, no memory access sits on a conditional path: loads are issued for
 // every face (clamped indices), and stores of lanes or planes without output
 // go past the end of a per-variable descriptor, where they are dropped.
@@ -147,7 +153,8 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
             }
             // y faces of row j at plane kk: below (rows j-2 .. j+1) and above
             // (rows j-1 .. j+2). With D[r] = U[r] - U[r-1], the own row's
-            // slope minmod(D[j], D[j+1]) serves both faces (minmod is symmetric).
+            // limited slope lim(D[j], D[j+1]) serves both faces (minmod and van
+            // Leer are symmetric).
             double Fyb[NV], Fyt[NV];  // times 2, like Fz
             double qLt[NV], qRt[NV];
 #pragma unroll
@@ -160,11 +167,11 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
                     qLt[v] = fma(ka, d2, fma(kb, d3, c[v]));
                     qRt[v] = fma(-kb, d3, fma(-ka, d4, Y[2][v]));
                 } else {
-                    const double m = UNL ? 0.0 : minmod(d2, d3);
-                    qL[v] = Y[1][v] + 0.5 * (UNL ? d1 : minmod(d1, d2));
+                    const double m = UNL ? 0.0 : limited_slope<LIM>(d2, d3);
+                    qL[v] = Y[1][v] + 0.5 * (UNL ? d1 : limited_slope<LIM>(d1, d2));
                     qR[v] = c[v] - 0.5 * (UNL ? d3 : m);
                     qLt[v] = c[v] + 0.5 * (UNL ? d2 : m);
-                    qRt[v] = Y[2][v] - 0.5 * (UNL ? d4 : minmod(d4, d3));
+                    qRt[v] = Y[2][v] - 0.5 * (UNL ? d4 : limited_slope<LIM>(d4, d3));
                 }
             }
             roe_flux<3, 1, true>(qL, qR, G.gm1, Fyb);
@@ -180,7 +187,7 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
                     qR[v] = fma(-kb, d, fma(-ka, dn, c[v]));
                     qL[v] = lane_shift1<true>(fma(ka, d, fma(kb, dn, c[v])));
                 } else {
-                    const double mr = UNL ? dn : minmod(d, dn);
+                    const double mr = UNL ? dn : limited_slope<LIM>(d, dn);
                     qR[v] = c[v] - 0.5 * mr;
                     qL[v] = lane_shift1<true>(c[v] + 0.5 * (UNL ? d : mr));
                 }
@@ -250,6 +257,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         uint32_t fl = 0;
         if (G.scheme == 0) {
             fused3d_planes<STAGE, 0>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+        } else if (G.scheme == 5) {
+            fused3d_planes<STAGE, 3>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
         } else if (G.scheme == 1) {
             fused3d_planes<STAGE, 1>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
         } else {

@@ -86,6 +86,13 @@ __device__ __forceinline__ double lane_shift1(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The limited slope of a cell from its two differences for the limiter
+// variant LIM of the fused kernels: 0 minmod, 3 van Leer (both symmetric).
+template <int LIM>
+__device__ __forceinline__ double limited_slope(double a, double b) {
+    return LIM == 3 ? vanleer(a, b) : minmod(a, b);
+}
+
 // Block index with the hardware's round-robin spread over the 8 XCDs undone:
 // block b runs on XCD b % 8, and the blocks of one XCD get a contiguous range
 // of logical indices, so vertically adjacent segments (which share halo rows)

@@ -31,16 +31,23 @@ FV_SCHEME_UNLIMITED = 1
 FV_SCHEME_FROMM = 2
 FV_SCHEME_THIRD = 3
 FV_SCHEME_CENTRAL = 4
+FV_SCHEME_VANLEER = 5
 # kappa of the unlimited (Psi = 1) members of the MUSCL family
 _SCHEME_OF_KAPPA = ((-1.0, FV_SCHEME_UNLIMITED), (0.0, FV_SCHEME_FROMM), (1.0 / 3.0, FV_SCHEME_THIRD),
                     (1.0, FV_SCHEME_CENTRAL))
 
 
 def scheme_of(spec):
-    """FV_SCHEME_* of a grid spec: minmod unless spec.limiter is False, then the
-    unlimited member for spec.kappa (-1 by default; 0, 1/3 and 1 also exist)."""
-    if getattr(spec, "limiter", True):
+    """FV_SCHEME_* of a grid spec: spec.limiter True (or "minmod") gives minmod,
+    "vanleer" van Leer, False the unlimited member for spec.kappa (-1 by
+    default; 0, 1/3 and 1 also exist)."""
+    lim = getattr(spec, "limiter", True)
+    if lim == "vanleer":
+        return FV_SCHEME_VANLEER
+    if lim is True or lim == "minmod":
         return FV_SCHEME_MINMOD
+    if lim is not False and lim is not None:
+        raise ValueError(f"unknown limiter {lim!r}")
     kappa = float(getattr(spec, "kappa", -1.0))
     for k, code in _SCHEME_OF_KAPPA:
         if abs(kappa - k) <= 1e-12:

@@ -142,12 +142,16 @@ def test_vortex_order_of_accuracy():
     ns = (32, 64, 128)
     lim = [vortex_l1_error(n, T) for n in ns]
     unl = [vortex_l1_error(n, T, limiter=False) for n in ns]
+    vl = [vortex_l1_error(n, T, limiter="vanleer") for n in ns]
+    r_vl = [math.log2(vl[i][0] / vl[i + 1][0]) for i in range(2)]
     r_lim = [math.log2(lim[i][0] / lim[i + 1][0]) for i in range(2)]
     r_unl1 = [math.log2(unl[i][0] / unl[i + 1][0]) for i in range(2)]
     r_unlinf = [math.log2(unl[i][1] / unl[i + 1][1]) for i in range(2)]
     # minmod clips extrema: L1 approaches 2 from below; unlimited: both norms near 2
     assert r_lim[-1] > 1.6, (lim, r_lim)
     assert r_unl1[-1] > 1.8 and r_unlinf[-1] > 1.7, (unl, r_unl1, r_unlinf)
+    # van Leer clips less than minmod: L1 order between minmod's and the unlimited one's
+    assert r_vl[-1] > 1.7 and vl[-1][0] < lim[-1][0], (vl, r_vl)
 
 
 def test_exact_riemann_textbook_values():

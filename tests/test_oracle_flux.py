@@ -82,6 +82,35 @@ def test_muscl_kappa_family_pins():
     assert qL0 == 1.0 + (5.0 - 0.0) / 4.0 and qR0 == 5.0 - (2.0 - 1.0) / 4.0
 
 
+def test_van_leer_limiter_pins():
+    """van Leer's Psi(r) = (r + |r|)/(1 + |r|): Psi(1) = 1, zero for r <= 0,
+    symmetric (Psi(r)/r = Psi(1/r)), inside Sweby's second-order TVD region
+    (between minmod and superbee), and its limited difference is the harmonic
+    form 2ab/(a + b) for slopes of one sign. Being symmetric, it makes kappa
+    drop out of Eq. (flux) as minmod does."""
+    assert oracle.psi_vanleer(1.0) == 1.0
+    assert oracle.psi_vanleer(0.0) == 0.0 and oracle.psi_vanleer(-3.0) == 0.0
+    assert oracle.psi_vanleer(3.0) == 1.5
+    rng = np.random.default_rng(8)
+    for r in np.exp(rng.uniform(-6, 6, 200)):
+        psi = oracle.psi_vanleer(r)
+        assert abs(psi / r - oracle.psi_vanleer(1.0 / r)) <= 1e-15 * max(1.0, psi / r)
+        lo = min(r, 1.0)
+        hi = max(min(2.0 * r, 1.0), min(r, 2.0))
+        assert lo - 1e-15 <= psi <= hi + 1e-15, r
+    assert oracle.limited(3.0, 1.0, "vanleer") == 1.5      # 2*3*1/(3+1)
+    assert oracle.limited(-2.0, -6.0, "vanleer") == -3.0   # 2*(-2)(-6)/(-8)
+    assert oracle.limited(2.0, -1.0, "vanleer") == 0.0
+    assert oracle.limited(0.0, 5.0, "vanleer") == 0.0
+    # hand face states: cells 0, 1, 4, 5: QL = 1 + vl(1, 3)/2 = 1.75, QR = 4 - vl(3, 1)/2 = 3.25
+    for kappa in (-1.0, 0.0, 1.0 / 3.0, 1.0):
+        assert oracle.muscl(0.0, 1.0, 4.0, 5.0, limiter="vanleer", kappa=kappa) == (1.75, 3.25)
+    for _ in range(100):
+        q = rng.normal(size=4)
+        base = oracle.muscl(*q, limiter="vanleer")
+        assert np.allclose(oracle.muscl(*q, limiter="vanleer", kappa=1.0 / 3.0), base, rtol=1e-15, atol=1e-15)
+
+
 def test_physical_flux_hand_values():
     # rho = 1, u = (2, 0), p = 1 -> E = 1/0.4 + 0.5*4 = 4.5
     Q = [1.0, 2.0, 0.0, 4.5]
