@@ -123,6 +123,61 @@ def test_fused_full_size_one_step():
     close(got, ref, what="2048^2 fused")
 
 
+def test_fused_largest_2d_grid_sampled_patches():
+    """The largest 2D grid the fused path takes (a state just below 4 GiB, so
+    the 32-bit buffer offsets and the dropped stores run at their limits):
+    one fused step against the oracle on sampled periodic patches (a cell
+    depends on cells at most 6 away), and the next size refused."""
+    import torch
+    fv = _fv()
+    n = 11576
+    g = inputs.grid2d(n, n)
+    xs = (np.arange(n) + 0.5) * (10.0 / n)
+    X = 2 * np.pi * xs[None, :] / 10.0
+    Y = 2 * np.pi * xs[:, None] / 10.0
+    rho = 1.0 + 0.2 * np.sin(X + 0.3) * np.cos(Y + 1.1)
+    u = np.broadcast_to(0.4 + 0.1 * np.sin(Y + 0.7), (n, n))
+    v = np.broadcast_to(-0.3 + 0.1 * np.cos(X + 2.0), (n, n))
+    p = 1.0 + 0.1 * np.cos(X - Y)
+    U0 = np.empty((4, 1, n, n))
+    U0[0, 0] = rho
+    U0[1, 0] = rho * u
+    U0[2, 0] = rho * v
+    U0[3, 0] = p / (g.gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    del rho, p
+    s = fv.Solver(g)
+    s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    s.set_state(U0)
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(1, dt_out=dts)
+    rc, flags = s.status()
+    got = s.get_state()
+    s.close()
+    dt = float(dts.cpu()[0])
+    dt_ref, _ = oracle.dt(g, U0)
+    assert flags == 0 and abs(dt - dt_ref) <= 1e-14 * dt_ref
+    rng = np.random.default_rng(12)
+    P, H = 30, 6
+    for i in range(6):
+        o = rng.integers(0, n, size=2)
+        if i < 2:
+            o[i] = n - P // 2   # straddle the periodic seam of axis i
+        ix = (o[0] + np.arange(P)) % n
+        iy = (o[1] + np.arange(P)) % n
+        patch = U0[:, :, iy][:, :, :, ix]
+        pg = inputs.grid2d(P, P, hi=(P * 10.0 / n, P * 10.0 / n), bc=((1, 1), (1, 1)))
+        ref = oracle.rk3_step(pg, patch, dt)[:, :, H:-H, H:-H]
+        gp = got[:, :, iy][:, :, :, ix][:, :, H:-H, H:-H]
+        for var in range(4):
+            scale = np.abs(ref[var]).max()
+            assert np.abs(gp[var] - ref[var]).max() <= 1e-12 * scale, (o, var)
+    big = inputs.grid2d(n + 8, n + 8)
+    s = fv.Solver(big)
+    with pytest.raises(fv.FvError):
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    s.close()
+
+
 def smooth_3d(g, seed=0):
     """A smooth periodic 3D state with all velocity components non-zero."""
     x, y, z = g.centres()
@@ -215,6 +270,60 @@ def test_fused3d_full_size_sampled_patches():
         assert np.abs(gp - ref).max() <= 1e-12 * scale, o
         checked += 1
     assert checked >= 3
+
+
+def test_fused3d_largest_grid_sampled_patches():
+    """The largest cubic 3D grid the fused path takes (a 5-variable state just
+    below 4 GiB): one fused step against the oracle on sampled periodic
+    patches, and the next size refused."""
+    import torch
+    fv = _fv()
+    n = 468
+    g = inputs.grid3d(n, n, n, bc=((0, 0), (0, 0), (0, 0)))
+    c = 2 * np.pi * (np.arange(n) + 0.5) / n
+    X, Y, Z = c[None, None, :], c[None, :, None], c[:, None, None]
+    rho = 1.0 + 0.2 * np.sin(X + 0.3) * np.cos(Y + 1.1) * np.sin(Z + 0.5)
+    vel = (0.3 + 0.1 * np.sin(Y + 0.7) + 0 * Z, -0.2 + 0.1 * np.cos(Z + 2.0) + 0 * X, 0.25 + 0.1 * np.sin(X) + 0 * Y)
+    p = 1.0 + 0.1 * np.cos(X + Y + Z)
+    U0 = np.empty((5, n, n, n))
+    U0[0] = rho
+    ke = np.zeros_like(rho)
+    for d in range(3):
+        U0[1 + d] = rho * vel[d]
+        ke += vel[d] * vel[d]
+    U0[4] = p / (g.gamma - 1.0) + 0.5 * rho * ke
+    del rho, ke, p
+    s = fv.Solver(g)
+    s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    s.set_state(U0)
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(1, dt_out=dts)
+    rc, flags = s.status()
+    got = s.get_state()
+    s.close()
+    dt = float(dts.cpu()[0])
+    dt_ref, _ = oracle.dt(g, U0)
+    assert flags == 0 and abs(dt - dt_ref) <= 1e-14 * dt_ref
+    rng = np.random.default_rng(13)
+    P, H = 20, 6
+    for i in range(5):
+        o = rng.integers(0, n, size=3)
+        if i < 3:
+            o[i] = n - P // 2   # straddle the periodic seam of axis i
+        idx = [(o[a] + np.arange(P)) % n for a in range(3)]
+        patch = U0[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
+        pg = inputs.grid3d(P, P, P, hi=(P / n,) * 3, bc=((1, 1), (1, 1), (1, 1)))
+        ref = oracle.rk3_step(pg, patch, dt)[:, H:-H, H:-H, H:-H]
+        gp = got[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]][:, H:-H, H:-H, H:-H]
+        for var in range(5):
+            scale = np.abs(ref[var]).max()
+            assert np.abs(gp[var] - ref[var]).max() <= 1e-12 * scale, (o, var)
+    del U0, got
+    big = inputs.grid3d(n + 4, n + 4, n + 4, bc=((0, 0), (0, 0), (0, 0)))
+    s = fv.Solver(big)
+    with pytest.raises(fv.FvError):
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    s.close()
 
 
 def small_batch(seed=3, count=7):
