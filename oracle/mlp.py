@@ -17,33 +17,55 @@ Conventions (the paper does not print them; scikit-learn's documented ones):
     the epoch loss has failed to improve on the best by tol for more than
     n_iter_no_change consecutive epochs;
   * ReLU'(0) = 0.
-Parameter layout: W1[64][14], b1, W2[64][64], b2, W3[64][64], b3, W4[1][64], b4.
+Parameter layout: W1[64][n_in], b1, W2[64][64], b2, W3[64][64], b3, W4[1][64], b4,
+with n_in = 14 for the paper's network (the launch features) and n_in = 16 for
+the problem-size-conditioned one (the launch features, then the log2 cell
+count and the dimension); n_in follows from the length of theta.
 """
 from __future__ import annotations
 
 import numpy as np
 
 IN = 14
+IN_SIZED = 16
 H = 64
-SHAPES = [("W1", (H, IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)),
-          ("W3", (H, H)), ("b3", (H,)), ("W4", (1, H)), ("b4", (1,))]
-NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def shapes(n_in=IN):
+    return [("W1", (H, n_in)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)),
+            ("W3", (H, H)), ("b3", (H,)), ("W4", (1, H)), ("b4", (1,))]
+
+
+def nparam(n_in=IN):
+    return sum(int(np.prod(s)) for _, s in shapes(n_in))
+
+
+SHAPES = shapes(IN)
+NPARAM = nparam(IN)
+
+
+def n_in_of(theta):
+    """Input width of the network whose flat parameters are theta."""
+    n_in, rem = divmod(len(theta) - nparam(0), H)
+    if rem or n_in < 1:
+        raise ValueError("not a parameter vector of this network")
+    return n_in
 
 
 def unpack(theta):
     out = {}
     o = 0
-    for name, shp in SHAPES:
+    for name, shp in shapes(n_in_of(theta)):
         k = int(np.prod(shp))
         out[name] = theta[o:o + k].reshape(shp)
         o += k
     return out
 
 
-def weight_mask():
+def weight_mask(n_in=IN):
     """1 for weights, 0 for biases, in the flat layout."""
     m = []
-    for name, shp in SHAPES:
+    for name, shp in shapes(n_in):
         m.append(np.full(int(np.prod(shp)), 1.0 if name.startswith("W") else 0.0))
     return np.concatenate(m)
 
@@ -74,7 +96,8 @@ def loss_grad(theta, X, y, alpha):
     p = unpack(theta)
     out, (X, z1, z2, z3) = forward(theta, X)
     d = out - y
-    mask = weight_mask()
+    n_in = n_in_of(theta)
+    mask = weight_mask(n_in)
     loss = 0.5 * np.sum(d * d) / B + 0.5 * alpha * np.sum(theta * theta * mask) / B
     dout = d / B
     g = {}
@@ -92,7 +115,7 @@ def loss_grad(theta, X, y, alpha):
     d1 = (d2 @ p["W2"]) * (z1 > 0.0)
     g["W1"] = d1.T @ X
     g["b1"] = d1.sum(axis=0)
-    grad = np.concatenate([g[name].ravel() for name, _ in SHAPES])
+    grad = np.concatenate([g[name].ravel() for name, _ in shapes(n_in)])
     grad = grad + alpha / B * theta * mask
     return loss, grad
 

@@ -268,12 +268,13 @@ def random_directions(shape, count, seed, scales):
 MLP_LAYERS = ((14, 64), (64, 64), (64, 64), (64, 1))
 
 
-def mlp_init(seed: int):
-    """Flat float64 parameters W1, b1, ..., W4, b4 (W[out][in]); every layer
-    uniform in +-sqrt(6 / (fan_in + fan_out)) (Glorot & Bengio 2010)."""
+def mlp_init(seed: int, n_in: int = 14):
+    """Flat float64 parameters W1, b1, ..., W4, b4 (W[out][in]) of the network
+    with n_in inputs; every layer uniform in +-sqrt(6 / (fan_in + fan_out))
+    (Glorot & Bengio 2010)."""
     rng = np.random.default_rng(seed)
     parts = []
-    for fi, fo in MLP_LAYERS:
+    for fi, fo in ((n_in, 64),) + MLP_LAYERS[1:]:
         b = math.sqrt(6.0 / (fi + fo))
         parts.append(rng.uniform(-b, b, size=(fo, fi)).ravel())
         parts.append(rng.uniform(-b, b, size=fo))

@@ -140,3 +140,58 @@ def test_training_reduces_loss():
     order = inputs.epoch_orders(200, 50, 2)
     _, losses, ne, _, _, _ = mlp.train(theta, X, y, order, batch=50, max_epochs=50)
     assert losses[-1] < 0.5 * losses[0]
+
+
+# ---------------------------------------------------------------------------
+# The problem-size-conditioned network: 16 inputs, the launch features then
+# two problem features.
+
+def test_sized_parameter_count():
+    assert mlp.nparam(16) == 9473 == inputs.mlp_init(0, 16).size
+    assert mlp.n_in_of(np.zeros(9473)) == 16 and mlp.n_in_of(np.zeros(9345)) == 14
+    with pytest.raises(ValueError):
+        mlp.n_in_of(np.zeros(9400))
+
+
+def test_sized_network_with_zero_extra_columns_is_the_launch_network():
+    # W1 rows are [launch features | problem features]: zeroing the two last
+    # columns of every row gives the 14-input network of the same weights for
+    # any problem features (a transposed or misplaced W1 block fails this)
+    rng = np.random.default_rng(4)
+    th14 = inputs.mlp_init(7)
+    th16 = inputs.mlp_init(8, 16)
+    W1 = th14[:896].reshape(64, 14)
+    th16[:1024] = np.hstack([W1, np.zeros((64, 2))]).ravel()
+    th16[1024:] = th14[896:]
+    X = rng.standard_normal((50, 14))
+    E = rng.standard_normal((50, 2)) * 3.0
+    assert np.array_equal(mlp.predict(th16, np.hstack([X, E])), mlp.predict(th14, X))
+    # the penalty sees the same weights, the gradient's extra columns are the
+    # inputs' correlation with the first-layer deltas
+    y = rng.standard_normal(50)
+    L14, g14 = mlp.loss_grad(th14, X, y, 0.2)
+    L16, g16 = mlp.loss_grad(th16, np.hstack([X, E]), y, 0.2)
+    assert abs(L14 - L16) <= 1e-14 * abs(L14)
+    G1 = g16[:1024].reshape(64, 16)
+    assert np.allclose(G1[:, :14].ravel(), g14[:896], rtol=1e-13, atol=1e-16)
+    assert np.allclose(g16[1024:], g14[896:], rtol=1e-13, atol=1e-16)
+    # with one problem feature set to zero its column's gradient is zero too
+    _, gz = mlp.loss_grad(th16, np.hstack([X, np.zeros((50, 1)), E[:, 1:]]), y, 0.0)
+    assert np.all(gz[:1024].reshape(64, 16)[:, 14] == 0.0)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.3])
+def test_sized_gradient_matches_central_differences(alpha):
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((29, 16))
+    y = np.cos(X[:, 14]) + 0.2 * X[:, 15] * X[:, 2] + 0.1 * rng.standard_normal(29)
+    theta = inputs.mlp_init(9, 16)
+    L, g = mlp.loss_grad(theta, X, y, alpha)
+    h = 1e-6
+    cols = np.arange(64) * 16
+    idx = np.concatenate([rng.choice(9473, 40, replace=False), cols[:8] + 14, cols[8:16] + 15, [1023, 1024, 9472]])
+    for k in idx:
+        e = np.zeros(9473)
+        e[k] = h
+        fd = (mlp.loss_grad(theta + e, X, y, alpha)[0] - mlp.loss_grad(theta - e, X, y, alpha)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-7 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
