@@ -283,10 +283,17 @@ int fv_batch_destroy(fv_batch* b);
  * (Sec. "Hyperparameters", Table para-setting; Sec. "Feature Centering and
  * Scaling"), trained and evaluated by FP32 kernels.
  *
- * Network: FV_MLP_IN -> 64 -> 64 -> 64 -> 1, ReLU hidden layers, identity
- * output. Parameters are one flat FP32 array of FV_MLP_NPARAM floats:
- *   W1[64][14], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[1][64], b4[1]
- * (W[out][in]). Loss of a minibatch of B rows:
+ * Network: n_in -> 64 -> 64 -> 64 -> 1, ReLU hidden layers, identity
+ * output, where n_in is FV_MLP_IN (the paper's network: the 14 launch
+ * features) or FV_MLP_IN_SIZED (a problem-size-conditioned network, the
+ * extension proposed in Sec. "Broader Impact": the 14 launch features followed
+ * by FV_MLP_MAX_EXTRA problem features, here the standardised log2 of the
+ * grid's cell count and its dimension, so that one network serves grids of
+ * several sizes). Parameters are one flat FP32 array of
+ * FV_MLP_NPARAM_FOR(n_in) floats:
+ *   W1[64][n_in], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[1][64], b4[1]
+ * (W[out][in]); an n_in other than the two widths is FV_EINVAL. Rows of X
+ * hold n_in features. Loss of a minibatch of B rows:
  *   L = sum_r (yhat_r - y_r)^2 / (2B) + alpha / (2B) * sum of squared weights
  * (biases not penalised). Adam (Kingma & Ba, efficient form):
  *   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
@@ -295,8 +302,12 @@ int fv_batch_destroy(fv_batch* b);
  * on `stream` and returns without waiting.
  * ------------------------------------------------------------------------ */
 #define FV_MLP_IN 14
+#define FV_MLP_MAX_EXTRA 2
+#define FV_MLP_IN_SIZED 16
 #define FV_MLP_HID 64
+#define FV_MLP_NPARAM_FOR(n_in) (64 * (n_in) + 8449)
 #define FV_MLP_NPARAM 9345
+#define FV_MLP_NPARAM_SIZED 9473
 
 typedef struct fv_mlp_hparams {
     float lr;              /* learning rate (constant) */
@@ -313,17 +324,17 @@ typedef struct fv_mlp_hparams {
 /* Bytes of device scratch the MLP calls need for n rows (at most 65536). */
 int fv_mlp_workspace(int32_t n, size_t* bytes);
 
-/* Loss L and its gradient (FV_MLP_NPARAM floats) over all n rows of X
- * ([n][FV_MLP_IN], row-major) and y ([n]) at `params`, with penalty alpha.
+/* Loss L and its gradient (FV_MLP_NPARAM_FOR(n_in) floats) over all n rows
+ * of X ([n][n_in], row-major) and y ([n]) at `params`, with penalty alpha.
  * loss is one device float. */
-int fv_mlp_loss_grad(const float* params, const float* X, const float* y, int32_t n, float alpha,
+int fv_mlp_loss_grad(const float* params, int32_t n_in, const float* X, const float* y, int32_t n, float alpha,
                      float* grad, float* loss, void* workspace, size_t ws_bytes, void* stream);
 
-/* Predictions out[n] for the rows of X. */
-int fv_mlp_predict(const float* params, const float* X, int32_t n, float* out, void* stream);
+/* Predictions out[n] for the rows of X ([n][n_in]). */
+int fv_mlp_predict(const float* params, int32_t n_in, const float* X, int32_t n, float* out, void* stream);
 
-/* Trains params in place with Adam from the moments adam_m / adam_v
- * (FV_MLP_NPARAM floats each, zero for a fresh start) and step counter
+/* Trains params (n_in inputs) in place with Adam from the moments adam_m /
+ * adam_v (FV_MLP_NPARAM_FOR(n_in) floats each, zero for a fresh start) and step counter
  * *adam_t (device int32, 0 for a fresh start). Epoch e visits the rows in
  * the order order[e * n .. e * n + n - 1] (a permutation of 0..n-1 per epoch,
  * drawn by the caller), in minibatches of hp->batch rows. epoch_loss[e]
@@ -331,14 +342,17 @@ int fv_mlp_predict(const float* params, const float* X, int32_t n, float* out, v
  * the number of epochs done. Training stops early once the epoch loss has
  * failed to improve on the best so far by hp->tol for more than
  * hp->n_iter_no_change consecutive epochs. One workgroup does all the work. */
-int fv_mlp_train(float* params, float* adam_m, float* adam_v, int32_t* adam_t, const float* X, const float* y,
-                 int32_t n, const int32_t* order, const fv_mlp_hparams* hp, float* epoch_loss,
+int fv_mlp_train(float* params, int32_t n_in, float* adam_m, float* adam_v, int32_t* adam_t, const float* X,
+                 const float* y, int32_t n, const int32_t* order, const fv_mlp_hparams* hp, float* epoch_loss,
                  int32_t* epochs_run, void* workspace, size_t ws_bytes, void* stream);
 
 /* Search space of launch vectors: site s has radix[s] choices (1 = pinned);
  * choice c gives parameters (p1[s][c], p2[s][c]) and the network features
  * (f1[s][c], f2[s][c]), already standardised. Index decoding is mixed radix
- * with site 0 fastest: c_s = (idx / prod_{t<s} radix[t]) % radix[s]. */
+ * with site 0 fastest: c_s = (idx / prod_{t<s} radix[t]) % radix[s].
+ * n_extra is 0 (the network has FV_MLP_IN inputs) or FV_MLP_MAX_EXTRA (it has
+ * FV_MLP_IN_SIZED inputs, the last n_extra of which are extra[0..n_extra-1],
+ * standardised, the same for every index: the problem being tuned). */
 #define FV_SPACE_MAXC 32
 typedef struct fv_tune_space {
     int32_t radix[FV_NSITES];
@@ -346,10 +360,12 @@ typedef struct fv_tune_space {
     int32_t p2[FV_NSITES][FV_SPACE_MAXC];
     float f1[FV_NSITES][FV_SPACE_MAXC];
     float f2[FV_NSITES][FV_SPACE_MAXC];
+    int32_t n_extra;
+    float extra[FV_MLP_MAX_EXTRA];
 } fv_tune_space;
 
 /* Predicts every index in [begin, begin + count) of the space (host
- * pointer) and returns the k (1..8) lowest predictions, ascending, ties to
+ * pointer) with the network of 2 * FV_NSITES + space->n_extra inputs and returns the k (1..8) lowest predictions, ascending, ties to
  * the lower index: top_idx[k] (device int64) and top_val[k] (device float). */
 int fv_mlp_sweep(const float* params, const fv_tune_space* space, int64_t begin, int64_t count, int32_t k,
                  int64_t* top_idx, float* top_val, void* workspace, size_t ws_bytes, void* stream);

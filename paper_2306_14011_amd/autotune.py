@@ -15,7 +15,9 @@ The network is trained and evaluated by the library's FP32 kernels
 (fv_mlp_train / fv_mlp_predict / fv_mlp_sweep). This module is host-side
 orchestration only. Autotuner tunes the 14 launch parameters of the split
 step; BatchAutotuner applies the same loop to the schedule of a batch of
-grids (segment height per grid-size bucket and work-list order).
+grids (segment height per grid-size bucket and work-list order);
+SizedAutotuner trains one problem-size-conditioned network on the samples of
+several grids and tunes each of them, and grids it was not trained on.
 
 A sample is valid when its launch produced a state bitwise equal to the
 default launch's (every launch of the split step computes identical
@@ -33,7 +35,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import fv, inputs
-from .tune_space import LaunchSpace
+from .tune_space import LaunchSpace, problem_features
 
 # Table para-setting of the paper.
 PAPER_HPARAMS = dict(lr=9e-4, beta1=0.95, beta2=0.90, eps=1e-9, alpha=1e-4, tol=1e-6, batch=200,
@@ -66,13 +68,16 @@ def split_indices(n: int, seed: int, train_frac=0.75):
 
 
 class Network:
-    """FP32 network parameters and Adam state in device memory."""
+    """FP32 network parameters and Adam state in device memory; n_in is
+    fv.FV_MLP_IN (launch features) or fv.FV_MLP_IN_SIZED (launch features and
+    the two problem-size features)."""
 
-    def __init__(self, seed: int, device="cuda"):
+    def __init__(self, seed: int, device="cuda", n_in: int = fv.FV_MLP_IN):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.params = torch.as_tensor(inputs.mlp_init(seed), dtype=torch.float32).to(self.device)
+        self.n_in = int(n_in)
+        self.params = torch.as_tensor(inputs.mlp_init(seed, self.n_in), dtype=torch.float32).to(self.device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.t = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -81,12 +86,20 @@ class Network:
     def _stream(self):
         return self.torch.cuda.current_stream(self.device).cuda_stream
 
+    def _check_rows(self, X, y=None):
+        # the kernels read n_in floats per row of X and one per entry of y
+        if X.dim() != 2 or X.shape[1] != self.n_in:
+            raise ValueError(f"X must have shape (n, {self.n_in}), got {tuple(X.shape)}")
+        if y is not None and (y.dim() != 1 or y.shape[0] != X.shape[0]):
+            raise ValueError(f"y must have shape ({X.shape[0]},), got {tuple(y.shape)}")
+
     def train(self, X, y, order=None, **hp):
         torch = self.torch
         h = dict(PAPER_HPARAMS)
         h.update(hp)
         X = torch.as_tensor(np.ascontiguousarray(X), dtype=torch.float32).to(self.device)
         y = torch.as_tensor(np.ascontiguousarray(y), dtype=torch.float32).to(self.device)
+        self._check_rows(X, y)
         n = X.shape[0]
         if order is None:
             order = inputs.epoch_orders(n, h["max_epochs"], self.seed)
@@ -97,7 +110,7 @@ class Network:
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         losses = torch.zeros(max(h["max_epochs"], 1), dtype=torch.float32, device=self.device)
         ne = torch.zeros(1, dtype=torch.int32, device=self.device)
-        fv.fv_mlp_train(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), self.t.data_ptr(),
+        fv.fv_mlp_train(self.params.data_ptr(), self.n_in, self.m.data_ptr(), self.v.data_ptr(), self.t.data_ptr(),
                         X.data_ptr(), y.data_ptr(), n, order_t.data_ptr(), hpc, losses.data_ptr(), ne.data_ptr(),
                         ws.data_ptr(), ws_bytes, self._stream())
         nrun = int(ne.item())
@@ -107,25 +120,29 @@ class Network:
         torch = self.torch
         X = torch.as_tensor(np.ascontiguousarray(X), dtype=torch.float32).to(self.device)
         y = torch.as_tensor(np.ascontiguousarray(y), dtype=torch.float32).to(self.device)
+        self._check_rows(X, y)
         n = X.shape[0]
         ws_bytes = fv.fv_mlp_workspace(n)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         g = torch.zeros_like(self.params)
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)
-        fv.fv_mlp_loss_grad(self.params.data_ptr(), X.data_ptr(), y.data_ptr(), n, alpha, g.data_ptr(),
+        fv.fv_mlp_loss_grad(self.params.data_ptr(), self.n_in, X.data_ptr(), y.data_ptr(), n, alpha, g.data_ptr(),
                             loss.data_ptr(), ws.data_ptr(), ws_bytes, self._stream())
         return float(loss.item()), g.cpu().numpy()
 
     def predict(self, X):
         torch = self.torch
         X = torch.as_tensor(np.ascontiguousarray(X), dtype=torch.float32).to(self.device)
+        self._check_rows(X)
         n = X.shape[0]
         out = torch.zeros(n, dtype=torch.float32, device=self.device)
-        fv.fv_mlp_predict(self.params.data_ptr(), X.data_ptr(), n, out.data_ptr(), self._stream())
+        fv.fv_mlp_predict(self.params.data_ptr(), self.n_in, X.data_ptr(), n, out.data_ptr(), self._stream())
         return out.cpu().numpy()
 
     def sweep(self, space_struct, begin, count, k):
         torch = self.torch
+        if 2 * fv.NSITES + space_struct.n_extra != self.n_in:
+            raise ValueError(f"the space has {space_struct.n_extra} extra features, the network {self.n_in} inputs")
         ws_bytes = fv.fv_mlp_sweep_workspace()
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         ti = torch.zeros(k, dtype=torch.int64, device=self.device)
@@ -407,3 +424,97 @@ class BatchAutotuner:
 
     def close(self):
         self.batch.close()
+
+
+class SizedAutotuner:
+    """One network for several problem sizes, the extension proposed in the
+    paper's Sec. "Broader Impact" (and the single-GPU analog of Sec. "Combined
+    Training", where a hardware figure joins the launch features): the
+    network has fv.FV_MLP_IN_SIZED inputs, the 14 launch features followed by
+    the grid's problem features (tune_space.problem_features: log2 of the
+    cell count, dimension). Samples of every grid not in `holdout` are pooled
+    into one training set (75 / 25 split over the pool); the target is the
+    standardised log of the runtime, so that a launch's relative effect is
+    comparable across grids whose runtimes differ many times over. Every grid,
+    held out or not, is then swept with its own problem features, its k best
+    predictions are measured and the fastest valid one is kept."""
+
+    def __init__(self, grids, states, seed=0, holdout=(), **tuner_kw):
+        self.grids = list(grids)
+        self.holdout = set(int(h) for h in holdout)
+        self.seed = seed
+        self.extra = [problem_features(g) for g in self.grids]
+        self.tuners = [Autotuner(g, U, seed=seed + 1000 * i, **tuner_kw)
+                       for i, (g, U) in enumerate(zip(self.grids, states))]
+
+    def fit(self, samples):
+        """samples[g]: the samples of grid g (None for a held-out grid)."""
+        rows, extra, t, gid = [], [], [], []
+        for g, smp in enumerate(samples):
+            if smp is None:
+                continue
+            good = [s for s in smp if s.valid and np.isfinite(s.ms) and s.ms > 0.0]
+            rows.append(self.tuners[g].space.features([s.index for s in good]))
+            extra += [self.extra[g]] * len(good)
+            t += [s.ms for s in good]
+            gid += [g] * len(good)
+        F = np.hstack([np.vstack(rows), np.asarray(extra, dtype=np.float64)])
+        t = np.asarray(t, dtype=np.float64)
+        gid = np.asarray(gid)
+        tr, te = split_indices(len(t), self.seed)
+        z = np.log(t)
+        z_mean, z_std = target_scaler(z[tr])
+        y = (z - z_mean) / z_std
+        mean = F[tr].mean(axis=0)
+        std = F[tr].std(axis=0)
+        std = np.where(std == 0.0, 1.0, std)
+        X = (F - mean) / std
+        net = Network(self.seed, n_in=fv.FV_MLP_IN_SIZED)
+        losses = net.train(X[tr], y[tr])
+        pred = net.predict(X)
+        per_grid = {}
+        for g in sorted(set(gid.tolist())):
+            m = te[gid[te] == g]
+            per_grid[g] = r2_score(y[m], pred[m]) if len(m) >= 3 else None
+        return dict(net=net, mean=mean, std=std, z_mean=z_mean, z_std=z_std, losses=losses,
+                    r2_test=r2_score(y[te], pred[te]), r2_train=r2_score(y[tr], pred[tr]),
+                    r2_test_per_grid=per_grid, n_train=len(tr), n_test=len(te))
+
+    def sweep(self, model, g, k=8):
+        import torch
+        at = self.tuners[g]
+        sp = at.space.struct(model["mean"], model["std"], self.extra[g])
+        t0 = time.perf_counter()
+        idx, val = model["net"].sweep(sp, 0, at.space.size, k)
+        torch.cuda.synchronize()
+        return idx, val, time.perf_counter() - t0
+
+    def run(self, count=300, k=8, rounds=5):
+        t0 = time.perf_counter()
+        samples = [None if g in self.holdout else at.collect(count) for g, at in enumerate(self.tuners)]
+        t_collect = time.perf_counter() - t0
+        model = self.fit(samples)
+        out = []
+        for g, at in enumerate(self.tuners):
+            top_idx, top_val, t_sweep = self.sweep(model, g, k)
+            cands = [at.space.decode(i) for i in top_idx]
+            cand_ms = [at.measure(l) for l in cands]
+            ok = [(ms, i) for i, (ms, v) in enumerate(cand_ms) if v]
+            best = cands[min(ok)[1]] if ok else at.default
+            final = at.interleaved([at.default, best], rounds=rounds)
+            spec = self.grids[g]
+            out.append(dict(
+                n=[int(v) for v in spec.n[:spec.ndim]], ndim=spec.ndim, held_out=g in self.holdout,
+                n_samples=0 if samples[g] is None else len(samples[g]),
+                n_valid=0 if samples[g] is None else sum(1 for s in samples[g] if s.valid),
+                default_launch=at.default, tuned_launch=best, default_ms=final[0], tuned_ms=final[1],
+                factor_vs_default=final[0] / final[1], n_valid_candidates=len(ok),
+                top_pred_ms=[float(math.exp(v * model["z_std"] + model["z_mean"])) for v in top_val],
+                top_measured_ms=[m for m, _ in cand_ms], r2_test=model["r2_test_per_grid"].get(g),
+                sweep_seconds=t_sweep, space_size=at.space.size, steps_per_sample=at.steps))
+        return dict(grids=out, r2_test=model["r2_test"], r2_train=model["r2_train"], n_train=model["n_train"],
+                    n_test=model["n_test"], epochs=len(model["losses"]), collect_seconds=t_collect)
+
+    def close(self):
+        for at in self.tuners:
+            at.close()

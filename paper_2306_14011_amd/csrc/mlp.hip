@@ -3,8 +3,10 @@
 // loss/gradient, prediction, and the exhaustive sweep of the launch space
 // with a top-k selection of the lowest predicted runtimes.
 //
-// Network 14 -> 64 -> 64 -> 64 -> 1 with ReLU hidden layers; parameters are
-// one flat array W1[64][14], b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4.
+// Network IN -> 64 -> 64 -> 64 -> 1 with ReLU hidden layers; parameters are
+// one flat array W1[64][IN], b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4.
+// IN is 14 (the launch features) or 16 (the launch features followed by two
+// problem-size features); every kernel is instantiated for both widths.
 #include <float.h>
 #include <math.h>
 #include <stdint.h>
@@ -16,18 +18,25 @@
 
 namespace mlp {
 
-constexpr int IN = FV_MLP_IN;
 constexpr int H = FV_MLP_HID;
-constexpr int oW1 = 0;
-constexpr int oB1 = oW1 + H * IN;
-constexpr int oW2 = oB1 + H;
-constexpr int oB2 = oW2 + H * H;
-constexpr int oW3 = oB2 + H;
-constexpr int oB3 = oW3 + H * H;
-constexpr int oW4 = oB3 + H;
-constexpr int oB4 = oW4 + H;
-constexpr int NP = oB4 + 1;
-static_assert(NP == FV_MLP_NPARAM, "parameter count");
+
+// Offsets of the flat parameter array of the network with IN inputs.
+template <int IN>
+struct Lay {
+    static constexpr int oW1 = 0;
+    static constexpr int oB1 = oW1 + H * IN;
+    static constexpr int oW2 = oB1 + H;
+    static constexpr int oB2 = oW2 + H * H;
+    static constexpr int oW3 = oB2 + H;
+    static constexpr int oB3 = oW3 + H * H;
+    static constexpr int oW4 = oB3 + H;
+    static constexpr int oB4 = oW4 + H;
+    static constexpr int NP = oB4 + 1;
+};
+static_assert(Lay<FV_MLP_IN>::NP == FV_MLP_NPARAM, "parameter count");
+static_assert(Lay<FV_MLP_IN_SIZED>::NP == FV_MLP_NPARAM_SIZED, "parameter count");
+static_assert(FV_MLP_IN_SIZED == FV_MLP_IN + FV_MLP_MAX_EXTRA, "input widths");
+constexpr int NP_MAX = Lay<FV_MLP_IN_SIZED>::NP;
 constexpr int MAXN = 65536;
 constexpr int TB = 1024;  // threads of the single-workgroup kernels
 
@@ -40,10 +49,10 @@ struct Scratch {
     float* Db;
     float* out;   // [n]
     float* dout;  // [n]
-    float* grad;  // [NP]
+    float* grad;  // [NP_MAX]
 };
 
-inline size_t scratch_bytes(int n) { return ((size_t)5 * n * H + 2 * (size_t)n + NP) * sizeof(float) + 256; }
+inline size_t scratch_bytes(int n) { return ((size_t)5 * n * H + 2 * (size_t)n + NP_MAX) * sizeof(float) + 256; }
 
 inline Scratch carve(void* ws, int n) {
     float* p = (float*)ws;
@@ -88,7 +97,7 @@ __device__ __forceinline__ int row_of(const int32_t* rows, int r) { return rows 
 
 // Dense layer over a minibatch: Z[r][o] = b[o] + sum_i W[o][i] act(A[r][i]).
 // act is identity for the input layer (A = X rows) and ReLU otherwise.
-template <int NIN, bool INPUT>
+template <int IN, int NIN, bool INPUT>
 __device__ void layer_fwd(const float* __restrict__ P, int oW, int oB, const float* A, const float* __restrict__ X,
                           const int32_t* rows, int sz, float* Z) {
     for (int e = threadIdx.x; e < sz * H; e += blockDim.x) {
@@ -106,14 +115,18 @@ __device__ void layer_fwd(const float* __restrict__ P, int oW, int oB, const flo
 }
 
 // Forward + loss + backward over sz rows; gradient into s.grad, returns the loss.
+template <int IN>
 __device__ float forward_backward(const float* __restrict__ P, const float* __restrict__ X,
                                   const float* __restrict__ Y, const int32_t* rows, int sz, float alpha,
                                   const Scratch& s, float* sm) {
-    layer_fwd<IN, true>(P, oW1, oB1, nullptr, X, rows, sz, s.Z1);
+    using L = Lay<IN>;
+    constexpr int oW1 = L::oW1, oB1 = L::oB1, oW2 = L::oW2, oB2 = L::oB2, oW3 = L::oW3, oB3 = L::oB3,
+                  oW4 = L::oW4, oB4 = L::oB4, NP = L::NP;
+    layer_fwd<IN, IN, true>(P, oW1, oB1, nullptr, X, rows, sz, s.Z1);
     __syncthreads();
-    layer_fwd<H, false>(P, oW2, oB2, s.Z1, X, rows, sz, s.Z2);
+    layer_fwd<IN, H, false>(P, oW2, oB2, s.Z1, X, rows, sz, s.Z2);
     __syncthreads();
-    layer_fwd<H, false>(P, oW3, oB3, s.Z2, X, rows, sz, s.Z3);
+    layer_fwd<IN, H, false>(P, oW3, oB3, s.Z2, X, rows, sz, s.Z3);
     __syncthreads();
     float sq = 0.f;
     const float inv = 1.0f / (float)sz;
@@ -202,15 +215,17 @@ __device__ float forward_backward(const float* __restrict__ P, const float* __re
     return loss;
 }
 
+template <int IN>
 __global__ void __launch_bounds__(TB) k_loss_grad(const float* __restrict__ P, const float* __restrict__ X,
                                                   const float* __restrict__ Y, int n, float alpha, float* grad,
                                                   float* loss, Scratch s) {
     __shared__ float sm[TB / 64];
-    const float l = forward_backward(P, X, Y, nullptr, n, alpha, s, sm);
-    for (int p = threadIdx.x; p < NP; p += blockDim.x) grad[p] = s.grad[p];
+    const float l = forward_backward<IN>(P, X, Y, nullptr, n, alpha, s, sm);
+    for (int p = threadIdx.x; p < Lay<IN>::NP; p += blockDim.x) grad[p] = s.grad[p];
     if (threadIdx.x == 0) *loss = l;
 }
 
+template <int IN>
 __global__ void __launch_bounds__(TB) k_train(float* P, float* M, float* V, int32_t* tptr, const float* __restrict__ X,
                                               const float* __restrict__ Y, int n, const int32_t* __restrict__ order,
                                               fv_mlp_hparams hp, float* epoch_loss, int32_t* epochs_run, Scratch s) {
@@ -223,14 +238,14 @@ __global__ void __launch_bounds__(TB) k_train(float* P, float* M, float* V, int3
         float acc = 0.f;
         for (int start = 0; start < n; start += hp.batch) {
             const int sz = min(hp.batch, n - start);
-            const float lb = forward_backward(P, X, Y, order + (size_t)e * n + start, sz, hp.alpha, s, sm);
+            const float lb = forward_backward<IN>(P, X, Y, order + (size_t)e * n + start, sz, hp.alpha, s, sm);
             acc += lb * (float)sz;
             ++t;
             // bias-corrected step size, scalar, in double
             const double c2 = 1.0 - pow((double)hp.beta2, (double)t);
             const double c1 = 1.0 - pow((double)hp.beta1, (double)t);
             const float lrt = (float)((double)hp.lr * sqrt(c2) / c1);
-            for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+            for (int p = threadIdx.x; p < Lay<IN>::NP; p += blockDim.x) {
                 const float g = s.grad[p];
                 const float m = hp.beta1 * M[p] + (1.f - hp.beta1) * g;
                 const float v = hp.beta2 * V[p] + (1.f - hp.beta2) * g * g;
@@ -257,7 +272,11 @@ __global__ void __launch_bounds__(TB) k_train(float* P, float* M, float* V, int3
 }
 
 // Forward pass of one row, weights read uniformly across the wave.
+template <int IN>
 __device__ __forceinline__ float forward_row(const float* __restrict__ P, const float* x) {
+    using L = Lay<IN>;
+    constexpr int oW1 = L::oW1, oB1 = L::oB1, oW2 = L::oW2, oB2 = L::oB2, oW3 = L::oW3, oB3 = L::oB3,
+                  oW4 = L::oW4, oB4 = L::oB4;
     float h1[H], h2[H];
 #pragma unroll
     for (int o = 0; o < H; ++o) {
@@ -284,6 +303,7 @@ __device__ __forceinline__ float forward_row(const float* __restrict__ P, const 
     return out;
 }
 
+template <int IN>
 __global__ void __launch_bounds__(256) k_predict(const float* __restrict__ P, const float* __restrict__ X, int n,
                                                  float* __restrict__ out) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,7 +311,7 @@ __global__ void __launch_bounds__(256) k_predict(const float* __restrict__ P, co
     float x[IN];
 #pragma unroll
     for (int i = 0; i < IN; ++i) x[i] = X[(size_t)r * IN + i];
-    out[r] = forward_row(P, x);
+    out[r] = forward_row<IN>(P, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,6 +325,7 @@ struct SweepTab {
     int32_t radix[FV_NSITES];
     float f1[FV_NSITES][FV_SPACE_MAXC];
     float f2[FV_NSITES][FV_SPACE_MAXC];
+    float extra[FV_MLP_MAX_EXTRA];
 };
 
 // (v, i) orders before (w, j): lower value, ties to the lower index; NaN last.
@@ -395,6 +416,7 @@ __device__ void select_topk(float* vals, long long* idxs, int cnt, int k, float*
     }
 }
 
+template <int IN>
 __global__ void __launch_bounds__(SWEEP_T) k_sweep(const float* __restrict__ P, SweepTab tab, long long begin,
                                                     long long count, int k, float* __restrict__ pv,
                                                     long long* __restrict__ pi) {
@@ -418,11 +440,13 @@ __global__ void __launch_bounds__(SWEEP_T) k_sweep(const float* __restrict__ P, 
             x[2 * site] = tab.f1[site][c];
             x[2 * site + 1] = tab.f2[site][c];
         }
+#pragma unroll
+        for (int j = 2 * FV_NSITES; j < IN; ++j) x[j] = tab.extra[j - 2 * FV_NSITES];
         // an opaque copy of the (uniform) weight pointer per iteration keeps the
         // ~9k scalar weight loads inside the loop instead of hoisted out of it
         const float* Pl = P;
         asm volatile("" : "+s"(Pl));
-        top.insert(forward_row(Pl, x), idx);
+        top.insert(forward_row<IN>(Pl, x), idx);
     }
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
@@ -475,30 +499,42 @@ int fv_mlp_workspace(int32_t n, size_t* bytes) {
     return FV_OK;
 }
 
-int fv_mlp_loss_grad(const float* params, const float* X, const float* y, int32_t n, float alpha, float* grad,
-                     float* loss, void* workspace, size_t ws_bytes, void* stream) {
+int fv_mlp_loss_grad(const float* params, int32_t n_in, const float* X, const float* y, int32_t n, float alpha,
+                     float* grad, float* loss, void* workspace, size_t ws_bytes, void* stream) {
     if (!params || !X || !y || !grad || !loss || !workspace) return FV_EINVAL;
+    if (n_in != FV_MLP_IN && n_in != FV_MLP_IN_SIZED) return FV_EINVAL;
     if (n < 1 || n > mlp::MAXN || !(alpha >= 0.f)) return FV_EINVAL;
     if (ws_bytes < mlp::scratch_bytes(n)) return FV_EWORKSPACE;
     mlp::Scratch s = mlp::carve(workspace, n);
-    hipLaunchKernelGGL(mlp::k_loss_grad, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params, X, y, n, alpha, grad,
-                       loss, s);
+    if (n_in == FV_MLP_IN)
+        hipLaunchKernelGGL(mlp::k_loss_grad<FV_MLP_IN>, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params, X, y,
+                           n, alpha, grad, loss, s);
+    else
+        hipLaunchKernelGGL(mlp::k_loss_grad<FV_MLP_IN_SIZED>, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params,
+                           X, y, n, alpha, grad, loss, s);
     return mlp_check_launch();
 }
 
-int fv_mlp_predict(const float* params, const float* X, int32_t n, float* out, void* stream) {
+int fv_mlp_predict(const float* params, int32_t n_in, const float* X, int32_t n, float* out, void* stream) {
     if (!params || !X || !out || n < 0) return FV_EINVAL;
+    if (n_in != FV_MLP_IN && n_in != FV_MLP_IN_SIZED) return FV_EINVAL;
     if (n == 0) return FV_OK;
-    hipLaunchKernelGGL(mlp::k_predict, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, X, n, out);
+    if (n_in == FV_MLP_IN)
+        hipLaunchKernelGGL(mlp::k_predict<FV_MLP_IN>, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                           params, X, n, out);
+    else
+        hipLaunchKernelGGL(mlp::k_predict<FV_MLP_IN_SIZED>, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                           params, X, n, out);
     return mlp_check_launch();
 }
 
-int fv_mlp_train(float* params, float* adam_m, float* adam_v, int32_t* adam_t, const float* X, const float* y,
-                 int32_t n, const int32_t* order, const fv_mlp_hparams* hp, float* epoch_loss, int32_t* epochs_run,
-                 void* workspace, size_t ws_bytes, void* stream) {
+int fv_mlp_train(float* params, int32_t n_in, float* adam_m, float* adam_v, int32_t* adam_t, const float* X,
+                 const float* y, int32_t n, const int32_t* order, const fv_mlp_hparams* hp, float* epoch_loss,
+                 int32_t* epochs_run, void* workspace, size_t ws_bytes, void* stream) {
     if (!params || !adam_m || !adam_v || !adam_t || !X || !y || !order || !hp || !epoch_loss || !epochs_run ||
         !workspace)
         return FV_EINVAL;
+    if (n_in != FV_MLP_IN && n_in != FV_MLP_IN_SIZED) return FV_EINVAL;
     if (n < 1 || n > mlp::MAXN || hp->batch < 1 || hp->max_epochs < 0 || hp->n_iter_no_change < 0) return FV_EINVAL;
     if (!(hp->lr > 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
         !(hp->eps > 0.f) || !(hp->alpha >= 0.f))
@@ -506,8 +542,12 @@ int fv_mlp_train(float* params, float* adam_m, float* adam_v, int32_t* adam_t, c
     const int bmax = hp->batch < n ? hp->batch : n;
     if (ws_bytes < mlp::scratch_bytes(bmax)) return FV_EWORKSPACE;
     mlp::Scratch s = mlp::carve(workspace, bmax);
-    hipLaunchKernelGGL(mlp::k_train, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params, adam_m, adam_v, adam_t, X,
-                       y, n, order, *hp, epoch_loss, epochs_run, s);
+    if (n_in == FV_MLP_IN)
+        hipLaunchKernelGGL(mlp::k_train<FV_MLP_IN>, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params, adam_m,
+                           adam_v, adam_t, X, y, n, order, *hp, epoch_loss, epochs_run, s);
+    else
+        hipLaunchKernelGGL(mlp::k_train<FV_MLP_IN_SIZED>, dim3(1), dim3(mlp::TB), 0, (hipStream_t)stream, params,
+                           adam_m, adam_v, adam_t, X, y, n, order, *hp, epoch_loss, epochs_run, s);
     return mlp_check_launch();
 }
 
@@ -521,6 +561,7 @@ int fv_mlp_sweep(const float* params, const fv_tune_space* space, int64_t begin,
                  int64_t* top_idx, float* top_val, void* workspace, size_t ws_bytes, void* stream) {
     if (!params || !space || !top_idx || !top_val || !workspace) return FV_EINVAL;
     if (k < 1 || k > mlp::KMAX || begin < 0 || count < 1) return FV_EINVAL;
+    if (space->n_extra != 0 && space->n_extra != FV_MLP_MAX_EXTRA) return FV_EINVAL;
     size_t need = 0;
     fv_mlp_sweep_workspace(&need);
     if (ws_bytes < need) return FV_EWORKSPACE;
@@ -536,14 +577,19 @@ int fv_mlp_sweep(const float* params, const fv_tune_space* space, int64_t begin,
             tab.f2[s][c] = c < r ? space->f2[s][c] : 0.f;
         }
     }
+    for (int j = 0; j < FV_MLP_MAX_EXTRA; ++j) tab.extra[j] = j < space->n_extra ? space->extra[j] : 0.f;
     if (begin + count > total) return FV_EINVAL;
     long long blocks = (count + mlp::SWEEP_T - 1) / mlp::SWEEP_T;
     if (blocks > mlp::SWEEP_MAXB) blocks = mlp::SWEEP_MAXB;
     float* pv = (float*)workspace;
     long long* pi = (long long*)((char*)workspace + (((size_t)mlp::SWEEP_MAXB * mlp::KMAX * sizeof(float) + 255) & ~(size_t)255));
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(mlp::k_sweep, dim3((unsigned)blocks), dim3(mlp::SWEEP_T), 0, st, params, tab,
-                       (long long)begin, (long long)count, k, pv, pi);
+    if (space->n_extra == 0)
+        hipLaunchKernelGGL(mlp::k_sweep<FV_MLP_IN>, dim3((unsigned)blocks), dim3(mlp::SWEEP_T), 0, st, params, tab,
+                           (long long)begin, (long long)count, k, pv, pi);
+    else
+        hipLaunchKernelGGL(mlp::k_sweep<FV_MLP_IN_SIZED>, dim3((unsigned)blocks), dim3(mlp::SWEEP_T), 0, st, params,
+                           tab, (long long)begin, (long long)count, k, pv, pi);
     hipLaunchKernelGGL(mlp::k_sweep_final, dim3(1), dim3(1024), 0, st, pv, pi, (int)(blocks * mlp::KMAX), k, top_val,
                        (long long*)top_idx);
     return mlp_check_launch();

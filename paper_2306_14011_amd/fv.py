@@ -88,8 +88,15 @@ class fv_launch(ctypes.Structure):
 
 
 FV_MLP_IN = 14
+FV_MLP_MAX_EXTRA = 2
+FV_MLP_IN_SIZED = 16
 FV_MLP_HID = 64
 FV_MLP_NPARAM = 9345
+FV_MLP_NPARAM_SIZED = 9473
+
+
+def fv_mlp_nparam(n_in):
+    return 64 * int(n_in) + 8449
 FV_SPACE_MAXC = 32
 
 
@@ -115,6 +122,8 @@ class fv_tune_space(ctypes.Structure):
         ("p2", (ctypes.c_int32 * FV_SPACE_MAXC) * NSITES),
         ("f1", (ctypes.c_float * FV_SPACE_MAXC) * NSITES),
         ("f2", (ctypes.c_float * FV_SPACE_MAXC) * NSITES),
+        ("n_extra", ctypes.c_int32),
+        ("extra", ctypes.c_float * FV_MLP_MAX_EXTRA),
     ]
 
 
@@ -174,10 +183,10 @@ def lib():
         L.fv_batch_last_error.restype = ctypes.c_char_p
         L.fv_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
         L.fv_mlp_sweep_workspace.argtypes = [ctypes.POINTER(ctypes.c_size_t)]
-        L.fv_mlp_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp, _vp,
-                                       ctypes.c_size_t, _vp]
-        L.fv_mlp_predict.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
-        L.fv_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+        L.fv_mlp_loss_grad.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, _vp,
+                                       _vp, ctypes.c_size_t, _vp]
+        L.fv_mlp_predict.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp]
+        L.fv_mlp_train.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
                                    ctypes.POINTER(fv_mlp_hparams), _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.fv_mlp_sweep.argtypes = [_vp, ctypes.POINTER(fv_tune_space), ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -405,22 +414,23 @@ def _mlp_check(rc, what):
     return rc
 
 
-def fv_mlp_loss_grad(params_ptr, X_ptr, y_ptr, n, alpha, grad_ptr, loss_ptr, ws_ptr, ws_bytes, stream_ptr):
-    return _mlp_check(lib().fv_mlp_loss_grad(_vp(params_ptr), _vp(X_ptr), _vp(y_ptr), int(n), float(alpha),
-                                             _vp(grad_ptr), _vp(loss_ptr), _vp(ws_ptr), ws_bytes,
+def fv_mlp_loss_grad(params_ptr, n_in, X_ptr, y_ptr, n, alpha, grad_ptr, loss_ptr, ws_ptr, ws_bytes, stream_ptr):
+    return _mlp_check(lib().fv_mlp_loss_grad(_vp(params_ptr), int(n_in), _vp(X_ptr), _vp(y_ptr), int(n),
+                                             float(alpha), _vp(grad_ptr), _vp(loss_ptr), _vp(ws_ptr), ws_bytes,
                                              _vp(stream_ptr)), "fv_mlp_loss_grad")
 
 
-def fv_mlp_predict(params_ptr, X_ptr, n, out_ptr, stream_ptr):
-    return _mlp_check(lib().fv_mlp_predict(_vp(params_ptr), _vp(X_ptr), int(n), _vp(out_ptr), _vp(stream_ptr)),
-                      "fv_mlp_predict")
+def fv_mlp_predict(params_ptr, n_in, X_ptr, n, out_ptr, stream_ptr):
+    return _mlp_check(lib().fv_mlp_predict(_vp(params_ptr), int(n_in), _vp(X_ptr), int(n), _vp(out_ptr),
+                                           _vp(stream_ptr)), "fv_mlp_predict")
 
 
-def fv_mlp_train(params_ptr, m_ptr, v_ptr, t_ptr, X_ptr, y_ptr, n, order_ptr, hp, loss_ptr, epochs_ptr,
+def fv_mlp_train(params_ptr, n_in, m_ptr, v_ptr, t_ptr, X_ptr, y_ptr, n, order_ptr, hp, loss_ptr, epochs_ptr,
                  ws_ptr, ws_bytes, stream_ptr):
-    return _mlp_check(lib().fv_mlp_train(_vp(params_ptr), _vp(m_ptr), _vp(v_ptr), _vp(t_ptr), _vp(X_ptr),
-                                         _vp(y_ptr), int(n), _vp(order_ptr), ctypes.byref(hp), _vp(loss_ptr),
-                                         _vp(epochs_ptr), _vp(ws_ptr), ws_bytes, _vp(stream_ptr)), "fv_mlp_train")
+    return _mlp_check(lib().fv_mlp_train(_vp(params_ptr), int(n_in), _vp(m_ptr), _vp(v_ptr), _vp(t_ptr),
+                                         _vp(X_ptr), _vp(y_ptr), int(n), _vp(order_ptr), ctypes.byref(hp),
+                                         _vp(loss_ptr), _vp(epochs_ptr), _vp(ws_ptr), ws_bytes, _vp(stream_ptr)),
+                      "fv_mlp_train")
 
 
 def fv_mlp_sweep(params_ptr, space, begin, count, k, top_idx_ptr, top_val_ptr, ws_ptr, ws_bytes, stream_ptr):

@@ -19,7 +19,10 @@ table (stencil (64, 256), one-dimensional (0, 256)) is a point of the space.
 Indices are mixed radix with site 0 fastest.
 
 Network features per site: log2 of (block width, threads) for stencil sites
-and log2 of (elements per thread, threads) for one-dimensional sites.
+and log2 of (elements per thread, threads) for one-dimensional sites. The
+problem-size-conditioned network (the extension proposed in Sec.
+"Broader Impact") appends two features of the grid, the same for every launch vector:
+log2 of its interior cell count and its dimension (problem_features).
 """
 from __future__ import annotations
 
@@ -50,6 +53,15 @@ def site_elements(spec):
     ncell = nx * ny * nz
     ghosts = 4 * ny * nz + 4 * nx * nz + (4 * nx * ny if spec.ndim == 3 else 0)
     return {3: ncell, 4: ncell, 5: ghosts, 6: ncell}
+
+
+def problem_features(spec):
+    """Raw problem features of a grid for the size-conditioned network:
+    (log2 of the interior cell count, dimension)."""
+    cells = 1
+    for v in spec.n[:spec.ndim]:
+        cells *= int(v)
+    return [math.log2(cells), float(spec.ndim)]
 
 
 class MixedRadixSpace:
@@ -116,10 +128,19 @@ class MixedRadixSpace:
             f2.append([(b - mean[2 * s + 1]) / std[2 * s + 1] for _, b in self.feats[s]])
         return f1, f2
 
-    def struct(self, mean, std):
-        """fv_tune_space describing this space with the given feature scaler."""
-        from .fv import fv_tune_space
+    def struct(self, mean, std, extra=None):
+        """fv_tune_space describing this space with the given feature scaler.
+        extra: raw problem features appended to every vector (the size-
+        conditioned network), standardised with the scaler's trailing columns."""
+        from .fv import FV_MLP_MAX_EXTRA, fv_tune_space
         sp = fv_tune_space()
+        if extra is not None:
+            extra = list(extra)
+            if len(extra) != FV_MLP_MAX_EXTRA or len(mean) != 2 * NSITES + len(extra) or len(std) != len(mean):
+                raise ValueError("extra features do not match the scaler")
+            sp.n_extra = len(extra)
+            for j, v in enumerate(extra):
+                sp.extra[j] = (v - mean[2 * NSITES + j]) / std[2 * NSITES + j]
         f1, f2 = self.tables(mean, std)
         for s in range(NSITES):
             sp.radix[s] = self.radix[s]

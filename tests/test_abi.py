@@ -150,3 +150,22 @@ def test_batch_query_offsets_and_validation():
         fv.fv_batch_query([inputs.grid2d(8192, 16384)])
     assert e.value.code == fv.FV_EINVAL and "4 GiB" in str(e.value)   # the library's own message
 
+
+
+def test_mlp_entry_points_reject_other_input_widths():
+    # validated before any device work: non-null dummy pointers are never touched
+    L = fv.lib()
+    p = 256
+    for n_in in (0, 13, 15, 17):
+        assert L.fv_mlp_predict(p, n_in, p, 10, p, None) == fv.FV_EINVAL
+        assert L.fv_mlp_loss_grad(p, n_in, p, p, 10, 0.0, p, p, p, 1 << 30, None) == fv.FV_EINVAL
+        hp = fv.fv_mlp_hparams(1e-3, 0.9, 0.9, 1e-8, 0.0, 0.0, 10, 1, 1, 0)
+        assert L.fv_mlp_train(p, n_in, p, p, p, p, p, 10, p, hp, p, p, p, 1 << 30, None) == fv.FV_EINVAL
+    sp = fv.fv_tune_space()
+    for s in range(fv.NSITES):
+        sp.radix[s] = 1
+    for n_extra in (1, 3, -1):
+        sp.n_extra = n_extra
+        assert L.fv_mlp_sweep(p, sp, 0, 1, 1, p, p, p, 1 << 30, None) == fv.FV_EINVAL
+    assert fv.fv_mlp_nparam(fv.FV_MLP_IN) == fv.FV_MLP_NPARAM
+    assert fv.fv_mlp_nparam(fv.FV_MLP_IN_SIZED) == fv.FV_MLP_NPARAM_SIZED

@@ -1,0 +1,226 @@
+"""The problem-size-conditioned network (16 inputs: the 14 launch features,
+then log2 of the cell count and the dimension) through the C ABI: its FP32
+kernels against the FP64 oracle, what conditioning gains over the 14-input
+network on a synthetic cost whose optimum moves with the problem size, and
+the tuning loop on real grids."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2306_14011_amd import inputs
+from paper_2306_14011_amd.autotune import r2_score, target_scaler
+from paper_2306_14011_amd.tune_space import LaunchSpace
+
+pytestmark = pytest.mark.gpu
+
+N_IN = 16
+
+
+def net(seed, n_in=N_IN):
+    from paper_2306_14011_amd.autotune import Network
+    return Network(seed, n_in=n_in)
+
+
+def problem(n=225, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, N_IN)).astype(np.float32).astype(np.float64)
+    y = 1.0 + 0.3 * np.sin(X[:, 14]) + 0.2 * X[:, 3] * X[:, 15] + 0.05 * rng.standard_normal(n)
+    return X, y
+
+
+def f32(theta):
+    return theta.astype(np.float32).astype(np.float64)
+
+
+def test_sized_loss_and_gradient_match_oracle():
+    X, y = problem()
+    N = net(3)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    assert theta.size == 9473 and np.array_equal(theta, f32(inputs.mlp_init(3, N_IN)))
+    for alpha in (0.0, 1e-4, 0.5):
+        L, g = N.loss_grad(X, y, alpha)
+        Lr, gr = mlp.loss_grad(theta, X, y, alpha)
+        assert abs(L - Lr) <= 1e-5 * abs(Lr)
+        assert np.linalg.norm(g - gr) <= 1e-4 * np.linalg.norm(gr)
+        assert np.abs(g - gr).max() <= 1e-4 * np.abs(gr).max()
+    # the gradient of the problem-feature columns of W1 in particular
+    G, Gr = g[:1024].reshape(64, 16)[:, 14:], gr[:1024].reshape(64, 16)[:, 14:]
+    assert np.abs(G - Gr).max() <= 1e-4 * np.abs(Gr).max()
+
+
+def test_sized_predict_matches_oracle():
+    X, _ = problem(1000, 1)
+    N = net(4)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    out = N.predict(X)
+    ref = mlp.predict(theta, X)
+    assert np.abs(out - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    with pytest.raises(ValueError):
+        N.predict(X[:, :14])          # rows of the other width are refused on the host
+
+
+def test_sized_training_tracks_oracle():
+    X, y = problem(225, 3)
+    order = inputs.epoch_orders(225, 30, 7)
+    N = net(6)
+    theta0 = N.params.cpu().numpy().astype(np.float64)
+    losses = N.train(X, y, order=order, max_epochs=30)
+    th_ref, lref, ne, _, _, _ = mlp.train(theta0, X, y, order, max_epochs=30)
+    assert len(losses) == ne == 30
+    assert np.allclose(losses, lref, rtol=2e-3, atol=0)
+    assert np.abs(N.predict(X) - mlp.predict(th_ref, X)).max() <= 1e-2 * np.abs(y).max()
+
+
+def window_rows(sp, mean, std, extra, begin, count):
+    """Standardised rows of indices [begin, begin + count), the problem features appended (FP32 values)."""
+    idx = np.arange(begin, begin + count)
+    rem = idx.copy()
+    f1, f2 = sp.tables(mean, std)
+    X = np.zeros((count, N_IN))
+    for s, r in enumerate(sp.radix):
+        d = rem % r
+        rem //= r
+        X[:, 2 * s] = np.asarray(f1[s], dtype=np.float32)[d]
+        X[:, 2 * s + 1] = np.asarray(f2[s], dtype=np.float32)[d]
+    for j in range(2):
+        X[:, 14 + j] = np.float32((extra[j] - mean[14 + j]) / std[14 + j])
+    return X
+
+
+@pytest.mark.parametrize("ndim,begin", [(2, 1_234_567), (3, 3_000_000_000)])
+def test_sized_sweep_topk_matches_brute_force(ndim, begin):
+    sp = LaunchSpace(ndim)
+    F = np.hstack([sp.features(sp.sample(200, 3)), np.tile([20.0, 2.0], (200, 1))])
+    F[::3, 14:] = [24.0, 3.0]
+    mean, std = mlp.standard_scaler(F)
+    extra = [22.0, float(ndim)]
+    N = net(9)
+    theta = N.params.cpu().numpy().astype(np.float64)
+    count = 100_000
+    ti, tv = N.sweep(sp.struct(mean, std, extra), begin, count, 8)
+    pred = mlp.predict(theta, window_rows(sp, mean, std, extra, begin, count))
+    order = np.argsort(pred, kind="stable")
+    scale = np.abs(pred).max()
+    assert all(begin <= i < begin + count for i in ti)
+    assert list(tv) == sorted(tv)
+    assert np.allclose(tv, pred[order[:8]], rtol=0, atol=2e-5 * scale)
+    for i, v in zip(ti, tv):
+        assert abs(pred[i - begin] - v) <= 2e-5 * scale
+    # the problem features move the prediction: another size ranks differently
+    ti2, tv2 = N.sweep(sp.struct(mean, std, [16.0, float(ndim)]), begin, count, 8)
+    assert tv2 != tv
+    with pytest.raises(ValueError):
+        N.sweep(sp.struct(mean[:14], std[:14]), begin, count, 8)   # 14-feature table for a 16-input network
+
+
+# ---------------------------------------------------------------------------
+# What conditioning gains: a synthetic runtime whose optimal launch moves with
+# the grid size. The runtime scales with the cell count and, at each size, is a
+# separable quadratic in the launch features around an optimum that slides
+# from OPT_SMALL (2^16 cells) to OPT_LARGE (2^22 cells).
+
+SIZES = (16.0, 20.0, 22.0)          # log2 cells of the training grids (2D)
+HELD_OUT = 18.0                     # a size the networks never see
+OPT_SMALL = np.array([4, 6, 6, 8, 6, 8, 0, 7, 0, 6, 0, 6, 0, 7], dtype=float)
+OPT_LARGE = np.array([7, 9, 6, 8, 6, 8, 4, 9, 3, 9, 2, 8, 3, 10], dtype=float)
+W = np.array([0.3, 0.2, 0.25, 0.15, 0.0, 0.0, 0.1, 0.2, 0.15, 0.1, 0.05, 0.05, 0.1, 0.1])
+
+
+def opt_of(s):
+    u = (s - 16.0) / 6.0
+    return OPT_SMALL * (1.0 - u) + OPT_LARGE * u
+
+
+def sized_cost(sp, idx, s, rng=None, noise=0.02):
+    L = sp.features(idx)
+    c = 2.0 ** (s - 16.0) * (1.0 + (W * (L - opt_of(s)) ** 2).sum(axis=1))
+    if rng is not None:
+        c = c * (1.0 + noise * rng.standard_normal(len(c)))
+    return c
+
+
+def sized_optimum(sp, s):
+    """Exact minimum over the space: the cost separates over the sites."""
+    o = opt_of(s)
+    tot = 0.0
+    for site in range(7):
+        tot += min(W[2 * site] * (a - o[2 * site]) ** 2 + W[2 * site + 1] * (b - o[2 * site + 1]) ** 2
+                   for a, b in sp.feats[site])
+    return 2.0 ** (s - 16.0) * (1.0 + tot)
+
+
+def test_size_conditioning_gains_over_the_launch_only_network():
+    # 1500 samples per training size, one network for all of them. The
+    # conditioned network's exhaustive-sweep pick lands near each size's exact
+    # optimum, also at a size it was not trained on (measured: 1.00-1.21x; the
+    # FP64 oracle network trained on the same rows picks 1.38x at 2^20 cells,
+    # about the best of 2e5 random configurations, hence the 1.45 bound), and
+    # beats the best of that size's 1500 samples (1.6-2.0x); the 14-input
+    # network on the same pooled samples cannot tell the sizes apart and its
+    # picks cost 4-6x the optimum.
+    sp = LaunchSpace(2)
+    rng = np.random.default_rng(3)
+    per = 1500
+    F, E, t = [], [], []
+    for j, s in enumerate(SIZES):
+        idx = sp.sample(per, 40 + j)
+        F.append(sp.features(idx))
+        E.append(np.tile([s, 2.0], (per, 1)))
+        t.append(sized_cost(sp, idx, s, rng))
+    F, E, t = np.vstack(F), np.vstack(E), np.concatenate(t)
+    n = len(t)
+    perm = np.random.default_rng(5).permutation(n)
+    tr, te = perm[:int(0.75 * n)], perm[int(0.75 * n):]
+    z = np.log(t)
+    zm, zs = target_scaler(z[tr])
+    y = (z - zm) / zs
+    order = inputs.epoch_orders(len(tr), 200, 12)
+    ratios, r2 = {}, {}
+    for name, X0 in (("sized", np.hstack([F, E])), ("launch_only", F)):
+        mean, std = mlp.standard_scaler(X0[tr])
+        X = (X0 - mean) / std
+        N = net(12, X.shape[1])
+        N.train(X[tr], y[tr], order=order)
+        r2[name] = r2_score(y[te], N.predict(X[te]))
+        ratios[name] = []
+        for s in SIZES + (HELD_OUT,):
+            st = sp.struct(mean, std, [s, 2.0]) if name == "sized" else sp.struct(mean, std)
+            ti, _ = N.sweep(st, 0, sp.size, 8)
+            ratios[name].append(float(sized_cost(sp, ti, s).min() / sized_optimum(sp, s)))
+    best_random = [float(sized_cost(sp, sp.sample(per, 40 + j), s).min() / sized_optimum(sp, s))
+                   for j, s in enumerate(SIZES)]
+    info = dict(r2=r2, ratios=ratios, best_random=best_random)
+    print(info)
+    assert r2["sized"] > 0.98, info
+    assert max(ratios["sized"]) <= 1.45, info
+    assert all(a < b for a, b in zip(ratios["sized"], best_random)), info
+    assert min(ratios["launch_only"]) >= 2.0 * max(ratios["sized"]), info
+
+
+# ---------------------------------------------------------------------------
+# The loop on real grids.
+
+def test_sized_tuning_end_to_end():
+    # two sampled grids of different size and dimension and one held-out grid;
+    # every sampled launch is bitwise valid, one network is trained on the pool
+    # and each grid gets a tuned launch from its own sweep
+    from paper_2306_14011_amd.autotune import SizedAutotuner
+    g1, U1 = inputs.vortex_bumps_case(128, seed=1)
+    g2, U2 = inputs.sod3d_case(32, seed=2)
+    g3, U3 = inputs.vortex_bumps_case(256, seed=3)
+    at = SizedAutotuner([g1, g2, g3], [U1, U2, U3], seed=4, holdout=[2], repeats=1, warmup=1, min_ms=2.0)
+    res = at.run(count=40, k=4, rounds=1)
+    at.close()
+    assert res["n_train"] == 60 and res["n_test"] == 20
+    gs = res["grids"]
+    assert [g["held_out"] for g in gs] == [False, False, True]
+    assert [g["n_samples"] for g in gs] == [40, 40, 0]
+    assert gs[0]["n_valid"] == 40 and gs[1]["n_valid"] == 40
+    assert gs[0]["space_size"] == gs[2]["space_size"] == 189_062_500
+    assert gs[1]["space_size"] == 22 ** 3 * 25 ** 4
+    for g in gs:
+        assert g["tuned_ms"] > 0 and g["default_ms"] > 0
+        assert len(g["tuned_launch"]) == 14
+        assert all(math.isfinite(v) and v > 0 for v in g["top_pred_ms"])

@@ -117,3 +117,29 @@ def test_batch_space_buckets_and_schedules():
     assert sp2.radix == [len(BATCH_SEGS), 1, 1, len(BATCH_SEGS), 2, 1, 1]
     X = sp2.features(sp2.sample(20, 1))
     assert X.shape == (20, 14) and np.all(X[:, 1::2] == 0.0)
+
+
+def test_problem_features():
+    from paper_2306_14011_amd.tune_space import problem_features
+    g2, _ = inputs.vortex_bumps_case(256, seed=0)
+    assert problem_features(g2) == [16.0, 2.0]
+    g3 = inputs.sod3d_case(32, seed=0)[0]
+    assert problem_features(g3) == [15.0, 3.0]
+
+
+def test_struct_appends_standardised_problem_features():
+    from paper_2306_14011_amd.fv import FV_MLP_MAX_EXTRA
+    sp = LaunchSpace(2)
+    F = sp.features(sp.sample(50, 1))
+    E = np.tile([18.0, 2.0], (50, 1))
+    E[::2] = [22.0, 2.0]
+    mean, std = mlp.standard_scaler(np.hstack([F, E]))
+    s = sp.struct(mean, std, [22.0, 2.0])
+    assert s.n_extra == FV_MLP_MAX_EXTRA == 2
+    assert abs(s.extra[0] - 1.0) < 1e-6 and s.extra[1] == 0.0     # (22 - 20) / 2; zero spread -> 0
+    s14 = sp.struct(mean[:14], std[:14])
+    assert s14.n_extra == 0
+    for a, b in zip(s.f1[2], s14.f1[2]):
+        assert a == b
+    with pytest.raises(ValueError):
+        sp.struct(mean[:14], std[:14], [22.0, 2.0])
