@@ -196,6 +196,25 @@ def split_leg(torch, fv, traffic, g, U0, a, samples, tune_it, sample_timing=(3, 
     return out
 
 
+def sized_leg(torch, inputs, seed, samples):
+    """One problem-size-conditioned network (launch features plus log2 cells
+    and dimension) trained on the pooled timed samples of the 2048^2 2D and
+    256^3 3D split-path workloads, then used to tune both and a 1024^2 2D grid
+    it has no samples of."""
+    from paper_2306_14011_amd.autotune import SizedAutotuner
+    g2, U2 = inputs.vortex_bumps_case(2048, seed=seed)
+    g3, U3 = inputs.sod3d_case(256, seed=seed)
+    gh, Uh = inputs.vortex_bumps_case(1024, seed=seed + 1)
+    t0 = time.perf_counter()
+    at = SizedAutotuner([g2, g3, gh], [U2, U3, Uh], seed=seed, holdout=[2], repeats=1, warmup=2, min_ms=10.0,
+                        check_steps=2)
+    res = at.run(count=samples, k=8, rounds=5)
+    at.close()
+    res["tuning_seconds"] = round(time.perf_counter() - t0, 1)
+    res["grids"] = [{k: v for k, v in r.items() if k != "top_pred_relative"} for r in res["grids"]]
+    return res
+
+
 def fused_leg(torch, fv, traffic, g, U0, a):
     """The fused path: segment heights swept, the fastest kept and timed."""
     s = fv.Solver(g)
@@ -527,6 +546,12 @@ def main():
         out["small"] = small_leg(torch, fv, inputs)
         out["schemes"] = schemes_leg(torch, fv, traffic, g, U0, 50)
         log("schemes (fused 2D): " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in out["schemes"].items()))
+        if not a.no_tune and not a.no_3d:
+            out["sized_tuner"] = sized_leg(torch, inputs, a.seed, a.samples)
+            sz = out["sized_tuner"]
+            log(f"size-conditioned tuner in {sz['tuning_seconds']} s, R2(test) {sz['r2_test']:.3f}: " + ", ".join(
+                f"{'x'.join(map(str, r['n']))}{' (held out)' if r['held_out'] else ''} default/tuned "
+                f"{r['factor_vs_default']:.3f}" for r in sz["grids"]))
     if not a.no_batch:
         out["batch"] = batch_leg(torch, fv, inputs, 100, 0 if a.no_tune else a.samples_batch)
         log(f"batch: {out['batch']['value']:.3e} cell-updates/s")

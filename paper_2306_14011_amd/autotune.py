@@ -60,6 +60,25 @@ def target_scaler(t_train):
     return float(t_train.mean()), (sd if sd > 0.0 else 1.0)
 
 
+def grid_relative_target(t, gid, train):
+    """Target of the pooled, size-conditioned fit: the log of each runtime
+    relative to the geometric mean of its grid's training runtimes, then
+    standardised over the training rows. Runtimes of different grids differ
+    many times over while a launch moves a grid's runtime by tens of percent;
+    relative to its grid, a launch's effect is the same quantity on every grid
+    and the fit is spent on it rather than on the grids' sizes. Returns
+    (y, (mean, sigma) of the standardisation, {grid: log offset})."""
+    z = np.log(np.asarray(t, dtype=np.float64))
+    gid = np.asarray(gid)
+    offset = {}
+    for g in sorted(set(gid.tolist())):
+        rows = train[gid[train] == g]
+        offset[g] = float(z[rows].mean()) if len(rows) else float(z[gid == g].mean())
+        z[gid == g] -= offset[g]
+    z_mean, z_std = target_scaler(z[train])
+    return (z - z_mean) / z_std, (z_mean, z_std), offset
+
+
 def split_indices(n: int, seed: int, train_frac=0.75):
     rng = np.random.default_rng(seed + 17)
     perm = rng.permutation(n)
@@ -434,9 +453,8 @@ class SizedAutotuner:
     the grid's problem features (tune_space.problem_features: log2 of the
     cell count, dimension). Samples of every grid not in `holdout` are pooled
     into one training set (75 / 25 split over the pool); the target is the
-    standardised log of the runtime, so that a launch's relative effect is
-    comparable across grids whose runtimes differ many times over. Every grid,
-    held out or not, is then swept with its own problem features, its k best
+    log runtime relative to its grid (grid_relative_target). Every grid, held
+    out or not, is then swept with its own problem features, its k best
     predictions are measured and the fastest valid one is kept."""
 
     def __init__(self, grids, states, seed=0, holdout=(), **tuner_kw):
@@ -462,9 +480,7 @@ class SizedAutotuner:
         t = np.asarray(t, dtype=np.float64)
         gid = np.asarray(gid)
         tr, te = split_indices(len(t), self.seed)
-        z = np.log(t)
-        z_mean, z_std = target_scaler(z[tr])
-        y = (z - z_mean) / z_std
+        y, (z_mean, z_std), _ = grid_relative_target(t, gid, tr)
         mean = F[tr].mean(axis=0)
         std = F[tr].std(axis=0)
         std = np.where(std == 0.0, 1.0, std)
@@ -509,7 +525,7 @@ class SizedAutotuner:
                 n_valid=0 if samples[g] is None else sum(1 for s in samples[g] if s.valid),
                 default_launch=at.default, tuned_launch=best, default_ms=final[0], tuned_ms=final[1],
                 factor_vs_default=final[0] / final[1], n_valid_candidates=len(ok),
-                top_pred_ms=[float(math.exp(v * model["z_std"] + model["z_mean"])) for v in top_val],
+                top_pred_relative=[float(math.exp(v * model["z_std"] + model["z_mean"])) for v in top_val],
                 top_measured_ms=[m for m, _ in cand_ms], r2_test=model["r2_test_per_grid"].get(g),
                 sweep_seconds=t_sweep, space_size=at.space.size, steps_per_sample=at.steps))
         return dict(grids=out, r2_test=model["r2_test"], r2_train=model["r2_train"], n_train=model["n_train"],

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import mlp
 from paper_2306_14011_amd import inputs
-from paper_2306_14011_amd.autotune import r2_score, target_scaler
+from paper_2306_14011_amd.autotune import grid_relative_target, r2_score
 from paper_2306_14011_amd.tune_space import LaunchSpace
 
 pytestmark = pytest.mark.gpu
@@ -152,30 +152,32 @@ def sized_optimum(sp, s):
 
 
 def test_size_conditioning_gains_over_the_launch_only_network():
-    # 1500 samples per training size, one network for all of them. The
-    # conditioned network's exhaustive-sweep pick lands near each size's exact
-    # optimum, also at a size it was not trained on (measured: 1.00-1.21x; the
-    # FP64 oracle network trained on the same rows picks 1.38x at 2^20 cells,
-    # about the best of 2e5 random configurations, hence the 1.45 bound), and
-    # beats the best of that size's 1500 samples (1.6-2.0x); the 14-input
-    # network on the same pooled samples cannot tell the sizes apart and its
-    # picks cost 4-6x the optimum.
+    # 1500 samples per training size, one network for all of them, on the
+    # grid-relative log target of the tuner. The conditioned network ranks
+    # configurations within each size (FP64 oracle network on the same rows:
+    # test R^2 0.94-0.98 per size) and its exhaustive-sweep pick lands near each
+    # size's exact optimum, also at a size it was not trained on (the oracle
+    # network's pick from 2e5 random configurations: 1.30-1.45x, the best
+    # configuration of that pool at every size), beating the best of that
+    # size's 1500 samples (1.6-2.0x); the 14-input network on the same samples
+    # cannot tell the sizes apart and fits the launches' average effect, whose
+    # optimum is far off at the sizes away from the middle (oracle: 1.5-8.7x).
     sp = LaunchSpace(2)
     rng = np.random.default_rng(3)
     per = 1500
-    F, E, t = [], [], []
+    F, E, t, gid = [], [], [], []
     for j, s in enumerate(SIZES):
         idx = sp.sample(per, 40 + j)
         F.append(sp.features(idx))
         E.append(np.tile([s, 2.0], (per, 1)))
         t.append(sized_cost(sp, idx, s, rng))
+        gid += [j] * per
     F, E, t = np.vstack(F), np.vstack(E), np.concatenate(t)
     n = len(t)
     perm = np.random.default_rng(5).permutation(n)
     tr, te = perm[:int(0.75 * n)], perm[int(0.75 * n):]
-    z = np.log(t)
-    zm, zs = target_scaler(z[tr])
-    y = (z - zm) / zs
+    y, _, _ = grid_relative_target(t, gid, tr)
+    gte = np.asarray(gid)[te]
     order = inputs.epoch_orders(len(tr), 200, 12)
     ratios, r2 = {}, {}
     for name, X0 in (("sized", np.hstack([F, E])), ("launch_only", F)):
@@ -183,7 +185,8 @@ def test_size_conditioning_gains_over_the_launch_only_network():
         X = (X0 - mean) / std
         N = net(12, X.shape[1])
         N.train(X[tr], y[tr], order=order)
-        r2[name] = r2_score(y[te], N.predict(X[te]))
+        pred = N.predict(X[te])
+        r2[name] = [r2_score(y[te][gte == j], pred[gte == j]) for j in range(len(SIZES))]
         ratios[name] = []
         for s in SIZES + (HELD_OUT,):
             st = sp.struct(mean, std, [s, 2.0]) if name == "sized" else sp.struct(mean, std)
@@ -193,10 +196,11 @@ def test_size_conditioning_gains_over_the_launch_only_network():
                    for j, s in enumerate(SIZES)]
     info = dict(r2=r2, ratios=ratios, best_random=best_random)
     print(info)
-    assert r2["sized"] > 0.98, info
-    assert max(ratios["sized"]) <= 1.45, info
+    assert min(r2["sized"]) > 0.9, info
+    assert max(ratios["sized"]) <= 1.5, info
     assert all(a < b for a, b in zip(ratios["sized"], best_random)), info
-    assert min(ratios["launch_only"]) >= 2.0 * max(ratios["sized"]), info
+    assert np.mean(ratios["launch_only"]) >= 1.5 * np.mean(ratios["sized"]), info
+    assert max(ratios["launch_only"]) >= 2.0 * max(ratios["sized"]), info
 
 
 # ---------------------------------------------------------------------------
@@ -223,4 +227,4 @@ def test_sized_tuning_end_to_end():
     for g in gs:
         assert g["tuned_ms"] > 0 and g["default_ms"] > 0
         assert len(g["tuned_launch"]) == 14
-        assert all(math.isfinite(v) and v > 0 for v in g["top_pred_ms"])
+        assert all(math.isfinite(v) and v > 0 for v in g["top_pred_relative"])

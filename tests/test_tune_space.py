@@ -143,3 +143,18 @@ def test_struct_appends_standardised_problem_features():
         assert a == b
     with pytest.raises(ValueError):
         sp.struct(mean[:14], std[:14], [22.0, 2.0])
+
+
+def test_grid_relative_target():
+    from paper_2306_14011_amd.autotune import grid_relative_target
+    # two grids 8x apart in runtime; the same relative launch effects on both
+    t = np.array([1.0, 2.0, 4.0, 8.0, 16.0, 32.0])
+    gid = [0, 0, 0, 1, 1, 1]
+    tr = np.arange(6)
+    y, (m, s), off = grid_relative_target(t, gid, tr)
+    assert abs(off[0] - math.log(2.0)) < 1e-15 and abs(off[1] - math.log(16.0)) < 1e-15
+    assert np.allclose(y[:3], y[3:], rtol=0, atol=1e-15)           # the size factor is gone
+    assert abs(y[tr].mean()) < 1e-15 and abs(y[tr].std() - 1.0) < 1e-14
+    # offsets come from the training rows only
+    y2, _, off2 = grid_relative_target(t, gid, np.array([0, 1, 3, 4]))
+    assert abs(off2[0] - 0.5 * math.log(2.0)) < 1e-15 and abs(off2[1] - 0.5 * math.log(128.0)) < 1e-15
