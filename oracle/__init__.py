@@ -38,6 +38,7 @@ class OrGrid(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("kappa", ctypes.c_double),
+        ("source", ctypes.c_void_p),
     ]
 
 
@@ -94,9 +95,17 @@ def limiter_code(limiter):
     raise ValueError(f"unknown limiter {limiter!r}")
 
 
-def make_grid(spec, limiter=True, kappa=-1.0):
-    """OrGrid from any object with ndim, n, lo, hi, bc, gamma, cfl attributes."""
+def make_grid(spec, limiter=True, kappa=-1.0, source=None):
+    """OrGrid from any object with ndim, n, lo, hi, bc, gamma, cfl attributes.
+    source: cell-averaged source S, shape (nvar, nz, ny, nx) or (nvar, ny, nx),
+    or None for S = 0 (Eq. residual)."""
     g = OrGrid()
+    if source is not None:
+        src = np.ascontiguousarray(source, dtype=np.float64)
+        if src.size != (spec.ndim + 2) * int(np.prod([int(v) for v in spec.n])):
+            raise ValueError("source has the wrong number of cells or variables")
+        g._source_ref = src          # kept alive with the struct
+        g.source = src.ctypes.data
     g.ndim = spec.ndim
     g.limiter = limiter_code(limiter)
     for d in range(3):
@@ -148,8 +157,8 @@ def roe_flux(ndim, ax, QL, QR, gamma=1.4):
     return F
 
 
-def residual(spec, U, limiter=True, kappa=-1.0):
-    g = make_grid(spec, limiter, kappa)
+def residual(spec, U, limiter=True, kappa=-1.0, source=None):
+    g = make_grid(spec, limiter, kappa, source)
     U = _arr(U)
     R = np.zeros_like(U)
     lib().or_residual(ctypes.byref(g), _p(U), _p(R))
@@ -182,8 +191,8 @@ def dt(spec, U):
     return v, fl.value
 
 
-def rk3_step(spec, U, dt_, limiter=True, kappa=-1.0):
-    g = make_grid(spec, limiter, kappa)
+def rk3_step(spec, U, dt_, limiter=True, kappa=-1.0, source=None):
+    g = make_grid(spec, limiter, kappa, source)
     U = _arr(U).copy()
     lib().or_rk3_step(ctypes.byref(g), _p(U), float(dt_))
     return U
@@ -199,9 +208,9 @@ def rk3_step_cs(spec, U, V, dt_, h=1e-30, limiter=True):
     return Un, dUn
 
 
-def run(spec, U, nsteps, dt_in=None, limiter=True, kappa=-1.0):
+def run(spec, U, nsteps, dt_in=None, limiter=True, kappa=-1.0, source=None):
     """Advance ``nsteps`` SSP-RK3 steps; returns (U, dt per step, flags)."""
-    g = make_grid(spec, limiter, kappa)
+    g = make_grid(spec, limiter, kappa, source)
     U = _arr(U).copy()
     dts = np.zeros(max(nsteps, 1))
     fl = ctypes.c_uint32(0)
@@ -223,9 +232,10 @@ def residual_vjp(spec, U, w, limiter=True):
     return mu
 
 
-def rk3_step_vjp(spec, U, dt_, lam, limiter=True, kappa=-1.0):
-    """dJ/dU^n from dJ/dU^{n+1} = lam for one step at frozen dt."""
-    g = make_grid(spec, limiter, kappa)
+def rk3_step_vjp(spec, U, dt_, lam, limiter=True, kappa=-1.0, source=None):
+    """dJ/dU^n from dJ/dU^{n+1} = lam for one step at frozen dt (a source
+    moves the stage states the derivative is taken at, not the derivative's form)."""
+    g = make_grid(spec, limiter, kappa, source)
     U = _arr(U)
     lam = _arr(lam).copy()
     lib().or_rk3_step_vjp(ctypes.byref(g), _p(U), float(dt_), _p(lam))

@@ -51,6 +51,7 @@ struct OrGrid {
     double gamma;       // ratio of specific heats
     double cfl;         // CFL number for the stable time step
     double kappa;       // MUSCL kappa (-1 on the measured path)
+    const double* source;  // cell-averaged source S[v][k][j][i], or null for S = 0
 };
 }
 
@@ -271,7 +272,8 @@ static inline double cell_volume(const OrGrid* g) {
     return v;
 }
 
-// R_c = sum_ax (F_{c+1/2} - F_{c-1/2}) * A_ax   (Eq. residual, S = 0).
+// R_c = sum_ax (F_{c+1/2} - F_{c-1/2}) * A_ax - |Omega| S_c   (Eq. residual;
+// S_c is the cell average of the source, zero when none is given).
 template <class T>
 static void residual(const OrGrid* g, const T* U, T* R) {
     const int nv = g->ndim + 2;
@@ -290,6 +292,10 @@ static void residual(const OrGrid* g, const T* U, T* R) {
             face_flux(g, U, ax, im[0], im[1], im[2], Fm);
             double A = face_area(g, ax);
             for (int v = 0; v < nv; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]) * A;
+        }
+        if (g->source) {
+            const double vol = cell_volume(g);
+            for (int v = 0; v < nv; ++v) acc[v] = acc[v] - vol * g->source[v * ncell + c];
         }
         for (int v = 0; v < nv; ++v) R[v * ncell + c] = acc[v];
     }

@@ -1,0 +1,93 @@
+"""Manufactured solution of the 2D Euler equations and its source term.
+
+TEST INFRASTRUCTURE (see the package docstring). The residual of Eq.
+(residual) carries a cell-averaged source S_h, and the cell-wise
+semi-discrete form of Eq. (governing_cv) holds the exact solution steady when
+S is the divergence of the inviscid flux of Eq. (QF) evaluated on it. Here the
+"exact solution" is a chosen smooth periodic field (the method of manufactured
+solutions: Roache 2002; Roy 2005 for the Euler form used as a template), and
+its source is that divergence, differentiated by hand with the product rule.
+Fed the cell averages of both, the discrete residual is the scheme's
+truncation error, which falls as h^2 for a second-order scheme.
+
+Fields on the periodic unit square (x, y in [0, 1]):
+  rho = 1   + 0.15 sin(2 pi x) + 0.10 cos(2 pi y)
+  u   = 0.7 + 0.05 sin(2 pi x) + 0.05 cos(4 pi y)
+  v   = 0.9 + 0.05 cos(4 pi x) + 0.08 sin(2 pi y)
+  p   = 1   + 0.20 cos(2 pi x) + 0.05 sin(2 pi y)
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+# (mean, (amp, kx, 'sin'|'cos') in x, (amp, ky, 'sin'|'cos') in y) per primitive
+FIELDS = {
+    "rho": (1.0, (0.15, 1, "sin"), (0.10, 1, "cos")),
+    "u": (0.7, (0.05, 1, "sin"), (0.05, 2, "cos")),
+    "v": (0.9, (0.05, 2, "cos"), (0.08, 1, "sin")),
+    "p": (1.0, (0.20, 1, "cos"), (0.05, 1, "sin")),
+}
+
+
+def _term(t, s):
+    """Value and derivative of amp * sin|cos(2 pi k s)."""
+    amp, k, kind = t
+    w = TWO_PI * k
+    if kind == "sin":
+        return amp * np.sin(w * s), amp * w * np.cos(w * s)
+    return amp * np.cos(w * s), -amp * w * np.sin(w * s)
+
+
+def primitive(name, x, y):
+    """(value, d/dx, d/dy) of a primitive field at points (x, y)."""
+    mean, tx, ty = FIELDS[name]
+    fx, dfx = _term(tx, x)
+    fy, dfy = _term(ty, y)
+    return mean + fx + fy, dfx + 0.0 * y, dfy + 0.0 * x
+
+
+def conserved(x, y, gamma=1.4):
+    """(rho, rho u, rho v, E) at points (x, y)."""
+    r, _, _ = primitive("rho", x, y)
+    u, _, _ = primitive("u", x, y)
+    v, _, _ = primitive("v", x, y)
+    p, _, _ = primitive("p", x, y)
+    E = p / (gamma - 1.0) + 0.5 * r * (u * u + v * v)
+    return np.stack([r, r * u, r * v, E])
+
+
+def source(x, y, gamma=1.4):
+    """S = d F/dx + d G/dy of the inviscid fluxes on the manufactured fields."""
+    r, rx, ry = primitive("rho", x, y)
+    u, ux, uy = primitive("u", x, y)
+    v, vx, vy = primitive("v", x, y)
+    p, px, py = primitive("p", x, y)
+    q2 = u * u + v * v
+    E = p / (gamma - 1.0) + 0.5 * r * q2
+    Ex = px / (gamma - 1.0) + 0.5 * rx * q2 + r * (u * ux + v * vx)
+    Ey = py / (gamma - 1.0) + 0.5 * ry * q2 + r * (u * uy + v * vy)
+    # F = (rho u, rho u^2 + p, rho u v, u (E + p)),  G = (rho v, rho u v, rho v^2 + p, v (E + p))
+    s0 = (rx * u + r * ux) + (ry * v + r * vy)
+    s1 = (rx * u * u + 2.0 * r * u * ux + px) + (ry * u * v + r * uy * v + r * u * vy)
+    s2 = (rx * u * v + r * ux * v + r * u * vx) + (ry * v * v + 2.0 * r * v * vy + py)
+    s3 = (ux * (E + p) + u * (Ex + px)) + (vy * (E + p) + v * (Ey + py))
+    return np.stack([s0, s1, s2, s3])
+
+
+def cell_averages(fn, n, order=4):
+    """Cell averages of fn(x, y) -> (4, ...) over an n x n grid of the unit
+    square by order x order Gauss-Legendre quadrature; shape (4, n, n) [v][j][i]."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    h = 1.0 / n
+    centres = (np.arange(n) + 0.5) * h
+    out = np.zeros((4, n, n))
+    for a, wa in zip(xg, wg):
+        for b, wb in zip(xg, wg):
+            X = centres[None, :] + 0.5 * h * a
+            Y = centres[:, None] + 0.5 * h * b
+            out += 0.25 * wa * wb * fn(np.broadcast_to(X, (n, n)), np.broadcast_to(Y, (n, n)))
+    return out
