@@ -279,6 +279,27 @@ def schemes_leg(torch, fv, traffic, g, U0, steps):
     return out
 
 
+def source_leg(torch, fv, inputs, g, U0, steps):
+    """The headline workload with a cell-averaged source term (the seeded
+    smooth field of inputs.smooth_source) on both paths: the split path folds
+    it into the residual kernel (|Omega| S read once per stage), the fused path
+    adds each stage's share in a pass after the stage kernel and takes the
+    step's wave speed again."""
+    S = inputs.smooth_source(g, 1)
+    out = {"workload": "2048x2048 vortex + bumps with a smooth source (amplitude 0.05)"}
+    for path in ("fused", "split"):
+        s = fv.Solver(g)
+        if path == "fused":
+            s.set_path(fv.FV_PATH_FUSED, 0, 0)
+        base = timed_steps(torch, s, U0, steps, 5)
+        s.set_source(S)
+        ms = timed_steps(torch, s, U0, steps, 5)
+        s.close()
+        out[path] = {"ms_per_step": round(ms, 4), "no_source_ms_per_step": round(base, 4),
+                     "value": g.ncells / (ms * 1e-3), "over_no_source": round(ms / base, 3)}
+    return out
+
+
 def small_leg(torch, fv, inputs):
     """64^2 vortex (launch-bound): split and fused by direct launches, fused as a
     graph-replayed batch of one."""
@@ -546,6 +567,9 @@ def main():
         out["small"] = small_leg(torch, fv, inputs)
         out["schemes"] = schemes_leg(torch, fv, traffic, g, U0, 50)
         log("schemes (fused 2D): " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in out["schemes"].items()))
+        out["source"] = source_leg(torch, fv, inputs, g, U0, 50)
+        log("source term: " + ", ".join(f"{p} {out['source'][p]['ms_per_step']:.4f} ms "
+                                        f"({out['source'][p]['over_no_source']:.3f}x)" for p in ("fused", "split")))
         if not a.no_tune and not a.no_3d:
             out["sized_tuner"] = sized_leg(torch, inputs, a.seed, a.samples)
             sz = out["sized_tuner"]

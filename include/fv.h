@@ -141,10 +141,23 @@ int fv_destroy(fv_ctx* ctx);
 int fv_set_stream(fv_ctx* ctx, void* stream);
 
 /* Spatial residual of Eq. (residual): R = sum over the 2*ndim faces of the
- * Roe flux of the MUSCL face states times the face area, S = 0. Fills the
- * ghost layers of U (the interior is not changed) and writes R in the dense
+ * Roe flux of the MUSCL face states times the face area, minus |Omega| S
+ * when a source is set (fv_set_source; S = 0 otherwise). Fills the ghost
+ * layers of U (the interior is not changed) and writes R in the dense
  * interior layout (nvar * ncell doubles). */
 int fv_residual(fv_ctx* ctx, double* U, double* R);
+
+/* Sets the cell-averaged source term S_h of Eq. (residual) (a body force, a
+ * manufactured solution's source): S is a device pointer to nvar * ncell
+ * doubles in the dense interior layout of fv_residual's R (variable, then
+ * cell with x fastest), or NULL to remove it. The caller keeps S allocated
+ * and unchanged while it is set: fv_residual, fv_step (both paths) and
+ * fv_adjoint_step read it on the device. The source does not depend on U, so
+ * the adjoint's transposed Jacobian is unchanged; its recomputed stage states
+ * include it. On the fused path each stage's share (1, 1/4, 2/3 times dt S)
+ * is added by a separate pass after the stage kernel, and the wave speed of
+ * the step's result is then taken again. Only a null context is rejected. */
+int fv_set_source(fv_ctx* ctx, const double* S);
 
 /* Advances U (ghosted layout, in place) by nsteps SSP-RK3 steps:
  *   U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1)),

@@ -35,6 +35,7 @@ struct fv_ctx {
     fvk::FGrid* fgrid;  // the fused path's grid description (an FGrid3 in 3D)
     unsigned long long* flam;
     double* fdt;
+    const double* src;  // caller's cell-averaged source S[v][cell], or null
     // per-site event timing (diagnostic)
     static const int kMaxEv = 64;
     bool timing;
@@ -208,6 +209,7 @@ Geo make_geo(const fv_grid_desc* d, const Layout& L) {
         g.area[a] = ar;
     }
     g.inv_vol = 1.0 / vol;
+    g.vol = vol;
     g.gamma = d->gamma;
     g.gm1 = d->gamma - 1.0;
     g.cfl = d->cfl;
@@ -274,8 +276,8 @@ void enqueue_fluxes(fv_ctx* c, const double* U) {
 
 void enqueue_residual(fv_ctx* c, double* R) {
     SiteTimer t(c, FV_SITE_RESIDUAL);
-    fvk::launch_residual(c->F[0], c->F[1], c->F[2], R, c->g, P(c, FV_SITE_RESIDUAL, 0), P(c, FV_SITE_RESIDUAL, 1),
-                         c->stream);
+    fvk::launch_residual(c->F[0], c->F[1], c->F[2], c->src, R, c->g, P(c, FV_SITE_RESIDUAL, 0),
+                         P(c, FV_SITE_RESIDUAL, 1), c->stream);
 }
 
 void enqueue_update(fv_ctx* c, int stage, const double* Un, const double* Us, double* Ud,
@@ -419,15 +421,23 @@ static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in
                                       dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status,
                                       c->stream);
         }
+        if (c->src) fvk::launch_source_add(c->U1, c->src, c->fdt, 1.0, c->g, c->stream);
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(1, c->fwaves, G, c->fitems, U, c->U1, c->U2, c->flam, c->fdt, nullptr,
                                       nullptr, c->status, c->stream);
         }
+        if (c->src) fvk::launch_source_add(c->U2, c->src, c->fdt, 0.25, c->g, c->stream);
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(2, c->fwaves, G, c->fitems, U, c->U2, U, c->flam, c->fdt, nullptr, nullptr,
                                       c->status, c->stream);
+        }
+        if (c->src) {
+            // the stage kernel's wave speed is that of the state before the
+            // source's share: take it again from the step's result
+            fvk::launch_source_add(U, c->src, c->fdt, 2.0 / 3.0, c->g, c->stream);
+            fvk::launch_fused3d_init(c->fwaves, G, c->fitems, U, c->flam, c->status, c->stream);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;
@@ -448,15 +458,23 @@ static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in,
                                     dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status, nullptr,
                                     c->stream);
         }
+        if (c->src) fvk::launch_source_add(c->U1, c->src, c->fdt, 1.0, c->g, c->stream);
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(1, c->fwaves, c->fgrid, 1, c->fitems, U, c->U1, c->U2, c->flam, c->fdt,
                                     nullptr, nullptr, c->status, nullptr, c->stream);
         }
+        if (c->src) fvk::launch_source_add(c->U2, c->src, c->fdt, 0.25, c->g, c->stream);
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(2, c->fwaves, c->fgrid, 1, c->fitems, U, c->U2, U, c->flam, c->fdt,
                                     nullptr, nullptr, c->status, nullptr, c->stream);
+        }
+        if (c->src) {
+            // the stage kernel's wave speed is that of the state before the
+            // source's share: take it again from the step's result
+            fvk::launch_source_add(U, c->src, c->fdt, 2.0 / 3.0, c->g, c->stream);
+            fvk::launch_fused_init(c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, c->stream);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;
@@ -580,6 +598,12 @@ int fv_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* d
         rc = drain_timing(c);
         if (rc != FV_OK) return rc;
     }
+    return FV_OK;
+}
+
+int fv_set_source(fv_ctx* c, const double* S) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    c->src = S;
     return FV_OK;
 }
 

@@ -46,6 +46,7 @@ struct Geo {
     double inv_dx[3];   // 1 / dx_d
     double area[3];     // face area of axis d: product of the other widths
     double inv_vol;     // 1 / |Omega|
+    double vol;         // |Omega|
     double gamma, gm1;  // gamma, gamma - 1
     double cfl;
     int bc[3][2];

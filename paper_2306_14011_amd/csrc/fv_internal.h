@@ -37,8 +37,10 @@ struct FGrid3 {
 
 void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t s);
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
-void launch_residual(const double* Fx, const double* Fy, const double* Fz, double* R, const Geo& g, int gang,
-                     int threads, hipStream_t s);
+void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
+                     int gang, int threads, hipStream_t s);
+// U[v][cell] += coef * dt * S[v][cell] over the interior cells (dt from device memory).
+void launch_source_add(double* U, const double* S, const double* dt, double coef, const Geo& g, hipStream_t s);
 void launch_update(int stage, const double* Un, const double* Us, double* Ud, const double* R, const double* dt,
                    const Geo& g, int gang, int threads, hipStream_t s);
 int cfl_blocks(const Geo& g, int gang, int threads);

@@ -162,12 +162,13 @@ __device__ __forceinline__ void decode_cell(int e, const Geo& g, int& i, int& j,
     j = (int)t - k * g.n[1];
 }
 
-// R[v][e] = sum_d (F_d[face e + e_d] - F_d[face e]) * area_d.
+// R[v][e] = sum_d (F_d[face e + e_d] - F_d[face e]) * area_d - |Omega| S[v][e]
+// (the source term of the residual; S null for none).
 template <int NDIM, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_residual(const double* __restrict__ Fx,
                                                    const double* __restrict__ Fy,
-                                                   const double* __restrict__ Fz, double* __restrict__ R,
-                                                   Geo g, int stride_all) {
+                                                   const double* __restrict__ Fz, const double* __restrict__ S,
+                                                   double* __restrict__ R, Geo g, int stride_all) {
     constexpr int NV = NDIM + 2;
     const int nx = g.n[0], ny = g.n[1];
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += stride_all) {
@@ -182,8 +183,26 @@ __global__ void __launch_bounds__(MAXT) k_residual(const double* __restrict__ Fx
             double r = (Fx[v * g.fsv[0] + fx + 1] - Fx[v * g.fsv[0] + fx]) * g.area[0];
             r += (Fy[v * g.fsv[1] + fy + nx] - Fy[v * g.fsv[1] + fy]) * g.area[1];
             if (NDIM == 3) r += (Fz[v * g.fsv[2] + fz + zs] - Fz[v * g.fsv[2] + fz]) * g.area[2];
+            if (S) r -= g.vol * S[(long long)v * g.ncell + e];
             R[(long long)v * g.ncell + e] = r;
         }
+    }
+}
+
+// The source term's share of a stage taken by the fused path, whose stage
+// kernels leave it out: U += coef dt S, with coef the stage's weight of
+// dt L (1, 1/4, 2/3).
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_source_add(double* __restrict__ U, const double* __restrict__ S,
+                                                    const double* __restrict__ dtp, double coef, Geo g) {
+    constexpr int NV = NDIM + 2;
+    const double c = coef * *dtp;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += gridDim.x * blockDim.x) {
+        int i, j, k;
+        decode_cell(e, g, i, j, k);
+        const int o = g.off0 + i + j * g.sy + k * g.sz;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U[v * g.sv + o] += c * S[(long long)v * g.ncell + e];
     }
 }
 
@@ -366,17 +385,25 @@ void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int t
     }
 }
 
-void launch_residual(const double* Fx, const double* Fy, const double* Fz, double* R, const Geo& g, int gang,
-                     int threads, hipStream_t s) {
+void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
+                     int gang, int threads, hipStream_t s) {
     int blocks, stride_all;
     grid1d(g.ncell, gang, threads, blocks, stride_all);
-#define FV_LR(T)                                                                                       \
-    if (g.ndim == 2)                                                                                   \
-        hipLaunchKernelGGL((k_residual<2, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, R, g, stride_all); \
-    else                                                                                               \
-        hipLaunchKernelGGL((k_residual<3, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, R, g, stride_all);
+#define FV_LR(T)                                                                                              \
+    if (g.ndim == 2)                                                                                          \
+        hipLaunchKernelGGL((k_residual<2, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, S, R, g, stride_all); \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_residual<3, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, S, R, g, stride_all);
     FV_DISPATCH_THREADS(threads, FV_LR)
 #undef FV_LR
+}
+
+void launch_source_add(double* U, const double* S, const double* dt, double coef, const Geo& g, hipStream_t s) {
+    const int blocks = blocks_for(g.ncell, 256) < 65536 ? blocks_for(g.ncell, 256) : 65536;
+    if (g.ndim == 2)
+        hipLaunchKernelGGL(k_source_add<2>, dim3(blocks), dim3(256), 0, s, U, S, dt, coef, g);
+    else
+        hipLaunchKernelGGL(k_source_add<3>, dim3(blocks), dim3(256), 0, s, U, S, dt, coef, g);
 }
 
 template <int STAGE>

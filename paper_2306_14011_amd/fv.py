@@ -156,6 +156,7 @@ def lib():
         L.fv_residual.argtypes = [_vp, _vp, _vp]
         L.fv_step.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
         L.fv_adjoint_step.argtypes = [_vp, _vp, _vp, _vp]
+        L.fv_set_source.argtypes = [_vp, _vp]
         L.fv_set_launch.argtypes = [_vp, ctypes.POINTER(fv_launch)]
         L.fv_get_launch.argtypes = [_vp, ctypes.POINTER(fv_launch)]
         L.fv_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
@@ -191,7 +192,7 @@ def lib():
         L.fv_mlp_sweep.argtypes = [_vp, ctypes.POINTER(fv_tune_space), ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
-                     "fv_adjoint_step", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
+                     "fv_adjoint_step", "fv_set_source", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
                      "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_batch_query", "fv_batch_create",
                      "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_set_schedule", "fv_batch_destroy",
                      "fv_mlp_workspace", "fv_mlp_sweep_workspace",
@@ -262,6 +263,10 @@ def fv_residual(ctx, U_ptr, R_ptr):
 
 def fv_step(ctx, U_ptr, nsteps, dt_in_ptr=None, dt_out_ptr=None):
     return _check(lib().fv_step(_vp(ctx), _vp(U_ptr), int(nsteps), _vp(dt_in_ptr), _vp(dt_out_ptr)), ctx)
+
+
+def fv_set_source(ctx, S_ptr):
+    return _check(lib().fv_set_source(_vp(ctx), _vp(S_ptr)), ctx)
 
 
 def fv_adjoint_step(ctx, U_ptr, dt_ptr, lam_ptr):
@@ -512,6 +517,22 @@ class Solver:
         R = self.dense_zeros()
         fv_residual(self.ctx, self.U.data_ptr(), R.data_ptr())
         return R
+
+    def set_source(self, S_dense):
+        """Cell-averaged source of Eq. (residual), shape (nvar, nz, ny, nx) or
+        any shape of nvar * ncell values in that order; None removes it. The
+        device copy is held by the solver while set."""
+        torch = _torch()
+        if S_dense is None:
+            fv_set_source(self.ctx, None)
+            self._source = None
+            return
+        S = torch.as_tensor(np.ascontiguousarray(S_dense) if not torch.is_tensor(S_dense) else S_dense,
+                            dtype=torch.float64).to(self.device).contiguous()
+        if S.numel() != self.nvar * int(np.prod([int(v) for v in self.spec.n])):
+            raise ValueError("source has the wrong number of cells or variables")
+        fv_set_source(self.ctx, S.data_ptr())
+        self._source = S
 
     def step(self, nsteps, dt_in=None, dt_out=None):
         fv_step(self.ctx, self.U.data_ptr(), nsteps,

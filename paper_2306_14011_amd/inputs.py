@@ -261,6 +261,29 @@ def random_directions(shape, count, seed, scales):
     return out
 
 
+def smooth_source(g: GridSpec, seed: int, amp: float = 0.05):
+    """Seeded smooth source field (nvar, nz, ny, nx): per variable, amp times a
+    sum of three sine modes of random integer wavenumbers and phases over the
+    cell centres of the box (periodic in every direction of the box)."""
+    rng = np.random.default_rng(seed + 7919)
+    nx, ny, nz = (int(v) for v in g.n)
+    axes = []
+    for d, m in enumerate((nx, ny, nz)):
+        c = (np.arange(m) + 0.5) / m
+        axes.append(c)
+    X = axes[0][None, None, :]
+    Y = axes[1][None, :, None]
+    Z = axes[2][:, None, None]
+    out = np.zeros((g.nvar, nz, ny, nx))
+    for v in range(g.nvar):
+        for _ in range(3):
+            kx, ky = rng.integers(1, 4, 2)
+            kz = rng.integers(1, 4) if g.ndim == 3 else 0
+            ph = rng.uniform(0.0, 2.0 * math.pi)
+            out[v] += np.sin(2.0 * math.pi * (kx * X + ky * Y + kz * Z) + ph)
+    return amp * out
+
+
 # ---------------------------------------------------------------------------
 # Random draws of the autotuner's network (passed to both the GPU kernels and
 # the oracle): initial parameters and the row order of every epoch.
