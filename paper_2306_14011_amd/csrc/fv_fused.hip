@@ -37,10 +37,10 @@ namespace fvk {
 // drops them. A conditional load or store would make the compiler's wait
 // counting assume the shortest path and wait for every outstanding access
 // (the prefetches included) at the top of each row.
-template <int STAGE, int LIM>
+template <int STAGE, int LIM, bool SRC>
 __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip, int r0, double s, const double* Un,
                                              const double* Us, double* Ud, double& lmax, uint32_t& fl, double ka,
-                                             double kb) {
+                                             double kb, const double* src) {
     constexpr bool UNL = LIM == 1;
     constexpr int NV = 4;
     const int seg = G.seg;
@@ -63,6 +63,12 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     const int ocol = col < FW * strip ? FW * strip : (col < olast ? col : olast);
     const uint32_t oboff = (uint32_t)ocol * 8u;
     const uint32_t sboff = out_lane ? (uint32_t)col * 8u : DROP_OFFSET;
+    // source term S[v][row][col] (dense interior layout), read at the U^n
+    // columns; its plane and the grid's state are below 4 GiB
+    const long long splane = (long long)G.nx * G.ny;
+    Rsrc rsrc;
+    if (SRC) rsrc = grid_rsrc(src, 4 * splane * 8);
+    const double vol = G.ax * G.ay;
     const uint32_t vstride = (uint32_t)(G.sv * 8);
     const double hax = 0.5 * G.ax, hay = 0.5 * G.ay;
     // byte offset of U_s row r through the y boundary map (rows past the
@@ -192,12 +198,19 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             const bool row_ok = rr < G.ny;  // uniform
             const uint32_t p = out_row(rr);
             const uint32_t so = row_ok ? sboff : DROP_OFFSET;
+            double Sv[NV];
+            if (SRC) {
+                const uint32_t ps = (uint32_t)((long long)(rr < G.ny ? rr : G.ny - 1) * G.nx * 8);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Sv[v] = ld_buf(rsrc, oboff, ps + (uint32_t)(v * splane * 8));
+            }
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 // the doubled fluxes against halved areas: the same products
                 double r = (Fxr[v] - Fxl[v]) * hax;
                 r += (Fy[t & 1][v] - Fy[(t + 1) & 1][v]) * hay;
+                if (SRC) r -= vol * Sv[v];  // R = flux sum - |Omega| S
                 if (STAGE == 0) {
                     out[v] = c[v] + s * r;
                 } else if (STAGE == 1) {
@@ -218,12 +231,13 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     }
 }
 
-template <int STAGE>
+template <int STAGE, bool SRC>
 __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems,
                                                  const double* Un, const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                  const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
-                                                 uint32_t* __restrict__ status, unsigned long long* __restrict__ clk) {
+                                                 uint32_t* __restrict__ status, unsigned long long* __restrict__ clk,
+                                                 const double* __restrict__ src) {
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int wave0 = __builtin_amdgcn_readfirstlane(
@@ -253,15 +267,15 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         double lmax = 0.0;
         uint32_t fl = 0;
         if (G.scheme == 0) {
-            fused2d_rows<STAGE, 0>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+            fused2d_rows<STAGE, 0, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
         } else if (G.scheme == 5) {
-            fused2d_rows<STAGE, 3>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+            fused2d_rows<STAGE, 3, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
         } else if (G.scheme == 1) {
-            fused2d_rows<STAGE, 1>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+            fused2d_rows<STAGE, 1, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
         } else {
             double ka, kb;
             kappa_weights(G.scheme, ka, kb);
-            fused2d_rows<STAGE, 2>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb);
+            fused2d_rows<STAGE, 2, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb, src);
         }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
@@ -331,19 +345,33 @@ static inline int fused_blocks(int nitems, int waves) {
     return (w + 3) / 4;
 }
 
+template <bool SRC>
+static void launch_fused_stage_t(int stage, dim3 grid, dim3 block, const FGrid* grids, int ngrids, int nitems,
+                                 const double* Un, const double* Us, double* Ud, unsigned long long* lam,
+                                 double* dtg, const double* dt_fixed, double* dt_out, uint32_t* status,
+                                 unsigned long long* clk, const double* src, hipStream_t s) {
+    if (stage == 0)
+        hipLaunchKernelGGL((k_fused2d<0, SRC>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
+                           dt_fixed, dt_out, status, clk, src);
+    else if (stage == 1)
+        hipLaunchKernelGGL((k_fused2d<1, SRC>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
+                           dt_fixed, dt_out, status, clk, src);
+    else
+        hipLaunchKernelGGL((k_fused2d<2, SRC>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
+                           dt_fixed, dt_out, status, clk, src);
+}
+
 void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
-                        double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s) {
+                        double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s,
+                        const double* src) {
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
-    if (stage == 0)
-        hipLaunchKernelGGL(k_fused2d<0>, grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
-                           dt_fixed, dt_out, status, clk);
-    else if (stage == 1)
-        hipLaunchKernelGGL(k_fused2d<1>, grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
-                           dt_fixed, dt_out, status, clk);
+    if (src)
+        launch_fused_stage_t<true>(stage, grid, block, grids, ngrids, nitems, Un, Us, Ud, lam, dtg, dt_fixed,
+                                   dt_out, status, clk, src, s);
     else
-        hipLaunchKernelGGL(k_fused2d<2>, grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
-                           dt_fixed, dt_out, status, clk);
+        launch_fused_stage_t<false>(stage, grid, block, grids, ngrids, nitems, Un, Us, Ud, lam, dtg, dt_fixed,
+                                    dt_out, status, clk, nullptr, s);
 }
 
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
@@ -360,9 +388,9 @@ int fused_slots() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int b0 = 0, b1 = 0, b2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused2d<0>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused2d<1>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused2d<2>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused2d<0, false>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused2d<1, false>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused2d<2, false>, 256, 0) != hipSuccess)
         return 0;
     const int b = b0 < b1 ? (b0 < b2 ? b0 : b2) : (b1 < b2 ? b1 : b2);
     return b * 4 * cus;

@@ -53,7 +53,8 @@ int fused_items(const FGrid& G, int seg);  // work items of G at segment height 
 int fused_strips(int nx);
 void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
-                        double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s);
+                        double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s,
+                        const double* src = nullptr);
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, hipStream_t s);
 int fused_slots();
