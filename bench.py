@@ -281,22 +281,24 @@ def schemes_leg(torch, fv, traffic, g, U0, steps):
 
 def source_leg(torch, fv, inputs, g, U0, steps):
     """The headline workload with a cell-averaged source term (the seeded
-    smooth field of inputs.smooth_source) on both paths: the split path folds
-    it into the residual kernel (|Omega| S read once per stage), the fused path
-    adds each stage's share in a pass after the stage kernel and takes the
-    step's wave speed again."""
-    S = inputs.smooth_source(g, 1)
-    out = {"workload": "2048x2048 vortex + bumps with a smooth source (amplitude 0.05)"}
-    for path in ("fused", "split"):
-        s = fv.Solver(g)
+    smooth field of inputs.smooth_source) on both paths, and the 256^3 Sod
+    workload on the fused path: the split path folds S into the residual
+    kernel, the fused stage kernels read it with the state (|Omega| S once
+    per cell and stage either way)."""
+    out = {"workload": "2048x2048 vortex + bumps, and 256^3 tilted Sod, with a smooth source (amplitude 0.05)"}
+    g3, U3 = inputs.sod3d_case(256, seed=0)
+    for key, gg, UU, path in (("fused", g, U0, "fused"), ("split", g, U0, "split"), ("fused_3d", g3, U3, "fused")):
+        S = inputs.smooth_source(gg, 1)
+        s = fv.Solver(gg)
         if path == "fused":
             s.set_path(fv.FV_PATH_FUSED, 0, 0)
-        base = timed_steps(torch, s, U0, steps, 5)
+        n = steps if gg.ndim == 2 else max(steps // 5, 5)
+        base = timed_steps(torch, s, UU, n, 2)
         s.set_source(S)
-        ms = timed_steps(torch, s, U0, steps, 5)
+        ms = timed_steps(torch, s, UU, n, 2)
         s.close()
-        out[path] = {"ms_per_step": round(ms, 4), "no_source_ms_per_step": round(base, 4),
-                     "value": g.ncells / (ms * 1e-3), "over_no_source": round(ms / base, 3)}
+        out[key] = {"ms_per_step": round(ms, 4), "no_source_ms_per_step": round(base, 4),
+                    "value": gg.ncells / (ms * 1e-3), "over_no_source": round(ms / base, 3)}
     return out
 
 
@@ -569,7 +571,8 @@ def main():
         log("schemes (fused 2D): " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in out["schemes"].items()))
         out["source"] = source_leg(torch, fv, inputs, g, U0, 50)
         log("source term: " + ", ".join(f"{p} {out['source'][p]['ms_per_step']:.4f} ms "
-                                        f"({out['source'][p]['over_no_source']:.3f}x)" for p in ("fused", "split")))
+                                        f"({out['source'][p]['over_no_source']:.3f}x)"
+                                        for p in ("fused", "split", "fused_3d")))
         if not a.no_tune and not a.no_3d:
             out["sized_tuner"] = sized_leg(torch, inputs, a.seed, a.samples)
             sz = out["sized_tuner"]

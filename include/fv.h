@@ -154,11 +154,9 @@ int fv_residual(fv_ctx* ctx, double* U, double* R);
  * and unchanged while it is set: fv_residual, fv_step (both paths) and
  * fv_adjoint_step read it on the device. The source does not depend on U, so
  * the adjoint's transposed Jacobian is unchanged; its recomputed stage states
- * include it. The 2D fused stage kernels read S with the state (a kernel
- * instantiation of its own, so the source-free kernels are unchanged); on
- * the 3D fused path each stage's share (1, 1/4, 2/3 times dt S) is added by
- * a pass after the stage kernel and the wave speed of the step's result is
- * then taken again. Only a null context is rejected. */
+ * include it. The fused stage kernels (2D and 3D) read S with the state, in
+ * kernel instantiations of their own, so the source-free kernels are
+ * unchanged. Only a null context is rejected. */
 int fv_set_source(fv_ctx* ctx, const double* S);
 
 /* Advances U (ghosted layout, in place) by nsteps SSP-RK3 steps:

@@ -419,25 +419,17 @@ static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(0, c->fwaves, G, c->fitems, U, U, c->U1, c->flam, c->fdt,
                                       dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status,
-                                      c->stream);
+                                      c->stream, c->src, c->g.vol);
         }
-        if (c->src) fvk::launch_source_add(c->U1, c->src, c->fdt, 1.0, c->g, c->stream);
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(1, c->fwaves, G, c->fitems, U, c->U1, c->U2, c->flam, c->fdt, nullptr,
-                                      nullptr, c->status, c->stream);
+                                      nullptr, c->status, c->stream, c->src, c->g.vol);
         }
-        if (c->src) fvk::launch_source_add(c->U2, c->src, c->fdt, 0.25, c->g, c->stream);
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(2, c->fwaves, G, c->fitems, U, c->U2, U, c->flam, c->fdt, nullptr, nullptr,
-                                      c->status, c->stream);
-        }
-        if (c->src) {
-            // the stage kernel's wave speed is that of the state before the
-            // source's share: take it again from the step's result
-            fvk::launch_source_add(U, c->src, c->fdt, 2.0 / 3.0, c->g, c->stream);
-            fvk::launch_fused3d_init(c->fwaves, G, c->fitems, U, c->flam, c->status, c->stream);
+                                      c->status, c->stream, c->src, c->g.vol);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;

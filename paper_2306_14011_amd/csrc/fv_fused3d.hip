@@ -49,10 +49,10 @@ __device__ __forceinline__ void zface_states(double q0, double q1, double q2, do
 // 2D, no memory access sits on a conditional path: loads are issued for
 // every face (clamped indices), and stores of lanes or planes without output
 // go past the end of a per-variable descriptor, where they are dropped.
-template <int STAGE, int LIM>
+template <int STAGE, int LIM, bool SRC>
 __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int strip, int j, int k0, double s,
                                                const double* Un, const double* Us, double* Ud, double& lmax,
-                                               uint32_t& fl, double ka, double kb) {
+                                               uint32_t& fl, double ka, double kb, const double* src, double vol) {
     constexpr bool UNL = LIM == 1;
     constexpr int NV = 5;
     const int col = FW * strip - 2 + lane;
@@ -78,6 +78,11 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
     const uint32_t vstride = (uint32_t)(G.sv * 8);
     const uint32_t jo = (uint32_t)((long long)j * G.py * 8);
     const double hax = 0.5 * G.ax, hay = 0.5 * G.ay, haz = 0.5 * G.az;
+    // source term S[v][k][j][i] (dense interior layout), read at the U^n
+    // columns of row j; it is smaller than the grid's state (below 4 GiB)
+    const long long svol = (long long)G.nx * G.ny * G.nz;
+    Rsrc rsrc;
+    if (SRC) rsrc = grid_rsrc(src, NV * svol * 8);
     // byte offsets of rows j-2 .. j+2 and of plane kk through the boundary maps
     uint32_t ro[5];
 #pragma unroll
@@ -198,6 +203,13 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
             const bool plane_ok = kk < G.nz;  // uniform
             const uint32_t p = out_plane(kk);
             const uint32_t so = plane_ok ? sboff : DROP_OFFSET;
+            double Sv[NV];
+            if (SRC) {
+                const uint32_t ps =
+                    (uint32_t)((((long long)(kk < G.nz ? kk : G.nz - 1)) * G.ny + j) * G.nx * 8);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Sv[v] = ld_buf(rsrc, oboff, ps + (uint32_t)(v * svol * 8));
+            }
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -205,6 +217,7 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
                 double r = (Fxr[v] - Fxl[v]) * hax;
                 r += (Fyt[v] - Fyb[v]) * hay;
                 r += (Fz[t & 1][v] - Fz[(t + 1) & 1][v]) * haz;
+                if (SRC) r -= vol * Sv[v];  // R = flux sum - |Omega| S
                 if (STAGE == 0) {
                     out[v] = c[v] + s * r;
                 } else if (STAGE == 1) {
@@ -224,12 +237,13 @@ __device__ __forceinline__ void fused3d_planes(const FGrid3& G, int lane, int st
     }
 }
 
-template <int STAGE>
+template <int STAGE, bool SRC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
                                                  const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                  const double* __restrict__ dt_fixed, double* __restrict__ dt_out,
-                                                 uint32_t* __restrict__ status) {
+                                                 uint32_t* __restrict__ status, const double* __restrict__ src,
+                                                 double vol) {
     const int lane = threadIdx.x & 63;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int wave0 = __builtin_amdgcn_readfirstlane(
@@ -256,15 +270,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         double lmax = 0.0;
         uint32_t fl = 0;
         if (G.scheme == 0) {
-            fused3d_planes<STAGE, 0>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+            fused3d_planes<STAGE, 0, SRC>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
         } else if (G.scheme == 5) {
-            fused3d_planes<STAGE, 3>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+            fused3d_planes<STAGE, 3, SRC>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
         } else if (G.scheme == 1) {
-            fused3d_planes<STAGE, 1>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0);
+            fused3d_planes<STAGE, 1, SRC>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
         } else {
             double ka, kb;
             kappa_weights(G.scheme, ka, kb);
-            fused3d_planes<STAGE, 2>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb);
+            fused3d_planes<STAGE, 2, SRC>(G, lane, strip, j, zs * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb, src, vol);
         }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
@@ -326,16 +340,32 @@ static inline int blocks_for(int nitems, int waves) {
     return (w + 3) / 4;
 }
 
+template <bool SRC>
+static void launch_fused3d_stage_t(int stage, dim3 g, dim3 b, const FGrid3* grid, int nitems, const double* Un,
+                                   const double* Us, double* Ud, unsigned long long* lam, double* dtg,
+                                   const double* dt_fixed, double* dt_out, uint32_t* status, const double* src,
+                                   double vol, hipStream_t s) {
+    if (stage == 0)
+        hipLaunchKernelGGL((k_fused3d<0, SRC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+                           status, src, vol);
+    else if (stage == 1)
+        hipLaunchKernelGGL((k_fused3d<1, SRC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+                           status, src, vol);
+    else
+        hipLaunchKernelGGL((k_fused3d<2, SRC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+                           status, src, vol);
+}
+
 void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
                           double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed, double* dt_out,
-                          uint32_t* status, hipStream_t s) {
+                          uint32_t* status, hipStream_t s, const double* src, double vol) {
     const dim3 g(blocks_for(nitems, waves)), b(256);
-    if (stage == 0)
-        hipLaunchKernelGGL(k_fused3d<0>, g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status);
-    else if (stage == 1)
-        hipLaunchKernelGGL(k_fused3d<1>, g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status);
+    if (src)
+        launch_fused3d_stage_t<true>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status, src,
+                                     vol, s);
     else
-        hipLaunchKernelGGL(k_fused3d<2>, g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status);
+        launch_fused3d_stage_t<false>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status,
+                                      nullptr, 0.0, s);
 }
 
 void launch_fused3d_init(int waves, const FGrid3* grid, int nitems, const double* U, unsigned long long* lam,
@@ -350,9 +380,9 @@ int fused3d_slots() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int b0 = 0, b1 = 0, b2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused3d<0>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused3d<1>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused3d<2>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused3d<0, false>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused3d<1, false>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused3d<2, false>, 256, 0) != hipSuccess)
         return 0;
     const int bmin = b0 < b1 ? (b0 < b2 ? b0 : b2) : (b1 < b2 ? b1 : b2);
     return bmin * 4 * cus;

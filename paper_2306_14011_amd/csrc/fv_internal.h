@@ -39,8 +39,6 @@ void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t 
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
                      int gang, int threads, hipStream_t s);
-// U[v][cell] += coef * dt * S[v][cell] over the interior cells (dt from device memory).
-void launch_source_add(double* U, const double* S, const double* dt, double coef, const Geo& g, hipStream_t s);
 void launch_update(int stage, const double* Un, const double* Us, double* Ud, const double* R, const double* dt,
                    const Geo& g, int gang, int threads, hipStream_t s);
 int cfl_blocks(const Geo& g, int gang, int threads);
@@ -61,7 +59,7 @@ int fused_slots();
 int fused3d_items(const FGrid3& G, int seg);
 void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
                           double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed, double* dt_out,
-                          uint32_t* status, hipStream_t s);
+                          uint32_t* status, hipStream_t s, const double* src = nullptr, double vol = 0.0);
 void launch_fused3d_init(int waves, const FGrid3* grid, int nitems, const double* U, unsigned long long* lam,
                          uint32_t* status, hipStream_t s);
 int fused3d_slots();

@@ -189,23 +189,6 @@ __global__ void __launch_bounds__(MAXT) k_residual(const double* __restrict__ Fx
     }
 }
 
-// The source term's share of a stage taken by the fused path, whose stage
-// kernels leave it out: U += coef dt S, with coef the stage's weight of
-// dt L (1, 1/4, 2/3).
-template <int NDIM>
-__global__ void __launch_bounds__(256) k_source_add(double* __restrict__ U, const double* __restrict__ S,
-                                                    const double* __restrict__ dtp, double coef, Geo g) {
-    constexpr int NV = NDIM + 2;
-    const double c = coef * *dtp;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += gridDim.x * blockDim.x) {
-        int i, j, k;
-        decode_cell(e, g, i, j, k);
-        const int o = g.off0 + i + j * g.sy + k * g.sz;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) U[v * g.sv + o] += c * S[(long long)v * g.ncell + e];
-    }
-}
-
 // SSP-RK3 stage update with L = -R / |Omega| and dt read from device memory.
 //   STAGE 0: Ud = Un + dt L
 //   STAGE 1: Ud = 3/4 Un + 1/4 (Us + dt L)          (Ud may alias Us)
@@ -396,14 +379,6 @@ void launch_residual(const double* Fx, const double* Fy, const double* Fz, const
         hipLaunchKernelGGL((k_residual<3, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, S, R, g, stride_all);
     FV_DISPATCH_THREADS(threads, FV_LR)
 #undef FV_LR
-}
-
-void launch_source_add(double* U, const double* S, const double* dt, double coef, const Geo& g, hipStream_t s) {
-    const int blocks = blocks_for(g.ncell, 256) < 65536 ? blocks_for(g.ncell, 256) : 65536;
-    if (g.ndim == 2)
-        hipLaunchKernelGGL(k_source_add<2>, dim3(blocks), dim3(256), 0, s, U, S, dt, coef, g);
-    else
-        hipLaunchKernelGGL(k_source_add<3>, dim3(blocks), dim3(256), 0, s, U, S, dt, coef, g);
 }
 
 template <int STAGE>
