@@ -23,8 +23,9 @@
 // Layout: interior cells only, U[v][k][j][i], v over (rho, rho u, rho v,
 // [rho w], E). Boundary conditions are index maps: a periodic face wraps the
 // index, a transmissive face clamps it to the nearest interior cell (a
-// zero-gradient ghost state). Two ghost layers are implied by the 4-cell
-// MUSCL stencil.
+// zero-gradient ghost state), a slip wall reflects it across the face and
+// reverses the momentum normal to the wall (the mirror image). Two ghost
+// layers are implied by the 4-cell MUSCL stencil.
 //
 // Every routine is a template over the scalar type so that the same code runs
 // on std::complex<double> for complex-step derivatives (Squire & Trapp 1998):
@@ -47,7 +48,7 @@ struct OrGrid {
     int32_t limiter;    // 1 = minmod, 2 = van Leer, 0 = unlimited (Psi = 1)
     int64_t n[3];       // cells per axis (n[2] = 1 in 2D)
     double dx[3];       // cell widths
-    int32_t bc[3][2];   // 0 = periodic, 1 = transmissive, per axis and side
+    int32_t bc[3][2];   // 0 = periodic, 1 = transmissive, 2 = slip wall, per axis and side
     double gamma;       // ratio of specific heats
     double cfl;         // CFL number for the stable time step
     double kappa;       // MUSCL kappa (-1 on the measured path)
@@ -225,13 +226,23 @@ static void roe_flux(int ndim, int ax, double gam, const T* QL, const T* QR, T* 
 static inline int64_t bc_index(int64_t i, int64_t n, int lo_kind, int hi_kind) {
     if (i < 0) {
         if (lo_kind == 0) return ((i % n) + n) % n;
+        if (lo_kind == 2) return -1 - i;  // mirror image across the face
         return 0;
     }
     if (i >= n) {
         if (hi_kind == 0) return i % n;
+        if (hi_kind == 2) return 2 * n - 1 - i;
         return n - 1;
     }
     return i;
+}
+
+// -1 for the normal momentum of a ghost position behind a slip wall (the
+// mirror image's velocity normal to the wall is reversed), else +1.
+static inline double bc_sign(int64_t i, int64_t n, int lo_kind, int hi_kind, int v, int ax) {
+    if (v != 1 + ax) return 1.0;
+    if ((i < 0 && lo_kind == 2) || (i >= n && hi_kind == 2)) return -1.0;
+    return 1.0;
 }
 
 static inline int64_t cell_offset(const OrGrid* g, int64_t i, int64_t j, int64_t k) {
@@ -244,17 +255,19 @@ static void face_flux(const OrGrid* g, const T* U, int ax, int64_t i, int64_t j,
     const int nv = g->ndim + 2;
     const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
     int64_t idx[3] = {i, j, k};
-    int64_t off[4];
+    int64_t off[4], pos[4];
     for (int m = 0; m < 4; ++m) {
         int64_t c[3] = {idx[0], idx[1], idx[2]};
-        c[ax] = idx[ax] - 1 + m;  // cells k-1, k, k+1, k+2 along the axis
-        c[ax] = bc_index(c[ax], g->n[ax], g->bc[ax][0], g->bc[ax][1]);
+        pos[m] = idx[ax] - 1 + m;  // cells k-1, k, k+1, k+2 along the axis
+        c[ax] = bc_index(pos[m], g->n[ax], g->bc[ax][0], g->bc[ax][1]);
         off[m] = cell_offset(g, c[0], c[1], c[2]);
     }
     T QL[5], QR[5];
     for (int v = 0; v < nv; ++v) {
         const T* Uv = U + v * ncell;
-        muscl(Uv[off[0]], Uv[off[1]], Uv[off[2]], Uv[off[3]], g->limiter, g->kappa, QL[v], QR[v]);
+        T q[4];
+        for (int m = 0; m < 4; ++m) q[m] = Uv[off[m]] * bc_sign(pos[m], g->n[ax], g->bc[ax][0], g->bc[ax][1], v, ax);
+        muscl(q[0], q[1], q[2], q[3], g->limiter, g->kappa, QL[v], QR[v]);
     }
     roe_flux(g->ndim, ax, g->gamma, QL, QR, F);
 }
@@ -441,6 +454,11 @@ void or_residual_vjp(const OrGrid* g, const double* U, const double* w, double* 
                             c2[ax] = bc_index(lo - 1 + m, n, g->bc[ax][0], g->bc[ax][1]);
                             off[m] = cell_offset(g, c2[0], c2[1], c2[2]);
                         }
+                        // slot value = sign * cell value (the wall's mirror reverses the
+                        // normal momentum), so the cell's derivative is sign * the slot's
+                        auto sgn = [&](int m, int v) {
+                            return bc_sign(lo - 1 + m, n, g->bc[ax][0], g->bc[ax][1], v, ax);
+                        };
                         // perturb one stencil entry (slot m, variable v) at a time
                         for (int m = 0; m < 4; ++m)
                             for (int v = 0; v < nv; ++v) {
@@ -448,7 +466,7 @@ void or_residual_vjp(const OrGrid* g, const double* U, const double* w, double* 
                                 // still its own input of the face flux; perturb the slot, not the cell
                                 cplx Q[4][5];
                                 for (int mm = 0; mm < 4; ++mm)
-                                    for (int vv = 0; vv < nv; ++vv) Q[mm][vv] = Uc[vv * ncell + off[mm]];
+                                    for (int vv = 0; vv < nv; ++vv) Q[mm][vv] = Uc[vv * ncell + off[mm]] * sgn(mm, vv);
                                 Q[m][v] += cplx(0.0, h);
                                 cplx QL[5], QR[5], F[5];
                                 for (int vv = 0; vv < nv; ++vv)
@@ -456,7 +474,7 @@ void or_residual_vjp(const OrGrid* g, const double* U, const double* w, double* 
                                 roe_flux(g->ndim, ax, g->gamma, QL, QR, F);
                                 double dot = 0.0;
                                 for (int vv = 0; vv < nv; ++vv) dot += F[vv].imag() / h * Fb[vv];
-                                mu[v * ncell + off[m]] += dot;
+                                mu[v * ncell + off[m]] += sgn(m, v) * dot;
                             }
                     }
                 }
