@@ -55,7 +55,14 @@ enum {
     FV_EWORKSPACE = -5   /* workspace missing, too small or misaligned */
 };
 
-enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1 };
+/* Boundary kinds per axis side. FV_BC_WALL is an inviscid slip wall (the
+ * inlet walls of the paper's test case, Sec. "A Test Case"): the ghost cells
+ * are the mirror image of the interior across the face with the velocity
+ * normal to the wall reversed, so no mass or energy crosses it. It needs at
+ * least 2 cells on its axis and runs on the split path (fv_residual, fv_step,
+ * fv_adjoint_step); the fused path and batches return FV_ENOTSUP / FV_EINVAL
+ * for it. */
+enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1, FV_BC_WALL = 2 };
 
 /* Status-word bits (set by the time-step reduction over the state). */
 enum { FV_FLAG_NAN = 1u, FV_FLAG_RHO = 2u, FV_FLAG_P = 4u, FV_FLAG_DT = 8u };

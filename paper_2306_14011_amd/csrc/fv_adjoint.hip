@@ -69,9 +69,10 @@ __global__ void __launch_bounds__(MAXT) k_adj_flux(const double* __restrict__ U,
 // Sum over the faces of axis `ax` whose stencil holds position x of the axis:
 // face f has cells f-2, f-1, f, f+1 at slots 0..3, so position x is slot m of
 // face x + 2 - m. Ghost positions -2, -1, n, n+1 add their slots to the
-// interior cell they copy.
+// interior cell they copy; behind a slip wall the copy is the mirror image,
+// times wsign (-1 for the momentum normal to the wall, else 1).
 __device__ __forceinline__ double gather_axis(const double* __restrict__ Gv, long long ms, int x, int n, int lo_kind,
-                                              int hi_kind, long long fbase, long long fstride) {
+                                              int hi_kind, long long fbase, long long fstride, double wsign) {
     double acc = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -84,12 +85,13 @@ __device__ __forceinline__ double gather_axis(const double* __restrict__ Gv, lon
         const int gp = gi < 2 ? gi - 2 : n + gi - 2;  // -2, -1, n, n+1
         const bool lo = gi < 2;
         const int kind = lo ? lo_kind : hi_kind;
-        const int src = kind == 0 ? ((gp % n) + n) % n : (lo ? 0 : n - 1);
+        const int src = kind == 0 ? ((gp % n) + n) % n : kind == 2 ? (lo ? -1 - gp : 2 * n - 1 - gp) : (lo ? 0 : n - 1);
         if (src != x) continue;
+        const double sg = kind == 2 ? wsign : 1.0;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int f = gp + 2 - m;
-            if (f >= 0 && f <= n) acc += Gv[m * ms + fbase + f * fstride];
+            if (f >= 0 && f <= n) acc += sg * Gv[m * ms + fbase + f * fstride];
         }
     }
     return acc;
@@ -113,11 +115,13 @@ __global__ void __launch_bounds__(MAXT) k_adj_gather(const double* __restrict__ 
         const long long bz = (long long)j * nx + i;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double acc = gather_axis(Gx + v * g.fsv[0], (long long)NV * g.fsv[0], i, nx, g.bc[0][0], g.bc[0][1], bx, 1);
-            acc += gather_axis(Gy + v * g.fsv[1], (long long)NV * g.fsv[1], j, ny, g.bc[1][0], g.bc[1][1], by, nx);
+            double acc = gather_axis(Gx + v * g.fsv[0], (long long)NV * g.fsv[0], i, nx, g.bc[0][0], g.bc[0][1], bx, 1,
+                                     v == 1 ? -1.0 : 1.0);
+            acc += gather_axis(Gy + v * g.fsv[1], (long long)NV * g.fsv[1], j, ny, g.bc[1][0], g.bc[1][1], by, nx,
+                               v == 2 ? -1.0 : 1.0);
             if (NDIM == 3)
                 acc += gather_axis(Gz + v * g.fsv[2], (long long)NV * g.fsv[2], k, nz, g.bc[2][0], g.bc[2][1], bz,
-                                   (long long)nx * ny);
+                                   (long long)nx * ny, v == 3 ? -1.0 : 1.0);
             mu[(long long)v * g.ncell + e] = acc;
         }
     }

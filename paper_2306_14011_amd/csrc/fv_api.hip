@@ -99,11 +99,16 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
             snprintf(why, 256, "hi must exceed lo on every axis");
             return FV_EINVAL;
         }
-        for (int s = 0; s < 2; ++s)
-            if (g->bc[d][s] != FV_BC_PERIODIC && g->bc[d][s] != FV_BC_TRANSMISSIVE) {
+        for (int s = 0; s < 2; ++s) {
+            if (g->bc[d][s] != FV_BC_PERIODIC && g->bc[d][s] != FV_BC_TRANSMISSIVE && g->bc[d][s] != FV_BC_WALL) {
                 snprintf(why, 256, "unknown boundary kind");
                 return FV_EINVAL;
             }
+            if (g->bc[d][s] == FV_BC_WALL && g->n[d] < 2) {
+                snprintf(why, 256, "a slip wall needs at least 2 cells on its axis");
+                return FV_EINVAL;
+            }
+        }
         if ((g->bc[d][0] == FV_BC_PERIODIC) != (g->bc[d][1] == FV_BC_PERIODIC)) {
             snprintf(why, 256, "periodic must be set on both faces of an axis");
             return FV_EINVAL;
@@ -475,6 +480,9 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         return FV_OK;
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
+    for (int d = 0; d < c->g.ndim; ++d)
+        if (c->g.bc[d][0] == FV_BC_WALL || c->g.bc[d][1] == FV_BC_WALL)
+            return fail(c, FV_ENOTSUP, "slip walls run on the split path only%s");
     if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
         return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
     if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))

@@ -14,7 +14,8 @@ namespace fvk {
 // Ghost fill. Element e enumerates, axis by axis, the 4 ghost layers
 // (-2, -1, n, n+1) times the interior cross-section of that axis; layer is the
 // fastest index. Periodic faces copy the opposite interior layers,
-// transmissive faces copy the nearest interior cell (zero gradient).
+// transmissive faces copy the nearest interior cell (zero gradient), slip
+// walls the mirror image across the face with the normal momentum reversed.
 template <int NV>
 __global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g, int total, int seg0,
                                                    int seg1, int stride_all) {
@@ -50,6 +51,8 @@ __global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g,
         const int kind = g.bc[ax][lo ? 0 : 1];
         if (kind == 0) {
             src = ((gpos % n) + n) % n;
+        } else if (kind == 2) {
+            src = lo ? -1 - gpos : 2 * n - 1 - gpos;
         } else {
             src = lo ? 0 : n - 1;
         }
@@ -64,7 +67,10 @@ __global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g,
         const int og = g.off0 + cg[0] + cg[1] * g.sy + cg[2] * g.sz;
         const int os = g.off0 + cs[0] + cs[1] * g.sy + cs[2] * g.sz;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v * g.sv + og] = U[v * g.sv + os];
+        for (int v = 0; v < NV; ++v) {
+            const double q = U[v * g.sv + os];
+            U[v * g.sv + og] = (kind == 2 && v == 1 + ax) ? -q : q;
+        }
     }
 }
 

@@ -56,6 +56,7 @@ def scheme_of(spec):
 
 FV_BC_PERIODIC = 0
 FV_BC_TRANSMISSIVE = 1
+FV_BC_WALL = 2
 
 FV_FLAG_NAN = 1
 FV_FLAG_RHO = 2

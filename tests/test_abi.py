@@ -169,3 +169,13 @@ def test_mlp_entry_points_reject_other_input_widths():
         assert L.fv_mlp_sweep(p, sp, 0, 1, 1, p, p, p, 1 << 30, None) == fv.FV_EINVAL
     assert fv.fv_mlp_nparam(fv.FV_MLP_IN) == fv.FV_MLP_NPARAM
     assert fv.fv_mlp_nparam(fv.FV_MLP_IN_SIZED) == fv.FV_MLP_NPARAM_SIZED
+
+
+def test_slip_walls_accepted_with_two_cells_or_more():
+    W = fv.FV_BC_WALL
+    fv.fv_query(fv.make_desc(inputs.grid2d(16, 2, bc=((W, W), (W, W)))))
+    fv.fv_query(fv.make_desc(inputs.grid2d(16, 9, bc=((W, fv.FV_BC_TRANSMISSIVE), (0, 0)))))
+    for g in (inputs.grid2d(16, 1, bc=((0, 0), (W, W))), inputs.grid2d(16, 9, bc=((3, W), (0, 0)))):
+        with pytest.raises(fv.FvError) as e:
+            fv.fv_query(fv.make_desc(g))
+        assert e.value.code == fv.FV_EINVAL
