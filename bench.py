@@ -302,6 +302,28 @@ def source_leg(torch, fv, inputs, g, U0, steps):
     return out
 
 
+def walls_leg(torch, fv, inputs, steps):
+    """A closed 2048^2 box (slip walls on all four sides) with a smooth
+    pressure pulse on the split path, against the same grid periodic: the
+    walls change only the ghost fill."""
+    import numpy as np
+    out = {"workload": "2048x2048 closed box, slip walls, pressure pulse, split path, default launch"}
+    n = 2048
+    for key, kind in (("walls", fv.FV_BC_WALL), ("periodic", fv.FV_BC_PERIODIC)):
+        g = inputs.grid2d(n, n, hi=(1.0, 1.0), bc=((kind, kind), (kind, kind)))
+        x = (np.arange(n) + 0.5) / n
+        X, Y = np.meshgrid(x, x)
+        b = np.exp(-((X - 0.4) ** 2 + (Y - 0.55) ** 2) / 0.01)
+        U0 = inputs.primitive_to_conserved(g, (1.0 + 0.3 * b)[None], (np.zeros((1, n, n)),) * 2,
+                                           (1.0 + 0.5 * b)[None])
+        s = fv.Solver(g)
+        ms = timed_steps(torch, s, U0, steps, 3)
+        s.close()
+        out[key] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3)}
+    out["walls_over_periodic"] = round(out["walls"]["ms_per_step"] / out["periodic"]["ms_per_step"], 3)
+    return out
+
+
 def small_leg(torch, fv, inputs):
     """64^2 vortex (launch-bound): split and fused by direct launches, fused as a
     graph-replayed batch of one."""
@@ -573,6 +595,9 @@ def main():
         log("source term: " + ", ".join(f"{p} {out['source'][p]['ms_per_step']:.4f} ms "
                                         f"({out['source'][p]['over_no_source']:.3f}x)"
                                         for p in ("fused", "split", "fused_3d")))
+        out["walls"] = walls_leg(torch, fv, inputs, 50)
+        log(f"slip walls (split 2048^2): {out['walls']['walls']['ms_per_step']:.4f} ms/step, "
+            f"{out['walls']['walls_over_periodic']:.3f}x the periodic grid")
         if not a.no_tune and not a.no_3d:
             out["sized_tuner"] = sized_leg(torch, inputs, a.seed, a.samples)
             sz = out["sized_tuner"]
