@@ -56,7 +56,8 @@ enum {
 };
 
 /* Boundary kinds per axis side. FV_BC_WALL is an inviscid slip wall (the
- * inlet walls of the paper's test case, Sec. "A Test Case"): the ghost cells
+ * reading for the solid boundaries of the supersonic inlet of Sec. "A Test
+ * Case"): the ghost cells
  * are the mirror image of the interior across the face with the velocity
  * normal to the wall reversed, so no mass or energy crosses it. It needs at
  * least 2 cells on its axis and runs on the split path (fv_residual, fv_step,

@@ -1,5 +1,5 @@
-"""Pins of the oracle's slip wall (the inlet walls of the paper's test case,
-Sec. "A Test Case", Table boundary_conditions): a closed box conserves mass
+"""Pins of the oracle's slip wall (the reading for the solid boundaries of the
+supersonic inlet of Sec. "A Test Case"): a closed box conserves mass
 and energy exactly, a box at rest stays at rest, mirror-symmetric states stay
 symmetric, and a walled grid equals the periodic grid of twice the size that
 holds the state and its mirror image."""
