@@ -39,6 +39,7 @@ class OrGrid(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("kappa", ctypes.c_double),
         ("source", ctypes.c_void_p),
+        ("bc_state", ((ctypes.c_double * 5) * 2) * 3),
     ]
 
 
@@ -116,6 +117,13 @@ def make_grid(spec, limiter=True, kappa=-1.0, source=None):
     g.gamma = float(spec.gamma)
     g.cfl = float(spec.cfl)
     g.kappa = float(kappa)
+    st = getattr(spec, "bc_state", None)
+    if st is not None:
+        st = np.asarray(st, dtype=np.float64)
+        for a in range(3):
+            for sd in range(2):
+                for v in range(min(5, st.shape[2])):
+                    g.bc_state[a][sd][v] = float(st[a, sd, v])
     return g
 
 

@@ -24,8 +24,10 @@
 // [rho w], E). Boundary conditions are index maps: a periodic face wraps the
 // index, a transmissive face clamps it to the nearest interior cell (a
 // zero-gradient ghost state), a slip wall reflects it across the face and
-// reverses the momentum normal to the wall (the mirror image). Two ghost
-// layers are implied by the 4-cell MUSCL stencil.
+// reverses the momentum normal to the wall (the mirror image), and an inflow
+// face holds a given state in its ghost cells (supersonic inflow: every
+// characteristic enters). Two ghost layers are implied by the 4-cell MUSCL
+// stencil.
 //
 // Every routine is a template over the scalar type so that the same code runs
 // on std::complex<double> for complex-step derivatives (Squire & Trapp 1998):
@@ -48,11 +50,12 @@ struct OrGrid {
     int32_t limiter;    // 1 = minmod, 2 = van Leer, 0 = unlimited (Psi = 1)
     int64_t n[3];       // cells per axis (n[2] = 1 in 2D)
     double dx[3];       // cell widths
-    int32_t bc[3][2];   // 0 = periodic, 1 = transmissive, 2 = slip wall, per axis and side
+    int32_t bc[3][2];   // 0 = periodic, 1 = transmissive, 2 = slip wall, 3 = inflow, per axis and side
     double gamma;       // ratio of specific heats
     double cfl;         // CFL number for the stable time step
     double kappa;       // MUSCL kappa (-1 on the measured path)
     const double* source;  // cell-averaged source S[v][k][j][i], or null for S = 0
+    double bc_state[3][2][5];  // conserved state of the ghost cells of an inflow face
 };
 }
 
@@ -237,6 +240,14 @@ static inline int64_t bc_index(int64_t i, int64_t n, int lo_kind, int hi_kind) {
     return i;
 }
 
+// The given state when position i lies behind an inflow face (else null).
+static inline const double* bc_fixed(const OrGrid* g, int ax, int64_t i) {
+    const int64_t n = g->n[ax];
+    if (i < 0 && g->bc[ax][0] == 3) return g->bc_state[ax][0];
+    if (i >= n && g->bc[ax][1] == 3) return g->bc_state[ax][1];
+    return nullptr;
+}
+
 // -1 for the normal momentum of a ghost position behind a slip wall (the
 // mirror image's velocity normal to the wall is reversed), else +1.
 static inline double bc_sign(int64_t i, int64_t n, int lo_kind, int hi_kind, int v, int ax) {
@@ -266,7 +277,10 @@ static void face_flux(const OrGrid* g, const T* U, int ax, int64_t i, int64_t j,
     for (int v = 0; v < nv; ++v) {
         const T* Uv = U + v * ncell;
         T q[4];
-        for (int m = 0; m < 4; ++m) q[m] = Uv[off[m]] * bc_sign(pos[m], g->n[ax], g->bc[ax][0], g->bc[ax][1], v, ax);
+        for (int m = 0; m < 4; ++m) {
+            const double* fixed = bc_fixed(g, ax, pos[m]);
+            q[m] = fixed ? T(fixed[v]) : Uv[off[m]] * bc_sign(pos[m], g->n[ax], g->bc[ax][0], g->bc[ax][1], v, ax);
+        }
         muscl(q[0], q[1], q[2], q[3], g->limiter, g->kappa, QL[v], QR[v]);
     }
     roe_flux(g->ndim, ax, g->gamma, QL, QR, F);
@@ -465,8 +479,13 @@ void or_residual_vjp(const OrGrid* g, const double* U, const double* w, double* 
                                 // a ghost slot that maps to the same cell as another slot is
                                 // still its own input of the face flux; perturb the slot, not the cell
                                 cplx Q[4][5];
-                                for (int mm = 0; mm < 4; ++mm)
-                                    for (int vv = 0; vv < nv; ++vv) Q[mm][vv] = Uc[vv * ncell + off[mm]] * sgn(mm, vv);
+                                for (int mm = 0; mm < 4; ++mm) {
+                                    const double* fixed = bc_fixed(g, ax, lo - 1 + mm);
+                                    for (int vv = 0; vv < nv; ++vv)
+                                        Q[mm][vv] = fixed ? cplx(fixed[vv], 0.0) : Uc[vv * ncell + off[mm]] * sgn(mm, vv);
+                                }
+                                // a slot behind an inflow face depends on no cell
+                                if (bc_fixed(g, ax, lo - 1 + m)) continue;
                                 Q[m][v] += cplx(0.0, h);
                                 cplx QL[5], QR[5], F[5];
                                 for (int vv = 0; vv < nv; ++vv)

@@ -41,6 +41,7 @@ class GridSpec:
     cfl: float = 0.5
     limiter: bool = True   # False: unlimited MUSCL (Psi = 1)
     kappa: float = -1.0    # MUSCL kappa of the unlimited scheme: -1, 0, 1/3 or 1
+    bc_state: tuple = None  # (3, 2, nvar) conserved ghost state of inflow faces (kind 3)
 
     @property
     def nvar(self) -> int:
