@@ -63,7 +63,13 @@ enum {
  * least 2 cells on its axis and runs on the split path (fv_residual, fv_step,
  * fv_adjoint_step); the fused path and batches return FV_ENOTSUP / FV_EINVAL
  * for it. */
-enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1, FV_BC_WALL = 2 };
+/* FV_BC_INFLOW holds the given conserved state fv_grid_desc.bc_state[axis]
+ * [side] in the ghost cells (supersonic inflow: every characteristic enters
+ * through the face; the supersonic inlet of Sec. "A Test Case" takes in its
+ * free stream), with the same path limits as the wall. Its state must have
+ * a positive density and pressure. FV_BC_TRANSMISSIVE serves as the
+ * supersonic outflow. */
+enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1, FV_BC_WALL = 2, FV_BC_INFLOW = 3 };
 
 /* Status-word bits (set by the time-step reduction over the state). */
 enum { FV_FLAG_NAN = 1u, FV_FLAG_RHO = 2u, FV_FLAG_P = 4u, FV_FLAG_DT = 8u };
@@ -108,6 +114,7 @@ typedef struct fv_grid_desc {
     int32_t bc[3][2];
     double gamma;       /* ratio of specific heats, > 1 */
     double cfl;         /* CFL number, > 0 */
+    double bc_state[3][2][5];  /* conserved ghost state of FV_BC_INFLOW faces (rho, rho u, rho v, [rho w], E) */
 } fv_grid_desc;
 
 /* Launch parameters, two per site (FV_SITE_* order).

@@ -70,7 +70,8 @@ __global__ void __launch_bounds__(MAXT) k_adj_flux(const double* __restrict__ U,
 // face f has cells f-2, f-1, f, f+1 at slots 0..3, so position x is slot m of
 // face x + 2 - m. Ghost positions -2, -1, n, n+1 add their slots to the
 // interior cell they copy; behind a slip wall the copy is the mirror image,
-// times wsign (-1 for the momentum normal to the wall, else 1).
+// times wsign (-1 for the momentum normal to the wall, else 1); behind an
+// inflow face the ghost holds a given state and copies no cell.
 __device__ __forceinline__ double gather_axis(const double* __restrict__ Gv, long long ms, int x, int n, int lo_kind,
                                               int hi_kind, long long fbase, long long fstride, double wsign) {
     double acc = 0.0;
@@ -85,7 +86,10 @@ __device__ __forceinline__ double gather_axis(const double* __restrict__ Gv, lon
         const int gp = gi < 2 ? gi - 2 : n + gi - 2;  // -2, -1, n, n+1
         const bool lo = gi < 2;
         const int kind = lo ? lo_kind : hi_kind;
-        const int src = kind == 0 ? ((gp % n) + n) % n : kind == 2 ? (lo ? -1 - gp : 2 * n - 1 - gp) : (lo ? 0 : n - 1);
+        const int src = kind == 0   ? ((gp % n) + n) % n
+                        : kind == 2 ? (lo ? -1 - gp : 2 * n - 1 - gp)
+                        : kind == 3 ? -1
+                                    : (lo ? 0 : n - 1);
         if (src != x) continue;
         const double sg = kind == 2 ? wsign : 1.0;
 #pragma unroll

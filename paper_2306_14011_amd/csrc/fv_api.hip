@@ -1,5 +1,6 @@
 // C ABI of libfv.so: context, workspace carving, launch-table validation and
 // the orchestration of a step out of the kernels in fv_kernels.hip.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -36,6 +37,7 @@ struct fv_ctx {
     unsigned long long* flam;
     double* fdt;
     const double* src;  // caller's cell-averaged source S[v][cell], or null
+    fvk::BcState bcs;   // ghost states of inflow faces
     // per-site event timing (diagnostic)
     static const int kMaxEv = 64;
     bool timing;
@@ -100,9 +102,21 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
             return FV_EINVAL;
         }
         for (int s = 0; s < 2; ++s) {
-            if (g->bc[d][s] != FV_BC_PERIODIC && g->bc[d][s] != FV_BC_TRANSMISSIVE && g->bc[d][s] != FV_BC_WALL) {
+            if (g->bc[d][s] != FV_BC_PERIODIC && g->bc[d][s] != FV_BC_TRANSMISSIVE && g->bc[d][s] != FV_BC_WALL &&
+                g->bc[d][s] != FV_BC_INFLOW) {
                 snprintf(why, 256, "unknown boundary kind");
                 return FV_EINVAL;
+            }
+            if (g->bc[d][s] == FV_BC_INFLOW) {
+                const double* q = g->bc_state[d][s];
+                const int nv = g->ndim + 2;
+                double m2 = 0.0;
+                for (int a = 0; a < g->ndim; ++a) m2 += q[1 + a] * q[1 + a];
+                const double p = (g->gamma - 1.0) * (q[nv - 1] - 0.5 * m2 / q[0]);
+                if (!(q[0] > 0.0) || !(p > 0.0) || !isfinite(p)) {
+                    snprintf(why, 256, "an inflow state needs a positive density and pressure");
+                    return FV_EINVAL;
+                }
             }
             if (g->bc[d][s] == FV_BC_WALL && g->n[d] < 2) {
                 snprintf(why, 256, "a slip wall needs at least 2 cells on its axis");
@@ -268,7 +282,7 @@ int drain_timing(fv_ctx* c) {
 
 void enqueue_bc(fv_ctx* c, double* U) {
     SiteTimer t(c, FV_SITE_BC);
-    fvk::launch_bc_fill(U, c->g, P(c, FV_SITE_BC, 0), P(c, FV_SITE_BC, 1), c->stream);
+    fvk::launch_bc_fill(U, c->g, c->bcs, P(c, FV_SITE_BC, 0), P(c, FV_SITE_BC, 1), c->stream);
 }
 
 void enqueue_fluxes(fv_ctx* c, const double* U) {
@@ -357,6 +371,7 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
     memset(c, 0, sizeof(*c));
     c->desc = *g;
     c->g = make_geo(g, L);
+    memcpy(c->bcs.q, g->bc_state, sizeof(c->bcs.q));
     c->stream = (hipStream_t)stream;
     fv_default_launch(&c->launch);
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -481,8 +496,9 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
     for (int d = 0; d < c->g.ndim; ++d)
-        if (c->g.bc[d][0] == FV_BC_WALL || c->g.bc[d][1] == FV_BC_WALL)
-            return fail(c, FV_ENOTSUP, "slip walls run on the split path only%s");
+        for (int s = 0; s < 2; ++s)
+            if (c->g.bc[d][s] == FV_BC_WALL || c->g.bc[d][s] == FV_BC_INFLOW)
+                return fail(c, FV_ENOTSUP, "slip walls and inflow faces run on the split path only%s");
     if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
         return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
     if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))

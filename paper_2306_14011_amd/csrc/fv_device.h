@@ -34,6 +34,11 @@ __host__ __device__ inline uint32_t divq(uint32_t n, const DivMod& dm) {
 }
 
 // Geometry and constants of one grid, passed by value to every kernel.
+// Ghost state of inflow faces, per axis and side (conserved variables).
+struct BcState {
+    double q[3][2][5];
+};
+
 struct Geo {
     int ndim, nvar;
     int n[3];           // interior cells per axis

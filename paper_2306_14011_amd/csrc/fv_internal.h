@@ -35,7 +35,7 @@ struct FGrid3 {
     double inv_vol, inv_dx, inv_dy, inv_dz, cfl, gamma, gm1;
 };
 
-void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t s);
+void launch_bc_fill(double* U, const Geo& g, const BcState& bcs, int gang, int threads, hipStream_t s);
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
                      int gang, int threads, hipStream_t s);

@@ -15,9 +15,10 @@ namespace fvk {
 // (-2, -1, n, n+1) times the interior cross-section of that axis; layer is the
 // fastest index. Periodic faces copy the opposite interior layers,
 // transmissive faces copy the nearest interior cell (zero gradient), slip
-// walls the mirror image across the face with the normal momentum reversed.
+// walls the mirror image across the face with the normal momentum reversed,
+// inflow faces take their given state.
 template <int NV>
-__global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g, int total, int seg0,
+__global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g, BcState bcs, int total, int seg0,
                                                    int seg1, int stride_all) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride_all) {
         int ax, q, layer;
@@ -53,6 +54,8 @@ __global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g,
             src = ((gpos % n) + n) % n;
         } else if (kind == 2) {
             src = lo ? -1 - gpos : 2 * n - 1 - gpos;
+        } else if (kind == 3) {
+            src = lo ? 0 : n - 1;  // not read: the ghost takes the given state
         } else {
             src = lo ? 0 : n - 1;
         }
@@ -68,8 +71,12 @@ __global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g,
         const int os = g.off0 + cs[0] + cs[1] * g.sy + cs[2] * g.sz;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double q = U[v * g.sv + os];
-            U[v * g.sv + og] = (kind == 2 && v == 1 + ax) ? -q : q;
+            if (kind == 3) {
+                U[v * g.sv + og] = bcs.q[ax][lo ? 0 : 1][v];
+            } else {
+                const double q = U[v * g.sv + os];
+                U[v * g.sv + og] = (kind == 2 && v == 1 + ax) ? -q : q;
+            }
         }
     }
 }
@@ -314,7 +321,7 @@ static inline void grid1d(int64_t n, int gang, int threads, int& blocks, int& st
         default: MACRO(1024); break;  \
     }
 
-void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t s) {
+void launch_bc_fill(double* U, const Geo& g, const BcState& bcs, int gang, int threads, hipStream_t s) {
     const int seg0 = 4 * g.n[1] * g.n[2];
     const int seg1 = 4 * g.n[0] * g.n[2];
     const int seg2 = g.ndim == 3 ? 4 * g.n[0] * g.n[1] : 0;
@@ -322,9 +329,9 @@ void launch_bc_fill(double* U, const Geo& g, int gang, int threads, hipStream_t 
     int blocks, stride_all;
     grid1d(total, gang, threads, blocks, stride_all);
     if (g.ndim == 2)
-        hipLaunchKernelGGL(k_bc_fill<4>, dim3(blocks), dim3(threads), 0, s, U, g, total, seg0, seg1, stride_all);
+        hipLaunchKernelGGL(k_bc_fill<4>, dim3(blocks), dim3(threads), 0, s, U, g, bcs, total, seg0, seg1, stride_all);
     else
-        hipLaunchKernelGGL(k_bc_fill<5>, dim3(blocks), dim3(threads), 0, s, U, g, total, seg0, seg1, stride_all);
+        hipLaunchKernelGGL(k_bc_fill<5>, dim3(blocks), dim3(threads), 0, s, U, g, bcs, total, seg0, seg1, stride_all);
 }
 
 constexpr int FLUX_RUN = 8;  // faces per thread of the y / z flux kernels

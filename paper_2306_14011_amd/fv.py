@@ -57,6 +57,7 @@ def scheme_of(spec):
 FV_BC_PERIODIC = 0
 FV_BC_TRANSMISSIVE = 1
 FV_BC_WALL = 2
+FV_BC_INFLOW = 3
 
 FV_FLAG_NAN = 1
 FV_FLAG_RHO = 2
@@ -81,6 +82,7 @@ class fv_grid_desc(ctypes.Structure):
         ("bc", (ctypes.c_int32 * 2) * 3),
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("bc_state", ((ctypes.c_double * 5) * 2) * 3),
     ]
 
 
@@ -225,6 +227,13 @@ def make_desc(spec) -> fv_grid_desc:
         d.bc[a][1] = int(spec.bc[a][1])
     d.gamma = float(spec.gamma)
     d.cfl = float(spec.cfl)
+    st = getattr(spec, "bc_state", None)
+    if st is not None:
+        st = np.asarray(st, dtype=np.float64)
+        for a in range(3):
+            for sd in range(2):
+                for v in range(min(5, st.shape[2])):
+                    d.bc_state[a][sd][v] = float(st[a, sd, v])
     return d
 
 

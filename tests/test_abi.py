@@ -179,3 +179,20 @@ def test_slip_walls_accepted_with_two_cells_or_more():
         with pytest.raises(fv.FvError) as e:
             fv.fv_query(fv.make_desc(g))
         assert e.value.code == fv.FV_EINVAL
+
+
+def test_inflow_state_must_be_physical():
+    import dataclasses
+
+    import numpy as np
+    I = fv.FV_BC_INFLOW
+    st = np.zeros((3, 2, 4))
+    st[0, 0] = [1.0, 2.0, 0.1, 5.0]           # p = 0.4 * (5 - 0.5 * 4.01) > 0
+    g = dataclasses.replace(inputs.grid2d(16, 9, bc=((I, 1), (0, 0))), bc_state=st)
+    fv.fv_query(fv.make_desc(g))
+    for bad in ([0.0, 2.0, 0.1, 5.0], [1.0, 2.0, 0.1, 1.0]):   # no density; negative pressure
+        st2 = st.copy()
+        st2[0, 0] = bad
+        with pytest.raises(fv.FvError) as e:
+            fv.fv_query(fv.make_desc(dataclasses.replace(g, bc_state=st2)))
+        assert e.value.code == fv.FV_EINVAL
