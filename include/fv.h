@@ -162,6 +162,14 @@ int fv_set_stream(fv_ctx* ctx, void* stream);
  * interior layout (nvar * ncell doubles). */
 int fv_residual(fv_ctx* ctx, double* U, double* R);
 
+/* Per-variable L2 norm of the residual of U, the convergence monitor behind
+ * the relative residual history of Sec. "A Test Case" (Fig. inlet-resid):
+ * norms[v] = sqrt(sum over cells of R_v^2 / ncell), R as fv_residual
+ * computes it (source included). norms is a device pointer to nvar doubles;
+ * the residual itself goes to the context's scratch. Fills the ghost layers
+ * of U. The sums run in a fixed order: the same U gives the same bits. */
+int fv_residual_norm(fv_ctx* ctx, double* U, double* norms);
+
 /* Sets the cell-averaged source term S_h of Eq. (residual) (a body force, a
  * manufactured solution's source): S is a device pointer to nvar * ncell
  * doubles in the dense interior layout of fv_residual's R (variable, then

@@ -173,6 +173,13 @@ def residual(spec, U, limiter=True, kappa=-1.0, source=None):
     return R
 
 
+def residual_norm(spec, U, limiter=True, kappa=-1.0, source=None):
+    """Per-variable L2 norm of the residual: sqrt(sum over cells of R_v^2 / ncell)."""
+    R = residual(spec, U, limiter, kappa, source)
+    R = R.reshape(R.shape[0], -1)
+    return np.sqrt((R * R).sum(axis=1) / R.shape[1])
+
+
 def residual_cs(spec, U, V, h=1e-30, limiter=True):
     g = make_grid(spec, limiter)
     U = _arr(U)

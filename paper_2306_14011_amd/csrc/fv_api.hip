@@ -609,6 +609,18 @@ int fv_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* d
     return FV_OK;
 }
 
+int fv_residual_norm(fv_ctx* c, double* U, double* norms) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (!U || !norms) return fail(c, FV_EINVAL, "null state or norms pointer%s");
+    enqueue_bc(c, U);
+    enqueue_fluxes(c, U);
+    enqueue_residual(c, c->R);
+    fvk::launch_residual_norm(c->R, c->partial, norms, c->g, c->stream);
+    int rc = check_launch_error(c);
+    if (rc != FV_OK) return rc;
+    return drain_timing(c);
+}
+
 int fv_set_source(fv_ctx* c, const double* S) {
     if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
     c->src = S;

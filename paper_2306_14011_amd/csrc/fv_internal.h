@@ -39,6 +39,8 @@ void launch_bc_fill(double* U, const Geo& g, const BcState& bcs, int gang, int t
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
                      int gang, int threads, hipStream_t s);
+// norms[v] = sqrt(sum_e R[v][e]^2 / ncell) with partial (256 * nvar doubles) as scratch.
+void launch_residual_norm(const double* R, double* partial, double* norms, const Geo& g, hipStream_t s);
 void launch_update(int stage, const double* Un, const double* Us, double* Ud, const double* R, const double* dt,
                    const Geo& g, int gang, int threads, hipStream_t s);
 int cfl_blocks(const Geo& g, int gang, int threads);

@@ -202,6 +202,57 @@ __global__ void __launch_bounds__(MAXT) k_residual(const double* __restrict__ Fx
     }
 }
 
+// Residual norm: 256 blocks each sum R_v^2 over a grid-stride range of cells
+// (partial[v * 256 + block]), then one block adds the 256 partial sums of each
+// variable. Fixed block count and order, so the result does not depend on
+// timing.
+constexpr int NORM_BLOCKS = 256;
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_sumsq(const double* __restrict__ R, int ncell,
+                                               double* __restrict__ partial) {
+    __shared__ double sm[NV][4];
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ncell; e += gridDim.x * blockDim.x)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double r = R[(long long)v * ncell + e];
+            acc[v] = fma(r, r, acc[v]);
+        }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double t = acc[v];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((threadIdx.x & 63) == 0) sm[v][threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int v = threadIdx.x;
+        partial[v * NORM_BLOCKS + blockIdx.x] = ((sm[v][0] + sm[v][1]) + sm[v][2]) + sm[v][3];
+    }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_norm_final(const double* __restrict__ partial, int ncell,
+                                                    double* __restrict__ norms) {
+    __shared__ double sm[NV][4];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double t = partial[v * NORM_BLOCKS + threadIdx.x];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((threadIdx.x & 63) == 0) sm[v][threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int v = threadIdx.x;
+        norms[v] = sqrt((((sm[v][0] + sm[v][1]) + sm[v][2]) + sm[v][3]) / (double)ncell);
+    }
+}
+
 // SSP-RK3 stage update with L = -R / |Omega| and dt read from device memory.
 //   STAGE 0: Ud = Un + dt L
 //   STAGE 1: Ud = 3/4 Un + 1/4 (Us + dt L)          (Ud may alias Us)
@@ -392,6 +443,16 @@ void launch_residual(const double* Fx, const double* Fy, const double* Fz, const
         hipLaunchKernelGGL((k_residual<3, T>), dim3(blocks), dim3(T), 0, s, Fx, Fy, Fz, S, R, g, stride_all);
     FV_DISPATCH_THREADS(threads, FV_LR)
 #undef FV_LR
+}
+
+void launch_residual_norm(const double* R, double* partial, double* norms, const Geo& g, hipStream_t s) {
+    if (g.ndim == 2) {
+        hipLaunchKernelGGL(k_sumsq<4>, dim3(NORM_BLOCKS), dim3(256), 0, s, R, g.ncell, partial);
+        hipLaunchKernelGGL(k_norm_final<4>, dim3(1), dim3(256), 0, s, partial, g.ncell, norms);
+    } else {
+        hipLaunchKernelGGL(k_sumsq<5>, dim3(NORM_BLOCKS), dim3(256), 0, s, R, g.ncell, partial);
+        hipLaunchKernelGGL(k_norm_final<5>, dim3(1), dim3(256), 0, s, partial, g.ncell, norms);
+    }
 }
 
 template <int STAGE>

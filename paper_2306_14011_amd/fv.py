@@ -160,6 +160,7 @@ def lib():
         L.fv_step.argtypes = [_vp, _vp, ctypes.c_int32, _vp, _vp]
         L.fv_adjoint_step.argtypes = [_vp, _vp, _vp, _vp]
         L.fv_set_source.argtypes = [_vp, _vp]
+        L.fv_residual_norm.argtypes = [_vp, _vp, _vp]
         L.fv_set_launch.argtypes = [_vp, ctypes.POINTER(fv_launch)]
         L.fv_get_launch.argtypes = [_vp, ctypes.POINTER(fv_launch)]
         L.fv_status.argtypes = [_vp, ctypes.POINTER(ctypes.c_uint32)]
@@ -195,7 +196,7 @@ def lib():
         L.fv_mlp_sweep.argtypes = [_vp, ctypes.POINTER(fv_tune_space), ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
-                     "fv_adjoint_step", "fv_set_source", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
+                     "fv_adjoint_step", "fv_set_source", "fv_residual_norm", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
                      "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_batch_query", "fv_batch_create",
                      "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_set_schedule", "fv_batch_destroy",
                      "fv_mlp_workspace", "fv_mlp_sweep_workspace",
@@ -273,6 +274,10 @@ def fv_residual(ctx, U_ptr, R_ptr):
 
 def fv_step(ctx, U_ptr, nsteps, dt_in_ptr=None, dt_out_ptr=None):
     return _check(lib().fv_step(_vp(ctx), _vp(U_ptr), int(nsteps), _vp(dt_in_ptr), _vp(dt_out_ptr)), ctx)
+
+
+def fv_residual_norm(ctx, U_ptr, norms_ptr):
+    return _check(lib().fv_residual_norm(_vp(ctx), _vp(U_ptr), _vp(norms_ptr)), ctx)
 
 
 def fv_set_source(ctx, S_ptr):
@@ -527,6 +532,13 @@ class Solver:
         R = self.dense_zeros()
         fv_residual(self.ctx, self.U.data_ptr(), R.data_ptr())
         return R
+
+    def residual_norm(self):
+        """Per-variable L2 norm of the residual of the current state (numpy)."""
+        torch = _torch()
+        out = torch.zeros(self.nvar, dtype=torch.float64, device=self.device)
+        fv_residual_norm(self.ctx, self.U.data_ptr(), out.data_ptr())
+        return out.cpu().numpy()
 
     def set_source(self, S_dense):
         """Cell-averaged source of Eq. (residual), shape (nvar, nz, ny, nx) or
