@@ -101,6 +101,9 @@ def make_grid(spec, limiter=True, kappa=-1.0, source=None):
     source: cell-averaged source S, shape (nvar, nz, ny, nx) or (nvar, ny, nx),
     or None for S = 0 (Eq. residual)."""
     g = OrGrid()
+    for d in range(spec.ndim):
+        if 2 in (int(spec.bc[d][0]), int(spec.bc[d][1])) and int(spec.n[d]) < 2:
+            raise ValueError("a slip wall needs at least 2 cells on its axis")
     if source is not None:
         src = np.ascontiguousarray(source, dtype=np.float64)
         if src.size != (spec.ndim + 2) * int(np.prod([int(v) for v in spec.n])):

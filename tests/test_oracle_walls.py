@@ -88,3 +88,9 @@ def test_mirror_symmetric_state_stays_symmetric():
     M1 = U1[:, :, :, ::-1].copy()
     M1[1] = -M1[1]
     assert np.allclose(U1, M1, rtol=0, atol=1e-13)
+
+
+def test_wall_needs_two_cells():
+    g = inputs.grid2d(8, 1, hi=(1.0, 1.0), bc=((0, 0), (WALL, WALL)))
+    with pytest.raises(ValueError):
+        oracle.residual(g, np.ones((4, 1, 1, 8)))
