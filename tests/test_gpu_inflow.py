@@ -122,3 +122,26 @@ def test_fused_path_refuses_inflow():
         s.set_path(fv.FV_PATH_FUSED, 0, 0)
     assert e.value.code == fv.FV_ENOTSUP
     s.close()
+
+
+def test_large_inlet_channel_matches_oracle():
+    # many tiles and a ragged last block of every kernel: 517 x 389 cells,
+    # supersonic inflow, slip walls, outflow, 4 steps
+    import torch
+    from paper_2306_14011_amd import fv
+    q = free_stream(2, mach=2.5, angle=0.15)
+    g = inputs.grid2d(517, 389, hi=(2.0, 1.5), bc=((INFLOW, OUT), (WALL, WALL)))
+    st = np.zeros((3, 2, 4))
+    st[0, 0] = q
+    g = dataclasses.replace(g, bc_state=st)
+    U = bumped(g, q, 7)
+    s = fv.Solver(g)
+    s.set_state(U)
+    assert_pervar_close(s.residual().cpu().numpy(), oracle.residual(g, U), TOL, "residual")
+    dts = torch.zeros(4, dtype=torch.float64, device="cuda")
+    s.step(4, dt_out=dts)
+    got = s.get_state()
+    s.close()
+    ref, rdt, _ = oracle.run(g, U, 4)
+    assert np.allclose(dts.cpu().numpy(), rdt, rtol=1e-12, atol=0)
+    assert_pervar_close(got, ref, TOL, "4 steps")
