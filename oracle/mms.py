@@ -91,3 +91,72 @@ def cell_averages(fn, n, order=4):
             Y = centres[:, None] + 0.5 * h * b
             out += 0.25 * wa * wb * fn(np.broadcast_to(X, (n, n)), np.broadcast_to(Y, (n, n)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# 3D: the same construction on the periodic unit cube, with w and z terms.
+#   rho = 1   + 0.15 sin(2 pi x) + 0.10 cos(2 pi y) + 0.08 sin(2 pi z)
+#   u   = 0.6 + 0.05 sin(2 pi x) + 0.05 cos(4 pi y) + 0.04 cos(2 pi z)
+#   v   = 0.5 + 0.05 cos(4 pi x) + 0.08 sin(2 pi y) + 0.03 sin(2 pi z)
+#   w   = 0.4 + 0.04 sin(2 pi x) + 0.03 cos(2 pi y) + 0.06 cos(2 pi z)
+#   p   = 1   + 0.20 cos(2 pi x) + 0.05 sin(2 pi y) + 0.07 cos(4 pi z)
+
+FIELDS3 = {
+    "rho": (1.0, (0.15, 1, "sin"), (0.10, 1, "cos"), (0.08, 1, "sin")),
+    "u": (0.6, (0.05, 1, "sin"), (0.05, 2, "cos"), (0.04, 1, "cos")),
+    "v": (0.5, (0.05, 2, "cos"), (0.08, 1, "sin"), (0.03, 1, "sin")),
+    "w": (0.4, (0.04, 1, "sin"), (0.03, 1, "cos"), (0.06, 1, "cos")),
+    "p": (1.0, (0.20, 1, "cos"), (0.05, 1, "sin"), (0.07, 2, "cos")),
+}
+
+
+def primitive3(name, x, y, z):
+    """(value, d/dx, d/dy, d/dz) of a 3D primitive field."""
+    mean, tx, ty, tz = FIELDS3[name]
+    fx, dfx = _term(tx, x)
+    fy, dfy = _term(ty, y)
+    fz, dfz = _term(tz, z)
+    zero = 0.0 * (x + y + z)
+    return mean + fx + fy + fz, dfx + zero, dfy + zero, dfz + zero
+
+
+def conserved3(x, y, z, gamma=1.4):
+    r = primitive3("rho", x, y, z)[0]
+    vel = [primitive3(c, x, y, z)[0] for c in ("u", "v", "w")]
+    p = primitive3("p", x, y, z)[0]
+    E = p / (gamma - 1.0) + 0.5 * r * sum(c * c for c in vel)
+    return np.stack([r] + [r * c for c in vel] + [E])
+
+
+def source3(x, y, z, gamma=1.4):
+    """S = sum_d d F_d / d x_d of the 3D inviscid fluxes, by the product rule."""
+    r, *dr = primitive3("rho", x, y, z)
+    vel = [primitive3(c, x, y, z) for c in ("u", "v", "w")]
+    V = [q[0] for q in vel]
+    dV = [q[1:] for q in vel]          # dV[i][d] = d V_i / d x_d
+    p, *dp = primitive3("p", x, y, z)
+    q2 = sum(c * c for c in V)
+    E = p / (gamma - 1.0) + 0.5 * r * q2
+    dE = [dp[d] / (gamma - 1.0) + 0.5 * dr[d] * q2 + r * sum(V[i] * dV[i][d] for i in range(3)) for d in range(3)]
+    S = [0.0 * x for _ in range(5)]
+    for d in range(3):
+        # F_d = (rho V_d, rho V_1 V_d + p delta_1d, ..., V_d (E + p))
+        S[0] = S[0] + dr[d] * V[d] + r * dV[d][d]
+        for i in range(3):
+            S[1 + i] = S[1 + i] + dr[d] * V[i] * V[d] + r * dV[i][d] * V[d] + r * V[i] * dV[d][d] + (dp[d] if i == d else 0.0)
+        S[4] = S[4] + dV[d][d] * (E + p) + V[d] * (dE[d] + dp[d])
+    return np.stack(S)
+
+
+def cell_averages3(fn, n, order=3):
+    """Cell averages of fn(x, y, z) -> (5, ...) over an n^3 grid of the unit cube; shape (5, n, n, n) [v][k][j][i]."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    out = np.zeros((5, n, n, n))
+    for a, wa in zip(xg, wg):
+        for b, wb in zip(xg, wg):
+            for e, we in zip(xg, wg):
+                Z, Y, X = np.meshgrid(c + 0.5 * h * e, c + 0.5 * h * b, c + 0.5 * h * a, indexing="ij")
+                out += 0.125 * wa * wb * we * fn(X, Y, Z)
+    return out

@@ -99,3 +99,40 @@ def test_manufactured_steady_state_is_held():
     d_src = np.abs(U1 - U0).max()
     d_free = np.abs(U2 - U0).max()
     assert d_src * 30 < d_free, (d_src, d_free)
+
+
+def flux3(Q, ax):
+    r, m, E = Q[0], Q[1:4], Q[4]
+    V = m / r
+    p = (GAMMA - 1.0) * (E - 0.5 * r * (V * V).sum(axis=0))
+    out = [r * V[ax]] + [m[i] * V[ax] + (p if i == ax else 0.0) for i in range(3)] + [(E + p) * V[ax]]
+    return np.stack(out)
+
+
+def test_3d_source_is_the_flux_divergence():
+    rng = np.random.default_rng(5)
+    x, y, z = rng.random(150), rng.random(150), rng.random(150)
+    h = 1e-5
+    e = [np.array([h, 0, 0]), np.array([0, h, 0]), np.array([0, 0, h])]
+    fd = 0.0
+    for ax in range(3):
+        hp = mms.conserved3(x + e[ax][0], y + e[ax][1], z + e[ax][2])
+        hm = mms.conserved3(x - e[ax][0], y - e[ax][1], z - e[ax][2])
+        fd = fd + (flux3(hp, ax) - flux3(hm, ax)) / (2 * h)
+    S = mms.source3(x, y, z)
+    for v in range(5):
+        assert np.abs(S[v] - fd[v]).max() <= 1e-7 * np.abs(S[v]).max(), v
+
+
+def test_3d_truncation_error_is_second_order():
+    errs = []
+    for n in (24, 48):
+        spec = SimpleNamespace(ndim=3, n=(n, n, n), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                               bc=((0, 0), (0, 0), (0, 0)), gamma=GAMMA, cfl=0.5)
+        U = mms.cell_averages3(mms.conserved3, n)
+        S = mms.cell_averages3(mms.source3, n)
+        te = oracle.residual(spec, U, limiter=False, source=S) * n ** 3
+        errs.append(np.sqrt((te ** 2).mean(axis=(1, 2, 3))))
+    orders = np.log2(errs[0] / errs[1])
+    print(orders)
+    assert np.all(orders > 1.85) and np.all(orders < 2.3), orders   # 12 -> 24 is not yet asymptotic (w: 1.67)
