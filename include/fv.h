@@ -224,7 +224,8 @@ int fv_clear_status(fv_ctx* ctx);
  * same result. Both paths compute the same cell arithmetic; fv_residual and
  * fv_adjoint_step always use the split kernels. Returns FV_ENOTSUP for states
  * of 4 GiB or more (the fused kernels address a grid through 32-bit buffer
- * offsets) and FV_EINVAL for other seg values. */
+ * offsets) and for grids with slip-wall or inflow faces (the fused kernels
+ * map boundaries by index only), and FV_EINVAL for other seg values. */
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
 
