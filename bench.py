@@ -198,16 +198,19 @@ def split_leg(torch, fv, traffic, g, U0, a, samples, tune_it, sample_timing=(3, 
 
 def sized_leg(torch, inputs, seed, samples):
     """One problem-size-conditioned network (launch features plus log2 cells
-    and dimension) trained on the pooled timed samples of the 2048^2 2D and
-    256^3 3D split-path workloads, then used to tune both and a 1024^2 2D grid
-    it has no samples of."""
+    and dimension) trained on the pooled timed samples of 1024^2 and 4096^2 2D
+    grids and the 256^3 3D workload, then used to tune all three and the
+    2048^2 headline grid, whose size lies between the 2D ones and of which it
+    has no samples (the 2D-only tuner of the split leg, trained on 2048^2
+    samples, is the comparison)."""
     from paper_2306_14011_amd.autotune import SizedAutotuner
-    g2, U2 = inputs.vortex_bumps_case(2048, seed=seed)
+    g1, U1 = inputs.vortex_bumps_case(1024, seed=seed + 1)
+    g4, U4 = inputs.vortex_bumps_case(4096, seed=seed + 2)
     g3, U3 = inputs.sod3d_case(256, seed=seed)
-    gh, Uh = inputs.vortex_bumps_case(1024, seed=seed + 1)
+    gh, Uh = inputs.vortex_bumps_case(2048, seed=seed)
     t0 = time.perf_counter()
-    at = SizedAutotuner([g2, g3, gh], [U2, U3, Uh], seed=seed, holdout=[2], repeats=1, warmup=2, min_ms=10.0,
-                        check_steps=2)
+    at = SizedAutotuner([g1, g4, g3, gh], [U1, U4, U3, Uh], seed=seed, holdout=[3], repeats=1, warmup=2,
+                        min_ms=10.0, check_steps=2)
     res = at.run(count=samples, k=8, rounds=5)
     at.close()
     res["tuning_seconds"] = round(time.perf_counter() - t0, 1)
