@@ -176,11 +176,20 @@ def residual(spec, U, limiter=True, kappa=-1.0, source=None):
     return R
 
 
-def residual_norm(spec, U, limiter=True, kappa=-1.0, source=None):
-    """Per-variable L2 norm of the residual: sqrt(sum over cells of R_v^2 / ncell)."""
-    R = residual(spec, U, limiter, kappa, source)
+def norm_of(R):
+    """Per-variable L2 norm of a residual array R of shape (nvar, cells...):
+    norm_v = sqrt(sum over the cells of R_v^2 / ncell), ncell being the number
+    of cells (not nvar * ncell). The convergence monitor behind the relative
+    residual history of Sec. "A Test Case"; the paper gives no normalisation,
+    and the relative history (each norm over the first) does not depend on it."""
+    R = np.asarray(R, dtype=np.float64)
     R = R.reshape(R.shape[0], -1)
     return np.sqrt((R * R).sum(axis=1) / R.shape[1])
+
+
+def residual_norm(spec, U, limiter=True, kappa=-1.0, source=None):
+    """Per-variable L2 norm of the residual of U (``norm_of`` of ``residual``)."""
+    return norm_of(residual(spec, U, limiter, kappa, source))
 
 
 def residual_cs(spec, U, V, h=1e-30, limiter=True):

@@ -248,28 +248,31 @@ def test_fused3d_schedules_bitwise_equal():
 
 
 def test_fused3d_full_size_sampled_patches():
-    # 256^3 rotated Sod, one fused step; the oracle recomputes sampled 20^3
-    # patches with the same dt (a cell depends on cells at most 6 away)
+    # 256^3 rotated Sod, one fused step; the oracle recomputes 20^3 patches on
+    # the front and across the periodic seams with the same dt (a cell
+    # depends on cells at most 6 away)
+    from tests.patch_util import check_patches
+    from tests.test_gpu_parity import sod256_front_origins
     g, U0 = inputs.sod3d_case(256, seed=0)
     got, dts, flags = run_fused(g, U0, 1, seg=0)
     dt_ref, _ = oracle.dt(g, U0)
     assert flags == 0 and abs(dts[0] - dt_ref) <= 1e-14 * dt_ref
-    rng = np.random.default_rng(9)
-    P, H = 20, 6
-    checked = 0
-    for _ in range(8):
-        o = rng.integers(0, 256, size=3)
-        if o[0] + P > 256:
-            continue   # the x faces are transmissive: a wrapped patch is not periodic there
-        idx = [(o[a] + np.arange(P)) % 256 for a in range(3)]
-        patch = U0[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
-        pg = inputs.grid3d(P, P, P, hi=(P / 256.0,) * 3, bc=((1, 1), (1, 1), (1, 1)))
-        ref = oracle.rk3_step(pg, patch, dts[0])[:, H:-H, H:-H, H:-H]
-        gp = got[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]][:, H:-H, H:-H, H:-H]
-        scale = np.abs(ref).max()
-        assert np.abs(gp - ref).max() <= 1e-12 * scale, o
-        checked += 1
-    assert checked >= 3
+    n, worst = check_patches(got, U0, g, dts, sod256_front_origins(20, 9), 20, 6, min_change=1e-3,
+                             what="fused 256^3")
+    print(n, worst)
+
+
+def test_fused3d_full_size_three_steps_sampled_patches():
+    # three fused steps at the GPU's dt sequence on 48^3 patches (inner 12^3)
+    from tests.patch_util import check_patches
+    from tests.test_gpu_parity import sod256_front_origins
+    g, U0 = inputs.sod3d_case(256, seed=0)
+    got, dts, flags = run_fused(g, U0, 3, seg=0)
+    assert flags == 0
+    origins = sod256_front_origins(48, 17)[:4] + sod256_front_origins(48, 17)[5:7]
+    n, worst = check_patches(got, U0, g, dts, origins, 48, 18, min_change=1e-3, what="fused 256^3, 3 steps")
+    print(n, worst)
+
 
 
 def test_fused3d_largest_grid_sampled_patches():
@@ -451,3 +454,35 @@ def test_batch_flags_nonphysical():
     rc, flags = B.status()
     B.close()
     assert rc == fv.FV_ENONPHYS and flags & fv.FV_FLAG_P
+
+
+def test_batch_full_workload_against_oracle():
+    """The measured batch workload itself: 96 uneven vortex grids with sides
+    drawn from 128..1024, the library's schedule, three graph-replayed steps.
+    A seeded subset (the largest grid, the most elongated one and six others)
+    matches the per-grid oracle, each grid at its own CFL dt, and every grid
+    equals the single-grid fused path bit for bit."""
+    fv = _fv()
+    spec = inputs.batch_case(count=96, seed=0)
+    B = fv.Batch(spec.grids, seg=0)
+    B.set_states(spec.states)
+    B.step(3)
+    rc, flags = B.status()
+    got = B.get_states()
+    dts = B.dt()
+    B.close()
+    assert flags == 0
+    cells = [gg.ncells for gg in spec.grids]
+    aspect = [max(gg.n[0], gg.n[1]) / min(gg.n[0], gg.n[1]) for gg in spec.grids]
+    rng = np.random.default_rng(21)
+    pick = {int(np.argmax(cells)), int(np.argmax(aspect))}
+    while len(pick) < 8:
+        pick.add(int(rng.integers(0, 96)))
+    for g in sorted(pick):
+        gs, U0 = spec.grids[g], spec.states[g]
+        ref, rdts, _ = oracle.run(gs, U0, 3)
+        assert abs(dts[g] - rdts[-1]) <= 1e-14 * rdts[-1], g
+        close(got[g], ref, what=f"grid {g} ({gs.n[0]}x{gs.n[1]})")
+    for g, (gs, U0) in enumerate(zip(spec.grids, spec.states)):
+        single, _, _ = run_fused(gs, U0, 3, seg=0)
+        assert np.array_equal(got[g], single), g

@@ -191,6 +191,36 @@ def test_tuner_at_300_samples_ranks_unseen_configurations():
     assert share_tuned * 4 <= share_random, info
 
 
+def test_tuner_at_300_samples_against_the_known_optimum():
+    """The known-optimum statement at the measured budget: 300 timed samples
+    (225 training rows), the whole 1.9e8-point space swept, the best of the 8
+    lowest predictions. The target of landing within 5% of the optimum is NOT
+    met at this budget: with the paper's minibatch of 200 and at most 200
+    epochs, 225 rows give at most 400 Adam steps at lr 9e-4, and the fit stays
+    partial (R^2 about 0.6). The pick is recorded, not bounded to the target:
+    it must stay within 2x of the optimum (measured 1.6-1.8x) and the test
+    prints where it lands against the best random sample."""
+    sp = LaunchSpace(2)
+    rng = np.random.default_rng(11)
+    idx = sp.sample(300, 21)
+    t = synthetic_cost(sp, idx, rng)
+    tr = np.arange(225)
+    F = sp.features(idx)
+    mean, std = mlp.standard_scaler(F[tr])
+    t_mean, t_std = target_scaler(t[tr])
+    X = (F - mean) / std
+    y = (t - t_mean) / t_std
+    N = net(12)
+    N.train(X[tr], y[tr])
+    ti, _ = N.sweep(sp.struct(mean, std), 0, sp.size, 8)
+    best_tuned = synthetic_cost(sp, ti).min()
+    best_random = synthetic_cost(sp, idx).min()
+    optimum = synthetic_optimum(sp)
+    info = dict(tuned_over_optimum=best_tuned / optimum, random_over_optimum=best_random / optimum)
+    print(info)
+    assert best_tuned <= 2.0 * optimum, info
+
+
 def test_tuner_with_the_papers_sample_budget_lands_near_the_optimum():
     # The paper trains on 7500 of 10000 samples (Sec. "Results"). The synthetic
     # cost is free to evaluate, so that budget is affordable here: with it the
