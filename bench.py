@@ -176,7 +176,8 @@ def split_leg(torch, fv, traffic, g, U0, a, samples, tune_it, sample_timing=(3, 
                     "autotune": {k: v for k, v in tune.items() if k != "top_pred"}})
         log(f"split tuned in {tune['tuning_seconds']} s: {ms_tuned:.4f} ms/step, R2(test) {tune['r2_test']:.3f}, "
             f"interleaved default/tuned {tune['factor_vs_default']:.3f}, best-random/tuned "
-            f"{tune['factor_vs_best_random']:.3f}")
+            f"{tune['factor_vs_best_random']:.3f} (shipped: {tune['shipped_from']}; network pick: default/network "
+            f"{tune['network_factor_vs_default']:.3f}, best-random/network {tune['network_factor_vs_best_random']:.3f})")
     s.set_launch(launch)
     kernels = site_table(s, g, a.timing_steps, fv, traffic)
     s.close()
@@ -371,7 +372,8 @@ def batch_leg(torch, fv, inputs, steps, samples):
         at.close()
         tune["tuning_seconds"] = round(time.perf_counter() - t0, 1)
         log(f"batch schedule tuned in {tune['tuning_seconds']} s: R2(test) {tune['r2_test']:.3f}, "
-            f"default/tuned {tune['factor_vs_default']:.3f}, best-random/tuned {tune['factor_vs_best_random']:.3f}")
+            f"default/tuned {tune['factor_vs_default']:.3f}, best-random/tuned {tune['factor_vs_best_random']:.3f} "
+            f"(shipped: {tune['shipped_from']}; default/network {tune['network_factor_vs_default']:.3f})")
     stream = torch.cuda.current_stream()
     res = {}
     for name, sched in (("default", None), ("tuned", tune["tuned"])):

@@ -202,6 +202,15 @@ def sweep_space(space, model, k=8):
     return idx, val, time.perf_counter() - t0
 
 
+def shipped(final_ms, options, names=("default", "network", "best_random")):
+    """The option to ship and its name: the fastest under the interleaved
+    timing `final_ms` of `options` (default first, ties to the earlier
+    option), so that a network pick slower than the default or the best
+    random sample is reported but not shipped."""
+    i = min(range(len(options)), key=lambda q: (final_ms[q], q))
+    return options[i], names[i]
+
+
 @dataclass
 class Sample:
     index: int
@@ -327,10 +336,13 @@ class Autotuner:
         good = model["good"]
         best_random = min(good, key=lambda s: s.ms).launch
         final = self.interleaved([self.default, best, best_random], rounds=rounds, steps=final_steps)
+        ship, shipped_from = shipped(final, [self.default, best, best_random])
         return dict(
-            default_launch=self.default, tuned_launch=best, best_random_launch=best_random,
-            default_ms=final[0], tuned_ms=final[1], best_random_ms=final[2],
-            factor_vs_default=final[0] / final[1], factor_vs_best_random=final[2] / final[1],
+            default_launch=self.default, tuned_launch=ship, network_launch=best, best_random_launch=best_random,
+            shipped_from=shipped_from, default_ms=final[0], tuned_ms=min(final), network_ms=final[1],
+            best_random_ms=final[2], factor_vs_default=final[0] / min(final),
+            factor_vs_best_random=final[2] / min(final), network_factor_vs_default=final[0] / final[1],
+            network_factor_vs_best_random=final[2] / final[1],
             r2_test=model["r2_test"], r2_train=model["r2_train"], n_samples=len(samples),
             n_valid=len(good), n_train=model["n_train"], n_test=model["n_test"],
             epochs=len(model["losses"]), final_loss=float(model["losses"][-1]) if len(model["losses"]) else None,
@@ -428,13 +440,17 @@ class BatchAutotuner:
         rnd = min(good, key=lambda s: s.ms)
         best_random = self.space.schedule(rnd.index)
         final = self.interleaved([self.default, best, best_random], rounds=rounds)
+        ship, shipped_from = shipped(final, [self.default, best, best_random])
         per_bucket = lambda sc: {b: sc[0][self.space.bucket.index(b)] for b in sorted(set(self.space.bucket))}
         return dict(
             default_schedule={"seg_per_bucket": per_bucket(self.default), "order": self.default[1]},
-            tuned_schedule={"seg_per_bucket": per_bucket(best), "order": best[1]},
+            tuned_schedule={"seg_per_bucket": per_bucket(ship), "order": ship[1]},
+            network_schedule={"seg_per_bucket": per_bucket(best), "order": best[1]},
             best_random_schedule={"seg_per_bucket": per_bucket(best_random), "order": best_random[1]},
-            tuned=best, default_ms=final[0], tuned_ms=final[1], best_random_ms=final[2],
-            factor_vs_default=final[0] / final[1], factor_vs_best_random=final[2] / final[1],
+            tuned=ship, shipped_from=shipped_from, default_ms=final[0], tuned_ms=min(final), network_ms=final[1],
+            best_random_ms=final[2], factor_vs_default=final[0] / min(final),
+            factor_vs_best_random=final[2] / min(final), network_factor_vs_default=final[0] / final[1],
+            network_factor_vs_best_random=final[2] / final[1],
             r2_test=model["r2_test"], r2_train=model["r2_train"], n_samples=len(samples), n_valid=len(good),
             n_train=model["n_train"], n_test=model["n_test"], epochs=len(model["losses"]),
             space_size=self.space.size, sweep_seconds=t_sweep, collect_seconds=t_collect,
@@ -518,13 +534,16 @@ class SizedAutotuner:
             ok = [(ms, i) for i, (ms, v) in enumerate(cand_ms) if v]
             best = cands[min(ok)[1]] if ok else at.default
             final = at.interleaved([at.default, best], rounds=rounds)
+            ship, shipped_from = shipped(final, [at.default, best], ("default", "network"))
             spec = self.grids[g]
             out.append(dict(
                 n=[int(v) for v in spec.n[:spec.ndim]], ndim=spec.ndim, held_out=g in self.holdout,
                 n_samples=0 if samples[g] is None else len(samples[g]),
                 n_valid=0 if samples[g] is None else sum(1 for s in samples[g] if s.valid),
-                default_launch=at.default, tuned_launch=best, default_ms=final[0], tuned_ms=final[1],
-                factor_vs_default=final[0] / final[1], n_valid_candidates=len(ok),
+                default_launch=at.default, tuned_launch=ship, network_launch=best, shipped_from=shipped_from,
+                default_ms=final[0], tuned_ms=min(final), network_ms=final[1],
+                factor_vs_default=final[0] / min(final), network_factor_vs_default=final[0] / final[1],
+                n_valid_candidates=len(ok),
                 top_pred_relative=[float(math.exp(v * model["z_std"] + model["z_mean"])) for v in top_val],
                 top_measured_ms=[m for m, _ in cand_ms], r2_test=model["r2_test_per_grid"].get(g),
                 sweep_seconds=t_sweep, space_size=at.space.size, steps_per_sample=at.steps))

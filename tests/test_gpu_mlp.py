@@ -191,15 +191,19 @@ def test_tuner_at_300_samples_ranks_unseen_configurations():
     assert share_tuned * 4 <= share_random, info
 
 
+@pytest.mark.xfail(strict=True, reason="the known-optimum target (within 5% at 300 samples) is not met by the "
+                   "paper's training budget: measured 2.42x the optimum, best random sample 2.28x")
 def test_tuner_at_300_samples_against_the_known_optimum():
-    """The known-optimum statement at the measured budget: 300 timed samples
-    (225 training rows), the whole 1.9e8-point space swept, the best of the 8
-    lowest predictions. The target of landing within 5% of the optimum is NOT
-    met at this budget: with the paper's minibatch of 200 and at most 200
-    epochs, 225 rows give at most 400 Adam steps at lr 9e-4, and the fit stays
-    partial (R^2 about 0.6). The pick is recorded, not bounded to the target:
-    it must stay within 2x of the optimum (measured 1.6-1.8x) and the test
-    prints where it lands against the best random sample."""
+    """The known-optimum pin at the measured budget: 300 timed samples (225
+    training rows), the whole 1.9e8-point space swept, the best of the 8
+    lowest predictions, asserted against the target of landing within 5% of
+    the optimum. The target is NOT met: with the paper's minibatch of 200 and
+    at most 200 epochs, 225 rows give at most 400 Adam steps at lr 9e-4, the
+    fit stays partial (R^2 about 0.6) and the exhaustive minimum lands among
+    the network's extrapolation errors (measured 2.42x the optimum, against
+    2.28x for the best of the 300 random samples). The test is a strict
+    expected failure: it records the miss and fails if the method starts
+    meeting the target without the record being updated."""
     sp = LaunchSpace(2)
     rng = np.random.default_rng(11)
     idx = sp.sample(300, 21)
@@ -218,7 +222,7 @@ def test_tuner_at_300_samples_against_the_known_optimum():
     optimum = synthetic_optimum(sp)
     info = dict(tuned_over_optimum=best_tuned / optimum, random_over_optimum=best_random / optimum)
     print(info)
-    assert best_tuned <= 2.0 * optimum, info
+    assert best_tuned <= 1.05 * optimum, info
 
 
 def test_tuner_with_the_papers_sample_budget_lands_near_the_optimum():
@@ -282,4 +286,11 @@ def test_batch_schedule_tuning_end_to_end():
     assert res["tuned_ms"] > 0 and res["default_ms"] > 0
     segs, order = res["tuned"]
     assert len(segs) == len(spec.grids) and order in (0, 1)
-    assert all(sg in BATCH_SEGS for sg in segs)
+    # the shipped schedule is the fastest of the default, the network's pick and
+    # the best random sample under the interleaved timing
+    assert res["shipped_from"] in ("default", "network", "best_random")
+    assert res["tuned_ms"] == min(res["default_ms"], res["network_ms"], res["best_random_ms"])
+    if res["shipped_from"] != "default":
+        assert all(sg in BATCH_SEGS for sg in segs)
+    net_segs, _ = res["network_schedule"]["seg_per_bucket"], res["network_schedule"]["order"]
+    assert all(sg in BATCH_SEGS for sg in net_segs.values())
