@@ -40,6 +40,8 @@ class OrGrid(ctypes.Structure):
         ("kappa", ctypes.c_double),
         ("source", ctypes.c_void_p),
         ("bc_state", ((ctypes.c_double * 5) * 2) * 3),
+        ("mu", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
     ]
 
 
@@ -75,6 +77,8 @@ def lib():
                                      c_double_p, c_double_p]
         L.or_run.argtypes = [g, c_double_p, ctypes.c_int32, c_double_p, c_double_p, c_u32_p]
         L.or_residual_vjp.argtypes = [g, c_double_p, c_double_p, c_double_p]
+        L.or_visc_face_flux.argtypes = [g, c_double_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, c_double_p]
         L.or_rk3_step_vjp.argtypes = [g, c_double_p, ctypes.c_double, c_double_p]
         _lib = L
     return _lib
@@ -120,6 +124,10 @@ def make_grid(spec, limiter=True, kappa=-1.0, source=None):
     g.gamma = float(spec.gamma)
     g.cfl = float(spec.cfl)
     g.kappa = float(kappa)
+    g.mu = float(getattr(spec, "mu", 0.0))
+    g.prandtl = float(getattr(spec, "prandtl", 0.72))
+    if g.mu < 0.0 or not g.prandtl > 0.0:
+        raise ValueError("viscosity must be >= 0 and the Prandtl number > 0")
     st = getattr(spec, "bc_state", None)
     if st is not None:
         st = np.asarray(st, dtype=np.float64)
@@ -202,6 +210,17 @@ def residual_cs(spec, U, V, h=1e-30, limiter=True):
     return R, dR
 
 
+def visc_face_flux(spec, U, ax, i, j, k=0):
+    """Viscous flux F_nu,n (Eq. QF, n = e_ax) through the face between cell
+    (i, j, k) and its neighbour along axis ax (indices may lie one cell
+    outside the grid: they go through the boundary maps)."""
+    g = make_grid(spec)
+    U = _arr(U)
+    F = np.zeros(spec.ndim + 2)
+    lib().or_visc_face_flux(ctypes.byref(g), _p(U), int(ax), int(i), int(j), int(k), _p(F))
+    return F
+
+
 def max_wavespeed(spec, U):
     g = make_grid(spec)
     U = _arr(U)
@@ -249,8 +268,14 @@ def run(spec, U, nsteps, dt_in=None, limiter=True, kappa=-1.0, source=None):
     return U, dts[:nsteps], fl.value
 
 
+def _inviscid_only(spec):
+    if getattr(spec, "mu", 0.0) > 0.0:
+        raise NotImplementedError("the reverse gradient covers the inviscid residual only")
+
+
 def residual_vjp(spec, U, w, limiter=True):
     """(dR/dU)^T w."""
+    _inviscid_only(spec)
     g = make_grid(spec, limiter)
     U = _arr(U)
     w = _arr(w)
@@ -262,6 +287,7 @@ def residual_vjp(spec, U, w, limiter=True):
 def rk3_step_vjp(spec, U, dt_, lam, limiter=True, kappa=-1.0, source=None):
     """dJ/dU^n from dJ/dU^{n+1} = lam for one step at frozen dt (a source
     moves the stage states the derivative is taken at, not the derivative's form)."""
+    _inviscid_only(spec)
     g = make_grid(spec, limiter, kappa, source)
     U = _arr(U)
     lam = _arr(lam).copy()

@@ -6,15 +6,17 @@
 //
 // What it computes, each part following the paper's description of SENSEI:
 //   * cell-wise semi-discrete form |Omega_k| dU/dt + R = 0 (Eq. spatial_residual),
-//   * residual R = sum over faces of the normal inviscid flux times face area,
-//     source term zero (Eq. residual; the inviscid flux of Eq. QF),
+//   * residual R = sum over faces of the normal inviscid minus viscous flux
+//     times face area, minus |Omega| times the cell-averaged source (Eq.
+//     residual; the fluxes of Eq. QF; the viscous flux, with Stokes stresses
+//     and Fourier heat conduction, only when a viscosity is given),
 //   * face states by MUSCL extrapolation with epsilon = 1 and a limiter Psi
 //     (Eq. flux); kappa is a parameter, -1 (fully upwind) on the measured path,
 //   * an explicit Runge-Kutta march (Sec. "A Test Case"), here the three-stage
 //     strong-stability-preserving scheme of Shu and Osher,
-//   * a stability-limited time step (Sec. "The CFD Code Base": the ODE solver is
-//     used "provided stability conditions are met"): dt = CFL / max_cells
-//     sum_d (|u_d| + c) / dx_d.
+//   * a stability-limited time step (Sec. "The CFD Code Base" asks only that the
+//     time march be stable): dt = CFL / max_cells sum_d (|u_d| + c) / dx_d,
+//     plus the explicit diffusion limit when a viscosity is given.
 // The paper names no limiter, flux function or Runge-Kutta order; this oracle
 // uses the minmod limiter, Roe's approximate Riemann solver (Roe 1981; Toro,
 // "Riemann Solvers and Numerical Methods for Fluid Dynamics", ch. 11) and
@@ -56,6 +58,8 @@ struct OrGrid {
     double kappa;       // MUSCL kappa (-1 on the measured path)
     const double* source;  // cell-averaged source S[v][k][j][i], or null for S = 0
     double bc_state[3][2][5];  // conserved state of the ghost cells of an inflow face
+    double mu;          // dynamic viscosity (constant); 0 for the Euler equations
+    double prandtl;     // Prandtl number of the heat flux (used when mu > 0)
 };
 }
 
@@ -286,6 +290,107 @@ static void face_flux(const OrGrid* g, const T* U, int ax, int64_t i, int64_t j,
     roe_flux(g->ndim, ax, g->gamma, QL, QR, F);
 }
 
+// Conserved state at cell position p (each axis index in [-2, n + 1]) through
+// the boundary maps of every axis it lies outside of: the index is mapped
+// axis by axis, a slip wall reverses that axis's momentum, and a position
+// behind an inflow face takes the face's given state. A corner position (out
+// of range on two axes) composes the maps of both.
+template <class T>
+static void cell_state(const OrGrid* g, const T* U, const int64_t p[3], T* q) {
+    const int nv = g->ndim + 2;
+    const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
+    int64_t c[3];
+    double sgn[5] = {1.0, 1.0, 1.0, 1.0, 1.0};
+    for (int ax = 0; ax < 3; ++ax) {
+        if (ax < g->ndim) {
+            const double* fixed = bc_fixed(g, ax, p[ax]);
+            if (fixed) {
+                for (int v = 0; v < nv; ++v) q[v] = T(fixed[v]);
+                return;
+            }
+            for (int v = 0; v < nv; ++v) sgn[v] *= bc_sign(p[ax], g->n[ax], g->bc[ax][0], g->bc[ax][1], v, ax);
+            c[ax] = bc_index(p[ax], g->n[ax], g->bc[ax][0], g->bc[ax][1]);
+        } else {
+            c[ax] = 0;
+        }
+    }
+    const int64_t off = cell_offset(g, c[0], c[1], c[2]);
+    for (int v = 0; v < nv; ++v) q[v] = U[v * ncell + off] * sgn[v];
+}
+
+// Velocity and temperature of a conserved state: T = p / rho, the ideal gas
+// with unit gas constant of the nondimensional states used here.
+template <class T>
+static void velocity_temperature(int ndim, double gam, const T* q, T* w) {
+    const T rho = q[0];
+    T qq = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        w[d] = q[1 + d] / rho;
+        qq = qq + w[d] * w[d];
+    }
+    const T p = (gam - 1.0) * (q[ndim + 1] - 0.5 * rho * qq);
+    w[ndim] = p / rho;
+}
+
+// Viscous flux normal to axis `ax` through the face between cell c and
+// c + e_ax (F_nu,n of Eq. QF with n = e_ax):
+//   (0, tau_{x,ax}, tau_{y,ax}, [tau_{z,ax}], Theta_ax),
+//   tau_ab = mu (du_a/dx_b + du_b/dx_a) - 2/3 mu delta_ab div(u)   (Stokes),
+//   Theta_ax = sum_b u_b tau_{b,ax} + k dT/dx_ax,   k = mu c_p / Pr,
+//   c_p = gamma / (gamma - 1) (unit gas constant).
+// Face gradients, second order on the uniform grid: the normal derivative is
+// the difference of the two cells across the face over dx_ax; a tangential
+// derivative along t is the mean of the central differences of those two
+// cells, (w(c+e_t) - w(c-e_t) + w(c+e_ax+e_t) - w(c+e_ax-e_t)) / (4 dx_t);
+// the velocity in Theta is the mean of the two cells.
+template <class T>
+static void visc_face_flux(const OrGrid* g, const T* U, int ax, int64_t i, int64_t j, int64_t k, T* F) {
+    const int ndim = g->ndim, nv = ndim + 2;
+    const double mu = g->mu;
+    const double kc = mu * (g->gamma / (g->gamma - 1.0)) / g->prandtl;
+    const int64_t c0[3] = {i, j, k};
+    // w = (u, v, [w], T) at the two cells across the face
+    T q[5], wa[4], wb[4];
+    int64_t p[3] = {c0[0], c0[1], c0[2]};
+    cell_state(g, U, p, q);
+    velocity_temperature(ndim, g->gamma, q, wa);
+    p[ax] += 1;
+    cell_state(g, U, p, q);
+    velocity_temperature(ndim, g->gamma, q, wb);
+    // grad[m][d] = d w_m / d x_d at the face
+    T grad[4][3];
+    for (int m = 0; m <= ndim; ++m) grad[m][ax] = (wb[m] - wa[m]) / g->dx[ax];
+    for (int t = 0; t < ndim; ++t) {
+        if (t == ax) continue;
+        T wp[2][4], wm[2][4];
+        for (int side = 0; side < 2; ++side) {
+            int64_t pp[3] = {c0[0], c0[1], c0[2]};
+            pp[ax] += side;
+            pp[t] += 1;
+            cell_state(g, U, pp, q);
+            velocity_temperature(ndim, g->gamma, q, wp[side]);
+            pp[t] -= 2;
+            cell_state(g, U, pp, q);
+            velocity_temperature(ndim, g->gamma, q, wm[side]);
+        }
+        for (int m = 0; m <= ndim; ++m)
+            grad[m][t] = ((wp[0][m] - wm[0][m]) + (wp[1][m] - wm[1][m])) / (4.0 * g->dx[t]);
+    }
+    T divu = T(0.0);
+    for (int d = 0; d < ndim; ++d) divu = divu + grad[d][d];
+    // tau_{a,ax} for every a, then Theta_ax
+    T tau[3];
+    for (int a = 0; a < ndim; ++a) {
+        tau[a] = mu * (grad[a][ax] + grad[ax][a]);
+        if (a == ax) tau[a] = tau[a] - (2.0 / 3.0) * mu * divu;
+    }
+    T theta = kc * grad[ndim][ax];
+    for (int b = 0; b < ndim; ++b) theta = theta + 0.5 * (wa[b] + wb[b]) * tau[b];
+    F[0] = T(0.0);
+    for (int a = 0; a < ndim; ++a) F[1 + a] = tau[a];
+    F[nv - 1] = theta;
+}
+
 static inline double face_area(const OrGrid* g, int ax) {
     double a = 1.0;
     for (int d = 0; d < g->ndim; ++d)
@@ -317,6 +422,16 @@ static void residual(const OrGrid* g, const T* U, T* R) {
             T Fp[5], Fm[5];
             face_flux(g, U, ax, i, j, k, Fp);
             face_flux(g, U, ax, im[0], im[1], im[2], Fm);
+            if (g->mu > 0.0) {
+                // F_i,n - F_nu,n on each face (Eq. residual)
+                T Vp[5], Vm[5];
+                visc_face_flux(g, U, ax, i, j, k, Vp);
+                visc_face_flux(g, U, ax, im[0], im[1], im[2], Vm);
+                for (int v = 0; v < nv; ++v) {
+                    Fp[v] = Fp[v] - Vp[v];
+                    Fm[v] = Fm[v] - Vm[v];
+                }
+            }
             double A = face_area(g, ax);
             for (int v = 0; v < nv; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]) * A;
         }
@@ -398,6 +513,15 @@ double or_max_wavespeed(const OrGrid* g, const double* U, uint32_t* flags) {
         double cs = std::sqrt(g->gamma * p / rho);
         double lam = 0.0;
         for (int d = 0; d < ndim; ++d) lam += (std::fabs(u[d]) + cs) / g->dx[d];
+        if (g->mu > 0.0) {
+            // explicit diffusion limit: 2 nu_eff sum_d 1/dx_d^2 with the larger
+            // of the momentum (4/3 mu / rho) and heat (gamma mu / (Pr rho))
+            // diffusivities
+            const double nu = (g->mu / rho) * std::fmax(4.0 / 3.0, g->gamma / g->prandtl);
+            double s2 = 0.0;
+            for (int d = 0; d < ndim; ++d) s2 += 1.0 / (g->dx[d] * g->dx[d]);
+            lam += 2.0 * nu * s2;
+        }
         if (std::isnan(lam) || std::isnan(rho) || std::isnan(p)) fl |= OR_FLAG_NAN;
         if (!(rho > 0.0)) fl |= OR_FLAG_RHO;
         if (!(p > 0.0)) fl |= OR_FLAG_P;
@@ -405,6 +529,10 @@ double or_max_wavespeed(const OrGrid* g, const double* U, uint32_t* flags) {
     }
     if (flags) *flags |= fl;
     return lmax;
+}
+
+void or_visc_face_flux(const OrGrid* g, const double* U, int ax, int64_t i, int64_t j, int64_t k, double* F) {
+    visc_face_flux(g, U, ax, i, j, k, F);
 }
 
 double or_dt(const OrGrid* g, const double* U, uint32_t* flags) {

@@ -10,6 +10,12 @@ its source is that divergence, differentiated by hand with the product rule.
 Fed the cell averages of both, the discrete residual is the scheme's
 truncation error, which falls as h^2 for a second-order scheme.
 
+With a viscosity the same fields serve the Navier-Stokes form of Eq.
+(governing): the source becomes the divergence of the inviscid flux minus the
+divergence of the viscous flux F_nu of Eq. (QF) (Stokes stresses, heat flux
+k dT/dx_d with T = p / rho and k = mu gamma / ((gamma - 1) Pr)), also
+differentiated by hand (``viscous_divergence``, ``ns_source``).
+
 Fields on the periodic unit square (x, y in [0, 1]):
   rho = 1   + 0.15 sin(2 pi x) + 0.10 cos(2 pi y)
   u   = 0.7 + 0.05 sin(2 pi x) + 0.05 cos(4 pi y)
@@ -160,3 +166,74 @@ def cell_averages3(fn, n, order=3):
                 Z, Y, X = np.meshgrid(c + 0.5 * h * e, c + 0.5 * h * b, c + 0.5 * h * a, indexing="ij")
                 out += 0.125 * wa * wb * we * fn(X, Y, Z)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Navier-Stokes: the divergence of the viscous flux on the manufactured fields
+# (2D or 3D), for constant mu. Every field is a sum of one-variable terms, so
+# mixed second derivatives of the velocity vanish and, with
+# tau_bd = mu (du_b/dx_d + du_d/dx_b) - 2/3 mu delta_bd div(u),
+#   sum_d d tau_bd / dx_d = mu (lap u_b + 1/3 d/dx_b div u) = mu (lap u_b + 1/3 d2u_b/dx_b2),
+#   sum_d d Theta_d / dx_d = sum_bd du_b/dx_d tau_bd + sum_b u_b sum_d d tau_bd/dx_d + k lap T,
+# with Theta_d = sum_b u_b tau_bd + k dT/dx_d. T = p / rho is not a sum of
+# one-variable terms; only its pure second derivatives enter:
+#   T_d = (p_d - T rho_d) / rho,  T_dd = (p_dd - 2 T_d rho_d - T rho_dd) / rho.
+
+def _term2(t, s):
+    """Value, first and second derivative of amp * sin|cos(2 pi k s)."""
+    amp, k, kind = t
+    w = TWO_PI * k
+    if kind == "sin":
+        f = amp * np.sin(w * s)
+        return f, amp * w * np.cos(w * s), -w * w * f
+    f = amp * np.cos(w * s)
+    return f, -amp * w * np.sin(w * s), -w * w * f
+
+
+def _field_derivs(table, name, coords):
+    """(value, [d/dx_d], [d2/dx_d2]) of a primitive field of `table` at the points."""
+    mean, *terms = table[name]
+    zero = 0.0 * sum(coords)
+    val, d1, d2 = mean + zero, [], []
+    for t, c in zip(terms, coords):
+        f, df, ddf = _term2(t, c)
+        val = val + f
+        d1.append(df + zero)
+        d2.append(ddf + zero)
+    return val, d1, d2
+
+
+def viscous_divergence(coords, mu, prandtl, gamma=1.4):
+    """sum_d d F_nu,d / d x_d on the manufactured fields: (0, momentum..., energy).
+    coords = (x, y) uses the 2D fields, (x, y, z) the 3D ones."""
+    nd = len(coords)
+    table = FIELDS if nd == 2 else FIELDS3
+    names = ("u", "v") if nd == 2 else ("u", "v", "w")
+    vel = [_field_derivs(table, c, coords) for c in names]
+    r, rd, rdd = _field_derivs(table, "rho", coords)
+    p, pd, pdd = _field_derivs(table, "p", coords)
+    T = p / r
+    Td = [(pd[d] - T * rd[d]) / r for d in range(nd)]
+    Tdd = [(pdd[d] - 2.0 * Td[d] * rd[d] - T * rdd[d]) / r for d in range(nd)]
+    kc = mu * gamma / ((gamma - 1.0) * prandtl)
+    div = sum(vel[d][1][d] for d in range(nd))
+    tau = [[mu * (vel[b][1][d] + vel[d][1][b]) - (2.0 / 3.0 * mu * div if b == d else 0.0)
+            for d in range(nd)] for b in range(nd)]
+    mom = [mu * (sum(vel[b][2][d] for d in range(nd)) + vel[b][2][b] / 3.0) for b in range(nd)]
+    en = kc * sum(Tdd)
+    for b in range(nd):
+        en = en + vel[b][0] * mom[b]
+        for d in range(nd):
+            en = en + vel[b][1][d] * tau[b][d]
+    zero = 0.0 * r
+    return np.stack([zero] + [m + zero for m in mom] + [en])
+
+
+def ns_source(x, y, mu, prandtl=0.72, gamma=1.4):
+    """Source of the 2D manufactured solution for the Navier-Stokes equations."""
+    return source(x, y, gamma) - viscous_divergence((x, y), mu, prandtl, gamma)
+
+
+def ns_source3(x, y, z, mu, prandtl=0.72, gamma=1.4):
+    """Source of the 3D manufactured solution for the Navier-Stokes equations."""
+    return source3(x, y, z, gamma) - viscous_divergence((x, y, z), mu, prandtl, gamma)
