@@ -42,6 +42,7 @@ class OrGrid(ctypes.Structure):
         ("bc_state", ((ctypes.c_double * 5) * 2) * 3),
         ("mu", ctypes.c_double),
         ("prandtl", ctypes.c_double),
+        ("nodes", ctypes.c_void_p),
     ]
 
 
@@ -77,6 +78,8 @@ def lib():
                                      c_double_p, c_double_p]
         L.or_run.argtypes = [g, c_double_p, ctypes.c_int32, c_double_p, c_double_p, c_u32_p]
         L.or_residual_vjp.argtypes = [g, c_double_p, c_double_p, c_double_p]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_max_threads.restype = ctypes.c_int
         L.or_visc_face_flux.argtypes = [g, c_double_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int64, c_double_p]
         L.or_rk3_step_vjp.argtypes = [g, c_double_p, ctypes.c_double, c_double_p]
@@ -128,6 +131,17 @@ def make_grid(spec, limiter=True, kappa=-1.0, source=None):
     g.prandtl = float(getattr(spec, "prandtl", 0.72))
     if g.mu < 0.0 or not g.prandtl > 0.0:
         raise ValueError("viscosity must be >= 0 and the Prandtl number > 0")
+    nodes = getattr(spec, "nodes", None)
+    if nodes is not None:
+        if spec.ndim != 2:
+            raise NotImplementedError("curvilinear grids are 2D here")
+        if g.mu > 0.0:
+            raise NotImplementedError("the viscous flux is taken on uniform grids only")
+        nd = np.ascontiguousarray(nodes, dtype=np.float64)
+        if nd.shape != (2, int(spec.n[1]) + 1, int(spec.n[0]) + 1):
+            raise ValueError("nodes must have shape (2, ny + 1, nx + 1)")
+        g._nodes_ref = nd
+        g.nodes = nd.ctypes.data
     st = getattr(spec, "bc_state", None)
     if st is not None:
         st = np.asarray(st, dtype=np.float64)
@@ -271,6 +285,8 @@ def run(spec, U, nsteps, dt_in=None, limiter=True, kappa=-1.0, source=None):
 def _inviscid_only(spec):
     if getattr(spec, "mu", 0.0) > 0.0:
         raise NotImplementedError("the reverse gradient covers the inviscid residual only")
+    if getattr(spec, "nodes", None) is not None:
+        raise NotImplementedError("the reverse gradient covers uniform grids only")
 
 
 def residual_vjp(spec, U, w, limiter=True):
@@ -296,11 +312,10 @@ def rk3_step_vjp(spec, U, dt_, lam, limiter=True, kappa=-1.0, source=None):
 
 
 def omp_threads():
-    """Threads the oracle's OpenMP loops use (OMP_NUM_THREADS or all cores)."""
-    v = os.environ.get("OMP_NUM_THREADS")
-    if v:
-        try:
-            return int(v)
-        except ValueError:
-            pass
-    return os.cpu_count() or 1
+    """Threads the oracle's OpenMP loops use now."""
+    return int(lib().or_max_threads())
+
+
+def set_threads(n):
+    """Sets the threads of the oracle's OpenMP loops (n >= 1)."""
+    lib().or_set_threads(int(n))

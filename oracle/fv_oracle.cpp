@@ -37,6 +37,8 @@
 //
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (see oracle/build.py).
 
+#include <omp.h>
+
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -60,6 +62,8 @@ struct OrGrid {
     double bc_state[3][2][5];  // conserved state of the ghost cells of an inflow face
     double mu;          // dynamic viscosity (constant); 0 for the Euler equations
     double prandtl;     // Prandtl number of the heat flux (used when mu > 0)
+    const double* nodes;  // 2D curvilinear grid: node coordinates [2][ny+1][nx+1], or null for the
+                          // uniform box given by dx
 };
 }
 
@@ -391,6 +395,178 @@ static void visc_face_flux(const OrGrid* g, const T* U, int ax, int64_t i, int64
     F[nv - 1] = theta;
 }
 
+// ---------------------------------------------------------------------------
+// Curvilinear grids (2D): the cells are the quadrilaterals of a structured
+// node array; the fluxes of Eq. (QF) are taken normal to each face, V_n = n.u,
+// and scaled by the face's length (its area per unit depth); the residual is
+// divided by each cell's own area.
+
+static inline double node(const OrGrid* g, int d, int64_t i, int64_t j) {
+    return g->nodes[(int64_t)d * (g->n[0] + 1) * (g->n[1] + 1) + j * (g->n[0] + 1) + i];
+}
+
+// Area vector S (length times unit normal, pointing from cell c to c + e_ax)
+// of the face between cell c = (i, j) and c + e_ax; the face runs along node
+// column i + 1 (ax = 0) or node row j + 1 (ax = 1), so c may be -1 on ax.
+static void face_vector(const OrGrid* g, int ax, int64_t i, int64_t j, double S[2]) {
+    double ax0, ay0, ax1, ay1;
+    if (ax == 0) {
+        ax0 = node(g, 0, i + 1, j), ay0 = node(g, 1, i + 1, j);
+        ax1 = node(g, 0, i + 1, j + 1), ay1 = node(g, 1, i + 1, j + 1);
+        S[0] = ay1 - ay0;
+        S[1] = -(ax1 - ax0);
+    } else {
+        ax0 = node(g, 0, i, j + 1), ay0 = node(g, 1, i, j + 1);
+        ax1 = node(g, 0, i + 1, j + 1), ay1 = node(g, 1, i + 1, j + 1);
+        S[0] = -(ay1 - ay0);
+        S[1] = ax1 - ax0;
+    }
+}
+
+// Area of quadrilateral cell (i, j): half the cross product of its diagonals.
+static double cell_area(const OrGrid* g, int64_t i, int64_t j) {
+    const double d1x = node(g, 0, i + 1, j + 1) - node(g, 0, i, j), d1y = node(g, 1, i + 1, j + 1) - node(g, 1, i, j);
+    const double d2x = node(g, 0, i, j + 1) - node(g, 0, i + 1, j), d2y = node(g, 1, i, j + 1) - node(g, 1, i + 1, j);
+    return 0.5 * (d1x * d2y - d1y * d2x);
+}
+
+// Roe flux along a unit normal n (Roe 1981; the normal form of Blazek,
+// "Computational Fluid Dynamics: Principles and Applications", sec. 4.3.3):
+//   F = (F_n(QL) + F_n(QR))/2 - 1/2 [ |V - c| (dp - rho c dV)/(2c^2) (1, u - c n, H - V c)
+//       + |V| ((drho - dp/c^2) (1, u, |u|^2/2) + rho (0, du - dV n, u.du - V dV))
+//       + |V + c| (dp + rho c dV)/(2c^2) (1, u + c n, H + V c) ],
+// V = n.u, Roe-averaged quantities without subscripts.
+template <class T>
+static void roe_flux_n(int ndim, const double* n, double gam, const T* QL, const T* QR, T* F) {
+    const int ie = ndim + 1;
+    T rL = QL[0], rR = QR[0];
+    T uL[3], uR[3];
+    T qqL = T(0.0), qqR = T(0.0), VL = T(0.0), VR = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        uL[d] = QL[1 + d] / rL;
+        uR[d] = QR[1 + d] / rR;
+        qqL = qqL + uL[d] * uL[d];
+        qqR = qqR + uR[d] * uR[d];
+        VL = VL + n[d] * uL[d];
+        VR = VR + n[d] * uR[d];
+    }
+    T pL = (gam - 1.0) * (QL[ie] - 0.5 * rL * qqL);
+    T pR = (gam - 1.0) * (QR[ie] - 0.5 * rR * qqR);
+    T HL = (QL[ie] + pL) / rL, HR = (QR[ie] + pR) / rR;
+    // physical normal fluxes (Eq. QF)
+    T FL[5], FR[5];
+    FL[0] = rL * VL;
+    FR[0] = rR * VR;
+    for (int d = 0; d < ndim; ++d) {
+        FL[1 + d] = QL[1 + d] * VL + n[d] * pL;
+        FR[1 + d] = QR[1 + d] * VR + n[d] * pR;
+    }
+    FL[ie] = rL * HL * VL;
+    FR[ie] = rR * HR * VR;
+    // Roe averages
+    T sL = std::sqrt(rL), sR = std::sqrt(rR);
+    T u[3], qq = T(0.0), V = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        u[d] = (sL * uL[d] + sR * uR[d]) / (sL + sR);
+        qq = qq + u[d] * u[d];
+        V = V + n[d] * u[d];
+    }
+    T H = (sL * HL + sR * HR) / (sL + sR);
+    T rho = sL * sR;
+    T c = std::sqrt((gam - 1.0) * (H - 0.5 * qq));
+    T dp = pR - pL, drho = rR - rL, dV = VR - VL;
+    T du[3], udu = T(0.0);
+    for (int d = 0; d < ndim; ++d) {
+        du[d] = uR[d] - uL[d];
+        udu = udu + u[d] * du[d];
+    }
+    T l1 = absr(V - c), l2 = absr(V), l5 = absr(V + c);
+    T a1 = (dp - rho * c * dV) / (2.0 * c * c);
+    T a5 = (dp + rho * c * dV) / (2.0 * c * c);
+    T a2 = drho - dp / (c * c);
+    T D[5];
+    D[0] = l1 * a1 + l2 * a2 + l5 * a5;
+    for (int d = 0; d < ndim; ++d)
+        D[1 + d] = l1 * a1 * (u[d] - c * n[d]) + l2 * (a2 * u[d] + rho * (du[d] - dV * n[d])) +
+                   l5 * a5 * (u[d] + c * n[d]);
+    D[ie] = l1 * a1 * (H - V * c) + l2 * (a2 * 0.5 * qq + rho * (udu - V * dV)) + l5 * a5 * (H + V * c);
+    for (int v = 0; v < ndim + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
+}
+
+// Flux through the face between cell (i, j) and its neighbour along ax on a
+// curvilinear 2D grid, times the face length. The four stencil cells along
+// the grid line are mapped as on the uniform grid; behind a slip wall the
+// mirror cell's velocity is reflected about the wall face's unit normal
+// (u - 2 (u.n) n), which on a Cartesian face reverses the normal momentum.
+template <class T>
+static void face_flux_curv(const OrGrid* g, const T* U, int ax, int64_t i, int64_t j, T* F) {
+    const int nv = 4;
+    const int64_t ncell = g->n[0] * g->n[1];
+    const int64_t n = g->n[ax];
+    int64_t idx[2] = {i, j};
+    double S[2];
+    face_vector(g, ax, i, j, S);
+    const double len = std::sqrt(S[0] * S[0] + S[1] * S[1]);
+    const double nrm[3] = {S[0] / len, S[1] / len, 0.0};
+    T q[4][4];
+    for (int m = 0; m < 4; ++m) {
+        int64_t c[2] = {idx[0], idx[1]};
+        const int64_t pos = idx[ax] - 1 + m;
+        c[ax] = bc_index(pos, n, g->bc[ax][0], g->bc[ax][1]);
+        const double* fixed = bc_fixed(g, ax, pos);
+        if (fixed) {
+            for (int v = 0; v < nv; ++v) q[m][v] = T(fixed[v]);
+            continue;
+        }
+        const int64_t off = c[1] * g->n[0] + c[0];
+        for (int v = 0; v < nv; ++v) q[m][v] = U[v * ncell + off];
+        const bool wall = (pos < 0 && g->bc[ax][0] == 2) || (pos >= n && g->bc[ax][1] == 2);
+        if (wall) {
+            // unit normal of the wall face of this grid line
+            int64_t w[2] = {idx[0], idx[1]};
+            w[ax] = pos < 0 ? -1 : n - 1;
+            double Sw[2];
+            face_vector(g, ax, w[0], w[1], Sw);
+            const double lw = std::sqrt(Sw[0] * Sw[0] + Sw[1] * Sw[1]);
+            const double nw[2] = {Sw[0] / lw, Sw[1] / lw};
+            T mn = q[m][1] * nw[0] + q[m][2] * nw[1];
+            q[m][1] = q[m][1] - 2.0 * mn * nw[0];
+            q[m][2] = q[m][2] - 2.0 * mn * nw[1];
+        }
+    }
+    T QL[4], QR[4];
+    for (int v = 0; v < nv; ++v) muscl(q[0][v], q[1][v], q[2][v], q[3][v], g->limiter, g->kappa, QL[v], QR[v]);
+    roe_flux_n(2, nrm, g->gamma, QL, QR, F);
+    for (int v = 0; v < nv; ++v) F[v] = F[v] * len;
+}
+
+template <class T>
+static void residual_curv(const OrGrid* g, const T* U, T* R) {
+    const int64_t nx = g->n[0], ny = g->n[1];
+    const int64_t ncell = nx * ny;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < ncell; ++c) {
+        int64_t i = c % nx, j = c / nx;
+        T acc[4];
+        for (int v = 0; v < 4; ++v) acc[v] = T(0.0);
+        for (int ax = 0; ax < 2; ++ax) {
+            T Fp[4], Fm[4];
+            face_flux_curv(g, U, ax, i, j, Fp);
+            face_flux_curv(g, U, ax, ax == 0 ? i - 1 : i, ax == 1 ? j - 1 : j, Fm);
+            for (int v = 0; v < 4; ++v) acc[v] = acc[v] + (Fp[v] - Fm[v]);
+        }
+        if (g->source) {
+            const double vol = cell_area(g, i, j);
+            for (int v = 0; v < 4; ++v) acc[v] = acc[v] - vol * g->source[v * ncell + c];
+        }
+        for (int v = 0; v < 4; ++v) R[v * ncell + c] = acc[v];
+    }
+}
+
+// Volume of cell c (flattened index): the uniform box's, or the
+// quadrilateral's area on a curvilinear grid.
+static inline double cell_vol(const OrGrid* g, int64_t c);
+
 static inline double face_area(const OrGrid* g, int ax) {
     double a = 1.0;
     for (int d = 0; d < g->ndim; ++d)
@@ -404,10 +580,19 @@ static inline double cell_volume(const OrGrid* g) {
     return v;
 }
 
+static inline double cell_vol(const OrGrid* g, int64_t c) {
+    if (!g->nodes) return cell_volume(g);
+    return cell_area(g, c % g->n[0], c / g->n[0]);
+}
+
 // R_c = sum_ax (F_{c+1/2} - F_{c-1/2}) * A_ax - |Omega| S_c   (Eq. residual;
 // S_c is the cell average of the source, zero when none is given).
 template <class T>
 static void residual(const OrGrid* g, const T* U, T* R) {
+    if (g->nodes) {
+        residual_curv(g, U, R);
+        return;
+    }
     const int nv = g->ndim + 2;
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const int64_t ncell = nx * ny * nz;
@@ -450,17 +635,23 @@ static void rk3_step(const OrGrid* g, T* U, double dt) {
     const int nv = g->ndim + 2;
     const int64_t ncell = g->n[0] * g->n[1] * g->n[2];
     const int64_t N = nv * ncell;
-    const double vol = cell_volume(g);
+    std::vector<double> vol(ncell);
+    for (int64_t c = 0; c < ncell; ++c) vol[c] = cell_vol(g, c);
     std::vector<T> R(N), U1(N), U2(N);
     residual(g, U, R.data());
-    for (int64_t e = 0; e < N; ++e) U1[e] = U[e] + dt * (-R[e] / vol);
+    for (int64_t e = 0; e < N; ++e) U1[e] = U[e] + dt * (-R[e] / vol[e % ncell]);
     residual(g, U1.data(), R.data());
-    for (int64_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * (-R[e] / vol));
+    for (int64_t e = 0; e < N; ++e) U2[e] = 0.75 * U[e] + 0.25 * (U1[e] + dt * (-R[e] / vol[e % ncell]));
     residual(g, U2.data(), R.data());
-    for (int64_t e = 0; e < N; ++e) U[e] = (1.0 / 3.0) * U[e] + (2.0 / 3.0) * (U2[e] + dt * (-R[e] / vol));
+    for (int64_t e = 0; e < N; ++e)
+        U[e] = (1.0 / 3.0) * U[e] + (2.0 / 3.0) * (U2[e] + dt * (-R[e] / vol[e % ncell]));
 }
 
 extern "C" {
+
+// Threads of the OpenMP loops (for timing the oracle on one core and on all).
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_max_threads() { return omp_get_max_threads(); }
 
 double or_psi_minmod(double r) { return psi_minmod(r); }
 
@@ -512,7 +703,21 @@ double or_max_wavespeed(const OrGrid* g, const double* U, uint32_t* flags) {
         double p = (g->gamma - 1.0) * (U[ie * ncell + c] - 0.5 * rho * qq);
         double cs = std::sqrt(g->gamma * p / rho);
         double lam = 0.0;
-        for (int d = 0; d < ndim; ++d) lam += (std::fabs(u[d]) + cs) / g->dx[d];
+        if (g->nodes) {
+            // curvilinear: sum over the grid directions of (|u.S| + c |S|) / area,
+            // S the mean of the cell's two face area vectors on that direction
+            const int64_t i = c % g->n[0], j = c / g->n[0];
+            const double area = cell_area(g, i, j);
+            for (int ax = 0; ax < 2; ++ax) {
+                double Sa[2], Sb[2];
+                face_vector(g, ax, ax == 0 ? i - 1 : i, ax == 1 ? j - 1 : j, Sa);
+                face_vector(g, ax, i, j, Sb);
+                const double Sx = 0.5 * (Sa[0] + Sb[0]), Sy = 0.5 * (Sa[1] + Sb[1]);
+                lam += (std::fabs(u[0] * Sx + u[1] * Sy) + cs * std::sqrt(Sx * Sx + Sy * Sy)) / area;
+            }
+        } else {
+            for (int d = 0; d < ndim; ++d) lam += (std::fabs(u[d]) + cs) / g->dx[d];
+        }
         if (g->mu > 0.0) {
             // explicit diffusion limit: 2 nu_eff sum_d 1/dx_d^2 with the larger
             // of the momentum (4/3 mu / rho) and heat (gamma mu / (Pr rho))

@@ -44,6 +44,7 @@ class GridSpec:
     bc_state: tuple = None  # (3, 2, nvar) conserved ghost state of inflow faces (kind 3)
     mu: float = 0.0         # dynamic viscosity: 0 for the Euler equations, > 0 adds the viscous flux
     prandtl: float = 0.72   # Prandtl number of the heat flux
+    nodes: object = None    # 2D curvilinear grid: node coordinates, shape (2, ny + 1, nx + 1); None: the box
 
     @property
     def nvar(self) -> int:
@@ -110,15 +111,20 @@ def vortex_centre(seed: int, jitter=0.5, base=(5.0, 5.0)):
     return (base[0] + off[0], base[1] + off[1])
 
 
-def vortex_state(g: GridSpec, centre, beta=5.0, t=0.0, mach=0.5):
-    """Isentropic vortex point values at the cell centres at time ``t``.
+def vortex_state(g: GridSpec, centre, beta=5.0, t=0.0, mach=0.5, points=None):
+    """Isentropic vortex point values at the cell centres at time ``t`` (or
+    at ``points`` = (x, y), arrays of shape (ny, nx), e.g. the node centroids
+    of a curvilinear grid).
 
     At ``t > 0`` the vortex has been carried by the freestream, so this is also
     the exact solution of the Euler equations on the periodic box.
     """
     gam = g.gamma
-    x, y, _ = g.centres()
-    x, y = x[0], y[0]
+    if points is None:
+        x, y, _ = g.centres()
+        x, y = x[0], y[0]
+    else:
+        x, y = points
     ux, uy = freestream_velocity(gam, mach)
     Lx = g.hi[0] - g.lo[0]
     Ly = g.hi[1] - g.lo[1]
@@ -311,3 +317,27 @@ def epoch_orders(n: int, epochs: int, seed: int):
     """One random permutation of range(n) per epoch, shape (epochs, n), int32."""
     rng = np.random.default_rng(seed + 104729)
     return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+
+
+def wavy_nodes(nx, ny, lo=(0.0, 0.0), hi=(10.0, 10.0), amp=0.05, rot=0.0):
+    """Node coordinates (2, ny + 1, nx + 1) of a smoothly distorted grid of the
+    box: x = xi + amp Lx sin(2 pi (eta - lo_y) / Ly), y = eta + amp Ly sin(2 pi
+    (xi - lo_x) / Lx), then rotated by `rot` radians about the origin. The
+    distortion is periodic, so the grid wraps like the box (periodic axes
+    stay periodic in index space)."""
+    Lx, Ly = hi[0] - lo[0], hi[1] - lo[1]
+    xi = lo[0] + Lx * np.arange(nx + 1) / nx
+    eta = lo[1] + Ly * np.arange(ny + 1) / ny
+    E, X = np.meshgrid(eta, xi, indexing="ij")
+    x = X + amp * Lx * np.sin(2 * np.pi * (E - lo[1]) / Ly)
+    y = E + amp * Ly * np.sin(2 * np.pi * (X - lo[0]) / Lx)
+    c, s = math.cos(rot), math.sin(rot)
+    return np.stack([c * x - s * y, s * x + c * y])
+
+
+def node_centroids(nodes):
+    """Mean of each quadrilateral cell's four nodes: arrays (ny, nx) of x and y."""
+    x, y = nodes
+    cx = 0.25 * (x[:-1, :-1] + x[:-1, 1:] + x[1:, :-1] + x[1:, 1:])
+    cy = 0.25 * (y[:-1, :-1] + y[:-1, 1:] + y[1:, :-1] + y[1:, 1:])
+    return cx, cy
