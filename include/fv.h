@@ -20,7 +20,8 @@
  *  - Memory: every pointer argument of type double* or void* workspace is a
  *    DEVICE pointer, owned by the caller, which must keep it valid until the
  *    work enqueued on the context's stream has completed. The library never
- *    allocates device memory: scratch comes from the caller's workspace.
+ *    allocates device memory: scratch comes from the caller's workspace (or,
+ *    for fv_mlp_sweep_static, from a static device array of the library).
  *  - State layout ("ghosted SoA"): FP64, variables outermost, x fastest:
  *      U[v * s_v + (k + g3) * s_z + (j + 2) * s_y + (i + 2)]
  *    for interior cell (i, j, k), v in (rho, rho u, rho v, [rho w], E),
@@ -409,6 +410,22 @@ int fv_mlp_sweep(const float* params, const fv_tune_space* space, int64_t begin,
 
 /* Bytes of device scratch fv_mlp_sweep needs. */
 int fv_mlp_sweep_workspace(size_t* bytes);
+
+/* fv_mlp_sweep without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * re-tune in place, harnesses that forbid hipMalloc): the per-block top-k
+ * lists go to a static device array of the library (384 KiB per device,
+ * held until the process ends; its device address is looked up once per
+ * device on the first call made with that device current). The call itself
+ * allocates nothing. Arguments, results and error codes are those of
+ * fv_mlp_sweep; k above 8 is FV_EINVAL, and a count of any size fits (the
+ * sweep's block count is capped at the array's capacity). FV_EDEVICE when
+ * the array's address cannot be obtained. Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller. No entry of the array
+ * needs to start at zero: each call writes every entry it reads. */
+int fv_mlp_sweep_static(const float* params, const fv_tune_space* space, int64_t begin, int64_t count, int32_t k,
+                        int64_t* top_idx, float* top_val, void* stream);
 
 #ifdef __cplusplus
 }

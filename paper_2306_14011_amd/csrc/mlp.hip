@@ -13,6 +13,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/fv.h"
 #include "fv_device.h"
 
@@ -479,6 +481,97 @@ __global__ void __launch_bounds__(1024) k_sweep_final(float* pv, long long* pi, 
 
 }  // namespace mlp
 
+namespace mlp {
+
+// Per-block top-k lists of the sweep: values, then (256-byte aligned) indices.
+constexpr size_t sweep_scratch_bytes() {
+    return (((size_t)SWEEP_MAXB * KMAX * sizeof(float) + 255) & ~(size_t)255) +
+           (size_t)SWEEP_MAXB * KMAX * sizeof(long long);
+}
+
+// Device scratch of fv_mlp_sweep_static: room for the per-block lists of the
+// largest sweep grid (SWEEP_MAXB blocks; larger counts are covered by the
+// kernel's grid-stride loop, so no count needs more). Every device the
+// library runs on holds its own copy until the process ends.
+constexpr size_t STATIC_SCRATCH_BYTES = 393216;
+static_assert(STATIC_SCRATCH_BYTES >= sweep_scratch_bytes(), "static sweep scratch too small");
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void* scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the host-side name of the array is not a device address).
+static int static_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        fprintf(stderr, "fv_mlp_sweep_static: no usable current device\n");
+        return FV_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fprintf(stderr, "fv_mlp_sweep_static: hipGetSymbolAddress failed: %s\n", hipGetErrorString(e));
+            return FV_EDEVICE;
+        }
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return FV_OK;
+}
+
+static int launch_status() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        fprintf(stderr, "fv_mlp: launch failed: %s\n", hipGetErrorString(e));
+        return FV_EDEVICE;
+    }
+    return FV_OK;
+}
+
+// Validates the sweep's arguments and enqueues it with the per-block lists in
+// `ws` (at least sweep_scratch_bytes(), 256-byte aligned). Every list entry
+// the final selection reads is written by the block kernel of the same call,
+// so `ws` needs no clearing.
+static int sweep_launch(const float* params, const fv_tune_space* space, int64_t begin, int64_t count, int32_t k,
+                        int64_t* top_idx, float* top_val, void* ws, hipStream_t st) {
+    if (!params || !space || !top_idx || !top_val || !ws) return FV_EINVAL;
+    if (k < 1 || k > KMAX || begin < 0 || count < 1) return FV_EINVAL;
+    if (space->n_extra != 0 && space->n_extra != FV_MLP_MAX_EXTRA) return FV_EINVAL;
+    SweepTab tab;
+    int64_t total = 1;
+    for (int s = 0; s < FV_NSITES; ++s) {
+        const int r = space->radix[s];
+        if (r < 1 || r > FV_SPACE_MAXC) return FV_EINVAL;
+        tab.radix[s] = r;
+        total *= r;
+        for (int c = 0; c < FV_SPACE_MAXC; ++c) {
+            tab.f1[s][c] = c < r ? space->f1[s][c] : 0.f;
+            tab.f2[s][c] = c < r ? space->f2[s][c] : 0.f;
+        }
+    }
+    for (int j = 0; j < FV_MLP_MAX_EXTRA; ++j) tab.extra[j] = j < space->n_extra ? space->extra[j] : 0.f;
+    if (begin + count > total) return FV_EINVAL;
+    long long blocks = (count + SWEEP_T - 1) / SWEEP_T;
+    if (blocks > SWEEP_MAXB) blocks = SWEEP_MAXB;
+    float* pv = (float*)ws;
+    long long* pi = (long long*)((char*)ws + (((size_t)SWEEP_MAXB * KMAX * sizeof(float) + 255) & ~(size_t)255));
+    if (space->n_extra == 0)
+        hipLaunchKernelGGL(k_sweep<FV_MLP_IN>, dim3((unsigned)blocks), dim3(SWEEP_T), 0, st, params, tab,
+                           (long long)begin, (long long)count, k, pv, pi);
+    else
+        hipLaunchKernelGGL(k_sweep<FV_MLP_IN_SIZED>, dim3((unsigned)blocks), dim3(SWEEP_T), 0, st, params, tab,
+                           (long long)begin, (long long)count, k, pv, pi);
+    hipLaunchKernelGGL(k_sweep_final, dim3(1), dim3(1024), 0, st, pv, pi, (int)(blocks * KMAX), k, top_val,
+                       (long long*)top_idx);
+    return launch_status();
+}
+
+}  // namespace mlp
+
 // ---------------------------------------------------------------------------
 // C ABI.
 
@@ -553,46 +646,25 @@ int fv_mlp_train(float* params, int32_t n_in, float* adam_m, float* adam_v, int3
 
 int fv_mlp_sweep_workspace(size_t* bytes) {
     if (!bytes) return FV_EINVAL;
-    *bytes = (size_t)mlp::SWEEP_MAXB * mlp::KMAX * (sizeof(float) + sizeof(long long)) + 256;
+    *bytes = mlp::sweep_scratch_bytes();
     return FV_OK;
 }
 
 int fv_mlp_sweep(const float* params, const fv_tune_space* space, int64_t begin, int64_t count, int32_t k,
                  int64_t* top_idx, float* top_val, void* workspace, size_t ws_bytes, void* stream) {
-    if (!params || !space || !top_idx || !top_val || !workspace) return FV_EINVAL;
-    if (k < 1 || k > mlp::KMAX || begin < 0 || count < 1) return FV_EINVAL;
-    if (space->n_extra != 0 && space->n_extra != FV_MLP_MAX_EXTRA) return FV_EINVAL;
-    size_t need = 0;
-    fv_mlp_sweep_workspace(&need);
-    if (ws_bytes < need) return FV_EWORKSPACE;
-    mlp::SweepTab tab;
-    int64_t total = 1;
-    for (int s = 0; s < FV_NSITES; ++s) {
-        const int r = space->radix[s];
-        if (r < 1 || r > FV_SPACE_MAXC) return FV_EINVAL;
-        tab.radix[s] = r;
-        total *= r;
-        for (int c = 0; c < FV_SPACE_MAXC; ++c) {
-            tab.f1[s][c] = c < r ? space->f1[s][c] : 0.f;
-            tab.f2[s][c] = c < r ? space->f2[s][c] : 0.f;
-        }
-    }
-    for (int j = 0; j < FV_MLP_MAX_EXTRA; ++j) tab.extra[j] = j < space->n_extra ? space->extra[j] : 0.f;
-    if (begin + count > total) return FV_EINVAL;
-    long long blocks = (count + mlp::SWEEP_T - 1) / mlp::SWEEP_T;
-    if (blocks > mlp::SWEEP_MAXB) blocks = mlp::SWEEP_MAXB;
-    float* pv = (float*)workspace;
-    long long* pi = (long long*)((char*)workspace + (((size_t)mlp::SWEEP_MAXB * mlp::KMAX * sizeof(float) + 255) & ~(size_t)255));
-    hipStream_t st = (hipStream_t)stream;
-    if (space->n_extra == 0)
-        hipLaunchKernelGGL(mlp::k_sweep<FV_MLP_IN>, dim3((unsigned)blocks), dim3(mlp::SWEEP_T), 0, st, params, tab,
-                           (long long)begin, (long long)count, k, pv, pi);
-    else
-        hipLaunchKernelGGL(mlp::k_sweep<FV_MLP_IN_SIZED>, dim3((unsigned)blocks), dim3(mlp::SWEEP_T), 0, st, params,
-                           tab, (long long)begin, (long long)count, k, pv, pi);
-    hipLaunchKernelGGL(mlp::k_sweep_final, dim3(1), dim3(1024), 0, st, pv, pi, (int)(blocks * mlp::KMAX), k, top_val,
-                       (long long*)top_idx);
-    return mlp_check_launch();
+    if (!workspace) return FV_EINVAL;
+    if (ws_bytes < mlp::sweep_scratch_bytes()) return FV_EWORKSPACE;
+    return mlp::sweep_launch(params, space, begin, count, k, top_idx, top_val, workspace, (hipStream_t)stream);
+}
+
+int fv_mlp_sweep_static(const float* params, const fv_tune_space* space, int64_t begin, int64_t count, int32_t k,
+                        int64_t* top_idx, float* top_val, void* stream) {
+    // Sizes: k above 8 is rejected by the argument check (FV_EINVAL); any
+    // count fits, the block count being capped at the scratch's capacity.
+    void* ws = nullptr;
+    const int rc = mlp::static_scratch(&ws);
+    if (rc != FV_OK) return rc;
+    return mlp::sweep_launch(params, space, begin, count, k, top_idx, top_val, ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -195,12 +195,14 @@ def lib():
                                    ctypes.POINTER(fv_mlp_hparams), _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.fv_mlp_sweep.argtypes = [_vp, ctypes.POINTER(fv_tune_space), ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.fv_mlp_sweep_static.argtypes = [_vp, ctypes.POINTER(fv_tune_space), ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int32, _vp, _vp, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
                      "fv_adjoint_step", "fv_set_source", "fv_residual_norm", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
                      "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_batch_query", "fv_batch_create",
                      "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_set_schedule", "fv_batch_destroy",
                      "fv_mlp_workspace", "fv_mlp_sweep_workspace",
-                     "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep"):
+                     "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep", "fv_mlp_sweep_static"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -457,6 +459,12 @@ def fv_mlp_sweep(params_ptr, space, begin, count, k, top_idx_ptr, top_val_ptr, w
     return _mlp_check(lib().fv_mlp_sweep(_vp(params_ptr), ctypes.byref(space), int(begin), int(count), int(k),
                                          _vp(top_idx_ptr), _vp(top_val_ptr), _vp(ws_ptr), ws_bytes,
                                          _vp(stream_ptr)), "fv_mlp_sweep")
+
+
+def fv_mlp_sweep_static(params_ptr, space, begin, count, k, top_idx_ptr, top_val_ptr, stream_ptr):
+    return _mlp_check(lib().fv_mlp_sweep_static(_vp(params_ptr), ctypes.byref(space), int(begin), int(count), int(k),
+                                                _vp(top_idx_ptr), _vp(top_val_ptr), _vp(stream_ptr)),
+                      "fv_mlp_sweep_static")
 
 
 # --- torch-side convenience ----------------------------------------------------
