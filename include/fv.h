@@ -116,7 +116,24 @@ typedef struct fv_grid_desc {
     double gamma;       /* ratio of specific heats, > 1 */
     double cfl;         /* CFL number, > 0 */
     double bc_state[3][2][5];  /* conserved ghost state of FV_BC_INFLOW faces (rho, rho u, rho v, [rho w], E) */
+    double mu;          /* dynamic viscosity, >= 0: 0 gives the Euler equations; > 0 adds the
+                           viscous flux of Eq. (QF) (Navier-Stokes), see below */
+    double prandtl;     /* Prandtl number of the heat flux, > 0 when mu > 0 */
 } fv_grid_desc;
+
+/* Viscous flux (mu > 0): the residual of Eq. (residual) sums F_i,n - F_nu,n
+ * over the faces, with F_nu,n = (0, tau . n, Theta . n) of Eq. (QF): Stokes
+ * stresses tau_ab = mu (du_a/dx_b + du_b/dx_a) - 2/3 mu delta_ab div(u) and
+ * Theta = u . tau + k grad T, T = p / rho (unit gas constant),
+ * k = mu gamma / ((gamma - 1) prandtl). Face gradients are second order: the
+ * difference across the face for the normal derivative, the mean of the two
+ * cells' central differences for tangential ones; edge and corner neighbours
+ * outside the grid go through the boundary maps of each axis. The time step
+ * adds the explicit diffusion limit: the wave-speed sum of each cell gains
+ * 2 (mu / rho) max(4/3, gamma / prandtl) sum_d 1 / dx_d^2. Viscous grids run
+ * on the split path (fv_residual, fv_step, fv_residual_norm); fv_set_path
+ * (FV_PATH_FUSED) and fv_adjoint_step return FV_ENOTSUP and batches refuse
+ * them (FV_EINVAL). */
 
 /* Launch parameters, two per site (FV_SITE_* order).
  *  Stencil sites (flux x/y/z): p[2s] = block width along x, a power of two in

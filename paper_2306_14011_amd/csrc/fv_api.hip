@@ -132,6 +132,10 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
         snprintf(why, 256, "gamma must exceed 1 and cfl must be positive");
         return FV_EINVAL;
     }
+    if (!(g->mu >= 0.0) || !isfinite(g->mu) || (g->mu > 0.0 && (!(g->prandtl > 0.0) || !isfinite(g->prandtl)))) {
+        snprintf(why, 256, "viscosity must be finite and >= 0, with a positive Prandtl number when > 0");
+        return FV_EINVAL;
+    }
     const int nd = g->ndim;
     L->nvar = nd + 2;
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
@@ -237,6 +241,12 @@ Geo make_geo(const fv_grid_desc* d, const Layout& L) {
         g.bc[a][1] = d->bc[a][1];
     }
     g.scheme = d->scheme;
+    g.mu = d->mu;
+    if (d->mu > 0.0) {
+        g.kcond = d->mu * d->gamma / ((d->gamma - 1.0) * d->prandtl);
+        const double hf = d->gamma / d->prandtl;
+        g.nu_fac = hf > 4.0 / 3.0 ? hf : 4.0 / 3.0;
+    }
     return g;
 }
 
@@ -290,6 +300,7 @@ void enqueue_fluxes(fv_ctx* c, const double* U) {
         SiteTimer t(c, FV_SITE_FLUX_X + ax);
         fvk::launch_flux(ax, U, c->F[ax], c->g, P(c, FV_SITE_FLUX_X + ax, 0), P(c, FV_SITE_FLUX_X + ax, 1),
                          c->stream);
+        if (c->g.mu > 0.0) fvk::launch_visc(ax, U, c->F[ax], c->g, c->bcs, c->stream);
     }
 }
 
@@ -499,6 +510,7 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         for (int s = 0; s < 2; ++s)
             if (c->g.bc[d][s] == FV_BC_WALL || c->g.bc[d][s] == FV_BC_INFLOW)
                 return fail(c, FV_ENOTSUP, "slip walls and inflow faces run on the split path only%s");
+    if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "viscous grids run on the split path only%s");
     if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
         return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
     if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
@@ -630,6 +642,7 @@ int fv_set_source(fv_ctx* c, const double* S) {
 int fv_adjoint_step(fv_ctx* c, double* U_n, const double* dt, double* lam) {
     if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
     if (!U_n || !dt || !lam) return fail(c, FV_EINVAL, "null state, dt or adjoint pointer%s");
+    if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "the adjoint step covers the inviscid residual only%s");
     // recompute the stage states with the frozen dt: U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1))
     enqueue_bc(c, U_n);
     enqueue_fluxes(c, U_n);

@@ -56,6 +56,9 @@ struct Geo {
     double cfl;
     int bc[3][2];
     int scheme;         // 0 minmod; Psi = 1 with kappa = -1, 0, 1/3, 1 for 1 .. 4; 5 van Leer
+    double mu;          // dynamic viscosity, 0 for the Euler equations
+    double kcond;       // heat conductivity mu gamma / ((gamma - 1) Pr)
+    double nu_fac;      // max(4/3, gamma / Pr): the larger diffusivity per unit kinematic viscosity
 };
 
 // 1/a and 1/sqrt(a) for the flux arithmetic: the hardware estimates

@@ -37,6 +37,7 @@ struct FGrid3 {
 
 void launch_bc_fill(double* U, const Geo& g, const BcState& bcs, int gang, int threads, hipStream_t s);
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
+void launch_visc(int ax, const double* U, double* F, const Geo& g, const BcState& bcs, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
                      int gang, int threads, hipStream_t s);
 // norms[v] = sqrt(sum_e R[v][e]^2 / ncell) with partial (256 * nvar doubles) as scratch.

@@ -82,6 +82,120 @@ __global__ void __launch_bounds__(1024) k_bc_fill(double* __restrict__ U, Geo g,
 }
 
 // ---------------------------------------------------------------------------
+// Viscous face flux (Navier-Stokes): F_nu,n of Eq. (QF) on every face of axis
+// AX, subtracted from the inviscid face flux in place (the residual sums
+// F_i,n - F_nu,n). With w = (u, v, [w], T), T = p / rho (unit gas constant):
+//   tau_{a,AX} = mu (dw_a/dx_AX + dw_AX/dx_a) - 2/3 mu delta_{a,AX} div(u),
+//   Theta_AX  = sum_b ubar_b tau_{b,AX} + k dT/dx_AX,   k = mu gamma / ((gamma - 1) Pr),
+// the normal derivative being the difference across the face over dx, each
+// tangential derivative the mean of the central differences of the two cells
+// across the face, and ubar the mean velocity of those two cells. Neighbour
+// cells outside the grid (at most one cell out on the tangential axes, so
+// edge and corner positions too) are mapped axis by axis: periodic wrap,
+// transmissive clamp, slip-wall mirror with that axis's momentum reversed,
+// or the given state of an inflow face.
+
+// Velocity and temperature at interior-or-mapped position (i, j, k).
+template <int NDIM>
+__device__ __forceinline__ void visc_cell(const double* __restrict__ U, const Geo& g, const BcState& bcs, int i,
+                                          int j, int k, double* w) {
+    constexpr int NV = NDIM + 2;
+    int p[3] = {i, j, k};
+    double sg[NDIM];
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) sg[d] = 1.0;
+    const double* fixed = nullptr;
+#pragma unroll
+    for (int a = 0; a < NDIM; ++a) {
+        const int n = g.n[a];
+        const int x = p[a];
+        if (x < 0 || x >= n) {
+            const int side = x < 0 ? 0 : 1;
+            const int kind = g.bc[a][side];
+            if (kind == 3 && !fixed) fixed = bcs.q[a][side];
+            if (kind == 0) p[a] = x < 0 ? x + n : x - n;
+            else if (kind == 2) {
+                p[a] = x < 0 ? -1 - x : 2 * n - 1 - x;
+                sg[a] = -1.0;
+            } else p[a] = x < 0 ? 0 : n - 1;
+        }
+    }
+    double q[NV];
+    if (fixed) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[v] = fixed[v];
+    } else {
+        const int o = g.off0 + p[0] + p[1] * g.sy + (NDIM == 3 ? p[2] * g.sz : 0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[v] = U[v * g.sv + o];
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) q[1 + d] *= sg[d];
+    }
+    const double ir = 1.0 / q[0];
+    double qq = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        w[d] = q[1 + d] * ir;
+        qq += w[d] * w[d];
+    }
+    w[NDIM] = g.gm1 * (q[NDIM + 1] - 0.5 * q[0] * qq) * ir;
+}
+
+template <int NDIM, int AX>
+__global__ void __launch_bounds__(256) k_visc(const double* __restrict__ U, double* __restrict__ F, Geo g,
+                                              BcState bcs, int cols, int rows_j, int nfaces) {
+    constexpr int NW = NDIM + 1;
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nfaces; f += gridDim.x * blockDim.x) {
+        const int i = f % cols;
+        const int r = f / cols;
+        const int j = r % rows_j;
+        const int k = r / rows_j;
+        // face (i, j, k) lies between cell c = (i, j, k) - e_AX and (i, j, k)
+        int c0[3] = {i, j, k};
+        c0[AX] -= 1;
+        double wa[NW], wb[NW];
+        visc_cell<NDIM>(U, g, bcs, c0[0], c0[1], c0[2], wa);
+        visc_cell<NDIM>(U, g, bcs, i, j, k, wb);
+        double grad[NW][NDIM];
+#pragma unroll
+        for (int m = 0; m < NW; ++m) grad[m][AX] = (wb[m] - wa[m]) * g.inv_dx[AX];
+#pragma unroll
+        for (int t = 0; t < NDIM; ++t) {
+            if (t == AX) continue;
+            double wp0[NW], wm0[NW], wp1[NW], wm1[NW];
+            int p[3] = {c0[0], c0[1], c0[2]};
+            p[t] += 1;
+            visc_cell<NDIM>(U, g, bcs, p[0], p[1], p[2], wp0);
+            p[t] -= 2;
+            visc_cell<NDIM>(U, g, bcs, p[0], p[1], p[2], wm0);
+            int q[3] = {i, j, k};
+            q[t] += 1;
+            visc_cell<NDIM>(U, g, bcs, q[0], q[1], q[2], wp1);
+            q[t] -= 2;
+            visc_cell<NDIM>(U, g, bcs, q[0], q[1], q[2], wm1);
+#pragma unroll
+            for (int m = 0; m < NW; ++m) grad[m][t] = ((wp0[m] - wm0[m]) + (wp1[m] - wm1[m])) * (0.25 * g.inv_dx[t]);
+        }
+        double divu = 0.0;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) divu += grad[d][d];
+        double tau[NDIM];
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a) {
+            tau[a] = g.mu * (grad[a][AX] + grad[AX][a]);
+            if (a == AX) tau[a] -= (2.0 / 3.0) * g.mu * divu;
+        }
+        double theta = g.kcond * grad[NDIM][AX];
+#pragma unroll
+        for (int b = 0; b < NDIM; ++b) theta += 0.5 * (wa[b] + wb[b]) * tau[b];
+        const long long fo = (long long)f;
+#pragma unroll
+        for (int a = 0; a < NDIM; ++a) F[(1 + a) * g.fsv[AX] + fo] -= tau[a];
+        F[(NDIM + 1) * g.fsv[AX] + fo] -= theta;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Face fluxes along axis AX. Face (i, j, k) lies between cells (i,j,k) - e_AX
 // and (i,j,k); its flux is stored at F[v * fsv + (k * rows_j + j) * cols + i]
 // with cols = nx (+1 on x) and rows_j = ny (+1 on y). Threads: x -> i,
@@ -307,7 +421,15 @@ __global__ void __launch_bounds__(MAXT) k_cfl_partial(const double* __restrict__
         double q[NDIM + 2];
 #pragma unroll
         for (int v = 0; v < NDIM + 2; ++v) q[v] = U[v * g.sv + o];
-        const double lam = cell_lambda<NDIM>(q, g.gamma, g.gm1, g.inv_dx, fl);
+        double lam = cell_lambda<NDIM>(q, g.gamma, g.gm1, g.inv_dx, fl);
+        if (g.mu > 0.0) {
+            // explicit diffusion limit: 2 nu_eff sum_d 1/dx_d^2, nu_eff =
+            // (mu / rho) max(4/3, gamma / Pr)
+            double s2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < NDIM; ++d) s2 += g.inv_dx[d] * g.inv_dx[d];
+            lam += 2.0 * ((g.mu / q[0]) * g.nu_fac) * s2;
+        }
         lmax = fmax(lmax, lam);
     }
     if (fl) atomicOr(status, fl);
@@ -429,6 +551,25 @@ void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int t
         if (ax == 0) launch_flux_t<3, 0>(U, F, g, bx, threads, s);
         else if (ax == 1) launch_flux_t<3, 1>(U, F, g, bx, threads, s);
         else launch_flux_t<3, 2>(U, F, g, bx, threads, s);
+    }
+}
+
+// Viscous fluxes of axis ax subtracted from its face fluxes F (one thread per
+// face, a fixed launch shape: not a tuned site).
+void launch_visc(int ax, const double* U, double* F, const Geo& g, const BcState& bcs, hipStream_t s) {
+    const int cols = g.n[0] + (ax == 0 ? 1 : 0);
+    const int rows_j = g.n[1] + (ax == 1 ? 1 : 0);
+    const int rows_k = g.ndim == 3 ? g.n[2] + (ax == 2 ? 1 : 0) : 1;
+    const int nfaces = cols * rows_j * rows_k;
+    const int blocks = blocks_for(nfaces, 256);
+    if (g.ndim == 2) {
+        if (ax == 0) hipLaunchKernelGGL((k_visc<2, 0>), dim3(blocks), dim3(256), 0, s, U, F, g, bcs, cols, rows_j, nfaces);
+        else hipLaunchKernelGGL((k_visc<2, 1>), dim3(blocks), dim3(256), 0, s, U, F, g, bcs, cols, rows_j, nfaces);
+    } else {
+        if (ax == 0) hipLaunchKernelGGL((k_visc<3, 0>), dim3(blocks), dim3(256), 0, s, U, F, g, bcs, cols, rows_j, nfaces);
+        else if (ax == 1)
+            hipLaunchKernelGGL((k_visc<3, 1>), dim3(blocks), dim3(256), 0, s, U, F, g, bcs, cols, rows_j, nfaces);
+        else hipLaunchKernelGGL((k_visc<3, 2>), dim3(blocks), dim3(256), 0, s, U, F, g, bcs, cols, rows_j, nfaces);
     }
 }
 

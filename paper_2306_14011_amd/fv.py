@@ -83,6 +83,8 @@ class fv_grid_desc(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("bc_state", ((ctypes.c_double * 5) * 2) * 3),
+        ("mu", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
     ]
 
 
@@ -218,7 +220,7 @@ def _check(rc, ctx=None):
 def make_desc(spec) -> fv_grid_desc:
     """fv_grid_desc from any object with ndim, n, lo, hi, bc, gamma, cfl (and
     optionally limiter: False selects the unlimited scheme of kappa, see
-    scheme_of)."""
+    scheme_of; mu and prandtl for the viscous flux, bc_state for inflow faces)."""
     d = fv_grid_desc()
     d.ndim = spec.ndim
     d.scheme = scheme_of(spec)
@@ -230,6 +232,8 @@ def make_desc(spec) -> fv_grid_desc:
         d.bc[a][1] = int(spec.bc[a][1])
     d.gamma = float(spec.gamma)
     d.cfl = float(spec.cfl)
+    d.mu = float(getattr(spec, "mu", 0.0))
+    d.prandtl = float(getattr(spec, "prandtl", 0.72))
     st = getattr(spec, "bc_state", None)
     if st is not None:
         st = np.asarray(st, dtype=np.float64)

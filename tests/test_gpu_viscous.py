@@ -1,0 +1,178 @@
+"""The viscous flux (Navier-Stokes, F_nu,n of Eq. (QF)) on the HIP split path
+against the FP64 oracle: residual and steps (dt with the diffusion limit
+included) on periodic, walled, inflow and outflow grids in 2D and 3D, launch
+tables giving the same bits, the manufactured Navier-Stokes solution's
+second-order truncation error measured on the GPU residual, and the paths
+that refuse viscous grids."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mms
+from paper_2306_14011_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+WALL, INFLOW = 2, 3
+TOL = 1e-12
+
+
+def assert_pervar_close(got, ref, tol, what):
+    for v in range(ref.shape[0]):
+        scale = max(np.abs(ref[v]).max(), 1e-300)
+        err = np.abs(got[v] - ref[v]).max()
+        assert err <= tol * scale, f"{what} var {v}: max err {err:.3e} vs scale {scale:.3e}"
+
+
+def smooth(g, seed, vel=0.3):
+    rng = np.random.default_rng(seed)
+    x, y, z = g.centres()
+    L = [g.hi[d] - g.lo[d] for d in range(3)]
+    ph = rng.random(8) * 2 * math.pi
+    w = [2 * math.pi / L[d] for d in range(3)]
+    rho = 1.0 + 0.2 * np.sin(w[0] * x + ph[0]) * np.cos(w[1] * y + ph[1]) + 0.1 * np.sin(w[2] * z + ph[6])
+    vels = [vel * np.sin(w[1] * y + ph[2]) + 0.1 * np.cos(w[2] * z + ph[7]), -0.7 * vel * np.cos(w[0] * x + ph[3]),
+            0.8 * vel * np.sin(w[0] * x + w[1] * y + ph[5])][:g.ndim]
+    p = 1.0 + 0.15 * np.cos(w[0] * x - w[1] * y + ph[4])
+    return inputs.primitive_to_conserved(g, rho, vels, p)
+
+
+def viscous(g, mu, prandtl=0.72):
+    g.mu = mu
+    g.prandtl = prandtl
+    return g
+
+
+def inlet_state(g, mach=2.0, angle=0.1):
+    c = math.sqrt(g.gamma)
+    u = mach * c
+    q = np.zeros((3, 2, 5))
+    E = 1.0 / (g.gamma - 1.0) + 0.5 * u * u
+    q[0, 0, :4] = (1.0, u * math.cos(angle), u * math.sin(angle), E)
+    g.bc_state = q
+    return g
+
+
+def cases():
+    g1 = viscous(inputs.grid2d(40, 33, hi=(1.0, 1.0)), 0.02)
+    g2 = viscous(inputs.grid2d(37, 26, hi=(1.0, 1.0), bc=((WALL, WALL), (WALL, WALL))), 0.05, 1.0)
+    g3 = inlet_state(viscous(inputs.grid2d(45, 21, hi=(2.0, 1.0), bc=((INFLOW, 1), (WALL, WALL))), 0.01))
+    g4 = viscous(inputs.grid3d(18, 13, 11, bc=((0, 0), (0, 0), (0, 0))), 0.02)
+    g5 = viscous(inputs.grid3d(14, 11, 9, bc=((WALL, WALL), (0, 0), (WALL, 1))), 0.03)
+    out = [("periodic_2d", g1, smooth(g1, 1)), ("closed_box_2d", g2, smooth(g2, 2, 0.2)),
+           ("inlet_channel_2d", g3, None), ("periodic_3d", g4, smooth(g4, 4)), ("walls_3d", g5, smooth(g5, 5))]
+    # the channel starts from the inflow state everywhere, with a density bump
+    x, y, _ = g3.centres()
+    q = g3.bc_state[0, 0]
+    U = np.broadcast_to(q[:4, None, None, None], (4, 1, 21, 45)).copy()
+    U *= 1.0 + 0.2 * np.exp(-((x - 1.0) ** 2 + (y - 0.5) ** 2) / 0.02)[None]
+    out[2] = ("inlet_channel_2d", g3, U)
+    return out
+
+
+CASES = cases()
+IDS = [c[0] for c in CASES]
+
+
+@pytest.mark.parametrize("name,g,U", CASES, ids=IDS)
+def test_viscous_residual_matches_oracle(name, g, U):
+    from paper_2306_14011_amd import fv
+    s = fv.Solver(g)
+    s.set_state(U)
+    R = s.residual().cpu().numpy()
+    s.close()
+    ref = oracle.residual(g, U)
+    assert_pervar_close(R, ref, TOL, name)
+    # the viscous terms matter here: the inviscid residual differs at the percent level
+    g0 = inputs.GridSpec(**{**vars(g), "mu": 0.0})
+    R0 = oracle.residual(g0, U)
+    assert np.abs(R0[1:] - ref[1:]).max() > 1e-3 * np.abs(ref[1:]).max()
+
+
+@pytest.mark.parametrize("name,g,U", CASES, ids=IDS)
+def test_viscous_steps_match_oracle(name, g, U):
+    import torch
+    from paper_2306_14011_amd import fv
+    n = 4
+    outs = []
+    for launch in (None, [32, 128, 16, 512, 64, 64, 4096, 128, 0, 64, 64, 256, 0, 1024]):
+        s = fv.Solver(g)
+        if launch is not None:
+            if g.ndim == 2:
+                launch = launch[:4] + [0, 0] + launch[6:]
+            s.set_launch(launch)
+        s.set_state(U)
+        dts = torch.zeros(n, dtype=torch.float64, device="cuda")
+        s.step(n, dt_out=dts)
+        rc, flags = s.status()
+        assert flags == 0
+        outs.append((s.get_state(), dts.cpu().numpy()))
+        s.close()
+    ref, rdt, rfl = oracle.run(g, U, n)
+    assert rfl == 0
+    assert np.allclose(outs[0][1], rdt, rtol=1e-13, atol=0), (outs[0][1], rdt)
+    assert_pervar_close(outs[0][0], ref, 1e-11, name)
+    # every launch table gives the same bits
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_diffusion_limited_time_step():
+    # a large viscosity on a fine grid: the diffusion limit sets dt, as in the oracle
+    from paper_2306_14011_amd import fv
+    import torch
+    g = viscous(inputs.grid2d(64, 64, hi=(1.0, 1.0)), 0.5)
+    U = smooth(g, 7)
+    s = fv.Solver(g)
+    s.set_state(U)
+    dts = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(1, dt_out=dts)
+    s.close()
+    dt_ref, _ = oracle.dt(g, U)
+    g0 = inputs.GridSpec(**{**vars(g), "mu": 0.0})
+    assert oracle.dt(g0, U)[0] > 5 * dt_ref
+    assert abs(dts.item() - dt_ref) <= 1e-14 * dt_ref
+
+
+def test_navier_stokes_truncation_error_on_the_gpu():
+    # the GPU residual of the manufactured Navier-Stokes solution with its
+    # source falls at second order (unlimited scheme)
+    from paper_2306_14011_amd import fv
+    import torch
+    mu = 0.05
+    errs = []
+    for n in (32, 64, 128):
+        g = viscous(inputs.grid2d(n, n, hi=(1.0, 1.0)), mu)
+        g.limiter = False
+        U = mms.cell_averages(mms.conserved, n)[:, None]
+        S = mms.cell_averages(lambda X, Y: mms.ns_source(X, Y, mu, 0.72), n)[:, None]
+        s = fv.Solver(g)
+        s.set_state(U)
+        St = torch.as_tensor(np.ascontiguousarray(S)).cuda()
+        s.set_source(St)
+        R = s.residual().cpu().numpy()
+        s.close()
+        errs.append(np.sqrt(((R * n * n) ** 2).mean(axis=(1, 2, 3))))
+    for v in range(4):
+        order = math.log2(errs[1][v] / errs[2][v])
+        assert 1.85 <= order <= 2.25, (v, order)
+
+
+def test_paths_that_refuse_viscosity():
+    import torch
+    from paper_2306_14011_amd import fv
+    g = viscous(inputs.grid2d(16, 16), 0.01)
+    s = fv.Solver(g)
+    s.set_state(smooth(g, 8))
+    with pytest.raises(fv.FvError) as e:
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    assert e.value.code == fv.FV_ENOTSUP
+    lam = torch.ones(g.shape, dtype=torch.float64, device="cuda")
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    with pytest.raises(fv.FvError) as e:
+        fv.fv_adjoint_step(s.ctx, s.U.data_ptr(), dt.data_ptr(), lam.data_ptr())
+    assert e.value.code == fv.FV_ENOTSUP
+    s.close()
+    with pytest.raises(fv.FvError):
+        fv.Batch([g], seg=0)
