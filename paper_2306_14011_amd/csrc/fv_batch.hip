@@ -92,8 +92,8 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
             snprintf(why, 256, "grid %d: gamma must exceed 1 and cfl be positive", g);
             return FV_EINVAL;
         }
-        if (d.mu != 0.0) {
-            snprintf(why, 256, "grid %d: batches take inviscid grids only (mu = 0)", g);
+        if (d.mu != 0.0 || d.nodes) {
+            snprintf(why, 256, "grid %d: batches take inviscid uniform grids only (mu = 0, no nodes)", g);
             return FV_EINVAL;
         }
         L->offsets[g + 1] = L->offsets[g] + 4 * d.n[0] * d.n[1];

@@ -59,7 +59,30 @@ struct Geo {
     double mu;          // dynamic viscosity, 0 for the Euler equations
     double kcond;       // heat conductivity mu gamma / ((gamma - 1) Pr)
     double nu_fac;      // max(4/3, gamma / Pr): the larger diffusivity per unit kinematic viscosity
+    // Curvilinear 2D grid (null for the uniform box): metric streams in the
+    // workspace, SoA. x faces ((nx + 1) ny each, face (i, j) between cells
+    // (i - 1, j) and (i, j)): unit normal x, unit normal y, length; then y
+    // faces (nx (ny + 1) each, face (i, j) between (i, j - 1) and (i, j)): the
+    // same three; then per cell: area and 1 / area.
+    const double* met;
 };
+
+// Offsets of the metric streams of a curvilinear grid (elements).
+struct MetricOffsets {
+    long long fx, fy, cell;  // first element of the x-face, y-face and cell blocks
+    long long nfx, nfy, nc;  // entries per stream of each block
+};
+
+__host__ __device__ inline MetricOffsets metric_offsets(int nx, int ny) {
+    MetricOffsets m;
+    m.nfx = (long long)(nx + 1) * ny;
+    m.nfy = (long long)nx * (ny + 1);
+    m.nc = (long long)nx * ny;
+    m.fx = 0;
+    m.fy = 3 * m.nfx;
+    m.cell = m.fy + 3 * m.nfy;
+    return m;
+}
 
 // 1/a and 1/sqrt(a) for the flux arithmetic: the hardware estimates
 // (v_rcp_f64, v_rsq_f64, relative error about 5e-8) refined by one
@@ -269,6 +292,29 @@ __host__ __device__ __forceinline__ void roe_flux(const double* qL, const double
         F[1 + d] = h * (fl + fr - D[1 + d]);
     }
     F[IE] = h * ((qL[IE] + pL) * vnL + (qR[IE] + pR) * vnR - D[IE]);
+}
+
+// Roe flux through a 2D face of unit normal (nx, ny), conserved face states
+// in, flux out: the momenta are turned into the face's frame (normal
+// nx u + ny v, tangential -ny u + nx v), the flux of the x-axis form above is
+// taken there, and its momentum part is turned back. The same flux as the
+// normal form F = (F_n(QL) + F_n(QR))/2 - |A_n| dQ / 2 with V_n = n.u.
+__host__ __device__ __forceinline__ void roe_flux_n2(const double* qL, const double* qR, double nx, double ny,
+                                                     double gm1, double* F) {
+    double a[4], b[4], G[4];
+    a[0] = qL[0];
+    a[1] = nx * qL[1] + ny * qL[2];
+    a[2] = -ny * qL[1] + nx * qL[2];
+    a[3] = qL[3];
+    b[0] = qR[0];
+    b[1] = nx * qR[1] + ny * qR[2];
+    b[2] = -ny * qR[1] + nx * qR[2];
+    b[3] = qR[3];
+    roe_flux<2, 0>(a, b, gm1, G);
+    F[0] = G[0];
+    F[1] = nx * G[1] - ny * G[2];
+    F[2] = ny * G[1] + nx * G[2];
+    F[3] = G[3];
 }
 
 // Wave-speed bound of one cell, sum_d (|u_d| + c) * inv_dx[d], and the

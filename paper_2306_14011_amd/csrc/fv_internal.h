@@ -37,6 +37,9 @@ struct FGrid3 {
 
 void launch_bc_fill(double* U, const Geo& g, const BcState& bcs, int gang, int threads, hipStream_t s);
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s);
+void launch_metrics(const double* nodes, double* met, int nx, int ny, hipStream_t s);
+void launch_flux_curv(int ax, const double* U, double* F, const Geo& g, const BcState& bcs, int bx, int threads,
+                      hipStream_t s);
 void launch_visc(int ax, const double* U, double* F, const Geo& g, const BcState& bcs, hipStream_t s);
 void launch_residual(const double* Fx, const double* Fy, const double* Fz, const double* S, double* R, const Geo& g,
                      int gang, int threads, hipStream_t s);

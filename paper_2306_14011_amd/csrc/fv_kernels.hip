@@ -281,6 +281,111 @@ __global__ void __launch_bounds__(MAXT) k_flux_run(const double* __restrict__ U,
 }
 
 // ---------------------------------------------------------------------------
+// Curvilinear 2D grids. The metric streams (layout in fv_device.h) are
+// computed once from the node coordinates nodes[d][j][i] ((nx + 1) x
+// (ny + 1) nodes, x then y): a face's area vector is its edge turned by a
+// right angle towards the higher-index cell, its length the edge length, a
+// cell's area half the cross product of its diagonals.
+__global__ void __launch_bounds__(256) k_metrics(const double* __restrict__ nodes, double* __restrict__ met,
+                                                 int nx, int ny) {
+    const MetricOffsets mo = metric_offsets(nx, ny);
+    const long long nn = (long long)(nx + 1) * (ny + 1);
+    auto X = [&](int i, int j) { return nodes[(long long)j * (nx + 1) + i]; };
+    auto Y = [&](int i, int j) { return nodes[nn + (long long)j * (nx + 1) + i]; };
+    const long long total = mo.nfx + mo.nfy + mo.nc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (e < mo.nfx) {
+            // x face (i, j): edge from node (i, j) to (i, j + 1)
+            const int i = (int)(e % (nx + 1)), j = (int)(e / (nx + 1));
+            const double ex = X(i, j + 1) - X(i, j), ey = Y(i, j + 1) - Y(i, j);
+            const double len = sqrt(ex * ex + ey * ey);
+            met[mo.fx + e] = ey / len;
+            met[mo.fx + mo.nfx + e] = -ex / len;
+            met[mo.fx + 2 * mo.nfx + e] = len;
+        } else if (e < mo.nfx + mo.nfy) {
+            // y face (i, j): edge from node (i, j) to (i + 1, j)
+            const long long q = e - mo.nfx;
+            const int i = (int)(q % nx), j = (int)(q / nx);
+            const double ex = X(i + 1, j) - X(i, j), ey = Y(i + 1, j) - Y(i, j);
+            const double len = sqrt(ex * ex + ey * ey);
+            met[mo.fy + q] = -ey / len;
+            met[mo.fy + mo.nfy + q] = ex / len;
+            met[mo.fy + 2 * mo.nfy + q] = len;
+        } else {
+            const long long q = e - mo.nfx - mo.nfy;
+            const int i = (int)(q % nx), j = (int)(q / nx);
+            const double d1x = X(i + 1, j + 1) - X(i, j), d1y = Y(i + 1, j + 1) - Y(i, j);
+            const double d2x = X(i, j + 1) - X(i + 1, j), d2y = Y(i, j + 1) - Y(i + 1, j);
+            const double area = 0.5 * (d1x * d2y - d1y * d2x);
+            met[mo.cell + q] = area;
+            met[mo.cell + mo.nc + q] = 1.0 / area;
+        }
+    }
+}
+
+// Face fluxes on a curvilinear 2D grid, times the face length, along AX.
+// The same face indexing and launch shape as k_flux. The four stencil cells
+// along the grid line are read through the boundary maps (no ghost layer is
+// used): periodic wrap, transmissive clamp, the given state of an inflow
+// face, or a slip wall's mirror cell with its velocity reflected about the
+// wall face's unit normal, u - 2 (u.n) n.
+template <int AX, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_flux_curv(const double* __restrict__ U, double* __restrict__ F, Geo g,
+                                                    BcState bcs) {
+    constexpr int NV = 4;
+    const int nx = g.n[0], ny = g.n[1];
+    const int cols = nx + (AX == 0 ? 1 : 0);
+    const int rows_j = ny + (AX == 1 ? 1 : 0);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cols) return;
+    const MetricOffsets mo = metric_offsets(nx, ny);
+    const long long mbase = AX == 0 ? mo.fx : mo.fy;
+    const long long mstride = AX == 0 ? mo.nfx : mo.nfy;
+    const int n = g.n[AX];
+    const long long fsv = g.fsv[AX];
+    for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < rows_j; j += gridDim.y * blockDim.y) {
+        const long long f = (long long)j * cols + i;
+        const double fnx = g.met[mbase + f], fny = g.met[mbase + mstride + f], len = g.met[mbase + 2 * mstride + f];
+        const int a0 = AX == 0 ? i : j;  // index of the face's right cell on AX
+        double q[4][NV];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int pos = a0 - 2 + m;
+            const bool lo = pos < 0, hi = pos >= n;
+            const int kind = lo ? g.bc[AX][0] : (hi ? g.bc[AX][1] : -1);
+            int p = pos;
+            if (kind == 0) p = lo ? pos + n : pos - n;
+            else if (kind == 2) p = lo ? -1 - pos : 2 * n - 1 - pos;
+            else if (kind == 1 || kind == 3) p = lo ? 0 : n - 1;
+            const int ci = AX == 0 ? p : i, cj = AX == 0 ? j : p;
+            const int o = g.off0 + ci + cj * g.sy;
+            if (kind == 3) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) q[m][v] = bcs.q[AX][lo ? 0 : 1][v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) q[m][v] = U[v * g.sv + o];
+            }
+            if (kind == 2) {
+                // the wall face of this grid line: face 0 or face n on AX
+                const long long wf = AX == 0 ? (long long)j * cols + (lo ? 0 : n) : (long long)(lo ? 0 : n) * cols + i;
+                const double wx = g.met[mbase + wf], wy = g.met[mbase + mstride + wf];
+                const double mn = q[m][1] * wx + q[m][2] * wy;
+                q[m][1] -= 2.0 * mn * wx;
+                q[m][2] -= 2.0 * mn * wy;
+            }
+        }
+        double qL[NV], qR[NV], Fl[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) muscl(q[0][v], q[1][v], q[2][v], q[3][v], g.scheme, qL[v], qR[v]);
+        roe_flux_n2(qL, qR, fnx, fny, g.gm1, Fl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v * fsv + f] = Fl[v] * len;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Interior cell e -> (i, j, k) and its offset in the ghosted layout.
 __device__ __forceinline__ void decode_cell(int e, const Geo& g, int& i, int& j, int& k) {
     const uint32_t t = divq((uint32_t)e, g.dnx);
@@ -310,7 +415,7 @@ __global__ void __launch_bounds__(MAXT) k_residual(const double* __restrict__ Fx
             double r = (Fx[v * g.fsv[0] + fx + 1] - Fx[v * g.fsv[0] + fx]) * g.area[0];
             r += (Fy[v * g.fsv[1] + fy + nx] - Fy[v * g.fsv[1] + fy]) * g.area[1];
             if (NDIM == 3) r += (Fz[v * g.fsv[2] + fz + zs] - Fz[v * g.fsv[2] + fz]) * g.area[2];
-            if (S) r -= g.vol * S[(long long)v * g.ncell + e];
+            if (S) r -= (g.met ? g.met[metric_offsets(nx, ny).cell + e] : g.vol) * S[(long long)v * g.ncell + e];
             R[(long long)v * g.ncell + e] = r;
         }
     }
@@ -377,11 +482,13 @@ __global__ void __launch_bounds__(MAXT) k_update(const double* Un, const double*
                                                  const double* __restrict__ dtp, Geo g, int stride_all) {
     constexpr int NV = NDIM + 2;
     const double dt = *dtp;
-    const double s = -dt * g.inv_vol;
+    const double s0 = -dt * g.inv_vol;
+    const long long inv_area = g.met ? metric_offsets(g.n[0], g.n[1]).cell + g.ncell : 0;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < g.ncell; e += stride_all) {
         int i, j, k;
         decode_cell(e, g, i, j, k);
         const int o = g.off0 + i + j * g.sy + k * g.sz;
+        const double s = g.met ? -dt * g.met[inv_area + e] : s0;  // -dt / |Omega| of this cell
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double Lr = R[(long long)v * g.ncell + e];
@@ -408,6 +515,33 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Wave-speed bound of a cell of a curvilinear 2D grid: sum over the two grid
+// directions of (|u.S| + c |S|) / area, S the mean of the cell's two face
+// area vectors (unit normal times length) on that direction. (The flags come
+// from cell_lambda, called first on the same state.)
+__device__ __forceinline__ double curv_lambda(const double* q, const Geo& g, int i, int j) {
+    const int nx = g.n[0], ny = g.n[1];
+    const MetricOffsets mo = metric_offsets(nx, ny);
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir, v = q[2] * ir;
+    const double p = g.gm1 * (q[3] - 0.5 * q[0] * (u * u + v * v));
+    const double c = sqrt(g.gamma * p * ir);
+    const long long e = (long long)j * nx + i;
+    const double area = g.met[mo.cell + e];
+    double lam = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const long long base = ax == 0 ? mo.fx : mo.fy, st = ax == 0 ? mo.nfx : mo.nfy;
+        const long long fa = ax == 0 ? (long long)j * (nx + 1) + i : e;
+        const long long fb = ax == 0 ? fa + 1 : e + nx;
+        const double la = g.met[base + 2 * st + fa], lb = g.met[base + 2 * st + fb];
+        const double sx = 0.5 * (g.met[base + fa] * la + g.met[base + fb] * lb);
+        const double sy = 0.5 * (g.met[base + st + fa] * la + g.met[base + st + fb] * lb);
+        lam += (fabs(u * sx + v * sy) + c * sqrt(sx * sx + sy * sy)) / area;
+    }
+    return lam;
+}
+
 template <int NDIM, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_cfl_partial(const double* __restrict__ U, double* __restrict__ partial,
                                                       uint32_t* __restrict__ status, Geo g, int stride_all) {
@@ -422,6 +556,7 @@ __global__ void __launch_bounds__(MAXT) k_cfl_partial(const double* __restrict__
 #pragma unroll
         for (int v = 0; v < NDIM + 2; ++v) q[v] = U[v * g.sv + o];
         double lam = cell_lambda<NDIM>(q, g.gamma, g.gm1, g.inv_dx, fl);
+        if (NDIM == 2 && g.met) lam = curv_lambda(q, g, i, j);
         if (g.mu > 0.0) {
             // explicit diffusion limit: 2 nu_eff sum_d 1/dx_d^2, nu_eff =
             // (mu / rho) max(4/3, gamma / Pr)
@@ -541,6 +676,34 @@ static void launch_flux_t(const double* U, double* F, const Geo& g, int bx, int 
 #define FV_LFR(T) hipLaunchKernelGGL((k_flux_run<NDIM, (AX > 0 ? AX : 1), T, FLUX_RUN>), grid, block, 0, s, U, F, g)
     FV_DISPATCH_THREADS(threads, FV_LFR)
 #undef FV_LFR
+}
+
+void launch_metrics(const double* nodes, double* met, int nx, int ny, hipStream_t s) {
+    const MetricOffsets mo = metric_offsets(nx, ny);
+    const long long total = mo.nfx + mo.nfy + mo.nc;
+    long long blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_metrics, dim3((unsigned)blocks), dim3(256), 0, s, nodes, met, nx, ny);
+}
+
+template <int AX>
+static void launch_flux_curv_t(const double* U, double* F, const Geo& g, const BcState& bcs, int bx, int threads,
+                               hipStream_t s) {
+    const int by = threads / bx;
+    const int cols = g.n[0] + (AX == 0 ? 1 : 0);
+    const int rows_j = g.n[1] + (AX == 1 ? 1 : 0);
+    int gy = blocks_for(rows_j, by);
+    if (gy > 65535) gy = 65535;
+    dim3 grid(blocks_for(cols, bx), gy, 1), block(bx, by);
+#define FV_LFC(T) hipLaunchKernelGGL((k_flux_curv<AX, T>), grid, block, 0, s, U, F, g, bcs)
+    FV_DISPATCH_THREADS(threads, FV_LFC)
+#undef FV_LFC
+}
+
+void launch_flux_curv(int ax, const double* U, double* F, const Geo& g, const BcState& bcs, int bx, int threads,
+                      hipStream_t s) {
+    if (ax == 0) launch_flux_curv_t<0>(U, F, g, bcs, bx, threads, s);
+    else launch_flux_curv_t<1>(U, F, g, bcs, bx, threads, s);
 }
 
 void launch_flux(int ax, const double* U, double* F, const Geo& g, int bx, int threads, hipStream_t s) {
