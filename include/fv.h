@@ -119,7 +119,26 @@ typedef struct fv_grid_desc {
     double mu;          /* dynamic viscosity, >= 0: 0 gives the Euler equations; > 0 adds the
                            viscous flux of Eq. (QF) (Navier-Stokes), see below */
     double prandtl;     /* Prandtl number of the heat flux, > 0 when mu > 0 */
+    const double* nodes;  /* curvilinear 2D grid (see below): DEVICE pointer to the node
+                             coordinates, or NULL for the uniform box [lo, hi] */
 } fv_grid_desc;
+
+/* Curvilinear grids (nodes != NULL, 2D only): the structured cells are the
+ * quadrilaterals of a node array of (nx + 1) x (ny + 1) points,
+ * nodes[d * (nx + 1) * (ny + 1) + j * (nx + 1) + i] for d = 0 (x), 1 (y),
+ * i increasing along the first grid direction and j along the second (a
+ * right-handed, non-degenerate grid: every cell's area is positive). The
+ * inviscid flux of Eq. (QF) is taken along each face's unit normal,
+ * V_n = n . u, times the face's length, and the residual is divided by each
+ * cell's area; MUSCL works along the grid lines as on the box; a slip wall's
+ * mirror cell has its velocity reflected about the wall face's normal. The
+ * metric streams (unit normal and length per face, area per cell) are
+ * computed on the device by fv_create into the context's workspace; the
+ * node array is read there only (the caller may free it once the stream has
+ * passed fv_create's work). lo and hi are not used. Curvilinear grids run on
+ * the split path (fv_residual, fv_step, fv_residual_norm); the viscous flux
+ * (mu > 0) is FV_EINVAL with them, fv_set_path(FV_PATH_FUSED) and
+ * fv_adjoint_step return FV_ENOTSUP, and batches refuse them. */
 
 /* Viscous flux (mu > 0): the residual of Eq. (residual) sums F_i,n - F_nu,n
  * over the faces, with F_nu,n = (0, tau . n, Theta . n) of Eq. (QF): Stokes
@@ -247,9 +266,32 @@ int fv_clear_status(fv_ctx* ctx);
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
 
-/* Reads back the path, the segment height in use (the library's choice when
- * fv_set_path was given 0; 0 on the split path) and the wave count. Outputs
- * may be NULL. */
+/* Launch table of the fused path, one entry per Runge-Kutta stage: seg[s]
+ * is the segment height of stage s's work items (0 = the library's choice, or
+ * a multiple of 4 in [4, 1024]) and waves[s] the wavefronts its launch holds
+ * (0 = one per work item, else a grid-stride loop; in 3D rounded up to whole
+ * workgroups of four). fv_set_path(FV_PATH_FUSED, seg, waves) gives all three
+ * stages the same pair. Every table gives bitwise the same result: the table
+ * changes only how the work is cut, the launch surface the autotuner searches
+ * for the fused path. fv_set_fused_launch needs the fused path selected
+ * (FV_EINVAL otherwise, and for an invalid entry, leaving the table as it
+ * was); fv_get_fused_launch reads the table in use (with the library's
+ * choices filled in). */
+typedef struct fv_fused_launch {
+    int32_t seg[3];
+    int32_t waves[3];
+} fv_fused_launch;
+int fv_set_fused_launch(fv_ctx* ctx, const fv_fused_launch* launch);
+int fv_get_fused_launch(const fv_ctx* ctx, fv_fused_launch* out);
+
+/* Wavefronts of the fused stage kernels of ctx's dimension that the current
+ * device holds at once (from its compute-unit count and the kernels'
+ * occupancy), the scale of fv_fused_launch.waves. */
+int fv_fused_slots(const fv_ctx* ctx, int32_t* waves);
+
+/* Reads back the path, the segment height in use by the first stage (the
+ * library's choice when fv_set_path was given 0; 0 on the split path) and its
+ * wave count. Outputs may be NULL. */
 int fv_get_path(const fv_ctx* ctx, int32_t* path, int32_t* seg, int32_t* waves);
 
 /* Per-site kernel timing, a diagnostic for profiling and the autotuner's

@@ -30,10 +30,8 @@ struct fv_ctx {
     double* lamB;
     double* G[3];   // face adjoint contributions [4][nvar][faces] per axis
     // fused path
-    int path, fseg, fwaves, fitems;
-    fvk::FGrid fgrid_host;
-    fvk::FGrid3 fgrid3_host;
-    fvk::FGrid* fgrid;  // the fused path's grid description (an FGrid3 in 3D)
+    int path, fseg[3], fwaves[3], fitems[3];   // per Runge-Kutta stage
+    fvk::FGrid* fgrid[3];  // the fused path's grid description per stage (an FGrid3 in 3D); they differ in seg
     unsigned long long* flam;
     double* fdt;
     const double* src;  // caller's cell-averaged source S[v][cell], or null
@@ -68,7 +66,8 @@ struct Layout {
     int64_t faces[3];
     int64_t ncell;
     int max_partial;
-    size_t off_status, off_dt, off_fused, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_G[3], total;
+    size_t off_status, off_dt, off_fused, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_G[3],
+        off_met, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -136,6 +135,14 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
         snprintf(why, 256, "viscosity must be finite and >= 0, with a positive Prandtl number when > 0");
         return FV_EINVAL;
     }
+    if (g->nodes && g->ndim != 2) {
+        snprintf(why, 256, "curvilinear grids (nodes) are 2D only");
+        return FV_EINVAL;
+    }
+    if (g->nodes && g->mu > 0.0) {
+        snprintf(why, 256, "the viscous flux is taken on uniform grids only");
+        return FV_EINVAL;
+    }
     const int nd = g->ndim;
     L->nvar = nd + 2;
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
@@ -159,8 +166,8 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     o += 256;
     L->off_dt = o;
     o += 256;
-    L->off_fused = o;   // FGrid (128 B) or FGrid3 (160 B), lambda slot at +160, dt slot at +168
-    o += 256;
+    L->off_fused = o;   // 3 x 256 B: an FGrid (128 B) or FGrid3 (160 B) per stage; lambda at +768, dt at +776
+    o += 1024;
     L->off_partial = o;
     o = align256(o + (size_t)L->max_partial * 8);
     const size_t state = (size_t)L->nvar * L->sv * 8;
@@ -182,6 +189,11 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     for (int d = 0; d < 3; ++d) {
         L->off_G[d] = o;
         o = align256(o + (size_t)4 * L->nvar * L->faces[d] * 8);
+    }
+    L->off_met = o;
+    if (g->nodes) {
+        const fvk::MetricOffsets mo = fvk::metric_offsets((int)nx, (int)ny);
+        o = align256(o + (size_t)(mo.cell + 2 * mo.nc) * 8);
     }
     L->total = o;
     return FV_OK;
@@ -241,6 +253,9 @@ Geo make_geo(const fv_grid_desc* d, const Layout& L) {
         g.bc[a][1] = d->bc[a][1];
     }
     g.scheme = d->scheme;
+    g.met = nullptr;  // set by fv_create for curvilinear grids
+    if (d->nodes)
+        for (int a = 0; a < 3; ++a) g.area[a] = 1.0;  // the face fluxes carry their lengths
     g.mu = d->mu;
     if (d->mu > 0.0) {
         g.kcond = d->mu * d->gamma / ((d->gamma - 1.0) * d->prandtl);
@@ -298,8 +313,12 @@ void enqueue_bc(fv_ctx* c, double* U) {
 void enqueue_fluxes(fv_ctx* c, const double* U) {
     for (int ax = 0; ax < c->g.ndim; ++ax) {
         SiteTimer t(c, FV_SITE_FLUX_X + ax);
-        fvk::launch_flux(ax, U, c->F[ax], c->g, P(c, FV_SITE_FLUX_X + ax, 0), P(c, FV_SITE_FLUX_X + ax, 1),
-                         c->stream);
+        if (c->g.met)
+            fvk::launch_flux_curv(ax, U, c->F[ax], c->g, c->bcs, P(c, FV_SITE_FLUX_X + ax, 0),
+                                  P(c, FV_SITE_FLUX_X + ax, 1), c->stream);
+        else
+            fvk::launch_flux(ax, U, c->F[ax], c->g, P(c, FV_SITE_FLUX_X + ax, 0), P(c, FV_SITE_FLUX_X + ax, 1),
+                             c->stream);
         if (c->g.mu > 0.0) fvk::launch_visc(ax, U, c->F[ax], c->g, c->bcs, c->stream);
     }
 }
@@ -401,10 +420,15 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
     c->lamA = (double*)(base + L.off_lamA);
     c->lamB = (double*)(base + L.off_lamB);
     for (int d = 0; d < 3; ++d) c->G[d] = (double*)(base + L.off_G[d]);
-    c->fgrid = (fvk::FGrid*)(base + L.off_fused);
-    c->flam = (unsigned long long*)(base + L.off_fused + 160);
-    c->fdt = (double*)(base + L.off_fused + 168);
+    for (int st = 0; st < 3; ++st) c->fgrid[st] = (fvk::FGrid*)(base + L.off_fused + 256 * st);
+    c->flam = (unsigned long long*)(base + L.off_fused + 768);
+    c->fdt = (double*)(base + L.off_fused + 776);
     c->path = FV_PATH_SPLIT;
+    if (g->nodes) {
+        double* met = (double*)(base + L.off_met);
+        fvk::launch_metrics(g->nodes, met, (int)g->n[0], (int)g->n[1], c->stream);
+        c->g.met = met;
+    }
     fvk::launch_set_u32(c->status, 0u, c->stream);
     if (check_launch_error(c) != FV_OK) {
         snprintf(g_err, 256, "%s", c->err);
@@ -440,27 +464,27 @@ int fv_residual(fv_ctx* c, double* U, double* R) {
     return drain_timing(c);
 }
 
-static_assert(sizeof(fvk::FGrid) <= 160 && sizeof(fvk::FGrid3) <= 160, "fused grid slot is 160 bytes");
+static_assert(sizeof(fvk::FGrid) <= 256 && sizeof(fvk::FGrid3) <= 256, "fused grid slot is 256 bytes");
 
 static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
-    const fvk::FGrid3* G = (const fvk::FGrid3*)c->fgrid;
-    fvk::launch_fused3d_init(c->fwaves, G, c->fitems, U, c->flam, c->status, c->stream);
+    const fvk::FGrid3* const* G = (const fvk::FGrid3* const*)c->fgrid;
+    fvk::launch_fused3d_init(c->fwaves[0], G[0], c->fitems[0], U, c->flam, c->status, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused3d_stage(0, c->fwaves, G, c->fitems, U, U, c->U1, c->flam, c->fdt,
+            fvk::launch_fused3d_stage(0, c->fwaves[0], G[0], c->fitems[0], U, U, c->U1, c->flam, c->fdt,
                                       dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status,
                                       c->stream, c->src, c->g.vol);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused3d_stage(1, c->fwaves, G, c->fitems, U, c->U1, c->U2, c->flam, c->fdt, nullptr,
-                                      nullptr, c->status, c->stream, c->src, c->g.vol);
+            fvk::launch_fused3d_stage(1, c->fwaves[1], G[1], c->fitems[1], U, c->U1, c->U2, c->flam, c->fdt,
+                                      nullptr, nullptr, c->status, c->stream, c->src, c->g.vol);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused3d_stage(2, c->fwaves, G, c->fitems, U, c->U2, U, c->flam, c->fdt, nullptr, nullptr,
-                                      c->status, c->stream, c->src, c->g.vol);
+            fvk::launch_fused3d_stage(2, c->fwaves[2], G[2], c->fitems[2], U, c->U2, U, c->flam, c->fdt, nullptr,
+                                      nullptr, c->status, c->stream, c->src, c->g.vol);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;
@@ -473,22 +497,22 @@ static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in
 static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (nsteps == 0) return FV_OK;
     if (c->g.ndim == 3) return fused_step3(c, U, nsteps, dt_in, dt_out);
-    fvk::launch_fused_init(c->fwaves, c->fgrid, 1, c->fitems, U, c->flam, c->status, c->stream);
+    fvk::launch_fused_init(c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, c->flam, c->status, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused_stage(0, c->fwaves, c->fgrid, 1, c->fitems, U, U, c->U1, c->flam, c->fdt,
+            fvk::launch_fused_stage(0, c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, U, c->U1, c->flam, c->fdt,
                                     dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status, nullptr,
                                     c->stream, c->src);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused_stage(1, c->fwaves, c->fgrid, 1, c->fitems, U, c->U1, c->U2, c->flam, c->fdt,
+            fvk::launch_fused_stage(1, c->fwaves[1], c->fgrid[1], 1, c->fitems[1], U, c->U1, c->U2, c->flam, c->fdt,
                                     nullptr, nullptr, c->status, nullptr, c->stream, c->src);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
-            fvk::launch_fused_stage(2, c->fwaves, c->fgrid, 1, c->fitems, U, c->U2, U, c->flam, c->fdt,
+            fvk::launch_fused_stage(2, c->fwaves[2], c->fgrid[2], 1, c->fitems[2], U, c->U2, U, c->flam, c->fdt,
                                     nullptr, nullptr, c->status, nullptr, c->stream, c->src);
         }
         int rc = check_launch_error(c);
@@ -499,25 +523,13 @@ static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in,
     return FV_OK;
 }
 
-int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
-    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
-    if (path == FV_PATH_SPLIT) {
-        c->path = FV_PATH_SPLIT;
-        return FV_OK;
-    }
-    if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
-    for (int d = 0; d < c->g.ndim; ++d)
-        for (int s = 0; s < 2; ++s)
-            if (c->g.bc[d][s] == FV_BC_WALL || c->g.bc[d][s] == FV_BC_INFLOW)
-                return fail(c, FV_ENOTSUP, "slip walls and inflow faces run on the split path only%s");
-    if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "viscous grids run on the split path only%s");
-    if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
-        return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
-    if (seg != 0 && (seg < 4 || seg > 1024 || seg % 4 != 0))
-        return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
-    if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");
+// Builds the fused grid description of stage `st` with segment height seg
+// (0: the library's choice) and wave count waves, uploads it to the stage's
+// slot and records the stage's work items.
+static int set_fused_stage(fv_ctx* c, int st, int32_t seg, int32_t waves) {
+    hipError_t e;
     if (c->g.ndim == 3) {
-        fvk::FGrid3& G = c->fgrid3_host;
+        fvk::FGrid3 G;
         memset(&G, 0, sizeof(G));
         G.nx = c->g.n[0];
         G.ny = c->g.n[1];
@@ -546,54 +558,111 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         G.gm1 = c->g.gm1;
         if (seg == 0) seg = fvk::fused3d_auto_seg(G, fvk::fused3d_slots());
         G.seg = seg;
-        hipError_t e = hipMemcpyAsync(c->fgrid, &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->fgrid[st], &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
-        c->fseg = seg;
-        c->fwaves = waves;
-        c->fitems = fvk::fused3d_items(G, seg);
-        c->path = FV_PATH_FUSED;
+        c->fitems[st] = fvk::fused3d_items(G, seg);
+    } else {
+        fvk::FGrid G;
+        memset(&G, 0, sizeof(G));
+        G.nx = c->g.n[0];
+        G.ny = c->g.n[1];
+        G.pitch = c->g.sy;
+        G.strips = fvk::fused_strips(G.nx);
+        G.work0 = 0;
+        G.scheme = c->g.scheme;
+        G.bcx0 = c->g.bc[0][0];
+        G.bcx1 = c->g.bc[0][1];
+        G.bcy0 = c->g.bc[1][0];
+        G.bcy1 = c->g.bc[1][1];
+        G.base = c->g.off0;
+        G.sv = c->g.sv;
+        G.ax = c->g.area[0];
+        G.ay = c->g.area[1];
+        G.inv_vol = c->g.inv_vol;
+        G.inv_dx = c->g.inv_dx[0];
+        G.inv_dy = c->g.inv_dx[1];
+        G.cfl = c->g.cfl;
+        G.gamma = c->g.gamma;
+        G.gm1 = c->g.gm1;
+        if (seg == 0) seg = fvk::fused_auto_seg(&G, 1, fvk::fused_slots());
+        G.seg = seg;
+        e = hipMemcpyAsync(c->fgrid[st], &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        c->fitems[st] = fvk::fused_items(G, seg);
+    }
+    if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
+    c->fseg[st] = seg;
+    c->fwaves[st] = waves;
+    return FV_OK;
+}
+
+static bool valid_fused_seg(int32_t seg) { return seg == 0 || (seg >= 4 && seg <= 1024 && seg % 4 == 0); }
+
+int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (path == FV_PATH_SPLIT) {
+        c->path = FV_PATH_SPLIT;
         return FV_OK;
     }
-    fvk::FGrid& G = c->fgrid_host;
-    memset(&G, 0, sizeof(G));
-    G.nx = c->g.n[0];
-    G.ny = c->g.n[1];
-    G.pitch = c->g.sy;
-    G.strips = fvk::fused_strips(G.nx);
-    G.work0 = 0;
-    G.scheme = c->g.scheme;
-    G.bcx0 = c->g.bc[0][0];
-    G.bcx1 = c->g.bc[0][1];
-    G.bcy0 = c->g.bc[1][0];
-    G.bcy1 = c->g.bc[1][1];
-    G.base = c->g.off0;
-    G.sv = c->g.sv;
-    G.ax = c->g.area[0];
-    G.ay = c->g.area[1];
-    G.inv_vol = c->g.inv_vol;
-    G.inv_dx = c->g.inv_dx[0];
-    G.inv_dy = c->g.inv_dx[1];
-    G.cfl = c->g.cfl;
-    G.gamma = c->g.gamma;
-    G.gm1 = c->g.gm1;
-    if (seg == 0) seg = fvk::fused_auto_seg(&G, 1, fvk::fused_slots());
-    G.seg = seg;
-    hipError_t e = hipMemcpyAsync(c->fgrid, &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return fail(c, FV_EDEVICE, "grid table upload failed: %s", hipGetErrorString(e));
-    c->fseg = seg;
-    c->fwaves = waves;
-    c->fitems = fvk::fused_items(G, seg);
+    if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
+    for (int d = 0; d < c->g.ndim; ++d)
+        for (int s = 0; s < 2; ++s)
+            if (c->g.bc[d][s] == FV_BC_WALL || c->g.bc[d][s] == FV_BC_INFLOW)
+                return fail(c, FV_ENOTSUP, "slip walls and inflow faces run on the split path only%s");
+    if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "viscous grids run on the split path only%s");
+    if (c->g.met) return fail(c, FV_ENOTSUP, "curvilinear grids run on the split path only%s");
+    if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
+        return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
+    if (!valid_fused_seg(seg))
+        return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
+    if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");
+    for (int st = 0; st < 3; ++st) {
+        const int rc = set_fused_stage(c, st, seg, waves);
+        if (rc != FV_OK) return rc;
+    }
     c->path = FV_PATH_FUSED;
+    return FV_OK;
+}
+
+int fv_set_fused_launch(fv_ctx* c, const fv_fused_launch* l) {
+    if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
+    if (!l) return fail(c, FV_EINVAL, "null launch table%s");
+    if (c->path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "select the fused path first (fv_set_path)%s");
+    for (int st = 0; st < 3; ++st) {
+        if (!valid_fused_seg(l->seg[st]))
+            return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
+        if (l->waves[st] < 0) return fail(c, FV_EINVAL, "negative wave count%s");
+    }
+    for (int st = 0; st < 3; ++st) {
+        const int rc = set_fused_stage(c, st, l->seg[st], l->waves[st]);
+        if (rc != FV_OK) return rc;
+    }
+    return FV_OK;
+}
+
+int fv_fused_slots(const fv_ctx* c, int32_t* waves) {
+    if (!c || !waves) return FV_EINVAL;
+    const int w = c->g.ndim == 3 ? 4 * fvk::fused3d_slots() : fvk::fused_slots();
+    if (w <= 0) return FV_EDEVICE;
+    *waves = w;
+    return FV_OK;
+}
+
+int fv_get_fused_launch(const fv_ctx* c, fv_fused_launch* out) {
+    if (!c || !out) return FV_EINVAL;
+    if (c->path != FV_PATH_FUSED) return FV_EINVAL;
+    for (int st = 0; st < 3; ++st) {
+        out->seg[st] = c->fseg[st];
+        out->waves[st] = c->fwaves[st];
+    }
     return FV_OK;
 }
 
 int fv_get_path(const fv_ctx* c, int32_t* path, int32_t* seg, int32_t* waves) {
     if (!c) return FV_EINVAL;
     if (path) *path = c->path;
-    if (seg) *seg = c->path == FV_PATH_FUSED ? c->fseg : 0;
-    if (waves) *waves = c->path == FV_PATH_FUSED ? c->fwaves : 0;
+    if (seg) *seg = c->path == FV_PATH_FUSED ? c->fseg[0] : 0;
+    if (waves) *waves = c->path == FV_PATH_FUSED ? c->fwaves[0] : 0;
     return FV_OK;
 }
 
@@ -643,6 +712,7 @@ int fv_adjoint_step(fv_ctx* c, double* U_n, const double* dt, double* lam) {
     if (!c) return fail(nullptr, FV_EINVAL, "null context%s");
     if (!U_n || !dt || !lam) return fail(c, FV_EINVAL, "null state, dt or adjoint pointer%s");
     if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "the adjoint step covers the inviscid residual only%s");
+    if (c->g.met) return fail(c, FV_ENOTSUP, "the adjoint step covers uniform grids only%s");
     // recompute the stage states with the frozen dt: U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1))
     enqueue_bc(c, U_n);
     enqueue_fluxes(c, U_n);

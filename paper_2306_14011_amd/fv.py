@@ -85,11 +85,16 @@ class fv_grid_desc(ctypes.Structure):
         ("bc_state", ((ctypes.c_double * 5) * 2) * 3),
         ("mu", ctypes.c_double),
         ("prandtl", ctypes.c_double),
+        ("nodes", ctypes.c_void_p),
     ]
 
 
 class fv_launch(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32 * 14)]
+
+
+class fv_fused_launch(ctypes.Structure):
+    _fields_ = [("seg", ctypes.c_int32 * 3), ("waves", ctypes.c_int32 * 3)]
 
 
 FV_MLP_IN = 14
@@ -171,6 +176,9 @@ def lib():
         L.fv_set_path.argtypes = [_vp, ctypes.c_int, ctypes.c_int32, ctypes.c_int32]
         L.fv_get_path.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32)]
+        L.fv_set_fused_launch.argtypes = [_vp, ctypes.POINTER(fv_fused_launch)]
+        L.fv_get_fused_launch.argtypes = [_vp, ctypes.POINTER(fv_fused_launch)]
+        L.fv_fused_slots.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
         L.fv_get_timing.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.fv_last_error.argtypes = [_vp]
         L.fv_last_error.restype = ctypes.c_char_p
@@ -201,7 +209,8 @@ def lib():
                                           ctypes.c_int32, _vp, _vp, _vp]
         for name in ("fv_query", "fv_create", "fv_destroy", "fv_set_stream", "fv_residual", "fv_step",
                      "fv_adjoint_step", "fv_set_source", "fv_residual_norm", "fv_set_launch", "fv_get_launch", "fv_status", "fv_clear_status",
-                     "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_batch_query", "fv_batch_create",
+                     "fv_set_timing", "fv_get_timing", "fv_set_path", "fv_get_path", "fv_set_fused_launch",
+                     "fv_get_fused_launch", "fv_fused_slots", "fv_batch_query", "fv_batch_create",
                      "fv_batch_step", "fv_batch_set_timing", "fv_batch_dt", "fv_batch_status", "fv_batch_info", "fv_batch_set_schedule", "fv_batch_destroy",
                      "fv_mlp_workspace", "fv_mlp_sweep_workspace",
                      "fv_mlp_loss_grad", "fv_mlp_predict", "fv_mlp_train", "fv_mlp_sweep", "fv_mlp_sweep_static"):
@@ -217,11 +226,15 @@ def _check(rc, ctx=None):
     return rc
 
 
-def make_desc(spec) -> fv_grid_desc:
+def make_desc(spec, nodes_ptr=None) -> fv_grid_desc:
     """fv_grid_desc from any object with ndim, n, lo, hi, bc, gamma, cfl (and
     optionally limiter: False selects the unlimited scheme of kappa, see
-    scheme_of; mu and prandtl for the viscous flux, bc_state for inflow faces)."""
+    scheme_of; mu and prandtl for the viscous flux, bc_state for inflow faces,
+    nodes for a curvilinear grid, whose device copy nodes_ptr points to)."""
+    if getattr(spec, "nodes", None) is not None and nodes_ptr is None:
+        raise ValueError("a curvilinear grid needs the device pointer of its nodes (Solver uploads them)")
     d = fv_grid_desc()
+    d.nodes = nodes_ptr
     d.ndim = spec.ndim
     d.scheme = scheme_of(spec)
     for a in range(3):
@@ -329,6 +342,34 @@ def fv_get_path(ctx):
     p, sg, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib().fv_get_path(_vp(ctx), ctypes.byref(p), ctypes.byref(sg), ctypes.byref(w)), ctx)
     return p.value, sg.value, w.value
+
+
+def fv_set_fused_launch(ctx, seg, waves):
+    """Per-stage fused launch table: seg and waves are 3-sequences."""
+    l = fv_fused_launch()
+    for st in range(3):
+        l.seg[st] = int(seg[st])
+        l.waves[st] = int(waves[st])
+    return _check(lib().fv_set_fused_launch(_vp(ctx), ctypes.byref(l)), ctx)
+
+
+def fv_get_fused_launch(ctx):
+    """(seg[3], waves[3]) of the fused path in use."""
+    l = fv_fused_launch()
+    _check(lib().fv_get_fused_launch(_vp(ctx), ctypes.byref(l)), ctx)
+    return list(l.seg), list(l.waves)
+
+
+def fv_fused_table(vec):
+    """(seg[3], waves[3]) of a fused-space launch vector (stage s in slots 2s, 2s + 1)."""
+    return [int(vec[0]), int(vec[2]), int(vec[4])], [int(vec[1]), int(vec[3]), int(vec[5])]
+
+
+def fv_fused_slots(ctx):
+    """Wave slots the device holds at once for the fused stage kernels."""
+    w = ctypes.c_int32()
+    _check(lib().fv_fused_slots(_vp(ctx), ctypes.byref(w)), ctx)
+    return w.value
 
 
 def fv_set_timing(ctx, enable):
@@ -494,10 +535,17 @@ class Solver:
     def __init__(self, spec, device="cuda", stream=None):
         torch = _torch()
         self.spec = spec
-        self.desc = make_desc(spec)
+        self.device = torch.device(device)
+        self.nodes = None
+        nodes = getattr(spec, "nodes", None)
+        if nodes is not None:
+            nx, ny = int(spec.n[0]), int(spec.n[1])
+            self.nodes = torch.as_tensor(np.ascontiguousarray(nodes, dtype=np.float64)).to(self.device)
+            if spec.ndim != 2 or tuple(self.nodes.shape) != (2, ny + 1, nx + 1):
+                raise ValueError("curvilinear nodes must have shape (2, ny + 1, nx + 1) on a 2D grid")
+        self.desc = make_desc(spec, self.nodes.data_ptr() if self.nodes is not None else None)
         self.strides, self.ws_bytes = fv_query(self.desc)
         self.nvar = spec.ndim + 2
-        self.device = torch.device(device)
         sx, sy, sz, sv = self.strides
         self.U = torch.zeros(self.nvar * sv, dtype=torch.float64, device=self.device)
         # workspace: torch's allocator returns blocks aligned to at least 256 B
@@ -588,6 +636,13 @@ class Solver:
 
     def get_path(self):
         return fv_get_path(self.ctx)
+
+    def set_fused_launch(self, seg, waves):
+        """Per-stage segment heights and wave counts of the fused path (selected first)."""
+        fv_set_fused_launch(self.ctx, seg, waves)
+
+    def get_fused_launch(self):
+        return fv_get_fused_launch(self.ctx)
 
     def set_timing(self, enable):
         fv_set_timing(self.ctx, enable)
