@@ -227,8 +227,8 @@ class Autotuner:
         import torch
         self.torch = torch
         self.spec = spec
-        self.space = LaunchSpace.for_grid(spec)
         self.solver = fv.Solver(spec)
+        self.space = self.make_space()
         self.U0 = U0
         self.seed = seed
         self.repeats = repeats
@@ -238,15 +238,25 @@ class Autotuner:
         self.log_path = log_path
         self.solver.set_state(U0)
         self.U_start = self.solver.U.clone()
-        self.default = fv.fv_default_launch()
+        self.default = self.default_launch()
         self.ref = self._reference_state(self.default)
         self.steps = 1
         t = self._time(self.default, 1, 1)
         self.steps = max(1, int(math.ceil(self.min_ms / max(t, 1e-3))))
 
+    def make_space(self):
+        return LaunchSpace.for_grid(self.spec)
+
+    def default_launch(self):
+        return fv.fv_default_launch()
+
+    def apply_launch(self, launch):
+        """Sets a launch vector of the space on the solver."""
+        self.solver.set_launch(launch)
+
     def _reference_state(self, launch):
         s = self.solver
-        s.set_launch(launch)
+        self.apply_launch(launch)
         s.U.copy_(self.U_start)
         s.step(self.check_steps)
         return s.U.clone()
@@ -254,7 +264,7 @@ class Autotuner:
     def _time(self, launch, steps, repeats):
         torch = self.torch
         s = self.solver
-        s.set_launch(launch)
+        self.apply_launch(launch)
         stream = torch.cuda.current_stream()
         s.step(self.warmup)
         reps = []
@@ -274,7 +284,7 @@ class Autotuner:
         torch = self.torch
         s = self.solver
         try:
-            s.set_launch(launch)
+            self.apply_launch(launch)
         except fv.FvError:
             return float("nan"), False
         s.U.copy_(self.U_start)
@@ -288,7 +298,11 @@ class Autotuner:
         ms = self._time(launch, self.steps, self.repeats)
         return ms, valid
 
-    def collect(self, count):
+    def collect(self, count, budget_s=None):
+        """Times up to `count` seeded samples; with a time budget (seconds)
+        sampling stops once it is spent and self.budget_hit records it."""
+        t0 = time.perf_counter()
+        self.budget_hit = False
         samples = []
         done = {}
         if self.log_path and os.path.exists(self.log_path):
@@ -296,6 +310,9 @@ class Autotuner:
                 r = json.loads(line)
                 done[r["index"]] = Sample(r["index"], r["launch"], r["ms"], r["valid"], r.get("reps", []))
         for idx in self.space.sample(count, self.seed):
+            if budget_s is not None and time.perf_counter() - t0 > budget_s:
+                self.budget_hit = True
+                break
             if idx in done:
                 samples.append(done[idx])
                 continue
@@ -323,9 +340,9 @@ class Autotuner:
                 res[i].append(self._time(l, steps, 1))
         return [float(np.median(r)) for r in res]
 
-    def run(self, count=300, k=8, rounds=5, final_steps=None):
+    def run(self, count=300, k=8, rounds=5, final_steps=None, budget_s=None):
         t0 = time.perf_counter()
-        samples = self.collect(count)
+        samples = self.collect(count, budget_s)
         t_collect = time.perf_counter() - t0
         model = self.fit(samples)
         top_idx, top_val, t_sweep = self.sweep(model, k)
@@ -348,10 +365,33 @@ class Autotuner:
             epochs=len(model["losses"]), final_loss=float(model["losses"][-1]) if len(model["losses"]) else None,
             space_size=self.space.size, sweep_seconds=t_sweep, collect_seconds=t_collect,
             top_pred=[v * model["t_std"] + model["t_mean"] for v in top_val], top_measured_ms=[m for m, _ in cand_ms], steps_per_sample=self.steps,
+            samples_requested=count, sampling_budget_s=budget_s, sampling_budget_hit=self.budget_hit,
         )
 
     def close(self):
         self.solver.close()
+
+
+class FusedAutotuner(Autotuner):
+    """The same loop on the fused path of one grid (the kernels the headline
+    step runs): the launch surface is FusedSpace, each stage's segment height
+    and wave count; the reference is the library's own table (automatic
+    segment height, one wave per work item). Every table gives the same bits,
+    which each sample's check confirms."""
+
+    def make_space(self):
+        from .tune_space import FusedSpace
+        self.solver.set_path(fv.FV_PATH_FUSED, 0, 0)
+        return FusedSpace(self.spec, fv.fv_fused_slots(self.solver.ctx))
+
+    def default_launch(self):
+        seg, waves = self.solver.get_fused_launch()
+        return [seg[0], waves[0], seg[1], waves[1], seg[2], waves[2]] + [0] * 8
+
+    def apply_launch(self, launch):
+        from .tune_space import FusedSpace
+        seg, waves = FusedSpace.table(launch)
+        self.solver.set_fused_launch(seg, waves)
 
 
 class BatchAutotuner:
@@ -406,9 +446,14 @@ class BatchAutotuner:
         valid = bool(self.torch.equal(got, self.ref)) and not flags
         return self._time(schedule, self.steps), valid
 
-    def collect(self, count):
+    def collect(self, count, budget_s=None):
+        t0 = time.perf_counter()
+        self.budget_hit = False
         samples = []
         for idx in self.space.sample(min(count, self.space.size), self.seed):
+            if budget_s is not None and time.perf_counter() - t0 > budget_s:
+                self.budget_hit = True
+                break
             segs, order = self.space.schedule(idx)
             ms, valid = self.measure((segs, order))
             d = self.space.digits(idx)
@@ -426,9 +471,9 @@ class BatchAutotuner:
                 res[i].append(self._time(sc, self.steps))
         return [float(np.median(r)) for r in res]
 
-    def run(self, count=300, k=8, rounds=5):
+    def run(self, count=300, k=8, rounds=5, budget_s=None):
         t0 = time.perf_counter()
-        samples = self.collect(count)
+        samples = self.collect(count, budget_s)
         t_collect = time.perf_counter() - t0
         model = fit_samples(self.space, samples, self.seed)
         top_idx, top_val, t_sweep = sweep_space(self.space, model, k)
@@ -454,7 +499,8 @@ class BatchAutotuner:
             r2_test=model["r2_test"], r2_train=model["r2_train"], n_samples=len(samples), n_valid=len(good),
             n_train=model["n_train"], n_test=model["n_test"], epochs=len(model["losses"]),
             space_size=self.space.size, sweep_seconds=t_sweep, collect_seconds=t_collect,
-            top_measured_ms=[m for m, _ in cand_ms],
+            top_measured_ms=[m for m, _ in cand_ms], samples_requested=count, sampling_budget_s=budget_s,
+            sampling_budget_hit=self.budget_hit,
         )
 
     def close(self):
@@ -521,9 +567,10 @@ class SizedAutotuner:
         torch.cuda.synchronize()
         return idx, val, time.perf_counter() - t0
 
-    def run(self, count=300, k=8, rounds=5):
+    def run(self, count=300, k=8, rounds=5, budget_s=None):
+        """budget_s: time budget of each grid's sampling (seconds), or None."""
         t0 = time.perf_counter()
-        samples = [None if g in self.holdout else at.collect(count) for g, at in enumerate(self.tuners)]
+        samples = [None if g in self.holdout else at.collect(count, budget_s) for g, at in enumerate(self.tuners)]
         t_collect = time.perf_counter() - t0
         model = self.fit(samples)
         out = []
@@ -548,7 +595,9 @@ class SizedAutotuner:
                 top_measured_ms=[m for m, _ in cand_ms], r2_test=model["r2_test_per_grid"].get(g),
                 sweep_seconds=t_sweep, space_size=at.space.size, steps_per_sample=at.steps))
         return dict(grids=out, r2_test=model["r2_test"], r2_train=model["r2_train"], n_train=model["n_train"],
-                    n_test=model["n_test"], epochs=len(model["losses"]), collect_seconds=t_collect)
+                    n_test=model["n_test"], epochs=len(model["losses"]), collect_seconds=t_collect,
+                    sampling_budget_s=budget_s,
+                    sampling_budget_hit=any(getattr(at, "budget_hit", False) for at in self.tuners))
 
     def close(self):
         for at in self.tuners:

@@ -216,3 +216,54 @@ class BatchSpace(MixedRadixSpace):
         d = self.digits(idx)
         segs = [self.choices[b][d[b]][0] for b in self.bucket]
         return segs, self.choices[4][d[4]][0]
+
+
+FUSED_SEGS = (8, 12, 16, 20, 24, 32, 40, 48)
+FUSED_WAVE_FACTORS = (0, 0.5, 1.0, 2.0)   # 0: one wave per work item, else x the resident wave slots
+
+
+def fused_items(spec, seg: int) -> int:
+    """Work items of one fused stage launch at segment height seg: 60-column
+    strips x row segments in 2D, 16 x 15-cell tiles x plane segments in 3D
+    (each 3D item is a workgroup of four waves)."""
+    nx, ny, nz = (int(v) for v in spec.n)
+    if spec.ndim == 2:
+        return -(-nx // 60) * -(-ny // seg)
+    return -(-nx // 16) * -(-ny // 15) * -(-nz // seg)
+
+
+class FusedSpace(MixedRadixSpace):
+    """Launch space of the fused path, the paper's method applied to the
+    kernels the headline step runs: for each Runge-Kutta stage (sites 0-2)
+    the segment height of its work items and the number of waves its launch
+    holds (one per item, or a grid-stride loop over 1/2, 1 or 2 times the
+    device's resident wave slots); sites 3-6 are pinned. 8 x 4 choices per
+    stage: 32^3 = 32768 points. Features: log2 of the segment height and
+    log2 of the waves actually launched (at most one per item)."""
+
+    def __init__(self, spec, slots: int):
+        self.spec = spec
+        self.slots = int(slots)
+        self.choices, self.feats = [], []
+        for _ in range(3):
+            ch, ft = [], []
+            for sg in FUSED_SEGS:
+                items = fused_items(spec, sg)
+                per_item = items if spec.ndim == 2 else 4 * items
+                for f in FUSED_WAVE_FACTORS:
+                    w = 0 if f == 0 else max(4, int(round(f * self.slots)))
+                    eff = per_item if w == 0 else min(w, per_item)
+                    ch.append((sg, w))
+                    ft.append((math.log2(sg), math.log2(eff)))
+            self.choices.append(ch)
+            self.feats.append(ft)
+        for _ in range(4):
+            self.choices.append([(0, 0)])
+            self.feats.append([(0.0, 0.0)])
+        self.radix = [len(c) for c in self.choices]
+        self.size = int(np.prod([int(r) for r in self.radix], dtype=object))
+
+    @staticmethod
+    def table(vec):
+        """(seg[3], waves[3]) of a decoded 14-vector."""
+        return [int(vec[0]), int(vec[2]), int(vec[4])], [int(vec[1]), int(vec[3]), int(vec[5])]

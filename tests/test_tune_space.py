@@ -158,3 +158,26 @@ def test_grid_relative_target():
     # offsets come from the training rows only
     y2, _, off2 = grid_relative_target(t, gid, np.array([0, 1, 3, 4]))
     assert abs(off2[0] - 0.5 * math.log(2.0)) < 1e-15 and abs(off2[1] - 0.5 * math.log(128.0)) < 1e-15
+
+
+def test_fused_space_tables_and_features():
+    from paper_2306_14011_amd.tune_space import FUSED_SEGS, FusedSpace, fused_items
+    g = inputs.grid2d(2048, 2048)
+    sp = FusedSpace(g, 3072)
+    assert sp.size == 32 ** 3 and sp.radix[:3] == [32, 32, 32] and sp.radix[3:] == [1, 1, 1, 1]
+    # 2048^2 at segment 24: 35 strips x 86 row segments
+    assert fused_items(g, 24) == 35 * 86
+    for idx in sp.sample(50, 3):
+        vec = sp.decode(idx)
+        seg, waves = FusedSpace.table(vec)
+        assert all(sg in FUSED_SEGS for sg in seg)
+        assert all(w in (0, 1536, 3072, 6144) for w in waves)
+        assert sp.encode(vec) == idx
+    F = sp.features(sp.sample(20, 4))
+    assert np.isfinite(F).all() and (F[:, 6:] == 0).all()
+    # the launched waves never exceed one per item
+    g3 = inputs.grid3d(256, 256, 256)
+    sp3 = FusedSpace(g3, 2048)
+    for c, (sg, w) in enumerate(sp3.choices[0]):
+        per_item = 4 * fused_items(g3, sg)
+        assert 2 ** sp3.feats[0][c][1] <= per_item + 1e-9
