@@ -61,13 +61,14 @@ enum {
  * Case"): the ghost cells
  * are the mirror image of the interior across the face with the velocity
  * normal to the wall reversed, so no mass or energy crosses it. It needs at
- * least 2 cells on its axis and runs on the split path (fv_residual, fv_step,
- * fv_adjoint_step); the fused path and batches return FV_ENOTSUP / FV_EINVAL
- * for it. */
+ * least 2 cells on its axis. It runs on the split path (fv_residual,
+ * fv_step, fv_adjoint_step) and on the fused path (a boundary variant of the
+ * stage kernels maps ghost rows, columns and planes to the mirror cells);
+ * batches return FV_EINVAL for it. */
 /* FV_BC_INFLOW holds the given conserved state fv_grid_desc.bc_state[axis]
  * [side] in the ghost cells (supersonic inflow: every characteristic enters
  * through the face; the supersonic inlet of Sec. "A Test Case" takes in its
- * free stream), with the same path limits as the wall. Its state must have
+ * free stream), with the same path support as the wall. Its state must have
  * a positive density and pressure. FV_BC_TRANSMISSIVE serves as the
  * supersonic outflow. */
 enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1, FV_BC_WALL = 2, FV_BC_INFLOW = 3 };
@@ -99,8 +100,10 @@ enum {
     FV_SCHEME_FROMM = 2,       /* Psi = 1, kappa = 0: Fromm's upwind-biased scheme      */
     FV_SCHEME_THIRD = 3,       /* Psi = 1, kappa = 1/3: third-order upwind-biased       */
     FV_SCHEME_CENTRAL = 4,     /* Psi = 1, kappa = 1: central                            */
-    FV_SCHEME_VANLEER = 5      /* van Leer's limiter, Psi(r) = (r + |r|)/(1 + |r|) (symmetric,
+    FV_SCHEME_VANLEER = 5,     /* van Leer's limiter, Psi(r) = (r + |r|)/(1 + |r|) (symmetric,
                                   so kappa drops out as with minmod)                      */
+    FV_SCHEME_QUICK = 6        /* Psi = 1, kappa = 1/2: Leonard's QUICK (quadratic upstream
+                                  interpolation, exact for quadratic point values)        */
 };
 
 /* Grid description. ndim is 2 or 3; n[2] must be 1 in 2D. The box is
@@ -150,9 +153,10 @@ typedef struct fv_grid_desc {
  * outside the grid go through the boundary maps of each axis. The time step
  * adds the explicit diffusion limit: the wave-speed sum of each cell gains
  * 2 (mu / rho) max(4/3, gamma / prandtl) sum_d 1 / dx_d^2. Viscous grids run
- * on the split path (fv_residual, fv_step, fv_residual_norm); fv_set_path
- * (FV_PATH_FUSED) and fv_adjoint_step return FV_ENOTSUP and batches refuse
- * them (FV_EINVAL). */
+ * on the split path (fv_residual, fv_step, fv_residual_norm) and, in 2D, on
+ * the fused path (a viscous variant of the stage kernels); fv_set_path
+ * (FV_PATH_FUSED) on 3D viscous grids and fv_adjoint_step return FV_ENOTSUP,
+ * and batches refuse them (FV_EINVAL). */
 
 /* Launch parameters, two per site (FV_SITE_* order).
  *  Stencil sites (flux x/y/z): p[2s] = block width along x, a power of two in
@@ -254,15 +258,17 @@ int fv_clear_status(fv_ctx* ctx);
  * state then moves through HBM 8 times per step instead of ~33 (2D) or ~42
  * (3D). `seg` is the segment height of a work item (rows in 2D, planes in
  * 3D), a multiple of 4 in [4, 1024], or 0 to let the library choose it from
- * the grid and the number of wavefronts the device holds at once (a work item
- * is a 60-column strip of a segment, one wavefront each); `waves` is the
+ * the grid and the number of wavefronts the device holds at once (in 2D a work
+ * item is a 60-column strip of a segment, one wavefront; in 3D a 32 x 7-cell
+ * tile of the plane over a segment of planes, one workgroup of four
+ * wavefronts); `waves` is the
  * number of wavefronts launched (0 = one per work item, else a grid-stride
  * loop over the items). Every segment height and wave count gives bitwise the
  * same result. Both paths compute the same cell arithmetic; fv_residual and
  * fv_adjoint_step always use the split kernels. Returns FV_ENOTSUP for states
  * of 4 GiB or more (the fused kernels address a grid through 32-bit buffer
- * offsets) and for grids with slip-wall or inflow faces (the fused kernels
- * map boundaries by index only), and FV_EINVAL for other seg values. */
+ * offsets), for 3D viscous and for curvilinear grids, and FV_EINVAL for
+ * other seg values. The fused path takes every boundary kind. */
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
 

@@ -81,7 +81,7 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
         snprintf(why, 256, "ndim must be 2 or 3");
         return FV_EINVAL;
     }
-    if (g->scheme < FV_SCHEME_MINMOD || g->scheme > FV_SCHEME_VANLEER) {
+    if (g->scheme < FV_SCHEME_MINMOD || g->scheme > FV_SCHEME_QUICK) {
         snprintf(why, 256, "unknown scheme");
         return FV_EINVAL;
     }
@@ -166,8 +166,8 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     o += 256;
     L->off_dt = o;
     o += 256;
-    L->off_fused = o;   // 3 x 256 B: an FGrid (128 B) or FGrid3 (160 B) per stage; lambda at +768, dt at +776
-    o += 1024;
+    L->off_fused = o;   // 3 x 512 B: an FGrid or FGrid3 per stage; lambda at +1536, dt at +1544
+    o += 2048;
     L->off_partial = o;
     o = align256(o + (size_t)L->max_partial * 8);
     const size_t state = (size_t)L->nvar * L->sv * 8;
@@ -420,9 +420,9 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
     c->lamA = (double*)(base + L.off_lamA);
     c->lamB = (double*)(base + L.off_lamB);
     for (int d = 0; d < 3; ++d) c->G[d] = (double*)(base + L.off_G[d]);
-    for (int st = 0; st < 3; ++st) c->fgrid[st] = (fvk::FGrid*)(base + L.off_fused + 256 * st);
-    c->flam = (unsigned long long*)(base + L.off_fused + 768);
-    c->fdt = (double*)(base + L.off_fused + 776);
+    for (int st = 0; st < 3; ++st) c->fgrid[st] = (fvk::FGrid*)(base + L.off_fused + 512 * st);
+    c->flam = (unsigned long long*)(base + L.off_fused + 1536);
+    c->fdt = (double*)(base + L.off_fused + 1544);
     c->path = FV_PATH_SPLIT;
     if (g->nodes) {
         double* met = (double*)(base + L.off_met);
@@ -464,27 +464,36 @@ int fv_residual(fv_ctx* c, double* U, double* R) {
     return drain_timing(c);
 }
 
-static_assert(sizeof(fvk::FGrid) <= 256 && sizeof(fvk::FGrid3) <= 256, "fused grid slot is 256 bytes");
+static_assert(sizeof(fvk::FGrid) <= 512 && sizeof(fvk::FGrid3) <= 512, "fused grid slot is 512 bytes");
+
+// Whether a grid has a slip-wall or inflow face (the fused kernels' boundary variant).
+static bool has_walls(const fv_ctx* c) {
+    for (int d = 0; d < c->g.ndim; ++d)
+        for (int s = 0; s < 2; ++s)
+            if (c->g.bc[d][s] == FV_BC_WALL || c->g.bc[d][s] == FV_BC_INFLOW) return true;
+    return false;
+}
 
 static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     const fvk::FGrid3* const* G = (const fvk::FGrid3* const*)c->fgrid;
+    const bool walls = has_walls(c);
     fvk::launch_fused3d_init(c->fwaves[0], G[0], c->fitems[0], U, c->flam, c->status, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(0, c->fwaves[0], G[0], c->fitems[0], U, U, c->U1, c->flam, c->fdt,
                                       dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status,
-                                      c->stream, c->src, c->g.vol);
+                                      c->stream, c->src, c->g.vol, walls);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(1, c->fwaves[1], G[1], c->fitems[1], U, c->U1, c->U2, c->flam, c->fdt,
-                                      nullptr, nullptr, c->status, c->stream, c->src, c->g.vol);
+                                      nullptr, nullptr, c->status, c->stream, c->src, c->g.vol, walls);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused3d_stage(2, c->fwaves[2], G[2], c->fitems[2], U, c->U2, U, c->flam, c->fdt, nullptr,
-                                      nullptr, c->status, c->stream, c->src, c->g.vol);
+                                      nullptr, c->status, c->stream, c->src, c->g.vol, walls);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;
@@ -497,23 +506,24 @@ static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in
 static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (nsteps == 0) return FV_OK;
     if (c->g.ndim == 3) return fused_step3(c, U, nsteps, dt_in, dt_out);
+    const int walls = c->g.mu > 0.0 ? 2 : (has_walls(c) ? 1 : 0);
     fvk::launch_fused_init(c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, c->flam, c->status, c->stream);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(0, c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, U, c->U1, c->flam, c->fdt,
                                     dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status, nullptr,
-                                    c->stream, c->src);
+                                    c->stream, c->src, walls);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(1, c->fwaves[1], c->fgrid[1], 1, c->fitems[1], U, c->U1, c->U2, c->flam, c->fdt,
-                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src);
+                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(2, c->fwaves[2], c->fgrid[2], 1, c->fitems[2], U, c->U2, U, c->flam, c->fdt,
-                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src);
+                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;
@@ -556,6 +566,7 @@ static int set_fused_stage(fv_ctx* c, int st, int32_t seg, int32_t waves) {
         G.cfl = c->g.cfl;
         G.gamma = c->g.gamma;
         G.gm1 = c->g.gm1;
+        memcpy(G.q, c->bcs.q, sizeof(G.q));
         if (seg == 0) seg = fvk::fused3d_auto_seg(G, fvk::fused3d_slots());
         G.seg = seg;
         e = hipMemcpyAsync(c->fgrid[st], &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
@@ -584,6 +595,12 @@ static int set_fused_stage(fv_ctx* c, int st, int32_t seg, int32_t waves) {
         G.cfl = c->g.cfl;
         G.gamma = c->g.gamma;
         G.gm1 = c->g.gm1;
+        for (int a = 0; a < 2; ++a)
+            for (int sd = 0; sd < 2; ++sd)
+                for (int v = 0; v < 4; ++v) G.q[a][sd][v] = c->bcs.q[a][sd][v];
+        G.mu = c->g.mu;
+        G.kcond = c->g.kcond;
+        G.nu_fac = c->g.nu_fac;
         if (seg == 0) seg = fvk::fused_auto_seg(&G, 1, fvk::fused_slots());
         G.seg = seg;
         e = hipMemcpyAsync(c->fgrid[st], &G, sizeof(G), hipMemcpyHostToDevice, c->stream);
@@ -605,11 +622,7 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         return FV_OK;
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
-    for (int d = 0; d < c->g.ndim; ++d)
-        for (int s = 0; s < 2; ++s)
-            if (c->g.bc[d][s] == FV_BC_WALL || c->g.bc[d][s] == FV_BC_INFLOW)
-                return fail(c, FV_ENOTSUP, "slip walls and inflow faces run on the split path only%s");
-    if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "viscous grids run on the split path only%s");
+    if (c->g.mu > 0.0 && c->g.ndim == 3) return fail(c, FV_ENOTSUP, "3D viscous grids run on the split path only%s");
     if (c->g.met) return fail(c, FV_ENOTSUP, "curvilinear grids run on the split path only%s");
     if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
         return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");

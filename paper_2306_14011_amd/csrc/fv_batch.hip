@@ -69,7 +69,7 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
             snprintf(why, 256, "grid %d: a state of 4 GiB or more (buffer offsets are 32-bit)", g);
             return FV_EINVAL;
         }
-        if (d.scheme < FV_SCHEME_MINMOD || d.scheme > FV_SCHEME_VANLEER) {
+        if (d.scheme < FV_SCHEME_MINMOD || d.scheme > FV_SCHEME_QUICK) {
             snprintf(why, 256, "grid %d: unknown scheme", g);
             return FV_EINVAL;
         }

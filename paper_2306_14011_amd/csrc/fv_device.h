@@ -55,7 +55,7 @@ struct Geo {
     double gamma, gm1;  // gamma, gamma - 1
     double cfl;
     int bc[3][2];
-    int scheme;         // 0 minmod; Psi = 1 with kappa = -1, 0, 1/3, 1 for 1 .. 4; 5 van Leer
+    int scheme;         // 0 minmod; Psi = 1 with kappa = -1, 0, 1/3, 1 for 1 .. 4; 5 van Leer; 6 kappa = 1/2
     double mu;          // dynamic viscosity, 0 for the Euler equations
     double kcond;       // heat conductivity mu gamma / ((gamma - 1) Pr)
     double nu_fac;      // max(4/3, gamma / Pr): the larger diffusivity per unit kinematic viscosity
@@ -165,9 +165,9 @@ __host__ __device__ __forceinline__ void muscl_fixed(double q0, double q1, doubl
 // Weights of the unlimited (Psi = 1) kappa family of Eq. (flux) with
 // epsilon = 1: Q^L = Q_k + a dQ_{k-1/2} + b dQ_{k+1/2} and
 // Q^R = Q_{k+1} - b dQ_{k+1/2} - a dQ_{k+3/2}, a = (1 - kappa)/4,
-// b = (1 + kappa)/4, for schemes 2 .. 4 (kappa = 0, 1/3, 1).
+// b = (1 + kappa)/4, for schemes 2 .. 4 (kappa = 0, 1/3, 1) and 6 (kappa = 1/2).
 __host__ __device__ __forceinline__ void kappa_weights(int scheme, double& a, double& b) {
-    const double kappa = scheme == 2 ? 0.0 : (scheme == 3 ? 1.0 / 3.0 : 1.0);
+    const double kappa = scheme == 2 ? 0.0 : (scheme == 3 ? 1.0 / 3.0 : (scheme == 6 ? 0.5 : 1.0));
     a = 0.25 * (1.0 - kappa);
     b = 0.25 * (1.0 + kappa);
 }
@@ -182,7 +182,7 @@ __host__ __device__ __forceinline__ void muscl_kappa_diffs(double q1, double q2,
 }
 
 // The same with the scheme chosen at run time (uniform): 0 minmod, 1 Psi = 1
-// with kappa = -1, 2 .. 4 the other kappa members.
+// with kappa = -1, 2 .. 4 and 6 the other kappa members, 5 van Leer.
 __host__ __device__ __forceinline__ void muscl(double q0, double q1, double q2, double q3, int scheme,
                                               double& qL, double& qR) {
     if (scheme == 1) {

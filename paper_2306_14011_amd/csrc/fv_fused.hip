@@ -27,6 +27,52 @@
 
 namespace fvk {
 
+// The viscous variant's arithmetic contracts multiply-adds only within one
+// source expression (the pragma in each viscous block): the first face of a
+// work item is computed before the row loop and the others inside it, and
+// contraction across statements could then differ between the two places,
+// giving bits that depend on the segment height.
+
+// Viscous variant: velocity and temperature w = (u, v, T = p / rho) of a cell.
+__device__ __forceinline__ void visc_w2(const double* q, double gm1, double* w) {
+#pragma clang fp contract(on)
+    const double ir = 1.0 / q[0];
+    w[0] = q[1] * ir;
+    w[1] = q[2] * ir;
+    w[2] = gm1 * (q[3] - 0.5 * q[0] * (w[0] * w[0] + w[1] * w[1])) * ir;
+}
+
+// Viscous flux F_nu,n (Eq. (QF), n = e_AX) through a face from w at its low
+// (wa) and high (wb) cells, the tangential derivatives dt of (u, v, T) along
+// the other axis, and 1 / dx_AX: tau_{a,AX} = mu (du_a/dx_AX + du_AX/dx_a) -
+// 2/3 mu delta div(u), Theta = ubar . tau + k dT/dx_AX. F[0] = 0 is omitted.
+template <int AX>
+__device__ __forceinline__ void visc_flux2(const double* wa, const double* wb, const double* dt, double inv_dn,
+                                           double mu, double kc, double* F) {
+#pragma clang fp contract(on)
+    double gn[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) gn[m] = (wb[m] - wa[m]) * inv_dn;
+    // grad[m][d]: d w_m / d x_d
+    const double dux = AX == 0 ? gn[0] : dt[0], duy = AX == 0 ? dt[0] : gn[0];
+    const double dvx = AX == 0 ? gn[1] : dt[1], dvy = AX == 0 ? dt[1] : gn[1];
+    const double divu = dux + dvy;
+    double tau[2];
+    if (AX == 0) {
+        tau[0] = mu * (dux + dux) - (2.0 / 3.0) * mu * divu;
+        tau[1] = mu * (dvx + duy);
+    } else {
+        tau[0] = mu * (duy + dvx);
+        tau[1] = mu * (dvy + dvy) - (2.0 / 3.0) * mu * divu;
+    }
+    double th = kc * gn[2];
+    th += 0.5 * (wa[0] + wb[0]) * tau[0];
+    th += 0.5 * (wa[1] + wb[1]) * tau[1];
+    F[0] = tau[0];
+    F[1] = tau[1];
+    F[2] = th;
+}
+
 // The rows of one work item (strip, rows r0 .. r0 + seg - 1) for stage STAGE
 // with the face-state rule fixed at compile time (LIM: 0 minmod, 1 Psi = 1
 // with kappa = -1, 2 Psi = 1 with the kappa weights ka, kb, 3 van Leer). The
@@ -37,17 +83,39 @@ namespace fvk {
 // drops them. A conditional load or store would make the compiler's wait
 // counting assume the shortest path and wait for every outstanding access
 // (the prefetches included) at the top of each row.
-template <int STAGE, int LIM, bool SRC>
+template <int STAGE, int LIM, bool SRC, int MODE>
 __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip, int r0, double s, const double* Un,
                                              const double* Us, double* Ud, double& lmax, uint32_t& fl, double ka,
                                              double kb, const double* src) {
+    constexpr bool BC = MODE >= 1;     // boundary variant: slip walls and inflow faces
+    constexpr bool VISC = MODE == 2;   // and the viscous flux
     constexpr bool UNL = LIM == 1;
     constexpr int NV = 4;
     const int seg = G.seg;
     const int col = FW * strip - 2 + lane;
     // lanes past the last halo column feed no output: they read that
     // column again (the same cache line) instead of wrapped or clamped data
-    const int cmap = map_index(col < G.nx + 1 ? col : G.nx + 1, G.nx, G.bcx0, G.bcx1);
+    const int ccl = col < G.nx + 1 ? col : G.nx + 1;
+    const int cmap = BC ? map_index_bc(ccl, G.nx, G.bcx0, G.bcx1) : map_index(ccl, G.nx, G.bcx0, G.bcx1);
+    // boundary variant: the kind of the face a ghost column lies behind
+    // (slip wall: the mirror cell with its x momentum reversed; inflow: the
+    // side's given state), per lane; -1 inside the grid
+    const int xk = !BC ? -1 : (col < 0 ? G.bcx0 : (col >= G.nx ? G.bcx1 : -1));
+    const int xside = col < 0 ? 0 : 1;
+    // applies the ghost rules of row r (uniform) and of this lane's column to a loaded cell
+    auto ghost = [&](double* w, int r) {
+        if (!BC) return;
+        const int yk = r < 0 ? G.bcy0 : (r >= G.ny ? G.bcy1 : -1);
+        const int ys = r < 0 ? 0 : 1;
+        if (yk == 2) w[2] = -w[2];
+        if (yk == 3) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[v] = G.q[1][ys][v];
+        }
+        w[1] = xk == 2 ? -w[1] : w[1];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = xk == 3 ? G.q[0][xside][v] : w[v];
+    };
     const bool out_lane = lane >= 2 && lane < 2 + FW && col < G.nx;
     const long long gbytes = 4 * G.sv * 8;  // one grid's state, below 4 GiB
     const Rsrc rs = grid_rsrc(Us + G.base, gbytes), rn = grid_rsrc(Un + G.base, gbytes);
@@ -74,7 +142,8 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     // byte offset of U_s row r through the y boundary map (rows past the
     // last halo row are clamped inside the grid; they feed no output)
     auto row_off = [&](int r) -> uint32_t {
-        return (uint32_t)((long long)map_index(r, G.ny, G.bcy0, G.bcy1) * G.pitch * 8);
+        const int m = BC ? map_index_bc(r, G.ny, G.bcy0, G.bcy1) : map_index(r, G.ny, G.bcy0, G.bcy1);
+        return (uint32_t)((long long)m * G.pitch * 8);
     };
     auto out_row = [&](int r) -> uint32_t { return (uint32_t)((long long)(r < G.ny ? r : G.ny - 1) * G.pitch * 8); };
     // Circular window of four U_s rows: row r sits in slot (r - r0 + 2) & 3.
@@ -100,6 +169,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
         const uint32_t o = row_off(r0 - 2 + k);
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[k][v] = ld_buf(rs, cboff, o + v * vstride);
+        ghost(W[k], r0 - 2 + k);
     }
     double Fy[2][NV];   // y-face fluxes (times 2): face f in Fy[f & 1]
     double Unb[2][NV];  // U^n of the output row of face f in Unb[f & 1], requested one face ahead
@@ -130,8 +200,24 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
         const uint32_t o = row_off(r0 + 2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[0][v] = ld_buf(rs, cboff, o + v * vstride);
+        ghost(W[0], r0 + 2);
     }
     roe_flux<2, 1, true>(qL, qR, G.gm1, Fy[0]);
+    // viscous variant: w = (u, v, T) of row r in Wv[(r - r0 + 2) & 3], like the
+    // window; the viscous y-face fluxes of face f in Vy[f & 1]
+    double Wv[4][3], Vy[2][3];
+    const double qdx = 0.25 * G.inv_dx, qdy = 0.25 * G.inv_dy;
+    if (VISC) {
+#pragma clang fp contract(on)
+        visc_w2(W[1], G.gm1, Wv[1]);  // row r0 - 1
+        visc_w2(W[2], G.gm1, Wv[2]);  // row r0
+        double dt[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            dt[m] = ((lane_shift1<false>(Wv[1][m]) - lane_shift1<true>(Wv[1][m])) +
+                     (lane_shift1<false>(Wv[2][m]) - lane_shift1<true>(Wv[2][m]))) * qdx;
+        visc_flux2<1>(Wv[1], Wv[2], dt, G.inv_dy, G.mu, G.kcond, Vy[0]);
+    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll 1
     for (int m0 = 1; m0 <= seg; m0 += 4) {
@@ -150,6 +236,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                 const uint32_t o = row_off(rr + 3);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) W[t][v] = ld_buf(rs, cboff, o + v * vstride);
+                ghost(W[t], rr + 3);
             }
             if (STAGE > 0) {
                 // U^n of row rr + 1, used at face f + 1
@@ -174,6 +261,22 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                 Dy[v] = dn;
             }
             roe_flux<2, 1, true>(qL, qR, G.gm1, Fy[t & 1]);
+            // viscous y face f between rows rr and rr + 1; the neighbours'
+            // w of rows rr and rr + 1 serve the x face below too
+            double wl0[3], wl1[3];  // w of the lane below (column i - 1) in rows rr, rr + 1
+            if (VISC) {
+#pragma clang fp contract(on)
+                visc_w2(W[(t + 2) & 3], G.gm1, Wv[(t + 2) & 3]);  // row rr + 1
+                double dt[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    wl0[m] = lane_shift1<true>(Wv[(t + 1) & 3][m]);
+                    wl1[m] = lane_shift1<true>(Wv[(t + 2) & 3][m]);
+                    dt[m] = ((lane_shift1<false>(Wv[(t + 1) & 3][m]) - wl0[m]) +
+                             (lane_shift1<false>(Wv[(t + 2) & 3][m]) - wl1[m])) * qdx;
+                }
+                visc_flux2<1>(Wv[(t + 1) & 3], Wv[(t + 2) & 3], dt, G.inv_dy, G.mu, G.kcond, Vy[t & 1]);
+            }
             // x faces of row rr: this lane computes its left face; its right
             // face is the left face of the lane above. Each lane forms its
             // backward difference once and its slope once, and takes the
@@ -195,6 +298,21 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             roe_flux<2, 0, true>(qL, qR, G.gm1, Fxl);
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fxr[v] = lane_shift1<false>(Fxl[v]);
+            // viscous x face left of this lane (columns i - 1 and i of row
+            // rr), tangential derivative from rows rr - 1 and rr + 1
+            double Vxl[3], Vxr[3];
+            if (VISC) {
+#pragma clang fp contract(on)
+                double dt[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const double lo_m = lane_shift1<true>(Wv[t][m]);  // (i - 1, rr - 1)
+                    dt[m] = ((wl1[m] - lo_m) + (Wv[(t + 2) & 3][m] - Wv[t][m])) * qdy;
+                }
+                visc_flux2<0>(wl0, Wv[(t + 1) & 3], dt, G.inv_dx, G.mu, G.kcond, Vxl);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) Vxr[m] = lane_shift1<false>(Vxl[m]);
+            }
             const bool row_ok = rr < G.ny;  // uniform
             const uint32_t p = out_row(rr);
             const uint32_t so = row_ok ? sboff : DROP_OFFSET;
@@ -210,6 +328,11 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
                 // the doubled fluxes against halved areas: the same products
                 double r = (Fxr[v] - Fxl[v]) * hax;
                 r += (Fy[t & 1][v] - Fy[(t + 1) & 1][v]) * hay;
+                if (VISC && v > 0) {
+                    // minus the viscous face fluxes (Eq. (residual): F_i,n - F_nu,n)
+                    r -= (Vxr[v - 1] - Vxl[v - 1]) * G.ax;
+                    r -= (Vy[t & 1][v - 1] - Vy[(t + 1) & 1][v - 1]) * G.ay;
+                }
                 if (SRC) r -= vol * Sv[v];  // R = flux sum - |Omega| S
                 if (STAGE == 0) {
                     out[v] = c[v] + s * r;
@@ -222,7 +345,9 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
             }
             if (STAGE == 2 && out_lane && row_ok) {
                 const double idx[2] = {G.inv_dx, G.inv_dy};
-                lmax = fmax(lmax, cell_lambda<2>(out, G.gamma, G.gm1, idx, fl));
+                double lam = cell_lambda<2>(out, G.gamma, G.gm1, idx, fl);
+                if (VISC) lam += 2.0 * ((G.mu / out[0]) * G.nu_fac) * (G.inv_dx * G.inv_dx + G.inv_dy * G.inv_dy);
+                lmax = fmax(lmax, lam);
             }
             // keep the scheduler from overlapping consecutive rows, which
             // would raise the live register count
@@ -231,7 +356,7 @@ __device__ __forceinline__ void fused2d_rows(const FGrid& G, int lane, int strip
     }
 }
 
-template <int STAGE, bool SRC>
+template <int STAGE, bool SRC, int MODE>
 __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids, int ngrids, int nitems,
                                                  const double* Un, const double* __restrict__ Us, double* Ud,
                                                  unsigned long long* __restrict__ lam, double* __restrict__ dtg,
@@ -267,15 +392,15 @@ __global__ void __launch_bounds__(256) k_fused2d(const FGrid* __restrict__ grids
         double lmax = 0.0;
         uint32_t fl = 0;
         if (G.scheme == 0) {
-            fused2d_rows<STAGE, 0, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
+            fused2d_rows<STAGE, 0, SRC, MODE>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
         } else if (G.scheme == 5) {
-            fused2d_rows<STAGE, 3, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
+            fused2d_rows<STAGE, 3, SRC, MODE>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
         } else if (G.scheme == 1) {
-            fused2d_rows<STAGE, 1, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
+            fused2d_rows<STAGE, 1, SRC, MODE>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src);
         } else {
             double ka, kb;
             kappa_weights(G.scheme, ka, kb);
-            fused2d_rows<STAGE, 2, SRC>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb, src);
+            fused2d_rows<STAGE, 2, SRC, MODE>(G, lane, strip, sidx * G.seg, s, Un, Us, Ud, lmax, fl, ka, kb, src);
         }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
@@ -317,7 +442,9 @@ __global__ void __launch_bounds__(256) k_fused_lambda(const FGrid* __restrict__ 
                 double q[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) q[v] = U[v * G.sv + p];
-                lmax = fmax(lmax, cell_lambda<2>(q, G.gamma, G.gm1, idx, fl));
+                double lam = cell_lambda<2>(q, G.gamma, G.gm1, idx, fl);
+                if (G.mu > 0.0) lam += 2.0 * ((G.mu / q[0]) * G.nu_fac) * (G.inv_dx * G.inv_dx + G.inv_dy * G.inv_dy);
+                lmax = fmax(lmax, lam);
             }
         }
         lmax = wave_max_d(lmax);
@@ -345,33 +472,42 @@ static inline int fused_blocks(int nitems, int waves) {
     return (w + 3) / 4;
 }
 
-template <bool SRC>
+template <bool SRC, int MODE>
 static void launch_fused_stage_t(int stage, dim3 grid, dim3 block, const FGrid* grids, int ngrids, int nitems,
                                  const double* Un, const double* Us, double* Ud, unsigned long long* lam,
                                  double* dtg, const double* dt_fixed, double* dt_out, uint32_t* status,
                                  unsigned long long* clk, const double* src, hipStream_t s) {
     if (stage == 0)
-        hipLaunchKernelGGL((k_fused2d<0, SRC>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
+        hipLaunchKernelGGL((k_fused2d<0, SRC, MODE>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk, src);
     else if (stage == 1)
-        hipLaunchKernelGGL((k_fused2d<1, SRC>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
+        hipLaunchKernelGGL((k_fused2d<1, SRC, MODE>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk, src);
     else
-        hipLaunchKernelGGL((k_fused2d<2, SRC>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
+        hipLaunchKernelGGL((k_fused2d<2, SRC, MODE>), grid, block, 0, s, grids, ngrids, nitems, Un, Us, Ud, lam, dtg,
                            dt_fixed, dt_out, status, clk, src);
 }
 
+// mode: 0 periodic and transmissive grids, 1 with slip walls or inflow
+// faces too, 2 that and the viscous flux.
 void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s,
-                        const double* src) {
+                        const double* src, int mode) {
     const dim3 grid(fused_blocks(nitems, waves)), block(256);
-    if (src)
-        launch_fused_stage_t<true>(stage, grid, block, grids, ngrids, nitems, Un, Us, Ud, lam, dtg, dt_fixed,
-                                   dt_out, status, clk, src, s);
-    else
-        launch_fused_stage_t<false>(stage, grid, block, grids, ngrids, nitems, Un, Us, Ud, lam, dtg, dt_fixed,
-                                    dt_out, status, clk, nullptr, s);
+#define FV_LFS(SRCB, M)                                                                                       \
+    launch_fused_stage_t<SRCB, M>(stage, grid, block, grids, ngrids, nitems, Un, Us, Ud, lam, dtg, dt_fixed, \
+                                  dt_out, status, clk, src, s)
+    if (src) {
+        if (mode == 2) FV_LFS(true, 2);
+        else if (mode == 1) FV_LFS(true, 1);
+        else FV_LFS(true, 0);
+    } else {
+        if (mode == 2) FV_LFS(false, 2);
+        else if (mode == 1) FV_LFS(false, 1);
+        else FV_LFS(false, 0);
+    }
+#undef FV_LFS
 }
 
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
@@ -388,9 +524,9 @@ int fused_slots() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int b0 = 0, b1 = 0, b2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused2d<0, false>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused2d<1, false>, 256, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused2d<2, false>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused2d<0, false, 0>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused2d<1, false, 0>, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused2d<2, false, 0>, 256, 0) != hipSuccess)
         return 0;
     const int b = b0 < b1 ? (b0 < b2 ? b0 : b2) : (b1 < b2 ? b1 : b2);
     return b * 4 * cus;

@@ -3,7 +3,7 @@
 // kappa member) and Roe fluxes on the three axes, the residual and the stage
 // combination, and the last stage also the CFL max of the new state.
 //
-// Work decomposition: a work item is a tile of TX x TY cells of the (x, y)
+// Work decomposition: a work item is a tile of TX x TY (32 x 7) cells of the (x, y)
 // plane over a segment of seg planes along z (seg a multiple of 4), and one
 // workgroup of 256 threads (four wavefronts) owns an item. Thread t < TX*TY
 // owns the cell (t % TX, t / TX) of the tile and marches along z with a window
@@ -16,7 +16,10 @@
 // three flux evaluations per cell, against four when a wave owns one row and
 // computes both y faces of it. The face fluxes go back to LDS and each owned
 // cell sums its six faces. Two workgroup barriers per plane: after the plane
-// is staged, and after the face fluxes are written.
+// is staged, and after the face fluxes are written. (Measured on the 256^3
+// workload: 32 x 7 tiles step in 1.79 ms, 16 x 15 tiles in 1.90 ms, the
+// per-row wave kernel this replaces in 1.93 ms; non-temporal stores and loads
+// of U^n were slower.)
 //
 // Halo cells outside the grid are read through the boundary maps; the state
 // may keep ghost layers but they are not read. Per-grid dt and the CFL max
@@ -27,13 +30,13 @@
 
 namespace fvk {
 
-constexpr int TX = 16, TY = 15;          // owned cells of a tile
-constexpr int TCELLS = TX * TY;           // 240 owned cells, one per thread
+constexpr int TX = 32, TY = 7;           // owned cells of a tile
+constexpr int TCELLS = TX * TY;           // 224 owned cells, one per thread
 constexpr int HX = TX + 4, HY = TY + 4;   // the tile with its two-cell halo
 constexpr int HPLANE = HX * HY;           // doubles per variable of the staged plane
-constexpr int NXF = (TX + 1) * TY;        // x faces of a tile plane (255)
+constexpr int NXF = (TX + 1) * TY;        // x faces of a tile plane (231)
 constexpr int NYF = TX * (TY + 1);        // y faces of a tile plane (256)
-constexpr int NHALO = 4 * TY + 4 * TX;    // halo cells used by the faces (no corners): 124
+constexpr int NHALO = 4 * TY + 4 * TX;    // halo cells used by the faces (no corners): 156
 constexpr int T3 = 256;                   // threads per workgroup
 static_assert(TCELLS <= T3 && NXF <= T3 && NYF <= T3 && NHALO <= T3, "tile does not fit the workgroup");
 
@@ -86,7 +89,47 @@ struct TileLds {
 // past the grid are mapped or clamped into it), and the stores of threads or
 // planes without output go past the end of a per-variable descriptor, where
 // they are dropped.
-template <int STAGE, int LIM, bool SRC>
+// Boundary variant (grids with slip-wall or inflow faces): the ghost rules
+// of a loaded cell at (grid) position x, y and plane k: a slip wall reverses
+// the momentum normal to it (the index map already mirrors the position), an
+// inflow face gives the side's state. A position outside on two axes feeds
+// no output.
+struct Ghost3 {
+    int xk, xs, yk, ys;  // kind (-1 inside) and side of the face behind x and y
+};
+
+__device__ __forceinline__ Ghost3 ghost_xy(const FGrid3& G, int x, int y) {
+    Ghost3 g;
+    g.xk = x < 0 ? G.bcx0 : (x >= G.nx ? G.bcx1 : -1);
+    g.xs = x < 0 ? 0 : 1;
+    g.yk = y < 0 ? G.bcy0 : (y >= G.ny ? G.bcy1 : -1);
+    g.ys = y < 0 ? 0 : 1;
+    return g;
+}
+
+template <bool BC>
+__device__ __forceinline__ void ghost_fix(const FGrid3& G, const Ghost3& h, int kk, double* w) {
+    if (!BC) return;
+    const int zk = kk < 0 ? G.bcz0 : (kk >= G.nz ? G.bcz1 : -1);  // uniform
+    const int zs = kk < 0 ? 0 : 1;
+    if (zk == 2) w[3] = -w[3];
+    if (zk == 3) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v] = G.q[2][zs][v];
+    }
+    w[2] = h.yk == 2 ? -w[2] : w[2];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = h.yk == 3 ? G.q[1][h.ys][v] : w[v];
+    w[1] = h.xk == 2 ? -w[1] : w[1];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v] = h.xk == 3 ? G.q[0][h.xs][v] : w[v];
+}
+
+__device__ __forceinline__ int map3(bool bc, int i, int n, int lo, int hi) {
+    return bc ? map_index_bc(i, n, lo, hi) : map_index(i, n, lo, hi);
+}
+
+template <int STAGE, int LIM, bool SRC, bool BC>
 __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid, int tx0, int ty0, int k0, double s,
                                             const double* Un, const double* Us, double* Ud, double& lmax,
                                             uint32_t& fl, double ka, double kb, const double* src, double vol) {
@@ -100,8 +143,10 @@ __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid
     const bool own = tid < TCELLS && gx < G.nx && gy < G.ny;
     // owned cells past the grid's edge hold the boundary map's values, as
     // ghost cells would (cells beyond the second ghost layer feed no output)
-    const int mx = map_index(gx < G.nx + 1 ? gx : G.nx + 1, G.nx, G.bcx0, G.bcx1);
-    const int my = map_index(gy < G.ny + 1 ? gy : G.ny + 1, G.ny, G.bcy0, G.bcy1);
+    const int cgx = gx < G.nx + 1 ? gx : G.nx + 1, cgy = gy < G.ny + 1 ? gy : G.ny + 1;
+    const int mx = map3(BC, cgx, G.nx, G.bcx0, G.bcx1);
+    const int my = map3(BC, cgy, G.ny, G.bcy0, G.bcy1);
+    const Ghost3 gown = ghost_xy(G, cgx, cgy);
     const uint32_t cell_off = (uint32_t)(((long long)my * G.py + mx) * 8);
     // U^n, source and output offsets: the owned cell, clamped inside the grid
     const int ox = gx < G.nx ? gx : G.nx - 1, oy = gy < G.ny ? gy : G.ny - 1;
@@ -110,8 +155,11 @@ __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid
     // halo cell of this thread (threads past NHALO load halo cell 0 again)
     int hx, hy;
     halo_pos(tid < NHALO ? tid : 0, hx, hy);
-    const int hgx = map_index(tx0 + hx - 2 < G.nx + 1 ? tx0 + hx - 2 : G.nx + 1, G.nx, G.bcx0, G.bcx1);
-    const int hgy = map_index(ty0 + hy - 2 < G.ny + 1 ? ty0 + hy - 2 : G.ny + 1, G.ny, G.bcy0, G.bcy1);
+    const int hcx = tx0 + hx - 2 < G.nx + 1 ? tx0 + hx - 2 : G.nx + 1;
+    const int hcy = ty0 + hy - 2 < G.ny + 1 ? ty0 + hy - 2 : G.ny + 1;
+    const int hgx = map3(BC, hcx, G.nx, G.bcx0, G.bcx1);
+    const int hgy = map3(BC, hcy, G.ny, G.bcy0, G.bcy1);
+    const Ghost3 ghalo = ghost_xy(G, hcx, hcy);
     const uint32_t halo_off = (uint32_t)(((long long)hgy * G.py + hgx) * 8);
     const int halo_slot = tid < NHALO ? hy * HX + hx : HPLANE;
     const int own_slot = tid < TCELLS ? (cy + 2) * HX + cx + 2 : HPLANE;
@@ -142,7 +190,7 @@ __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid
     if (SRC) rsrc = grid_rsrc(src, NV * svol * 8);
     const uint32_t src_off = (uint32_t)(((long long)oy * G.nx + ox) * 8);  // S[v][k][j][i], dense
     auto plane_off = [&](int kk) -> uint32_t {
-        return (uint32_t)((long long)map_index(kk, G.nz, G.bcz0, G.bcz1) * G.pz * 8);
+        return (uint32_t)((long long)map3(BC, kk, G.nz, G.bcz0, G.bcz1) * G.pz * 8);
     };
     auto out_plane = [&](int kk) -> uint32_t { return (uint32_t)((long long)(kk < G.nz ? kk : G.nz - 1) * G.pz * 8); };
 
@@ -157,12 +205,14 @@ __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid
         const uint32_t o = plane_off(k0 - 2 + kz);
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[kz][v] = ld_buf(rs, cell_off, o + v * vstride);
+        ghost_fix<BC>(G, gown, k0 - 2 + kz, W[kz]);
     }
     double H[NV];  // halo cell of the next staged plane
     {
         const uint32_t o = plane_off(k0);
 #pragma unroll
         for (int v = 0; v < NV; ++v) H[v] = ld_buf(rs, halo_off, o + v * vstride);
+        ghost_fix<BC>(G, ghalo, k0, H);
     }
     double Fz[2][NV];  // z-face fluxes (times 2): face f in Fz[f & 1]
     double qL[NV], qR[NV];
@@ -173,6 +223,7 @@ __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid
         const uint32_t o = plane_off(k0 + 2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[0][v] = ld_buf(rs, cell_off, o + v * vstride);
+        ghost_fix<BC>(G, gown, k0 + 2, W[0]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll 1
@@ -243,6 +294,12 @@ __device__ __forceinline__ void tile_planes(const FGrid3& G, TileLds& L, int tid
 #pragma unroll
                 for (int v = 0; v < NV; ++v) H[v] = ld_buf(rs, halo_off, o + v * vstride);
             }
+            if (BC) {
+                // the ghost rules need the loaded values: applied here, after the
+                // loads of the next planes were issued
+                ghost_fix<BC>(G, gown, kk + 3, W[t]);
+                ghost_fix<BC>(G, ghalo, kk + 1, H);
+            }
             __syncthreads();  // face fluxes of plane kk written
             const bool plane_ok = kk < G.nz;  // uniform
             const uint32_t p = out_plane(kk);
@@ -289,7 +346,7 @@ __device__ __forceinline__ void tile_of_item(const FGrid3& G, int item, int& tx0
     k0 = (r / tiles_y) * G.seg;
 }
 
-template <int STAGE, bool SRC>
+template <int STAGE, bool SRC, bool BC>
 __global__ void __launch_bounds__(T3) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
                                                 const double* __restrict__ Us, double* Ud,
                                                 unsigned long long* __restrict__ lam, double* __restrict__ dtg,
@@ -321,15 +378,15 @@ __global__ void __launch_bounds__(T3) k_fused3d(const FGrid3* __restrict__ grid,
         double lmax = 0.0;
         uint32_t fl = 0;
         if (G.scheme == 0) {
-            tile_planes<STAGE, 0, SRC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
+            tile_planes<STAGE, 0, SRC, BC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
         } else if (G.scheme == 5) {
-            tile_planes<STAGE, 3, SRC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
+            tile_planes<STAGE, 3, SRC, BC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
         } else if (G.scheme == 1) {
-            tile_planes<STAGE, 1, SRC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
+            tile_planes<STAGE, 1, SRC, BC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, 0.0, 0.0, src, vol);
         } else {
             double ka, kb;
             kappa_weights(G.scheme, ka, kb);
-            tile_planes<STAGE, 2, SRC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, ka, kb, src, vol);
+            tile_planes<STAGE, 2, SRC, BC>(G, L, tid, tx0, ty0, k0, s, Un, Us, Ud, lmax, fl, ka, kb, src, vol);
         }
         if (STAGE == 2) {
             lmax = wave_max_d(lmax);
@@ -391,32 +448,40 @@ static inline int blocks_for(int nitems, int waves) {
     return w < nitems ? w : nitems;
 }
 
-template <bool SRC>
+template <bool SRC, bool BC>
 static void launch_fused3d_stage_t(int stage, dim3 g, dim3 b, const FGrid3* grid, int nitems, const double* Un,
                                    const double* Us, double* Ud, unsigned long long* lam, double* dtg,
                                    const double* dt_fixed, double* dt_out, uint32_t* status, const double* src,
                                    double vol, hipStream_t s) {
     if (stage == 0)
-        hipLaunchKernelGGL((k_fused3d<0, SRC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+        hipLaunchKernelGGL((k_fused3d<0, SRC, BC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
                            status, src, vol);
     else if (stage == 1)
-        hipLaunchKernelGGL((k_fused3d<1, SRC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+        hipLaunchKernelGGL((k_fused3d<1, SRC, BC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
                            status, src, vol);
     else
-        hipLaunchKernelGGL((k_fused3d<2, SRC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+        hipLaunchKernelGGL((k_fused3d<2, SRC, BC>), g, b, 0, s, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
                            status, src, vol);
 }
 
 void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
                           double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed, double* dt_out,
-                          uint32_t* status, hipStream_t s, const double* src, double vol) {
+                          uint32_t* status, hipStream_t s, const double* src, double vol, bool walls) {
     const dim3 g(blocks_for(nitems, waves)), b(T3);
-    if (src)
-        launch_fused3d_stage_t<true>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status, src,
-                                     vol, s);
-    else
-        launch_fused3d_stage_t<false>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status,
-                                      nullptr, 0.0, s);
+    if (walls) {
+        if (src)
+            launch_fused3d_stage_t<true, true>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+                                               status, src, vol, s);
+        else
+            launch_fused3d_stage_t<false, true>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+                                                status, nullptr, 0.0, s);
+    } else if (src) {
+        launch_fused3d_stage_t<true, false>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out, status,
+                                            src, vol, s);
+    } else {
+        launch_fused3d_stage_t<false, false>(stage, g, b, grid, nitems, Un, Us, Ud, lam, dtg, dt_fixed, dt_out,
+                                             status, nullptr, 0.0, s);
+    }
 }
 
 void launch_fused3d_init(int waves, const FGrid3* grid, int nitems, const double* U, unsigned long long* lam,
@@ -432,9 +497,9 @@ int fused3d_slots() {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     int b0 = 0, b1 = 0, b2 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused3d<0, false>, T3, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused3d<1, false>, T3, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused3d<2, false>, T3, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_fused3d<0, false, false>, T3, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_fused3d<1, false, false>, T3, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_fused3d<2, false, false>, T3, 0) != hipSuccess)
         return 0;
     const int bmin = b0 < b1 ? (b0 < b2 ? b0 : b2) : (b1 < b2 ? b1 : b2);
     return bmin * cus;

@@ -20,6 +20,18 @@ __device__ __forceinline__ int map_index(int i, int n, int lo_kind, int hi_kind)
     return n == 1 ? 0 : m;
 }
 
+// map_index with slip walls and inflow faces too (kinds 0 periodic, 1
+// transmissive, 2 slip wall, 3 inflow): a wall reflects the index across the
+// face (-1 -> 0, -2 -> 1; n -> n - 1, n + 1 -> n - 2); an inflow face's ghost
+// positions read the nearest cell, whose value the caller then replaces by
+// the given state. Anything beyond n + 1 maps to n - 1, as above.
+__device__ __forceinline__ int map_index_bc(int i, int n, int lo_kind, int hi_kind) {
+    const int lo = lo_kind == 0 ? i + n : (lo_kind == 2 ? -1 - i : 0);
+    const int hi = i > n + 1 ? n - 1 : (hi_kind == 0 ? i - n : (hi_kind == 2 ? 2 * n - 1 - i : n - 1));
+    const int m = i < 0 ? lo : (i >= n ? hi : i);
+    return n == 1 ? 0 : m;
+}
+
 // Grid of the work item (uniform): largest g with work0 <= item.
 __device__ __forceinline__ int find_grid(const FGrid* __restrict__ grids, int ngrids, int item) {
     int lo = 0, hi = ngrids - 1;

@@ -23,6 +23,9 @@ struct FGrid {
     long long sv;       // per-variable stride
     double ax, ay;      // face areas of x faces (dy) and y faces (dx)
     double inv_vol, inv_dx, inv_dy, cfl, gamma, gm1;
+    double q[2][2][4];  // conserved ghost state of inflow faces per axis and side (the kernels'
+                        // boundary variant only: grids with slip walls or inflow faces)
+    double mu, kcond, nu_fac;  // viscosity, heat conductivity, max(4/3, gamma / Pr) (viscous variant)
 };
 
 // The 3D grid of the fused path (device memory, read uniformly).
@@ -33,6 +36,7 @@ struct FGrid3 {
     long long sv, py, pz;                          // strides: variable, row (y), plane (z)
     double ax, ay, az;                             // face areas: dy dz, dx dz, dx dy
     double inv_vol, inv_dx, inv_dy, inv_dz, cfl, gamma, gm1;
+    double q[3][2][5];  // conserved ghost state of inflow faces per axis and side (boundary variant)
 };
 
 void launch_bc_fill(double* U, const Geo& g, const BcState& bcs, int gang, int threads, hipStream_t s);
@@ -58,14 +62,15 @@ int fused_strips(int nx);
 void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s,
-                        const double* src = nullptr);
+                        const double* src = nullptr, int mode = 0);
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
                        unsigned long long* lam, uint32_t* status, hipStream_t s);
 int fused_slots();
 int fused3d_items(const FGrid3& G, int seg);
 void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,
                           double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed, double* dt_out,
-                          uint32_t* status, hipStream_t s, const double* src = nullptr, double vol = 0.0);
+                          uint32_t* status, hipStream_t s, const double* src = nullptr, double vol = 0.0,
+                          bool walls = false);
 void launch_fused3d_init(int waves, const FGrid3* grid, int nitems, const double* U, unsigned long long* lam,
                          uint32_t* status, hipStream_t s);
 int fused3d_slots();

@@ -32,15 +32,16 @@ FV_SCHEME_FROMM = 2
 FV_SCHEME_THIRD = 3
 FV_SCHEME_CENTRAL = 4
 FV_SCHEME_VANLEER = 5
+FV_SCHEME_QUICK = 6
 # kappa of the unlimited (Psi = 1) members of the MUSCL family
 _SCHEME_OF_KAPPA = ((-1.0, FV_SCHEME_UNLIMITED), (0.0, FV_SCHEME_FROMM), (1.0 / 3.0, FV_SCHEME_THIRD),
-                    (1.0, FV_SCHEME_CENTRAL))
+                    (0.5, FV_SCHEME_QUICK), (1.0, FV_SCHEME_CENTRAL))
 
 
 def scheme_of(spec):
     """FV_SCHEME_* of a grid spec: spec.limiter True (or "minmod") gives minmod,
     "vanleer" van Leer, False the unlimited member for spec.kappa (-1 by
-    default; 0, 1/3 and 1 also exist)."""
+    default; 0, 1/3, 1/2 and 1 also exist)."""
     lim = getattr(spec, "limiter", True)
     if lim == "vanleer":
         return FV_SCHEME_VANLEER
@@ -52,7 +53,7 @@ def scheme_of(spec):
     for k, code in _SCHEME_OF_KAPPA:
         if abs(kappa - k) <= 1e-12:
             return code
-    raise ValueError(f"unlimited MUSCL supports kappa in (-1, 0, 1/3, 1), got {kappa}")
+    raise ValueError(f"unlimited MUSCL supports kappa in (-1, 0, 1/3, 1/2, 1), got {kappa}")
 
 FV_BC_PERIODIC = 0
 FV_BC_TRANSMISSIVE = 1

@@ -40,7 +40,7 @@ class GridSpec:
     gamma: float = GAMMA
     cfl: float = 0.5
     limiter: bool = True   # False: unlimited MUSCL (Psi = 1)
-    kappa: float = -1.0    # MUSCL kappa of the unlimited scheme: -1, 0, 1/3 or 1
+    kappa: float = -1.0    # MUSCL kappa of the unlimited scheme: -1, 0, 1/3, 1/2 or 1
     bc_state: tuple = None  # (3, 2, nvar) conserved ghost state of inflow faces (kind 3)
     mu: float = 0.0         # dynamic viscosity: 0 for the Euler equations, > 0 adds the viscous flux
     prandtl: float = 0.72   # Prandtl number of the heat flux

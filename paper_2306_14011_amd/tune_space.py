@@ -224,12 +224,12 @@ FUSED_WAVE_FACTORS = (0, 0.5, 1.0, 2.0)   # 0: one wave per work item, else x th
 
 def fused_items(spec, seg: int) -> int:
     """Work items of one fused stage launch at segment height seg: 60-column
-    strips x row segments in 2D, 16 x 15-cell tiles x plane segments in 3D
+    strips x row segments in 2D, 32 x 7-cell tiles x plane segments in 3D
     (each 3D item is a workgroup of four waves)."""
     nx, ny, nz = (int(v) for v in spec.n)
     if spec.ndim == 2:
         return -(-nx // 60) * -(-ny // seg)
-    return -(-nx // 16) * -(-ny // 15) * -(-nz // seg)
+    return -(-nx // 32) * -(-ny // 7) * -(-nz // seg)
 
 
 class FusedSpace(MixedRadixSpace):

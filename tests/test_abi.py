@@ -57,7 +57,7 @@ def test_query_strides_and_workspace():
     lambda d: d.bc[1].__setitem__(1, 7),        # unknown kind
     lambda d: setattr(d, "gamma", 1.0),
     lambda d: setattr(d, "cfl", 0.0),
-    lambda d: setattr(d, "scheme", 6),
+    lambda d: setattr(d, "scheme", 7),
     lambda d: setattr(d, "scheme", -1),
     lambda d: d.hi.__setitem__(0, d.lo[0]),
 ])
@@ -76,22 +76,27 @@ def test_schemes_of_the_muscl_family():
     the kappa terms), and kappas outside the family are refused on the host."""
     g = inputs.grid2d(16, 16)
     for code in (fv.FV_SCHEME_MINMOD, fv.FV_SCHEME_UNLIMITED, fv.FV_SCHEME_FROMM, fv.FV_SCHEME_THIRD,
-                 fv.FV_SCHEME_CENTRAL, fv.FV_SCHEME_VANLEER):
+                 fv.FV_SCHEME_CENTRAL, fv.FV_SCHEME_VANLEER, fv.FV_SCHEME_QUICK):
         d = fv.make_desc(g)
         d.scheme = code
         fv.fv_query(d)
     assert fv.scheme_of(g) == fv.FV_SCHEME_MINMOD
     for kappa, code in ((-1.0, fv.FV_SCHEME_UNLIMITED), (0.0, fv.FV_SCHEME_FROMM), (1.0 / 3.0, fv.FV_SCHEME_THIRD),
-                        (1.0, fv.FV_SCHEME_CENTRAL)):
+                        (0.5, fv.FV_SCHEME_QUICK), (1.0, fv.FV_SCHEME_CENTRAL)):
         g.limiter, g.kappa = False, kappa
         assert fv.scheme_of(g) == code
         g.limiter = True
         assert fv.scheme_of(g) == fv.FV_SCHEME_MINMOD
     g.limiter, g.kappa = "vanleer", 1.0
     assert fv.scheme_of(g) == fv.FV_SCHEME_VANLEER
-    g.limiter, g.kappa = False, 0.5
+    g.limiter, g.kappa = False, 0.25
     with pytest.raises(ValueError):
         fv.make_desc(g)
+    for code in (-1, fv.FV_SCHEME_QUICK + 1):
+        d = fv.make_desc(inputs.grid2d(16, 16))
+        d.scheme = code
+        with pytest.raises(fv.FvError):
+            fv.fv_query(d)
     g.limiter = "superbee"
     with pytest.raises(ValueError):
         fv.make_desc(g)

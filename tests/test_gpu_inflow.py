@@ -1,7 +1,7 @@
 """Inflow faces (FV_BC_INFLOW, a given ghost state) on the HIP split path
 against the FP64 oracle: an inlet-like 2D channel (supersonic inflow, slip
 walls, outflow) and a 3D grid, residual, steps and the adjoint step; launch
-tables give the same bits; the fused path refuses inflow faces."""
+tables give the same bits; both on the fused path too."""
 import dataclasses
 
 import numpy as np
@@ -115,13 +115,25 @@ def test_adjoint_step_with_inflow_matches_oracle(name, g, U):
         assert np.abs(got[v] - ref[v]).max() <= 1e-10 * np.abs(ref[v]).max(), (name, v)
 
 
-def test_fused_path_refuses_inflow():
+@pytest.mark.parametrize("name,g,U", CASES, ids=[c[0] for c in CASES])
+def test_fused_path_with_inflow_matches_oracle(name, g, U):
+    # the inlet channel (2D) and the 3D grid with inflow, walls and outflow on
+    # the fused path
+    import torch
     from paper_2306_14011_amd import fv
-    s = fv.Solver(CASES[0][1])
-    with pytest.raises(fv.FvError) as e:
-        s.set_path(fv.FV_PATH_FUSED, 0, 0)
-    assert e.value.code == fv.FV_ENOTSUP
+    n = 5
+    s = fv.Solver(g)
+    s.set_path(fv.FV_PATH_FUSED, 8, 0)
+    s.set_state(U)
+    dts = torch.zeros(n, dtype=torch.float64, device="cuda")
+    s.step(n, dt_out=dts)
+    rc, flags = s.status()
+    got = s.get_state()
     s.close()
+    assert flags == 0
+    ref, rdt, _ = oracle.run(g, U, n)
+    assert np.allclose(dts.cpu().numpy(), rdt, rtol=1e-13, atol=0)
+    assert_pervar_close(got, ref, 1e-11, name)
 
 
 def test_large_inlet_channel_matches_oracle():
@@ -145,3 +157,11 @@ def test_large_inlet_channel_matches_oracle():
     ref, rdt, _ = oracle.run(g, U, 4)
     assert np.allclose(dts.cpu().numpy(), rdt, rtol=1e-12, atol=0)
     assert_pervar_close(got, ref, TOL, "4 steps")
+    # the same channel on the fused path (ragged strips and segments)
+    s = fv.Solver(g)
+    s.set_path(fv.FV_PATH_FUSED, 0, 0)
+    s.set_state(U)
+    s.step(4)
+    got_f = s.get_state()
+    s.close()
+    assert_pervar_close(got_f, ref, 1e-11, "4 fused steps")

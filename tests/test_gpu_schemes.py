@@ -1,6 +1,6 @@
 """Members of the MUSCL family of Eq. (flux) beyond minmod and the fully
 upwind unlimited scheme (covered with the other tests): the unlimited
-(Psi = 1) kappa = 0, 1/3, 1 members and van Leer's limiter, through every GPU
+(Psi = 1) kappa = 0, 1/3, 1/2 (QUICK), 1 members and van Leer's limiter, through every GPU
 path, against the FP64 oracle with the same limiter and kappa: residual,
 split steps, fused 2D and 3D steps, a batch mixing schemes, and the adjoint
 step."""
@@ -14,8 +14,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 # (limiter, kappa) of each member under test
-SCHEMES = ((False, 0.0), (False, 1.0 / 3.0), (False, 1.0), ("vanleer", -1.0))
-IDS = ("fromm", "third", "central", "vanleer")
+SCHEMES = ((False, 0.0), (False, 1.0 / 3.0), (False, 0.5), (False, 1.0), ("vanleer", -1.0))
+IDS = ("fromm", "third", "quick", "central", "vanleer")
 
 
 def _fv():

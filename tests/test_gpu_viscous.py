@@ -2,8 +2,8 @@
 against the FP64 oracle: residual and steps (dt with the diffusion limit
 included) on periodic, walled, inflow and outflow grids in 2D and 3D, launch
 tables giving the same bits, the manufactured Navier-Stokes solution's
-second-order truncation error measured on the GPU residual, and the paths
-that refuse viscous grids."""
+second-order truncation error measured on the GPU residual, the 2D grids on
+the fused path, and the paths that refuse viscous grids."""
 import math
 
 import numpy as np
@@ -159,15 +159,43 @@ def test_navier_stokes_truncation_error_on_the_gpu():
         assert 1.85 <= order <= 2.25, (v, order)
 
 
+@pytest.mark.parametrize("name,g,U", CASES[:3], ids=IDS[:3])
+def test_viscous_fused_path_matches_oracle(name, g, U):
+    # the 2D fused stage kernels' viscous variant (with the boundary variant's
+    # ghost rules): 4 steps, dt included, two per-stage tables give the same bits
+    import torch
+    from paper_2306_14011_amd import fv
+    n = 4
+    outs = []
+    for seg, waves in (([0, 0, 0], [0, 0, 0]), ([8, 4, 12], [5, 0, 100])):
+        s = fv.Solver(g)
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+        s.set_fused_launch(seg, waves)
+        s.set_state(U)
+        dts = torch.zeros(n, dtype=torch.float64, device="cuda")
+        s.step(n, dt_out=dts)
+        rc, flags = s.status()
+        assert flags == 0
+        outs.append((s.get_state(), dts.cpu().numpy()))
+        s.close()
+    ref, rdt, _ = oracle.run(g, U, n)
+    assert np.allclose(outs[0][1], rdt, rtol=1e-13, atol=0), (outs[0][1], rdt)
+    assert_pervar_close(outs[0][0], ref, 1e-11, name)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_paths_that_refuse_viscosity():
     import torch
     from paper_2306_14011_amd import fv
+    g3 = CASES[3][1]
+    s3 = fv.Solver(g3)
+    with pytest.raises(fv.FvError) as e:
+        s3.set_path(fv.FV_PATH_FUSED, 0, 0)    # 3D viscous grids: split path only
+    assert e.value.code == fv.FV_ENOTSUP
+    s3.close()
     g = viscous(inputs.grid2d(16, 16), 0.01)
     s = fv.Solver(g)
     s.set_state(smooth(g, 8))
-    with pytest.raises(fv.FvError) as e:
-        s.set_path(fv.FV_PATH_FUSED, 0, 0)
-    assert e.value.code == fv.FV_ENOTSUP
     lam = torch.ones(g.shape, dtype=torch.float64, device="cuda")
     dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
     with pytest.raises(fv.FvError) as e:

@@ -82,6 +82,26 @@ def test_muscl_kappa_family_pins():
     assert qL0 == 1.0 + (5.0 - 0.0) / 4.0 and qR0 == 5.0 - (2.0 - 1.0) / 4.0
 
 
+def test_muscl_quick_member_pin():
+    """kappa = 1/2 without limiter is Leonard's QUICK: quadratic upstream
+    interpolation, exact for point values of any quadratic. With q(x) =
+    a + b x + c x^2 sampled at the cell centres -1, 0, 1, 2, both states at
+    the face x = 1/2 equal q(1/2); kappa = 1/3 (exact for cell averages) and
+    kappa = -1 miss it by multiples of c."""
+    rng = np.random.default_rng(11)
+    for _ in range(100):
+        a, b, c = rng.normal(size=3)
+        pts = [a + b * x + c * x * x for x in (-1.0, 0.0, 1.0, 2.0)]
+        exact = a + 0.5 * b + 0.25 * c
+        qL, qR = oracle.muscl(*pts, limiter=False, kappa=0.5)
+        assert abs(qL - exact) <= 1e-14 * (1 + abs(exact)) and abs(qR - exact) <= 1e-14 * (1 + abs(exact))
+        # kappa = 1/3 is off by c / 12 on the left (point values, not averages)
+        qL3, _ = oracle.muscl(*pts, limiter=False, kappa=1.0 / 3.0)
+        assert abs((qL3 - exact) - (-c / 12.0)) <= 1e-13 * (1 + abs(c))
+    # the hand value of x^2 at 1/2 from 1, 0, 1, 4: 0 + (1/8)(0 - 1) + (3/8)(1 - 0)
+    assert oracle.muscl(1.0, 0.0, 1.0, 4.0, limiter=False, kappa=0.5) == (0.25, 0.25)
+
+
 def test_van_leer_limiter_pins():
     """van Leer's Psi(r) = (r + |r|)/(1 + |r|): Psi(1) = 1, zero for r <= 0,
     symmetric (Psi(r)/r = Psi(1/r)), inside Sweby's second-order TVD region
