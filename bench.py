@@ -107,10 +107,16 @@ def code_digest(root, sources):
     return h.hexdigest()
 
 
+def table_key(seg, waves):
+    """Key of a fused per-stage launch table in the traffic record."""
+    return ",".join(map(str, seg)) + "/" + ",".join(map(str, waves))
+
+
 def counted_traffic(path, key, n):
     """HBM bytes per launch counted by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled
-    by a copy of known size) for the 2048^2 workload, or None when the grid
-    differs or the kernels' code changed since the counters were taken."""
+    by a copy of known size) for the workload of the record (n cells per
+    side), or None when the grid or the launch differs or the kernels' code
+    changed since the counters were taken."""
     import os
     root = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -119,9 +125,9 @@ def counted_traffic(path, key, n):
         digest = code_digest(root, rec["sources"])
     except (OSError, KeyError, ValueError):
         return None
-    if n != 2048 or digest != rec["code_sha256"]:
+    if n != rec.get("n", 2048) or digest != rec["code_sha256"]:
         return None
-    table = rec.get("bytes_per_launch_by_seg") or rec.get("bytes_per_launch")
+    table = rec.get("bytes_per_launch_by_table") or rec.get("bytes_per_launch")
     return table.get(str(key))
 
 
@@ -256,7 +262,6 @@ def fused_leg(torch, fv, traffic, g, U0, a):
     k["achieved_TFLOPs"] = round(flops / avg_s / 1e12, 2)
     k["alg_bytes"] = stage_bytes
     k["achieved_GBps"] = round(stage_bytes / avg_s / 1e9, 1)
-    uniform = len(set(seg)) == 1 and len(set(waves)) == 1 and waves[0] == 0
     return {
         "ms_per_step": ms,
         "value": g.ncells / (ms * 1e-3),
@@ -274,7 +279,7 @@ def fused_leg(torch, fv, traffic, g, U0, a):
         # stage is reported against HBM, with its FP64 rate beside it.
         "roofline": {"bound": "hbm", "achieved": k["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(k["achieved_GBps"] / HBM_PEAK_GBPS, 4),
-                     "traffic": counted_traffic("fused", seg[0], g.n[0]) if uniform else None,
+                     "traffic": counted_traffic("fused", table_key(seg, waves), g.n[0]),
                      "kernel": "fused stage (k_fused2d)",
                      "alu_achieved_TFLOPs": k["achieved_TFLOPs"],
                      "alu_frac": round(k["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4)},
@@ -778,7 +783,9 @@ def main():
             "autotune": tune3,
             "stage_avg_us": k3["avg_us"], "over_split_default": round(out["split_3d"]["default_ms_per_step"] / ms3, 3),
             "alg_bytes_per_cell_update": traffic.fused_step_bytes(g3) / g3.ncells,
-            "hbm_achieved_GBps": round(traffic.fused_step_bytes(g3) / 3.0 / (k3["avg_us"] * 1e-6) / 1e9, 1)}
+            "hbm_achieved_GBps": round(traffic.fused_step_bytes(g3) / 3.0 / (k3["avg_us"] * 1e-6) / 1e9, 1),
+            "hbm_frac": round(traffic.fused_step_bytes(g3) / 3.0 / (k3["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+            "traffic": counted_traffic("fused3d", table_key(seg3, waves3), g3.n[0])}
         s3.close()
         log(f"fused 3D: {ms3:.4f} ms/step, {out['split_3d']['fused']['value']:.3e} cell-updates/s")
         del U3
