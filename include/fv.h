@@ -235,8 +235,14 @@ int fv_step(fv_ctx* ctx, double* U, int32_t nsteps, const double* dt_in, double*
 /* Reverse (adjoint) of one SSP-RK3 step with the step size frozen at *dt
  * (device scalar): on entry lam (dense interior layout) holds dJ/dU^{n+1};
  * on return it holds dJ/dU^n, where U^{n+1} = step(U_n, dt). U_n (ghosted
- * layout) is the state at the start of the step; its interior is not changed,
- * its ghosts are. The stage states are recomputed internally. */
+ * layout) is the state at the start of the step; its interior is not changed
+ * (its ghosts may be). The stage states U1, U2 are recomputed internally
+ * (the fused stage kernels, two launches; the split kernels on grids the
+ * fused path refuses). Each reverse stage is one kernel: mu = (dR/dU)^T w of
+ * Eq. (residual) by the reverse of the Roe flux and the MUSCL states of every
+ * face, gathered per cell (the transposed ghost rules included) and combined
+ * with the stage's recurrence, with no face array in the workspace. Viscous
+ * and curvilinear grids return FV_ENOTSUP. */
 int fv_adjoint_step(fv_ctx* ctx, double* U_n, const double* dt, double* lam);
 
 /* Sets / reads the 14 launch parameters. An invalid vector returns FV_EINVAL
@@ -264,8 +270,10 @@ int fv_clear_status(fv_ctx* ctx);
  * wavefronts); `waves` is the
  * number of wavefronts launched (0 = one per work item, else a grid-stride
  * loop over the items). Every segment height and wave count gives bitwise the
- * same result. Both paths compute the same cell arithmetic; fv_residual and
- * fv_adjoint_step always use the split kernels. Returns FV_ENOTSUP for states
+ * same result. Both paths compute the same cell arithmetic; fv_residual always
+ * uses the split kernels, and fv_adjoint_step recomputes its stage states with
+ * the fused stage kernels of the current table (the library's choice until a
+ * table is set) on every grid the fused path takes. Returns FV_ENOTSUP for states
  * of 4 GiB or more (the fused kernels address a grid through 32-bit buffer
  * offsets), for 3D viscous and for curvilinear grids, and FV_EINVAL for
  * other seg values. The fused path takes every boundary kind. */

@@ -28,12 +28,12 @@ struct fv_ctx {
     double* R;
     double* lamA;
     double* lamB;
-    double* G[3];   // face adjoint contributions [4][nvar][faces] per axis
     // fused path
     int path, fseg[3], fwaves[3], fitems[3];   // per Runge-Kutta stage
     fvk::FGrid* fgrid[3];  // the fused path's grid description per stage (an FGrid3 in 3D); they differ in seg
     unsigned long long* flam;
     double* fdt;
+    bool fused_ready;   // the per-stage tables are set (also used by the adjoint's forward recomputation)
     const double* src;  // caller's cell-averaged source S[v][cell], or null
     fvk::BcState bcs;   // ghost states of inflow faces
     // per-site event timing (diagnostic)
@@ -66,8 +66,8 @@ struct Layout {
     int64_t faces[3];
     int64_t ncell;
     int max_partial;
-    size_t off_status, off_dt, off_fused, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_G[3],
-        off_met, total;
+    size_t off_status, off_dt, off_fused, off_partial, off_U1, off_U2, off_F[3], off_R, off_lamA, off_lamB, off_met,
+        total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -186,10 +186,6 @@ int validate(const fv_grid_desc* g, Layout* L, char* why) {
     o = align256(o + dense);
     L->off_lamB = o;
     o = align256(o + dense);
-    for (int d = 0; d < 3; ++d) {
-        L->off_G[d] = o;
-        o = align256(o + (size_t)4 * L->nvar * L->faces[d] * 8);
-    }
     L->off_met = o;
     if (g->nodes) {
         const fvk::MetricOffsets mo = fvk::metric_offsets((int)nx, (int)ny);
@@ -336,12 +332,6 @@ void enqueue_update(fv_ctx* c, int stage, const double* Un, const double* Us, do
                        P(c, FV_SITE_UPDATE, 1), c->stream);
 }
 
-// mu = (dR/dU)^T w into c->R; the ghosts of Us must be filled.
-void enqueue_vjp(fv_ctx* c, const double* Us, const double* w) {
-    for (int ax = 0; ax < c->g.ndim; ++ax) fvk::launch_adj_flux(ax, Us, w, c->G[ax], c->g, c->stream);
-    fvk::launch_adj_gather(c->G[0], c->G[1], c->G[2], c->R, c->g, c->stream);
-}
-
 void enqueue_cfl(fv_ctx* c, const double* U, const double* dt_in, double* dt_out) {
     SiteTimer t(c, FV_SITE_CFL);
     fvk::launch_cfl(U, c->partial, c->status, dt_in, c->dt, dt_out, c->g, P(c, FV_SITE_CFL, 0), P(c, FV_SITE_CFL, 1),
@@ -387,6 +377,26 @@ int fv_query(const fv_grid_desc* g, int64_t strides_out[4], size_t* workspace_by
     return FV_OK;
 }
 
+static int set_fused_stage(fv_ctx* c, int st, int32_t seg, int32_t waves);
+
+// Whether the fused stage kernels can run this grid: not 3D viscous, not
+// curvilinear, a state below 4 GiB (their buffer offsets are 32-bit).
+static int fused_refusal(const fv_ctx* c, const char** why) {
+    if (c->g.mu > 0.0 && c->g.ndim == 3) {
+        *why = "3D viscous grids run on the split path only%s";
+        return FV_ENOTSUP;
+    }
+    if (c->g.met) {
+        *why = "curvilinear grids run on the split path only%s";
+        return FV_ENOTSUP;
+    }
+    if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32)) {
+        *why = "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s";
+        return FV_ENOTSUP;
+    }
+    return FV_OK;
+}
+
 int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, void* stream, fv_ctx** out) {
     if (!out) return fail(nullptr, FV_EINVAL, "null output pointer%s");
     *out = nullptr;
@@ -419,7 +429,6 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
     c->R = (double*)(base + L.off_R);
     c->lamA = (double*)(base + L.off_lamA);
     c->lamB = (double*)(base + L.off_lamB);
-    for (int d = 0; d < 3; ++d) c->G[d] = (double*)(base + L.off_G[d]);
     for (int st = 0; st < 3; ++st) c->fgrid[st] = (fvk::FGrid*)(base + L.off_fused + 512 * st);
     c->flam = (unsigned long long*)(base + L.off_fused + 1536);
     c->fdt = (double*)(base + L.off_fused + 1544);
@@ -434,6 +443,19 @@ int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, vo
         snprintf(g_err, 256, "%s", c->err);
         delete c;
         return FV_EDEVICE;
+    }
+    // the fused stage tables at the library's choice: fv_adjoint_step
+    // recomputes its stage states with the fused stage kernels
+    const char* why;
+    if (fused_refusal(c, &why) == FV_OK) {
+        for (int st = 0; st < 3; ++st) {
+            if (set_fused_stage(c, st, 0, 0) != FV_OK) {
+                snprintf(g_err, 256, "%s", c->err);
+                delete c;
+                return FV_EDEVICE;
+            }
+        }
+        c->fused_ready = true;
     }
     *out = c;
     return FV_OK;
@@ -622,10 +644,9 @@ int fv_set_path(fv_ctx* c, int path, int32_t seg, int32_t waves) {
         return FV_OK;
     }
     if (path != FV_PATH_FUSED) return fail(c, FV_EINVAL, "unknown path%s");
-    if (c->g.mu > 0.0 && c->g.ndim == 3) return fail(c, FV_ENOTSUP, "3D viscous grids run on the split path only%s");
-    if (c->g.met) return fail(c, FV_ENOTSUP, "curvilinear grids run on the split path only%s");
-    if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32))
-        return fail(c, FV_ENOTSUP, "the fused path needs a state below 4 GiB (buffer offsets are 32-bit)%s");
+    const char* why;
+    const int refused = fused_refusal(c, &why);
+    if (refused != FV_OK) return fail(c, refused, why);
     if (!valid_fused_seg(seg))
         return fail(c, FV_EINVAL, "seg must be 0 (automatic) or a multiple of 4 in [4, 1024]%s");
     if (waves < 0) return fail(c, FV_EINVAL, "negative wave count%s");
@@ -727,24 +748,34 @@ int fv_adjoint_step(fv_ctx* c, double* U_n, const double* dt, double* lam) {
     if (c->g.mu > 0.0) return fail(c, FV_ENOTSUP, "the adjoint step covers the inviscid residual only%s");
     if (c->g.met) return fail(c, FV_ENOTSUP, "the adjoint step covers uniform grids only%s");
     // recompute the stage states with the frozen dt: U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1))
-    enqueue_bc(c, U_n);
-    enqueue_fluxes(c, U_n);
-    enqueue_residual(c, c->R);
-    enqueue_update(c, 0, U_n, U_n, c->U1, dt);
-    enqueue_bc(c, c->U1);
-    enqueue_fluxes(c, c->U1);
-    enqueue_residual(c, c->R);
-    enqueue_update(c, 1, U_n, c->U1, c->U2, dt);
-    enqueue_bc(c, c->U2);
-    // stage 3: U' = 1/3 U + 2/3 (U2 + dt L(U2))
-    enqueue_vjp(c, c->U2, lam);
-    fvk::launch_adj_comb(3, lam, c->lamA, c->lamB, c->R, dt, c->g, c->stream);
-    // stage 2 (ghosts of U1 are still valid)
-    enqueue_vjp(c, c->U1, c->lamA);
-    fvk::launch_adj_comb(2, lam, c->lamA, c->lamB, c->R, dt, c->g, c->stream);
-    // stage 1 (ghosts of U still valid)
-    enqueue_vjp(c, U_n, lam);
-    fvk::launch_adj_comb(1, lam, c->lamA, c->lamB, c->R, dt, c->g, c->stream);
+    if (c->fused_ready) {
+        const bool walls = has_walls(c);
+        if (c->g.ndim == 3) {
+            const fvk::FGrid3* const* G = (const fvk::FGrid3* const*)c->fgrid;
+            fvk::launch_fused3d_stage(0, c->fwaves[0], G[0], c->fitems[0], U_n, U_n, c->U1, c->flam, c->fdt, dt,
+                                      nullptr, c->status, c->stream, c->src, c->g.vol, walls);
+            fvk::launch_fused3d_stage(1, c->fwaves[1], G[1], c->fitems[1], U_n, c->U1, c->U2, c->flam, c->fdt,
+                                      nullptr, nullptr, c->status, c->stream, c->src, c->g.vol, walls);
+        } else {
+            fvk::launch_fused_stage(0, c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U_n, U_n, c->U1, c->flam, c->fdt,
+                                    dt, nullptr, c->status, nullptr, c->stream, c->src, walls ? 1 : 0);
+            fvk::launch_fused_stage(1, c->fwaves[1], c->fgrid[1], 1, c->fitems[1], U_n, c->U1, c->U2, c->flam,
+                                    c->fdt, nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls ? 1 : 0);
+        }
+    } else {
+        enqueue_bc(c, U_n);
+        enqueue_fluxes(c, U_n);
+        enqueue_residual(c, c->R);
+        enqueue_update(c, 0, U_n, U_n, c->U1, dt);
+        enqueue_bc(c, c->U1);
+        enqueue_fluxes(c, c->U1);
+        enqueue_residual(c, c->R);
+        enqueue_update(c, 1, U_n, c->U1, c->U2, dt);
+    }
+    // reverse stages 3, 2, 1 (the kernels map the ghost positions themselves)
+    fvk::launch_adj_stage(3, c->U2, lam, lam, c->lamA, c->lamB, c->R, dt, c->g, c->bcs, c->stream);
+    fvk::launch_adj_stage(2, c->U1, c->lamA, lam, c->lamA, c->lamB, c->R, dt, c->g, c->bcs, c->stream);
+    fvk::launch_adj_stage(1, U_n, c->R, lam, c->lamA, c->lamB, c->R, dt, c->g, c->bcs, c->stream);
     int rc = check_launch_error(c);
     if (rc != FV_OK) return rc;
     return drain_timing(c);

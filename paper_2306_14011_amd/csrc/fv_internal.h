@@ -77,11 +77,8 @@ int fused3d_slots();
 int fused3d_auto_seg(const FGrid3& G, int slots);
 int fused_auto_seg(const FGrid* grids, int ngrids, int slots);
 
-// adjoint
-void launch_adj_flux(int ax, const double* U, const double* w, double* G, const Geo& g, hipStream_t s);
-void launch_adj_gather(const double* Gx, const double* Gy, const double* Gz, double* mu, const Geo& g,
-                       hipStream_t s);
-void launch_adj_comb(int mode, double* lam, double* lamA, double* lamB, const double* mu, const double* dt,
-                     const Geo& g, hipStream_t s);
+// adjoint: one reverse Runge-Kutta stage (mode 3, 2, 1 for stages 3, 2, 1)
+void launch_adj_stage(int mode, const double* Us, const double* w, double* lam, double* lamA, double* lamB, double* R,
+                      const double* dt, const Geo& g, const BcState& bcs, hipStream_t s);
 
 }  // namespace fvk
