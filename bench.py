@@ -332,10 +332,12 @@ def source_leg(torch, fv, inputs, g, U0, steps):
 
 def walls_leg(torch, fv, inputs, steps):
     """A closed 2048^2 box (slip walls on all four sides) with a smooth
-    pressure pulse on the split path, against the same grid periodic: the
-    walls change only the ghost fill."""
+    pressure pulse on the split path (the walls change only the ghost fill)
+    and on the fused path (the stage kernels' boundary variant), against the
+    same grid periodic."""
     import numpy as np
-    out = {"workload": "2048x2048 closed box, slip walls, pressure pulse, split path, default launch"}
+    out = {"workload": "2048x2048 closed box, slip walls, pressure pulse, split path (default launch) and fused path "
+                       "(library's table)"}
     n = 2048
     for key, kind in (("walls", fv.FV_BC_WALL), ("periodic", fv.FV_BC_PERIODIC)):
         g = inputs.grid2d(n, n, hi=(1.0, 1.0), bc=((kind, kind), (kind, kind)))
@@ -344,22 +346,25 @@ def walls_leg(torch, fv, inputs, steps):
         b = np.exp(-((X - 0.4) ** 2 + (Y - 0.55) ** 2) / 0.01)
         U0 = inputs.primitive_to_conserved(g, (1.0 + 0.3 * b)[None], (np.zeros((1, n, n)),) * 2,
                                            (1.0 + 0.5 * b)[None])
-        s = fv.Solver(g)
-        ms = timed_steps(torch, s, U0, steps, 3)
-        s.close()
-        out[key] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3)}
+        for path, pre in ((fv.FV_PATH_SPLIT, ""), (fv.FV_PATH_FUSED, "fused_")):
+            s = fv.Solver(g)
+            s.set_path(path, 0, 0)
+            ms = timed_steps(torch, s, U0, steps, 3)
+            s.close()
+            out[pre + key] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3)}
     out["walls_over_periodic"] = round(out["walls"]["ms_per_step"] / out["periodic"]["ms_per_step"], 3)
+    out["fused_walls_over_periodic"] = round(out["fused_walls"]["ms_per_step"] / out["fused_periodic"]["ms_per_step"], 3)
     return out
 
 
 def curvilinear_leg(torch, fv, inputs, steps):
     """The headline grid mapped to a smoothly distorted (wavy, periodic)
-    curvilinear grid on the split path, against the same grid uniform: the
-    flux kernels read each face's unit normal and length, the update each
-    cell's inverse area and the CFL reduction the four faces' metrics and the
-    area of each cell."""
+    curvilinear grid on the split path and on the fused path, against the
+    same grid uniform: the flux kernels read each face's unit normal and
+    length, the update each cell's inverse area and the CFL reduction the four
+    faces' metrics and the area of each cell."""
     out = {"workload": "2048x2048 vortex (at the cell centroids) on a wavy periodic curvilinear grid (amplitude 0.04, rotated 0.3), "
-                       "split path, default launch"}
+                       "split path (default launch) and fused path (library's table)"}
     n = 2048
     g, _ = inputs.vortex_bumps_case(n, seed=0)
     nodes = inputs.wavy_nodes(n, n, amp=0.04, rot=0.3)
@@ -368,33 +373,50 @@ def curvilinear_leg(torch, fv, inputs, steps):
     import copy
     gc = copy.copy(g)
     gc.nodes = nodes
-    for key, spec in (("curvilinear", gc), ("uniform", g)):
+    for key, spec, path in (("curvilinear", gc, fv.FV_PATH_SPLIT), ("uniform", g, fv.FV_PATH_SPLIT),
+                            ("fused_curvilinear", gc, fv.FV_PATH_FUSED), ("fused_uniform", g, fv.FV_PATH_FUSED)):
         s = fv.Solver(spec)
+        s.set_path(path, 0, 0)
         ms = timed_steps(torch, s, U0, steps, 3)
         s.close()
         out[key] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3)}
     out["curvilinear_over_uniform"] = round(out["curvilinear"]["ms_per_step"] / out["uniform"]["ms_per_step"], 3)
-    # per stage: 3 doubles per x face and per y face, 1 per cell (1 / area);
-    # per step: the CFL reduction reads 4 faces x 3 doubles + the area per cell
+    out["fused_curvilinear_over_uniform"] = round(out["fused_curvilinear"]["ms_per_step"] /
+                                                  out["fused_uniform"]["ms_per_step"], 3)
+    out["fused_over_split_curvilinear"] = round(out["curvilinear"]["ms_per_step"] /
+                                                out["fused_curvilinear"]["ms_per_step"], 3)
+    # split path, per stage: 3 doubles per x face and per y face, 1 per cell
+    # (1 / area); per step: the CFL reduction reads 4 faces x 3 doubles + the
+    # area per cell
     out["metric_bytes_per_cell_update"] = 8 * (3 * (3 + 3 + 1) + 13)
+    # fused path, per stage: the same 7 doubles (x face, y face, 1 / area),
+    # and in stage 3 the area (the wave speed; the neighbours' faces come from
+    # the lanes and rows that hold them)
+    out["fused_metric_bytes_per_cell_update"] = 8 * (3 * 7 + 1)
     return out
 
 
 def viscous_leg(torch, fv, inputs, steps):
-    """The headline workload with the viscous flux (mu = 1e-3, Pr = 0.72) on
-    the split path, against the inviscid step: one viscous face kernel per axis
-    and stage, reading the face's two cells and their tangential neighbours."""
-    out = {"workload": "2048x2048 vortex + bumps, Navier-Stokes (mu 1e-3, Pr 0.72), split path, default launch"}
+    """The headline workload with the viscous flux (mu = 1e-3, Pr = 0.72)
+    against the inviscid step, on the split path (one viscous face kernel per
+    axis and stage, reading the face's two cells and their tangential
+    neighbours) and on the fused path (the stage kernels' viscous variant)."""
+    out = {"workload": "2048x2048 vortex + bumps, Navier-Stokes (mu 1e-3, Pr 0.72), split path (default launch) and "
+                       "fused path (library's table)"}
     g, U0 = inputs.vortex_bumps_case(2048, seed=0)
     import copy
     gv = copy.copy(g)
     gv.mu, gv.prandtl = 1e-3, 0.72
     for key, spec in (("viscous", gv), ("inviscid", g)):
-        s = fv.Solver(spec)
-        ms = timed_steps(torch, s, U0, steps, 3)
-        s.close()
-        out[key] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3)}
+        for path, pre in ((fv.FV_PATH_SPLIT, ""), (fv.FV_PATH_FUSED, "fused_")):
+            s = fv.Solver(spec)
+            s.set_path(path, 0, 0)
+            ms = timed_steps(torch, s, U0, steps, 3)
+            s.close()
+            out[pre + key] = {"ms_per_step": round(ms, 4), "value": g.ncells / (ms * 1e-3)}
     out["viscous_over_inviscid"] = round(out["viscous"]["ms_per_step"] / out["inviscid"]["ms_per_step"], 3)
+    out["fused_viscous_over_inviscid"] = round(out["fused_viscous"]["ms_per_step"] /
+                                               out["fused_inviscid"]["ms_per_step"], 3)
     return out
 
 
@@ -804,14 +826,19 @@ def main():
                                         f"({out['source'][p]['over_no_source']:.3f}x)"
                                         for p in ("fused", "split", "fused_3d")))
         out["curvilinear"] = curvilinear_leg(torch, fv, inputs, 30)
-        log(f"curvilinear 2048^2 (split): {out['curvilinear']['curvilinear']['ms_per_step']:.4f} ms/step, "
-            f"{out['curvilinear']['curvilinear_over_uniform']:.3f}x the uniform grid")
+        log(f"curvilinear 2048^2: split {out['curvilinear']['curvilinear']['ms_per_step']:.4f} ms/step "
+            f"({out['curvilinear']['curvilinear_over_uniform']:.3f}x the uniform grid), fused "
+            f"{out['curvilinear']['fused_curvilinear']['ms_per_step']:.4f} ms/step "
+            f"({out['curvilinear']['fused_curvilinear_over_uniform']:.3f}x)")
         out["viscous"] = viscous_leg(torch, fv, inputs, 30)
-        log(f"viscous 2048^2 (split): {out['viscous']['viscous']['ms_per_step']:.4f} ms/step, "
-            f"{out['viscous']['viscous_over_inviscid']:.3f}x the inviscid step")
+        log(f"viscous 2048^2: split {out['viscous']['viscous']['ms_per_step']:.4f} ms/step "
+            f"({out['viscous']['viscous_over_inviscid']:.3f}x the inviscid step), fused "
+            f"{out['viscous']['fused_viscous']['ms_per_step']:.4f} ms/step "
+            f"({out['viscous']['fused_viscous_over_inviscid']:.3f}x)")
         out["walls"] = walls_leg(torch, fv, inputs, 50)
-        log(f"slip walls (split 2048^2): {out['walls']['walls']['ms_per_step']:.4f} ms/step, "
-            f"{out['walls']['walls_over_periodic']:.3f}x the periodic grid")
+        log(f"slip walls 2048^2: split {out['walls']['walls']['ms_per_step']:.4f} ms/step "
+            f"({out['walls']['walls_over_periodic']:.3f}x the periodic grid), fused "
+            f"{out['walls']['fused_walls']['ms_per_step']:.4f} ms/step ({out['walls']['fused_walls_over_periodic']:.3f}x)")
         if not a.no_tune and not a.no_3d:
             out["sized_tuner"] = sized_leg(torch, inputs, a.seed, a.samples)
             sz = out["sized_tuner"]

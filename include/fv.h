@@ -139,9 +139,10 @@ typedef struct fv_grid_desc {
  * computed on the device by fv_create into the context's workspace; the
  * node array is read there only (the caller may free it once the stream has
  * passed fv_create's work). lo and hi are not used. Curvilinear grids run on
- * the split path (fv_residual, fv_step, fv_residual_norm); the viscous flux
- * (mu > 0) is FV_EINVAL with them, fv_set_path(FV_PATH_FUSED) and
- * fv_adjoint_step return FV_ENOTSUP, and batches refuse them. */
+ * the split path (fv_residual, fv_step, fv_residual_norm) and on the fused
+ * path (a curvilinear variant of the 2D stage kernels that reads the metric
+ * streams, every boundary kind); the viscous flux (mu > 0) is FV_EINVAL with
+ * them, fv_adjoint_step returns FV_ENOTSUP, and batches refuse them. */
 
 /* Viscous flux (mu > 0): the residual of Eq. (residual) sums F_i,n - F_nu,n
  * over the faces, with F_nu,n = (0, tau . n, Theta . n) of Eq. (QF): Stokes
@@ -275,8 +276,8 @@ int fv_clear_status(fv_ctx* ctx);
  * the fused stage kernels of the current table (the library's choice until a
  * table is set) on every grid the fused path takes. Returns FV_ENOTSUP for states
  * of 4 GiB or more (the fused kernels address a grid through 32-bit buffer
- * offsets), for 3D viscous and for curvilinear grids, and FV_EINVAL for
- * other seg values. The fused path takes every boundary kind. */
+ * offsets) and for 3D viscous grids, and FV_EINVAL for other seg values. The
+ * fused path takes every boundary kind and curvilinear 2D grids. */
 enum { FV_PATH_SPLIT = 0, FV_PATH_FUSED = 1 };
 int fv_set_path(fv_ctx* ctx, int path, int32_t seg, int32_t waves);
 

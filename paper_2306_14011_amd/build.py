@@ -29,10 +29,11 @@ HIP_FLAGS = [
 # launch table; contracting multiply-adds only within one source expression
 # makes the fused multiply-adds independent of how the compiler shares
 # subexpressions between the faces a thread computes. The same holds for the
-# 3D stage kernels, whose first z face of a work item is computed before the
-# plane loop and the others inside it: every segment height must give the
-# same bits.
-FILE_FLAGS = {"fv_kernels.hip": ["-ffp-contract=on"], "fv_fused3d.hip": ["-ffp-contract=on"]}
+# 3D stage kernels and the curvilinear 2D ones, whose first face of a work
+# item is computed before the plane or row loop and the others inside it:
+# every segment height must give the same bits.
+FILE_FLAGS = {"fv_kernels.hip": ["-ffp-contract=on"], "fv_fused3d.hip": ["-ffp-contract=on"],
+              "fv_fused_curv.hip": ["-ffp-contract=on"]}
 
 
 def sources():

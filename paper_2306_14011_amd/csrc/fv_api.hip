@@ -379,15 +379,12 @@ int fv_query(const fv_grid_desc* g, int64_t strides_out[4], size_t* workspace_by
 
 static int set_fused_stage(fv_ctx* c, int st, int32_t seg, int32_t waves);
 
-// Whether the fused stage kernels can run this grid: not 3D viscous, not
-// curvilinear, a state below 4 GiB (their buffer offsets are 32-bit).
+// Whether the fused stage kernels can run this grid: not 3D viscous, a state
+// below 4 GiB (their buffer offsets are 32-bit; a curvilinear grid's metric
+// blocks are then below 4 GiB too).
 static int fused_refusal(const fv_ctx* c, const char** why) {
     if (c->g.mu > 0.0 && c->g.ndim == 3) {
         *why = "3D viscous grids run on the split path only%s";
-        return FV_ENOTSUP;
-    }
-    if (c->g.met) {
-        *why = "curvilinear grids run on the split path only%s";
         return FV_ENOTSUP;
     }
     if ((long long)c->g.nvar * c->g.sv * 8 >= (1ll << 32)) {
@@ -528,24 +525,24 @@ static int fused_step3(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in
 static int fused_step(fv_ctx* c, double* U, int32_t nsteps, const double* dt_in, double* dt_out) {
     if (nsteps == 0) return FV_OK;
     if (c->g.ndim == 3) return fused_step3(c, U, nsteps, dt_in, dt_out);
-    const int walls = c->g.mu > 0.0 ? 2 : (has_walls(c) ? 1 : 0);
-    fvk::launch_fused_init(c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, c->flam, c->status, c->stream);
+    const int walls = c->g.met ? 3 : (c->g.mu > 0.0 ? 2 : (has_walls(c) ? 1 : 0));
+    fvk::launch_fused_init(c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, c->flam, c->status, c->stream, c->g.met);
     for (int32_t s = 0; s < nsteps; ++s) {
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(0, c->fwaves[0], c->fgrid[0], 1, c->fitems[0], U, U, c->U1, c->flam, c->fdt,
                                     dt_in ? dt_in + s : nullptr, dt_out ? dt_out + s : nullptr, c->status, nullptr,
-                                    c->stream, c->src, walls);
+                                    c->stream, c->src, walls, c->g.met);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(1, c->fwaves[1], c->fgrid[1], 1, c->fitems[1], U, c->U1, c->U2, c->flam, c->fdt,
-                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls);
+                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls, c->g.met);
         }
         {
             SiteTimer t(c, FV_TIMER_FUSED);
             fvk::launch_fused_stage(2, c->fwaves[2], c->fgrid[2], 1, c->fitems[2], U, c->U2, U, c->flam, c->fdt,
-                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls);
+                                    nullptr, nullptr, c->status, nullptr, c->stream, c->src, walls, c->g.met);
         }
         int rc = check_launch_error(c);
         if (rc != FV_OK) return rc;

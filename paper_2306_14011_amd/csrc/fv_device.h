@@ -343,6 +343,35 @@ __host__ __device__ __forceinline__ double cell_lambda(const double* q, double g
     return lam;
 }
 
+// Wave-speed bound of a cell of a curvilinear 2D grid from its conserved
+// state, the unit normals and lengths (nx, ny, len) of its low and high x
+// faces (xa, xb) and y faces (ya, yb), and its area: per grid direction, the
+// mean of the two faces' area vectors S gives (|u . S| + c |S|) / area.
+__host__ __device__ __forceinline__ double curv_cell_lambda(const double* q, double gamma, double gm1,
+                                                            const double* xa, const double* xb, const double* ya,
+                                                            const double* yb, double area, uint32_t* fl = nullptr) {
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir, v = q[2] * ir;
+    const double p = gm1 * (q[3] - 0.5 * q[0] * (u * u + v * v));
+    const double c = sqrt(gamma * p * ir);
+    double lam = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const double* a = ax == 0 ? xa : ya;
+        const double* b = ax == 0 ? xb : yb;
+        const double sx = 0.5 * (a[0] * a[2] + b[0] * b[2]);
+        const double sy = 0.5 * (a[1] * a[2] + b[1] * b[2]);
+        lam += (fabs(u * sx + v * sy) + c * sqrt(sx * sx + sy * sy)) / area;
+    }
+    if (fl) {
+        // the non-physical flags of cell_lambda: 1 NaN, 2 rho <= 0, 4 p <= 0
+        if (isnan(lam) || isnan(q[0]) || isnan(p)) *fl |= 1u;
+        if (!(q[0] > 0.0)) *fl |= 2u;
+        if (!(p > 0.0)) *fl |= 4u;
+    }
+    return lam;
+}
+
 // ---------------------------------------------------------------------------
 // Reverse (adjoint) of the face computation, hand-derived from the forward
 // sequence above: given Fb = dJ/dF, accumulate dJ/dq of the four stencil

@@ -62,9 +62,9 @@ int fused_strips(int nx);
 void launch_fused_stage(int stage, int waves, const FGrid* grids, int ngrids, int nitems, const double* Un,
                         const double* Us, double* Ud, unsigned long long* lam, double* dtg, const double* dt_fixed,
                         double* dt_out, uint32_t* status, unsigned long long* clk, hipStream_t s,
-                        const double* src = nullptr, int mode = 0);
+                        const double* src = nullptr, int mode = 0, const double* met = nullptr);
 void launch_fused_init(int waves, const FGrid* grids, int ngrids, int nitems, const double* U,
-                       unsigned long long* lam, uint32_t* status, hipStream_t s);
+                       unsigned long long* lam, uint32_t* status, hipStream_t s, const double* met = nullptr);
 int fused_slots();
 int fused3d_items(const FGrid3& G, int seg);
 void launch_fused3d_stage(int stage, int waves, const FGrid3* grid, int nitems, const double* Un, const double* Us,

@@ -522,24 +522,20 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ double curv_lambda(const double* q, const Geo& g, int i, int j) {
     const int nx = g.n[0], ny = g.n[1];
     const MetricOffsets mo = metric_offsets(nx, ny);
-    const double ir = 1.0 / q[0];
-    const double u = q[1] * ir, v = q[2] * ir;
-    const double p = g.gm1 * (q[3] - 0.5 * q[0] * (u * u + v * v));
-    const double c = sqrt(g.gamma * p * ir);
     const long long e = (long long)j * nx + i;
-    const double area = g.met[mo.cell + e];
-    double lam = 0.0;
+    double m[2][2][3];  // [axis][low, high face][normal x, normal y, length]
 #pragma unroll
     for (int ax = 0; ax < 2; ++ax) {
         const long long base = ax == 0 ? mo.fx : mo.fy, st = ax == 0 ? mo.nfx : mo.nfy;
         const long long fa = ax == 0 ? (long long)j * (nx + 1) + i : e;
         const long long fb = ax == 0 ? fa + 1 : e + nx;
-        const double la = g.met[base + 2 * st + fa], lb = g.met[base + 2 * st + fb];
-        const double sx = 0.5 * (g.met[base + fa] * la + g.met[base + fb] * lb);
-        const double sy = 0.5 * (g.met[base + st + fa] * la + g.met[base + st + fb] * lb);
-        lam += (fabs(u * sx + v * sy) + c * sqrt(sx * sx + sy * sy)) / area;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            m[ax][0][c] = g.met[base + c * st + fa];
+            m[ax][1][c] = g.met[base + c * st + fb];
+        }
     }
-    return lam;
+    return curv_cell_lambda(q, g.gamma, g.gm1, m[0][0], m[0][1], m[1][0], m[1][1], g.met[mo.cell + e]);
 }
 
 template <int NDIM, int MAXT>
