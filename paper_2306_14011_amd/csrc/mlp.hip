@@ -418,38 +418,147 @@ __device__ void select_topk(float* vals, long long* idxs, int cnt, int k, float*
     }
 }
 
+// The sweep on the matrix cores. A wave takes 32 configurations at a time and
+// runs the network in transposed form, Z^T = W H^T, with
+// v_mfma_f32_32x32x2f32: M = 32 neurons of a block (two blocks per 64-wide
+// layer), N = the 32 configurations, K = 2 inputs per instruction. Operand
+// lanes: A (32 x 2) has neuron l % 32 and input l / 32, B (2 x 32) input
+// l / 32 and configuration l % 32; the 32 x 32 result holds configuration
+// l % 32 in every lane and, in register v, neuron 8 (v / 4) + 4 (l / 32) +
+// (v % 4). So the activations never move: the next layer takes register v of
+// block b as one K pair (lanes 0-31 and 32-63 hold different neurons), and its
+// weight operand is permuted to the same neuron order. Each layer's bias is
+// one more K step with inputs (1, 0). The weight operands are staged once per
+// workgroup in LDS, in the instruction's lane order; the sums run in another
+// order than the row-per-thread forward pass (FP32 rounding apart, the same
+// network).
+typedef float v16f __attribute__((ext_vector_type(16)));
+
 template <int IN>
-__global__ void __launch_bounds__(SWEEP_T) k_sweep(const float* __restrict__ P, SweepTab tab, long long begin,
-                                                    long long count, int k, float* __restrict__ pv,
-                                                    long long* __restrict__ pi) {
-    __shared__ float lv[SWEEP_T * KMAX];
-    __shared__ long long li[SWEEP_T * KMAX];
+struct MfLds {
+    static constexpr int S1 = IN / 2;                  // K steps of layer 1 (IN is even)
+    static constexpr int A1 = 0;                       // [block][step 0 .. S1][lane]
+    static constexpr int A2 = A1 + 2 * (S1 + 1) * 64;  // [block][step 0 .. 32][lane]
+    static constexpr int A3 = A2 + 2 * 33 * 64;
+    static constexpr int W4 = A3 + 2 * 33 * 64;        // [block * 16 + register][lane]
+    static constexpr int FLOATS = W4 + 32 * 64;
+};
+
+// Neuron of register v of block b in lane half h of a result.
+__device__ __forceinline__ int mf_neuron(int b, int v, int h) { return 32 * b + 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// One layer: c[b] = sum over the NST K steps of A (block b, step st) times
+// bval(st), the two blocks interleaved. The steps go in groups of four whose
+// weight operands are read from LDS while the previous group's instructions
+// issue; the scheduling barrier keeps the compiler from hoisting every read
+// of the layer (and the registers they take) to its start.
+template <int NST, int AOFF, class BF>
+__device__ __forceinline__ void mf_layer(const float* A, int lane, BF bval, v16f* c) {
+    constexpr int G = 4;
+    c[0] = v16f{};
+    c[1] = v16f{};
+    float a[2][2 * G];
+#pragma unroll
+    for (int q = 0; q < G; ++q)
+        if (q < NST)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) a[0][2 * q + b] = A[AOFF + (b * NST + q) * 64 + lane];
+#pragma unroll
+    for (int g = 0; g * G < NST; ++g) {
+        const int cur = g & 1;
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int st = (g + 1) * G + q;
+            if (st < NST)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) a[cur ^ 1][2 * q + b] = A[AOFF + (b * NST + st) * 64 + lane];
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            const int st = g * G + q;
+            if (st < NST) {
+                const float bv = bval(st);
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    c[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][2 * q + b], bv, c[b], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+constexpr int MF_LDS_BYTES = MfLds<FV_MLP_IN_SIZED>::FLOATS * 4 > SWEEP_T * KMAX * 12
+                                 ? MfLds<FV_MLP_IN_SIZED>::FLOATS * 4
+                                 : SWEEP_T * KMAX * 12;
+
+template <int IN>
+__global__ void __launch_bounds__(SWEEP_T) k_sweep_mfma(const float* __restrict__ P, SweepTab tab, long long begin,
+                                                         long long count, int k, float* __restrict__ pv,
+                                                         long long* __restrict__ pi) {
+    using L = Lay<IN>;
+    using M = MfLds<IN>;
+    static_assert(IN % 2 == 0, "layer 1 takes inputs in pairs");
+    __shared__ __align__(16) unsigned char lds[MF_LDS_BYTES];
     __shared__ float smv[SWEEP_T / 64];
     __shared__ long long smi[SWEEP_T / 64];
     __shared__ int smp[SWEEP_T / 64];
+    float* A = (float*)lds;
+    // stage the weight operands
+    for (int e = threadIdx.x; e < M::FLOATS; e += SWEEP_T) {
+        const int l = e & 63, row = e >> 6, m32 = l & 31, h = l >> 5;
+        float w;
+        if (e < M::A2) {
+            const int b = row / (M::S1 + 1), st = row % (M::S1 + 1), m = 32 * b + m32;
+            w = st < M::S1 ? P[L::oW1 + m * IN + 2 * st + h] : (h == 0 ? P[L::oB1 + m] : 0.f);
+        } else if (e < M::W4) {
+            const bool l2 = e < M::A3;
+            const int r = row - (l2 ? M::A2 : M::A3) / 64, b = r / 33, st = r % 33, m = 32 * b + m32;
+            const int oW = l2 ? L::oW2 : L::oW3, oB = l2 ? L::oB2 : L::oB3;
+            w = st < 32 ? P[oW + m * H + mf_neuron(st >> 4, st & 15, h)] : (h == 0 ? P[oB + m] : 0.f);
+        } else {
+            const int r = row - M::W4 / 64;
+            w = P[L::oW4 + mf_neuron(r >> 4, r & 15, h)];
+        }
+        A[e] = w;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const float one = h == 0 ? 1.f : 0.f;
+    const float b4 = P[L::oB4];
     TopK top;
     top.init();
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride) {
-        const long long idx = begin + t;
+    const long long tiles = (count + 31) / 32;
+    const long long nw = (long long)gridDim.x * (SWEEP_T / 64);
+    for (long long t = (long long)blockIdx.x * (SWEEP_T / 64) + (threadIdx.x >> 6); t < tiles; t += nw) {
+        const long long r = t * 32 + (lane & 31);
+        const bool valid = r < count;
+        const long long idx = begin + (valid ? r : count - 1);
         unsigned long long rem = (unsigned long long)idx;
         float x[IN];
 #pragma unroll
         for (int site = 0; site < FV_NSITES; ++site) {
-            const unsigned r = (unsigned)tab.radix[site];
-            const unsigned c = (unsigned)(rem % r);
-            rem /= r;
+            const unsigned rd = (unsigned)tab.radix[site];
+            const unsigned c = (unsigned)(rem % rd);
+            rem /= rd;
             x[2 * site] = tab.f1[site][c];
             x[2 * site + 1] = tab.f2[site][c];
         }
 #pragma unroll
         for (int j = 2 * FV_NSITES; j < IN; ++j) x[j] = tab.extra[j - 2 * FV_NSITES];
-        // an opaque copy of the (uniform) weight pointer per iteration keeps the
-        // ~9k scalar weight loads inside the loop instead of hoisted out of it
-        const float* Pl = P;
-        asm volatile("" : "+s"(Pl));
-        top.insert(forward_row<IN>(Pl, x), idx);
+        v16f c1[2], c2[2], c3[2];
+        mf_layer<M::S1 + 1, M::A1>(A, lane, [&](int st) { return st < M::S1 ? (h ? x[2 * st + 1] : x[2 * st]) : one; },
+                                   c1);
+        mf_layer<33, M::A2>(A, lane, [&](int st) { return st < 32 ? relu(c1[st >> 4][st & 15]) : one; }, c2);
+        mf_layer<33, M::A3>(A, lane, [&](int st) { return st < 32 ? relu(c2[st >> 4][st & 15]) : one; }, c3);
+        float part = 0.f;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) part = fmaf(A[M::W4 + q * 64 + lane], relu(c3[q >> 4][q & 15]), part);
+        const float out = b4 + (part + __shfl_xor(part, 32, 64));
+        if (valid && h == 0) top.insert(out, idx);
     }
+    __syncthreads();  // the weight operands are dead: the LDS takes the per-thread lists
+    float* lv = (float*)lds;
+    long long* li = (long long*)(lds + SWEEP_T * KMAX * 4);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
         lv[threadIdx.x * KMAX + q] = top.v[q];
@@ -555,15 +664,16 @@ static int sweep_launch(const float* params, const fv_tune_space* space, int64_t
     }
     for (int j = 0; j < FV_MLP_MAX_EXTRA; ++j) tab.extra[j] = j < space->n_extra ? space->extra[j] : 0.f;
     if (begin + count > total) return FV_EINVAL;
-    long long blocks = (count + SWEEP_T - 1) / SWEEP_T;
+    // a workgroup's four waves take 32 configurations each per round
+    long long blocks = (count + 4 * 32 - 1) / (4 * 32);
     if (blocks > SWEEP_MAXB) blocks = SWEEP_MAXB;
     float* pv = (float*)ws;
     long long* pi = (long long*)((char*)ws + (((size_t)SWEEP_MAXB * KMAX * sizeof(float) + 255) & ~(size_t)255));
     if (space->n_extra == 0)
-        hipLaunchKernelGGL(k_sweep<FV_MLP_IN>, dim3((unsigned)blocks), dim3(SWEEP_T), 0, st, params, tab,
+        hipLaunchKernelGGL(k_sweep_mfma<FV_MLP_IN>, dim3((unsigned)blocks), dim3(SWEEP_T), 0, st, params, tab,
                            (long long)begin, (long long)count, k, pv, pi);
     else
-        hipLaunchKernelGGL(k_sweep<FV_MLP_IN_SIZED>, dim3((unsigned)blocks), dim3(SWEEP_T), 0, st, params, tab,
+        hipLaunchKernelGGL(k_sweep_mfma<FV_MLP_IN_SIZED>, dim3((unsigned)blocks), dim3(SWEEP_T), 0, st, params, tab,
                            (long long)begin, (long long)count, k, pv, pi);
     hipLaunchKernelGGL(k_sweep_final, dim3(1), dim3(1024), 0, st, pv, pi, (int)(blocks * KMAX), k, top_val,
                        (long long*)top_idx);
