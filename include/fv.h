@@ -355,7 +355,8 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
                     void* workspace, size_t workspace_bytes, void* stream, fv_batch** out);
 
 /* Advances every grid of the batch state U (device) by nsteps steps, each
- * grid with its own CFL dt. */
+ * grid with its own CFL dt. The steps are replayed from HIP graphs captured
+ * at the first call for U (one of 8 steps, one of 1 step for the rest). */
 int fv_batch_step(fv_batch* b, double* U, int32_t nsteps);
 
 /* Device-clock record of each step: when history (device, max_steps *

@@ -1,5 +1,7 @@
 // C ABI of the batched fused step: many uneven 2D grids advanced together by
-// three fused stage launches per step, captured once in a HIP graph.
+// three fused stage launches per step, captured once in a HIP graph (a
+// one-step graph and a graph of GRAPH_STEPS steps, so that a long run pays one
+// graph launch per GRAPH_STEPS steps).
 #include <stdio.h>
 #include <string.h>
 
@@ -135,8 +137,8 @@ struct fv_batch {
     double* U2;
     std::vector<fvk::FGrid> by_grid;     // table entry of each grid, in the caller's order
     std::vector<fvk::FGrid> host_grids;  // the uploaded table, in work-list order
-    hipGraph_t graph;
-    hipGraphExec_t exec;
+    hipGraph_t graph, graph_many;  // one step; GRAPH_STEPS steps
+    hipGraphExec_t exec, exec_many;
     double* graph_U;
     bool graph_timed;
     unsigned long long* graph_history;  // history buffer baked into the captured graph
@@ -152,11 +154,17 @@ static int bfail(fv_batch* b, int code, const char* msg) {
     return code;
 }
 
+constexpr int GRAPH_STEPS = 8;
+
 static void drop_graph(fv_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_many) (void)hipGraphExecDestroy(b->exec_many);
+    if (b->graph_many) (void)hipGraphDestroy(b->graph_many);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->exec_many = nullptr;
+    b->graph_many = nullptr;
     b->graph_U = nullptr;
     b->graph_history = nullptr;
 }
@@ -308,6 +316,12 @@ int fv_batch_step(fv_batch* b, double* U, int32_t nsteps) {
             e = hipStreamEndCapture(b->cap, &b->graph);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            for (int s = 0; s < GRAPH_STEPS; ++s) enqueue_step(b, U, b->cap);
+            e = hipStreamEndCapture(b->cap, &b->graph_many);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec_many, b->graph_many, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             drop_graph(b);
             return bfail(b, FV_EDEVICE, "graph capture failed");
@@ -317,9 +331,11 @@ int fv_batch_step(fv_batch* b, double* U, int32_t nsteps) {
         b->graph_history = b->history;
     }
     fvk::launch_fused_init(b->waves, b->grids, b->ngrids, b->nitems, U, b->lam, b->status, b->stream);
-    for (int32_t s = 0; s < nsteps; ++s) {
-        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+    for (int32_t s = 0; s < nsteps;) {
+        const bool many = nsteps - s >= GRAPH_STEPS;
+        hipError_t e = hipGraphLaunch(many ? b->exec_many : b->exec, b->stream);
         if (e != hipSuccess) return bfail(b, FV_EDEVICE, "graph launch failed");
+        s += many ? GRAPH_STEPS : 1;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, FV_EDEVICE, hipGetErrorString(e));
