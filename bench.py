@@ -205,6 +205,27 @@ def split_leg(torch, fv, traffic, g, U0, a, samples, tune_it, sample_timing=(3, 
     return out
 
 
+def tuner_seeds_leg(torch, fv, g, U0, samples, seeds=(1, 2, 3)):
+    """The paper's method on the 2D split launch space (the 14 parameters)
+    repeated over seeds: for each seed its own 300 timed samples, network and
+    sweep, and the network's pick against the default launch and against the
+    best of its random samples (interleaved timing)."""
+    from paper_2306_14011_amd.autotune import Autotuner
+    runs = []
+    for sd in seeds:
+        at = Autotuner(g, U0, seed=sd, repeats=3, warmup=3, min_ms=20.0, check_steps=2)
+        r = at.run(count=samples, k=8, rounds=5, budget_s=120.0)
+        at.close()
+        runs.append({"seed": sd, "r2_test": round(r["r2_test"], 3),
+                     "network_over_default": round(r["network_factor_vs_default"], 4),
+                     "network_over_best_random": round(r["network_factor_vs_best_random"], 4),
+                     "shipped_from": r["shipped_from"], "shipped_over_default": round(r["factor_vs_default"], 4)})
+    f = [x["network_over_best_random"] for x in runs]
+    return {"workload": "2048x2048 vortex + bumps, split path, 14 launch parameters, 300 samples per seed",
+            "runs": runs, "network_over_best_random_mean": round(sum(f) / len(f), 4),
+            "network_over_best_random_min": min(f), "network_over_best_random_max": max(f)}
+
+
 def sized_leg(torch, inputs, seed, samples):
     """One problem-size-conditioned network (launch features plus log2 cells
     and dimension) trained on the pooled timed samples of 1024^2 and 4096^2 2D
@@ -845,6 +866,12 @@ def main():
         log(f"slip walls 2048^2: split {out['walls']['walls']['ms_per_step']:.4f} ms/step "
             f"({out['walls']['walls_over_periodic']:.3f}x the periodic grid), fused "
             f"{out['walls']['fused_walls']['ms_per_step']:.4f} ms/step ({out['walls']['fused_walls_over_periodic']:.3f}x)")
+        if not a.no_tune:
+            out["tuner_seeds"] = tuner_seeds_leg(torch, fv, g, U0, a.samples)
+            ts = out["tuner_seeds"]
+            log("tuner over seeds (2D split): network/best-random " + ", ".join(
+                f"seed {r['seed']} {r['network_over_best_random']:.3f}" for r in ts["runs"]) +
+                f"; network/default " + ", ".join(f"{r['network_over_default']:.3f}" for r in ts["runs"]))
         if not a.no_tune and not a.no_3d:
             out["sized_tuner"] = sized_leg(torch, inputs, a.seed, a.samples)
             sz = out["sized_tuner"]
