@@ -63,8 +63,8 @@ enum {
  * normal to the wall reversed, so no mass or energy crosses it. It needs at
  * least 2 cells on its axis. It runs on the split path (fv_residual,
  * fv_step, fv_adjoint_step) and on the fused path (a boundary variant of the
- * stage kernels maps ghost rows, columns and planes to the mirror cells);
- * batches return FV_EINVAL for it. */
+ * stage kernels maps ghost rows, columns and planes to the mirror cells),
+ * and in batches. */
 /* FV_BC_INFLOW holds the given conserved state fv_grid_desc.bc_state[axis]
  * [side] in the ghost cells (supersonic inflow: every characteristic enters
  * through the face; the supersonic inlet of Sec. "A Test Case" takes in its
@@ -155,9 +155,9 @@ typedef struct fv_grid_desc {
  * adds the explicit diffusion limit: the wave-speed sum of each cell gains
  * 2 (mu / rho) max(4/3, gamma / prandtl) sum_d 1 / dx_d^2. Viscous grids run
  * on the split path (fv_residual, fv_step, fv_residual_norm) and, in 2D, on
- * the fused path (a viscous variant of the stage kernels); fv_set_path
- * (FV_PATH_FUSED) on 3D viscous grids and fv_adjoint_step return FV_ENOTSUP,
- * and batches refuse them (FV_EINVAL). */
+ * the fused path (a viscous variant of the stage kernels), also in batches;
+ * fv_set_path (FV_PATH_FUSED) on 3D viscous grids and fv_adjoint_step
+ * return FV_ENOTSUP. */
 
 /* Launch parameters, two per site (FV_SITE_* order).
  *  Stencil sites (flux x/y/z): p[2s] = block width along x, a power of two in
@@ -341,8 +341,12 @@ typedef struct fv_batch fv_batch;
 enum { FV_ORDER_GIVEN = 0, FV_ORDER_LARGEST_FIRST = 1 };
 
 /* Validates the grids (2D each, each state below 4 GiB, i.e. under 2^27
- * cells) and reports the element offsets of every grid (offsets[0..ngrids],
- * host array, may be NULL) and the workspace size. */
+ * cells; every boundary kind and the viscous flux are taken, curvilinear
+ * grids are refused) and reports the element offsets of every grid
+ * (offsets[0..ngrids], host array, may be NULL) and the workspace size. A
+ * batch runs one variant of the stage kernels for all its grids: the viscous
+ * one if any grid is viscous, else the boundary one if any grid has a slip
+ * wall or an inflow face, else the plain one. */
 int fv_batch_query(int32_t ngrids, const fv_grid_desc* grids, int64_t* offsets, size_t* workspace_bytes);
 
 /* Creates a batch. seg: segment height of every grid, a multiple of 4 in

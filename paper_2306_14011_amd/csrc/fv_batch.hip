@@ -2,6 +2,7 @@
 // three fused stage launches per step, captured once in a HIP graph (a
 // one-step graph and a graph of GRAPH_STEPS steps, so that a long run pays one
 // graph launch per GRAPH_STEPS steps).
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -80,11 +81,26 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
                 snprintf(why, 256, "grid %d: hi must exceed lo", g);
                 return FV_EINVAL;
             }
-            for (int s = 0; s < 2; ++s)
-                if (d.bc[a][s] != FV_BC_PERIODIC && d.bc[a][s] != FV_BC_TRANSMISSIVE) {
+            for (int s = 0; s < 2; ++s) {
+                const int kind = d.bc[a][s];
+                if (kind != FV_BC_PERIODIC && kind != FV_BC_TRANSMISSIVE && kind != FV_BC_WALL &&
+                    kind != FV_BC_INFLOW) {
                     snprintf(why, 256, "grid %d: unknown boundary kind", g);
                     return FV_EINVAL;
                 }
+                if (kind == FV_BC_WALL && d.n[a] < 2) {
+                    snprintf(why, 256, "grid %d: a slip wall needs at least 2 cells on its axis", g);
+                    return FV_EINVAL;
+                }
+                if (kind == FV_BC_INFLOW) {
+                    const double* q = d.bc_state[a][s];
+                    const double p = (d.gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+                    if (!(q[0] > 0.0) || !(p > 0.0) || !isfinite(p)) {
+                        snprintf(why, 256, "grid %d: an inflow state needs a positive density and pressure", g);
+                        return FV_EINVAL;
+                    }
+                }
+            }
             if ((d.bc[a][0] == FV_BC_PERIODIC) != (d.bc[a][1] == FV_BC_PERIODIC)) {
                 snprintf(why, 256, "grid %d: periodic must be set on both faces", g);
                 return FV_EINVAL;
@@ -94,8 +110,12 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
             snprintf(why, 256, "grid %d: gamma must exceed 1 and cfl be positive", g);
             return FV_EINVAL;
         }
-        if (d.mu != 0.0 || d.nodes) {
-            snprintf(why, 256, "grid %d: batches take inviscid uniform grids only (mu = 0, no nodes)", g);
+        if (!(d.mu >= 0.0) || !isfinite(d.mu) || (d.mu > 0.0 && (!(d.prandtl > 0.0) || !isfinite(d.prandtl)))) {
+            snprintf(why, 256, "grid %d: viscosity must be finite and >= 0, with a positive Prandtl number", g);
+            return FV_EINVAL;
+        }
+        if (d.nodes) {
+            snprintf(why, 256, "grid %d: batches take uniform grids only (no nodes)", g);
             return FV_EINVAL;
         }
         L->offsets[g + 1] = L->offsets[g] + 4 * d.n[0] * d.n[1];
@@ -126,6 +146,7 @@ int validate_batch(int32_t ngrids, const fv_grid_desc* grids, BLayout* L, char* 
 
 struct fv_batch {
     int ngrids, waves, nitems, order;
+    int mode;  // stage-kernel variant: 0 periodic / transmissive, 1 walls or inflow faces, 2 viscous
     hipStream_t stream, cap;
     fvk::FGrid* grids;
     unsigned long long* lam;
@@ -175,11 +196,11 @@ static void enqueue_step(fv_batch* b, double* U, hipStream_t s) {
     unsigned long long* clk = b->history ? b->clk : nullptr;
     if (clk) hipLaunchKernelGGL(k_clk_reset, dim3(1), dim3(256), 0, s, b->clk, nclk);
     fvk::launch_fused_stage(0, b->waves, b->grids, b->ngrids, b->nitems, U, U, b->U1, b->lam, b->dt, nullptr,
-                            nullptr, b->status, clk, s);
+                            nullptr, b->status, clk, s, nullptr, b->mode);
     fvk::launch_fused_stage(1, b->waves, b->grids, b->ngrids, b->nitems, U, b->U1, b->U2, b->lam, b->dt,
-                            nullptr, nullptr, b->status, clk, s);
+                            nullptr, nullptr, b->status, clk, s, nullptr, b->mode);
     fvk::launch_fused_stage(2, b->waves, b->grids, b->ngrids, b->nitems, U, b->U2, U, b->lam, b->dt, nullptr,
-                            nullptr, b->status, clk, s);
+                            nullptr, b->status, clk, s, nullptr, b->mode);
     if (clk) hipLaunchKernelGGL(k_clk_store, dim3(1), dim3(256), 0, s, b->clk, nclk, b->history, b->max_steps, b->counter);
 }
 
@@ -282,6 +303,21 @@ int fv_batch_create(int32_t ngrids, const fv_grid_desc* grids, int32_t seg, int3
         G.cfl = d.cfl;
         G.gamma = d.gamma;
         G.gm1 = d.gamma - 1.0;
+        for (int a = 0; a < 2; ++a)
+            for (int sd = 0; sd < 2; ++sd)
+                for (int v = 0; v < 4; ++v) G.q[a][sd][v] = d.bc_state[a][sd][v];
+        G.mu = d.mu;
+        if (d.mu > 0.0) {
+            G.kcond = d.mu * d.gamma / ((d.gamma - 1.0) * d.prandtl);
+            const double hf = d.gamma / d.prandtl;
+            G.nu_fac = hf > 4.0 / 3.0 ? hf : 4.0 / 3.0;
+        }
+        // the stage kernels' variant: viscous if any grid is, else the
+        // boundary variant if any grid has a slip wall or an inflow face
+        for (int a = 0; a < 2; ++a)
+            for (int sd = 0; sd < 2; ++sd)
+                if ((d.bc[a][sd] == FV_BC_WALL || d.bc[a][sd] == FV_BC_INFLOW) && b->mode < 1) b->mode = 1;
+        if (d.mu > 0.0) b->mode = 2;
     }
     if (seg == 0) seg = fvk::fused_auto_seg(b->by_grid.data(), ngrids, fvk::fused_slots());
     for (int g = 0; g < ngrids; ++g) b->by_grid[g].seg = seg;

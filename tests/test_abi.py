@@ -154,6 +154,23 @@ def test_batch_query_offsets_and_validation():
     with pytest.raises(fv.FvError) as e:
         fv.fv_batch_query([inputs.grid2d(8192, 16384)])
     assert e.value.code == fv.FV_EINVAL and "4 GiB" in str(e.value)   # the library's own message
+    # slip walls, inflow faces and viscosity are taken, curvilinear grids are not
+    walled = inputs.grid2d(8, 8, bc=((2, 2), (2, 1)))
+    visc = inputs.grid2d(8, 8)
+    visc.mu, visc.prandtl = 0.01, 0.72
+    fv.fv_batch_query([walled, visc])
+    for mutate in (lambda d: setattr(d, "prandtl", 0.0), lambda d: setattr(d, "mu", -1.0)):
+        v2 = inputs.grid2d(8, 8)
+        v2.mu, v2.prandtl = 0.01, 0.72
+        mutate(v2)
+        with pytest.raises(fv.FvError):
+            fv.fv_batch_query([v2])
+    thin = inputs.grid2d(8, 1, bc=((0, 0), (2, 2)))   # a wall on an axis of one cell
+    with pytest.raises(fv.FvError):
+        fv.fv_batch_query([thin])
+    inflow = inputs.grid2d(8, 8, bc=((3, 1), (0, 0)))   # an inflow face without a physical state
+    with pytest.raises(fv.FvError):
+        fv.fv_batch_query([inflow])
 
 
 

@@ -202,5 +202,25 @@ def test_paths_that_refuse_viscosity():
         fv.fv_adjoint_step(s.ctx, s.U.data_ptr(), dt.data_ptr(), lam.data_ptr())
     assert e.value.code == fv.FV_ENOTSUP
     s.close()
-    with pytest.raises(fv.FvError):
-        fv.Batch([g], seg=0)
+
+
+def test_batch_with_viscous_walled_and_inflow_grids_matches_oracle():
+    # a batch holding the 2D viscous grids (periodic, closed box, inlet
+    # channel) and an inviscid periodic one runs the viscous variant of the
+    # stage kernels for all of them; each grid against its own oracle run
+    from paper_2306_14011_amd import fv
+    g0, U0 = inputs.vortex_case(36, seed=2)
+    grids = [CASES[0][1], CASES[1][1], CASES[2][1], g0]
+    states = [CASES[0][2], CASES[1][2], CASES[2][2], U0]
+    B = fv.Batch(grids, seg=8)
+    B.set_states(states)
+    B.step(3)
+    rc, flags = B.status()
+    got = B.get_states()
+    dts = B.dt()
+    B.close()
+    assert flags == 0
+    for gi, (g, U) in enumerate(zip(grids, states)):
+        ref, rdts, _ = oracle.run(g, U, 3)
+        assert abs(dts[gi] - rdts[-1]) <= 1e-13 * rdts[-1], gi
+        assert_pervar_close(got[gi], ref, 1e-11, f"grid {gi}")

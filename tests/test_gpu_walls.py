@@ -45,6 +45,30 @@ CASES = cases()
 IDS = [c[0] for c in CASES]
 
 
+def test_batch_with_walled_grids_matches_oracle():
+    # a batch of the 2D walled grids and a periodic vortex runs the boundary
+    # variant of the stage kernels; each grid against its own oracle run, and
+    # two schedules give the same bits
+    from paper_2306_14011_amd import fv
+    g0, U0 = inputs.vortex_case(40, seed=5)
+    grids = [CASES[0][1], CASES[1][1], g0]
+    states = [CASES[0][2], CASES[1][2], U0]
+    outs = []
+    for seg in (8, 20):
+        B = fv.Batch(grids, seg=seg)
+        B.set_states(states)
+        B.step(4)
+        rc, flags = B.status()
+        assert flags == 0
+        outs.append((B.get_states(), B.dt()))
+        B.close()
+    for gi, (g, U) in enumerate(zip(grids, states)):
+        ref, rdts, _ = oracle.run(g, U, 4)
+        assert abs(outs[0][1][gi] - rdts[-1]) <= 1e-13 * rdts[-1], gi
+        assert_pervar_close(outs[0][0][gi], ref, 1e-11, f"grid {gi}")
+        assert np.array_equal(outs[0][0][gi], outs[1][0][gi])
+
+
 @pytest.mark.parametrize("name,g,U", CASES, ids=IDS)
 def test_residual_with_walls_matches_oracle(name, g, U):
     from paper_2306_14011_amd import fv
