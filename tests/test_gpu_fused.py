@@ -373,6 +373,13 @@ def test_batch_schedules_and_graph_replays_bitwise_equal():
         got = run(*args)
         for g in range(len(base)):
             assert np.array_equal(got[g], base[g]), (args, g)
+    # 11 steps: the 8-step graph then three one-step replays, against eleven
+    # one-step replays and other splits
+    base11 = run(16, 0, 0, [11])
+    for chunks in ([1] * 11, [8, 3], [3, 8], [5, 6]):
+        got = run(16, 0, 0, chunks)
+        for g in range(len(base11)):
+            assert np.array_equal(got[g], base11[g]), (chunks, g)
 
 
 def test_batch_per_grid_schedules_bitwise_equal_and_validated():
