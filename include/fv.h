@@ -187,7 +187,11 @@ int fv_query(const fv_grid_desc* g, int64_t strides_out[4], size_t* workspace_by
  * device buffer of at least the queried size, 256-byte aligned, owned by the
  * caller and used exclusively by this context until fv_destroy. stream is a
  * hipStream_t (NULL = the default stream). The launch table starts at the
- * defaults and the status word at 0. */
+ * defaults and the status word at 0. On grids the fused path takes, it also
+ * uploads the fused path's per-stage tables at the library's choice (used
+ * by fv_adjoint_step's forward recomputation whichever path is selected) and
+ * synchronises the stream once to do so: create contexts outside stream
+ * capture. */
 int fv_create(const fv_grid_desc* g, void* workspace, size_t workspace_bytes, void* stream,
               fv_ctx** out);
 
