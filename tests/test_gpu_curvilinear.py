@@ -168,6 +168,35 @@ def test_curvilinear_fused_steps_match_oracle(name, g, U, limiter):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("limiter", [True, False], ids=["minmod", "unlimited"])
+def test_curvilinear_fused_several_strips(limiter):
+    # wider than one 60-column strip, with ragged last strips and segments:
+    # a wavy grid with walls on both y sides, and the ramp inlet at 131 x 45
+    import torch
+    from paper_2306_14011_amd import fv
+    g = inputs.grid2d(143, 61, hi=(3.0, 1.2), bc=((1, 1), (WALL, WALL)))
+    nodes = inputs.wavy_nodes(143, 61, hi=(3.0, 1.2), amp=0.03)
+    cases_ = [("wavy_walls", curved(g, nodes), wavy_state(g, nodes, 6)), ("ramp", *ramp_inlet(131, 45))]
+    for name, h, U in cases_:
+        h = spec_with(h, limiter)
+        outs = []
+        for seg, waves in (([0, 0, 0], [0, 0, 0]), ([8, 16, 12], [5, 0, 40])):
+            s = fv.Solver(h)
+            s.set_path(fv.FV_PATH_FUSED, 0, 0)
+            s.set_fused_launch(seg, waves)
+            s.set_state(U)
+            dts = torch.zeros(3, dtype=torch.float64, device="cuda")
+            s.step(3, dt_out=dts)
+            rc, flags = s.status()
+            assert flags == 0
+            outs.append((s.get_state(), dts.cpu().numpy()))
+            s.close()
+        ref, rdt, _ = oracle.run(h, U, 3, limiter=limiter)
+        assert np.allclose(outs[0][1], rdt, rtol=1e-13, atol=0), name
+        assert_pervar_close(outs[0][0], ref, 1e-11, name)
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), name
+
+
 def test_curvilinear_fused_source_matches_oracle():
     # the source term on a curvilinear grid enters as -area S per cell
     import torch

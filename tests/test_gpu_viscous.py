@@ -184,6 +184,36 @@ def test_viscous_fused_path_matches_oracle(name, g, U):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_viscous_fused_path_several_strips():
+    # wider than one 60-column strip, with a ragged last strip and a ragged
+    # last segment: a walled channel with an inflow face and a periodic grid
+    import torch
+    from paper_2306_14011_amd import fv
+    ga = inlet_state(viscous(inputs.grid2d(151, 53, hi=(3.0, 1.0), bc=((INFLOW, 1), (WALL, WALL))), 0.01))
+    x, y, _ = ga.centres()
+    q = ga.bc_state[0, 0]
+    Ua = np.broadcast_to(q[:4, None, None, None], ga.shape).copy()
+    Ua *= 1.0 + 0.2 * np.exp(-((x - 1.2) ** 2 + (y - 0.5) ** 2) / 0.02)[None]
+    gb = viscous(inputs.grid2d(127, 70, hi=(1.8, 1.0)), 0.03)
+    for name, g, U in (("channel", ga, Ua), ("periodic", gb, smooth(gb, 9))):
+        outs = []
+        for seg, waves in (([0, 0, 0], [0, 0, 0]), ([12, 8, 20], [7, 0, 33])):
+            s = fv.Solver(g)
+            s.set_path(fv.FV_PATH_FUSED, 0, 0)
+            s.set_fused_launch(seg, waves)
+            s.set_state(U)
+            dts = torch.zeros(3, dtype=torch.float64, device="cuda")
+            s.step(3, dt_out=dts)
+            rc, flags = s.status()
+            assert flags == 0
+            outs.append((s.get_state(), dts.cpu().numpy()))
+            s.close()
+        ref, rdt, _ = oracle.run(g, U, 3)
+        assert np.allclose(outs[0][1], rdt, rtol=1e-13, atol=0), name
+        assert_pervar_close(outs[0][0], ref, 1e-11, name)
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), name
+
+
 def test_paths_that_refuse_viscosity():
     import torch
     from paper_2306_14011_amd import fv

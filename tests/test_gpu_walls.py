@@ -45,6 +45,35 @@ CASES = cases()
 IDS = [c[0] for c in CASES]
 
 
+def test_fused_walls_several_strips():
+    # a closed box wider than one 60-column strip (x walls in the first and the
+    # ragged last strip), van Leer and minmod, against the oracle; two
+    # per-stage tables give the same bits
+    import torch
+    from paper_2306_14011_amd import fv
+    g = inputs.grid2d(133, 47, hi=(2.0, 0.8), bc=((WALL, WALL), (WALL, WALL)))
+    U = pulse(g, 7)
+    for lim in (True, "vanleer"):
+        h = g if lim is True else __import__("copy").copy(g)
+        h.limiter = lim
+        outs = []
+        for seg, waves in (([0, 0, 0], [0, 0, 0]), ([8, 20, 12], [3, 0, 21])):
+            s = fv.Solver(h)
+            s.set_path(fv.FV_PATH_FUSED, 0, 0)
+            s.set_fused_launch(seg, waves)
+            s.set_state(U)
+            dts = torch.zeros(4, dtype=torch.float64, device="cuda")
+            s.step(4, dt_out=dts)
+            rc, flags = s.status()
+            assert flags == 0
+            outs.append((s.get_state(), dts.cpu().numpy()))
+            s.close()
+        ref, rdt, _ = oracle.run(h, U, 4, limiter=lim)
+        assert np.allclose(outs[0][1], rdt, rtol=1e-13, atol=0), lim
+        assert_pervar_close(outs[0][0], ref, 1e-11, f"box {lim}")
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), lim
+
+
 def test_batch_with_walled_grids_matches_oracle():
     # a batch of the 2D walled grids and a periodic vortex runs the boundary
     # variant of the stage kernels; each grid against its own oracle run, and
