@@ -74,6 +74,36 @@ def test_fused_walls_several_strips():
         assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), lim
 
 
+def test_fused3d_walls_several_tiles():
+    # a 3D grid of several 32 x 7 tiles in x and y, walls on both x sides and
+    # the low y side, an inflow face on the high z side, transmissive low z:
+    # against the oracle, and two per-stage tables give the same bits
+    import math
+    import torch
+    from paper_2306_14011_amd import fv
+    g = inputs.grid3d(71, 23, 19, bc=((WALL, WALL), (WALL, 1), (1, 3)))
+    q = np.zeros((3, 2, 5))
+    q[2, 1] = (1.0, 0.1, 0.0, -0.9 * math.sqrt(g.gamma), 1.0 / (g.gamma - 1.0) + 0.5 * (0.01 + 0.81 * g.gamma))
+    g.bc_state = q
+    U = pulse(g, 11)
+    outs = []
+    for seg, waves in (([0, 0, 0], [0, 0, 0]), ([8, 4, 12], [5, 0, 9])):
+        s = fv.Solver(g)
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+        s.set_fused_launch(seg, waves)
+        s.set_state(U)
+        dts = torch.zeros(3, dtype=torch.float64, device="cuda")
+        s.step(3, dt_out=dts)
+        rc, flags = s.status()
+        assert flags == 0
+        outs.append((s.get_state(), dts.cpu().numpy()))
+        s.close()
+    ref, rdt, _ = oracle.run(g, U, 3)
+    assert np.allclose(outs[0][1], rdt, rtol=1e-13, atol=0)
+    assert_pervar_close(outs[0][0], ref, 1e-11, "walls 3d")
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_batch_with_walled_grids_matches_oracle():
     # a batch of the 2D walled grids and a periodic vortex runs the boundary
     # variant of the stage kernels; each grid against its own oracle run, and
