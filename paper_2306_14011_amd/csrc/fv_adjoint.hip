@@ -88,6 +88,15 @@ __device__ __forceinline__ void adj_axis(const double* __restrict__ Us, const do
     const bool periodic = lo == 0;
     const long long st = AX == 0 ? 1 : (AX == 1 ? g.sy : g.sz);
     const long long wst = AX == 0 ? 1 : (AX == 1 ? g.n[0] : (long long)g.n[0] * g.n[1]);
+    // the inflow states of this axis's two faces, read with constant indices
+    // and picked per stencil cell by a select (a run-time index into the
+    // table would move it to scratch memory)
+    double q_lo[NV], q_hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        q_lo[v] = bcs.q[AX][0][v];
+        q_hi[v] = bcs.q[AX][1][v];
+    }
     for (int fi = threadIdx.x; fi < NF; fi += ADJ_T) {
         int p[3];
         p[0] = o[0] + fi % EX;
@@ -113,7 +122,7 @@ __device__ __forceinline__ void adj_axis(const double* __restrict__ Us, const do
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     if (src < 0) {
-                        q[s][v] = bcs.q[AX][pos < 0 ? 0 : 1][v];
+                        q[s][v] = pos < 0 ? q_lo[v] : q_hi[v];
                     } else {
                         const double x = Us[v * g.sv + line + src * st];
                         q[s][v] = (flip && v == 1 + AX) ? -x : x;

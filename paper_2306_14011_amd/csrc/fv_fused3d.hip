@@ -346,8 +346,10 @@ __device__ __forceinline__ void tile_of_item(const FGrid3& G, int item, int& tx0
     k0 = (r / tiles_y) * G.seg;
 }
 
+// At least 2 waves per SIMD: the stage-3 kernel with the ghost rules and a
+// source term would take 257 registers and run at 1 wave per SIMD.
 template <int STAGE, bool SRC, bool BC>
-__global__ void __launch_bounds__(T3) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
+__global__ void __launch_bounds__(T3) __attribute__((amdgpu_waves_per_eu(2))) k_fused3d(const FGrid3* __restrict__ grid, int nitems, const double* Un,
                                                 const double* __restrict__ Us, double* Ud,
                                                 unsigned long long* __restrict__ lam, double* __restrict__ dtg,
                                                 const double* __restrict__ dt_fixed, double* __restrict__ dt_out,

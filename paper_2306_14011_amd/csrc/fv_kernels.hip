@@ -104,7 +104,13 @@ __device__ __forceinline__ void visc_cell(const double* __restrict__ U, const Ge
     double sg[NDIM];
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) sg[d] = 1.0;
-    const double* fixed = nullptr;
+    // the first inflow face crossed gives the state; its side is picked by a
+    // select between constant indices (a run-time index into the table would
+    // move it to scratch memory)
+    bool fixed = false;
+    double fq[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fq[v] = 0.0;
 #pragma unroll
     for (int a = 0; a < NDIM; ++a) {
         const int n = g.n[a];
@@ -112,7 +118,11 @@ __device__ __forceinline__ void visc_cell(const double* __restrict__ U, const Ge
         if (x < 0 || x >= n) {
             const int side = x < 0 ? 0 : 1;
             const int kind = g.bc[a][side];
-            if (kind == 3 && !fixed) fixed = bcs.q[a][side];
+            if (kind == 3 && !fixed) {
+                fixed = true;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) fq[v] = side ? bcs.q[a][1][v] : bcs.q[a][0][v];
+            }
             if (kind == 0) p[a] = x < 0 ? x + n : x - n;
             else if (kind == 2) {
                 p[a] = x < 0 ? -1 - x : 2 * n - 1 - x;
@@ -123,7 +133,7 @@ __device__ __forceinline__ void visc_cell(const double* __restrict__ U, const Ge
     double q[NV];
     if (fixed) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = fixed[v];
+        for (int v = 0; v < NV; ++v) q[v] = fq[v];
     } else {
         const int o = g.off0 + p[0] + p[1] * g.sy + (NDIM == 3 ? p[2] * g.sz : 0);
 #pragma unroll
