@@ -84,10 +84,13 @@ def test_every_kernel_runs_two_waves_per_simd(kernels):
 
 def test_headline_stage_kernels_run_three_waves_per_simd(kernels):
     # the periodic / transmissive 2D stage kernels without a source term
-    # (k_fused2d<STAGE, false, 0>) and the matrix-core sweep
+    # (k_fused2d<STAGE, false, 0>), the curvilinear stage-1 kernel without a
+    # source (k_fused2d<0, false, 3>, which asks for three waves) and the
+    # matrix-core sweep
     names = [n for n in kernels if "k_fused2dILi" in n and "ELb0ELi0EE" in n] + \
+            [n for n in kernels if "k_fused2dILi0ELb0ELi3EE" in n] + \
             [n for n in kernels if "k_sweep_mfma" in n]
-    assert len(names) >= 4
+    assert len(names) >= 5
     for n in names:
         assert waves_per_simd(kernels[n]["vgpr"]) >= 3, (n, kernels[n]["vgpr"])
 
