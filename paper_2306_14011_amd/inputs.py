@@ -221,6 +221,16 @@ def vortex_bumps_case(n=2048, seed=0, beta=5.0):
     return g, gaussian_bumps(g, U, seed)
 
 
+def tiled_case(g, U, k):
+    """k x k copies of the periodic 2D state U of grid g on a box k times as
+    long in x and y: the same cell size and flow, k^2 times the cells."""
+    if g.ndim != 2 or any(tuple(b) != (0, 0) for b in g.bc[:2]):
+        raise ValueError("tiled_case needs a periodic 2D grid")
+    hi = (g.lo[0] + k * (g.hi[0] - g.lo[0]), g.lo[1] + k * (g.hi[1] - g.lo[1]))
+    gk = grid2d(g.n[0] * k, g.n[1] * k, lo=(g.lo[0], g.lo[1]), hi=hi, bc=g.bc[:2], cfl=g.cfl, gamma=g.gamma)
+    return gk, np.ascontiguousarray(np.tile(U, (1, 1, k, k)))
+
+
 def sod3d_case(n=256, seed=0):
     """Rotated Sod tube on [0,1]^3, transmissive x faces, periodic y/z."""
     g = grid3d(n, n, n)

@@ -493,3 +493,17 @@ def test_batch_full_workload_against_oracle():
     for g, (gs, U0) in enumerate(zip(spec.grids, spec.states)):
         single, _, _ = run_fused(gs, U0, 3, seg=0)
         assert np.array_equal(got[g], single), g
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_fused_tiled_grid_is_the_tiling(k):
+    # k x k periodic copies of a state step to the k x k copies of its step,
+    # bit for bit (the same stencils and the same largest wave speed); the
+    # tiled grids cross other strip and segment boundaries than the original
+    g, U = inputs.vortex_bumps_case(96, seed=5)
+    gk, Uk = inputs.tiled_case(g, U, k)
+    got, dts, flags = run_fused(gk, Uk, 3, seg=0)
+    ref, dts1, flags1 = run_fused(g, U, 3, seg=0)
+    assert flags == 0 and flags1 == 0
+    assert np.array_equal(dts, dts1)
+    assert np.array_equal(got, np.tile(ref, (1, 1, k, k)))

@@ -229,3 +229,20 @@ def test_sod_matches_exact_solution():
             assert abs(rho[sel].mean() - gold["rho_star_L"]) < 0.01 * gold["rho_star_L"]
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert errs[0] < 0.02 and all(r > 0.6 for r in rates), (errs, rates)
+
+
+def test_tiled_case_is_a_periodic_copy():
+    # k x k copies of a periodic state on a box k times as long: every cell
+    # sees the same stencil and the grid the same largest wave speed, so two
+    # steps of the tiled grid are the tiling of two steps of the original
+    g, U = inputs.vortex_bumps_case(32, seed=3)
+    g2, U2 = inputs.tiled_case(g, U, 2)
+    assert g2.n[:2] == (64, 64) and np.allclose(g2.dx[:2], g.dx[:2], rtol=1e-15)
+    R, dts, _ = oracle.run(g, U, 2)
+    R2, dts2, _ = oracle.run(g2, U2, 2)
+    assert np.allclose(dts2, dts, rtol=1e-14, atol=0)
+    T = np.tile(R, (1, 1, 2, 2))
+    for v in range(g.nvar):
+        assert np.abs(R2[v] - T[v]).max() <= 1e-13 * np.abs(T[v]).max(), v
+    with pytest.raises(ValueError):
+        inputs.tiled_case(inputs.grid2d(8, 8, bc=((1, 1), (0, 0))), np.zeros((4, 1, 8, 8)), 2)
