@@ -15,6 +15,13 @@ space predicted, top 8 re-measured).
 Other legs (each reported in its own field):
   split_3d  256^3 rotated Sod, split path, default vs tuned (x/y/z fluxes separately),
             and the same workload on the fused path
+  sizes     the headline state tiled 2 x 2 and 4 x 4 (4096^2, 8192^2): the fused rate beyond the
+            last-level cache
+  schemes, source, curvilinear, viscous, walls
+            the fused and split paths on the MUSCL family, a source term, a wavy curvilinear
+            grid, the Navier-Stokes flux and a closed box with slip walls
+  tuner_seeds, sized_tuner
+            the paper's tuning loop over three seeds, and the size-conditioned network
   small     64^2 vortex: fused by direct launches vs graph-replayed batch of one
   batch     96 uneven 2D grids, fused stages in a HIP graph, schedule (segment height per
             grid-size bucket, work-list order) chosen by the MLP autotuner; p50/p99 per-grid step time
@@ -309,6 +316,31 @@ def fused_leg(torch, fv, traffic, g, U0, a):
                      "alu_achieved_TFLOPs": k["achieved_TFLOPs"],
                      "alu_frac": round(k["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4)},
     }
+
+
+def sizes_leg(torch, fv, inputs, traffic, g, U0, steps, stream_gbps):
+    """The headline step on 2 x 2 and 4 x 4 periodic tilings of the headline
+    state (4096^2 and 8192^2 cells, the same cell size and flow). A stage there
+    reads and writes 1.6 and 6.4 GB, far beyond the 256 MB last-level cache,
+    which the 2048^2 stage (0.4 GB) partly fits in: the algorithmic rate of
+    these grids is an HBM rate."""
+    out = {"workload": "2 x 2 and 4 x 4 periodic tilings of the 2048x2048 vortex + bumps state, fused path, "
+                       "library's table"}
+    for k in (2, 4):
+        gk, Uk = inputs.tiled_case(g, U0, k)
+        s = fv.Solver(gk)
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+        ms = timed_steps(torch, s, Uk, steps, 3)
+        st = site_table(s, gk, 5, fv, traffic)["fused"]
+        seg, waves = s.get_fused_launch()
+        s.close()
+        del Uk
+        gbps = traffic.fused_step_bytes(gk) / 3.0 / (st["avg_us"] * 1e-6) / 1e9
+        out[f"{gk.n[0]}x{gk.n[1]}"] = {
+            "ms_per_step": round(ms, 4), "value": gk.ncells / (ms * 1e-3), "table": {"seg": seg, "waves": waves},
+            "stage_avg_us": st["avg_us"], "alg_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "frac_of_measured_stream": round(gbps / stream_gbps, 4)}
+    return out
 
 
 def schemes_leg(torch, fv, traffic, g, U0, steps):
@@ -845,6 +877,10 @@ def main():
     out["roofline"]["frac_of_measured_stream"] = round(out["roofline"]["achieved"] /
                                                        out["copy"]["read2_write1"]["GBps"], 4)
     if not a.quick:
+        out["sizes"] = sizes_leg(torch, fv, inputs, traffic, g, U0, 30, out["copy"]["read2_write1"]["GBps"])
+        log("fused path beyond the last-level cache: " + ", ".join(
+            f"{n} {r['ms_per_step']:.4f} ms/step, {r['alg_GBps']:.0f} GB/s ({r['frac']:.3f} of 8 TB/s)"
+            for n, r in out["sizes"].items() if n != "workload"))
         out["small"] = small_leg(torch, fv, inputs)
         out["schemes"] = schemes_leg(torch, fv, traffic, g, U0, 50)
         log("schemes (fused 2D): " + ", ".join(f"{k} {v['ms_per_step']:.4f} ms" for k, v in out["schemes"].items()))
