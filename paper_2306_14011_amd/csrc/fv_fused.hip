@@ -118,20 +118,25 @@ int fused_slots() {
     return b * 4 * cus;
 }
 
-// Segment height for a set of grids: the multiple of 4, at most 24, that
+// Segment height for a set of grids: the multiple of 4, at most 24 rows
+// (16 when 24-row items fill the resident waves more than twice), that
 // minimises (rounds of resident waves) x (rows per item + 1), the item's
 // critical path in rows (one extra y face per item). Ties go to the taller
 // segment, which re-reads fewer halo rows. Without the bound the rule picks
 // tall segments for grids that take many rounds (96 rows at 4096^2, 124 at
-// 8192^2), which measured slower than 24 rows (4.31 against 4.11 ms per step
-// at 8192^2). A likely reason: with short segments the waves resident at
-// one time cover fewer rows, so the halo rows they share are more often
-// still in L2.
+// 8192^2), which measured slower: at 8192^2, 4.29 ms per step against 4.07
+// with 16 rows; at 4096^2, 16 rows ran 4.5% faster than 24, and at 2048^2
+// (one round of 24-row items) 24 rows ran 6% faster than 16. A likely
+// reason: with short segments the waves resident at one time cover fewer
+// rows, so the halo rows they share are more often still in L2.
 int fused_auto_seg(const FGrid* grids, int ngrids, int slots) {
     if (slots <= 0) return 16;
+    long long items24 = 0;
+    for (int g = 0; g < ngrids; ++g) items24 += (long long)fused_items(grids[g], 24);
+    const int max_seg = items24 > 2LL * slots ? 16 : 24;
     int best = 16;
     double best_cost = 0.0;
-    for (int seg = 4; seg <= 24; seg += 4) {
+    for (int seg = 4; seg <= max_seg; seg += 4) {
         long long items = 0;
         for (int g = 0; g < ngrids; ++g) items += (long long)fused_items(grids[g], seg);
         const long long rounds = (items + slots - 1) / slots;
