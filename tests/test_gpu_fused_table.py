@@ -82,3 +82,36 @@ def test_fused_tuning_loop_end_to_end():
     assert res["tuned_ms"] == min(res["default_ms"], res["network_ms"], res["best_random_ms"])
     net = res["network_launch"]
     assert all(net[2 * st] in FUSED_SEGS for st in range(3))
+
+
+def _auto_seg_rule(nx, ny, slots):
+    # the library's choice of the 2D segment height, restated: the multiple
+    # of 4 up to 24 rows (16 when 24-row items fill the resident waves more
+    # than twice) that minimises rounds x (rows + 1), ties to the taller
+    strips = -(-nx // 60)
+
+    def items(seg):
+        return strips * (-(-ny // seg))
+
+    max_seg = 16 if items(24) > 2 * slots else 24
+    best, best_cost = 16, None
+    for seg in range(4, max_seg + 1, 4):
+        cost = (-(-items(seg) // slots)) * (seg + 1)
+        if best_cost is None or cost <= best_cost:
+            best, best_cost = seg, cost
+    return best
+
+
+def test_automatic_segment_height():
+    from paper_2306_14011_amd import fv
+    got = {}
+    for nx, ny in ((64, 64), (300, 70), (2048, 2048), (4096, 4096)):
+        s = fv.Solver(inputs.grid2d(nx, ny))
+        s.set_path(fv.FV_PATH_FUSED, 0, 0)
+        slots = fv.fv_fused_slots(s.ctx)
+        got[nx] = s.get_path()[1]
+        s.close()
+        assert got[nx] == _auto_seg_rule(nx, ny, slots), (nx, ny, slots, got[nx])
+    # on a full MI355X (3072 wave slots): 24 rows at 2048^2, 16 at 4096^2
+    if slots == 3072:
+        assert got[2048] == 24 and got[4096] == 16
